@@ -1,0 +1,93 @@
+"""Small numpy helpers the tests use to check the oracle and the HIP library
+from outside: lattice reshapes, K(x), unitarity, Gell-Mann matrices, random
+SU(2)/SU(3) elements.  Nothing here is called by either implementation."""
+from __future__ import annotations
+
+import numpy as np
+
+SQ3 = np.sqrt(3.0)
+
+# Gell-Mann matrices, tr(l_a l_b) = 2 delta_ab
+GELLMANN = np.zeros((8, 3, 3), dtype=np.complex128)
+GELLMANN[0][0, 1] = GELLMANN[0][1, 0] = 1
+GELLMANN[1][0, 1] = -1j
+GELLMANN[1][1, 0] = 1j
+GELLMANN[2][0, 0] = 1
+GELLMANN[2][1, 1] = -1
+GELLMANN[3][0, 2] = GELLMANN[3][2, 0] = 1
+GELLMANN[4][0, 2] = -1j
+GELLMANN[4][2, 0] = 1j
+GELLMANN[5][1, 2] = GELLMANN[5][2, 1] = 1
+GELLMANN[6][1, 2] = -1j
+GELLMANN[6][2, 1] = 1j
+GELLMANN[7] = np.diag([1, 1, -2]) / SQ3
+
+PAULI = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]], [[1, 0], [0, -1]]], dtype=np.complex128)
+
+
+def dag(a):
+    return np.conj(np.swapaxes(a, -1, -2))
+
+
+def as_grid(dims, U):
+    """(V, 4, 3, 3) -> (Lt, Lz, Ly, Lx, 4, 3, 3) view"""
+    return U.reshape(*dims, 4, 3, 3)
+
+
+def backward(dims, U, mu):
+    """U_mu(x - mu) for every x, as a (Lt, Lz, Ly, Lx, 3, 3) array"""
+    G = as_grid(dims, U)
+    return np.roll(G[..., mu, :, :], 1, axis=mu)
+
+
+def K_field(dims, U):
+    """K(x) = sum_mu U_mu(x) + U_mu(x - mu)^dag on every site"""
+    G = as_grid(dims, U)
+    K = np.zeros(tuple(dims) + (3, 3), dtype=np.complex128)
+    for mu in range(4):
+        K += G[..., mu, :, :] + dag(backward(dims, U, mu))
+    return K
+
+
+def unitarity_error(U):
+    M = U.reshape(-1, 3, 3)
+    e1 = np.abs(M @ dag(M) - np.eye(3)).max()
+    e2 = np.abs(np.linalg.det(M) - 1.0).max()
+    return max(e1, e2)
+
+
+def parity_grid(dims):
+    t, z, y, x = np.meshgrid(*[np.arange(L) for L in dims], indexing="ij")
+    return (t + z + y + x) % 2
+
+
+def random_su2(rng, n):
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q
+
+
+def quat_matrix(q):
+    """s(q) = q0 + i q.sigma as 2x2 matrices, q of shape (..., 4)"""
+    q = np.asarray(q)
+    m = np.zeros(q.shape[:-1] + (2, 2), dtype=np.complex128)
+    m[..., 0, 0] = q[..., 0] + 1j * q[..., 3]
+    m[..., 0, 1] = q[..., 2] + 1j * q[..., 1]
+    m[..., 1, 0] = -q[..., 2] + 1j * q[..., 1]
+    m[..., 1, 1] = q[..., 0] - 1j * q[..., 3]
+    return m
+
+
+def random_su3(rng, n):
+    Z = (rng.normal(size=(n, 3, 3)) + 1j * rng.normal(size=(n, 3, 3))) / np.sqrt(2)
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R, axis1=1, axis2=2)
+    Q = Q * (d / np.abs(d))[:, None, :]
+    det = np.linalg.det(Q)
+    return Q * (det ** (-1.0 / 3.0))[:, None, None]
+
+
+def expm_hermitian(H, eps):
+    """exp(i eps H) for Hermitian H via its eigendecomposition"""
+    w, v = np.linalg.eigh(H)
+    return (v * np.exp(1j * eps * w)[..., None, :]) @ dag(v)
