@@ -1,0 +1,222 @@
+/*
+ * lgf.h -- C ABI of the MI355X (gfx950) lattice Landau gauge-fixing library.
+ *
+ * The library runs the checkerboard SU(3) relaxation of M. Schroeck and
+ * H. Vogt, "Gauge fixing in lattice QCD with multi-GPUs" (arXiv:1305.3440):
+ * for every site of one parity it gathers the 8 links touching the site into
+ * K(x) (Eq. (8)), maximises Re tr[g(x) K(x)] (Eq. (7)) through the three
+ * Cabibbo-Marinari SU(2) subgroups (Eq. (9), Sec. 3) with overrelaxation
+ * (Sec. 3.1) or stochastic relaxation (Sec. 3.2), applies g(x) to the 8 links
+ * (Eq. (3)), and measures the functional F (Eq. (2)) and the precision theta
+ * (Eqs. (4)-(5)), repeating until theta reaches a target (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *  - dims = {Lt, Lz, Ly, Lx}, each even and >= 2 (the checkerboard needs even
+ *    periodic extents), V = Lt*Lz*Ly*Lx <= 2^31.  Direction mu = 0 is t, 1 z,
+ *    2 y, 3 x.  Site index s = ((t*Lz + z)*Ly + y)*Lx + x; parity of a site is
+ *    (t+z+y+x) mod 2.
+ *  - Canonical link array (host or device): double[V][4][3][3][2]
+ *    (site, mu, row, column, re/im), 72 doubles per site, 4*V links.
+ *  - Device layouts are private to the library; only the canonical array
+ *    crosses the boundary.
+ *  - Every call enqueues its GPU work on the handle's stream.  Calls that
+ *    return host values (measure, store, peek, gauge_fix, ...) synchronise that
+ *    stream before returning.  A handle must not be used from two host threads
+ *    at once.
+ *  - Errors: every entry point returns an lgf_status and never throws;
+ *    lgf_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef LGF_H
+#define LGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LGF_OK = 0,
+    LGF_EINVAL = 1,   /* bad argument: null pointer, odd extent, omega/p out of range, size mismatch */
+    LGF_ENOMEM = 2,   /* device or host allocation failed */
+    LGF_EHIP = 3,     /* a HIP runtime call failed; lgf_last_error() has its message */
+    LGF_ENOTCONV = 4, /* gauge_fix reached max_sweeps; the result is still filled in */
+    LGF_ENUMERIC = 5, /* F or theta came out NaN or infinite */
+    LGF_ESTATE = 6    /* the operation is not valid in the handle's current state */
+} lgf_status;
+
+/* Link storage formats.  FP64_18 / FP32_18 store all 9 complex entries;
+ * the _12 formats store rows 0 and 1 and rebuild row 2 = conj(row0 x row1)
+ * in registers (exact for SU(3)).  Arithmetic is done in the storage
+ * precision, except reunitarization and the F/theta reductions, which are FP64
+ * for every format. */
+typedef enum {
+    LGF_FP64_18 = 0,
+    LGF_FP32_18 = 1,
+    LGF_FP32_12 = 2,
+    LGF_FP64_12 = 3
+} lgf_format;
+
+typedef struct lgf_lattice lgf_lattice;   /* opaque handle: one lattice on one GPU */
+
+/* Parameters of lgf_gauge_fix (Sec. 4: sweep the two parities in turn and
+ * iterate until the requested precision).  Defaults: lgf_fix_params_default. */
+typedef struct {
+    double omega;          /* overrelaxation parameter, [1, 2] (Sec. 3.1) */
+    double p_sr;           /* stochastic-relaxation probability, [0, 1] (Sec. 3.2) */
+    double theta_target;   /* stop at the first measurement with theta < target */
+    double theta_switch;   /* mixed precision: leave bulk_format once theta < switch (0 = never) */
+    int bulk_format;       /* format of the bulk sweeps (lgf_format); the handle's own when equal */
+    int check_every;       /* sweeps between reunitarize + measure, >= 1 (default 20) */
+    int use_graph;         /* capture each chunk of check_every sweeps in a hipGraph (default 1) */
+    int reserved;
+    int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
+    uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
+    uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
+} lgf_fix_params;
+
+/* Outcome of lgf_gauge_fix.  Times are in milliseconds, taken with HIP events
+ * on the handle's stream. */
+typedef struct {
+    int64_t sweeps;        /* full sweeps done (a multiple of check_every unless max_sweeps cut it) */
+    int64_t sweeps_bulk;   /* of which in bulk_format */
+    double theta;          /* last measured theta (Eq. (5)) */
+    double F;              /* last measured F (Eq. (2)) */
+    int status;            /* LGF_OK or LGF_ENOTCONV / LGF_ENUMERIC */
+    int n_history;         /* measurements written to the history buffer */
+    double t_total_ms;     /* wall time of the whole call (host clock, links resident) */
+    double t_sweep_bulk_ms;   /* sweep kernels in bulk_format */
+    double t_sweep_finish_ms; /* sweep kernels in the handle's format */
+    double t_measure_ms;   /* reunitarize + measure */
+    double t_convert_ms;   /* format conversions */
+} lgf_fix_result;
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *lgf_last_error(void);
+
+/* Library version string. */
+const char *lgf_version(void);
+
+/* Fill *p with the defaults: omega 1.7, p_sr 0, theta_target 1e-14,
+ * theta_switch 0, bulk_format -1 (= handle's format), check_every 20,
+ * use_graph 1, max_sweeps 100000, seed 0, sweep_offset 0. */
+lgf_status lgf_fix_params_default(lgf_fix_params *p);
+
+/* Device bytes of a link field of the given dims in the given format
+ * (4*V links of 18 or 12 reals); 0 for invalid arguments. */
+size_t lgf_required_bytes(const int dims[4], int format);
+
+/* Create a handle for a lattice.
+ *  stream:     hipStream_t the handle enqueues on; NULL makes the library
+ *              create its own (blocking, default-priority) stream.
+ *  device_buf: NULL makes the library allocate the link field; otherwise a
+ *              device buffer of at least lgf_required_bytes(dims, format) bytes
+ *              that the handle borrows (the caller keeps it alive until
+ *              lgf_destroy, and the library never frees it).
+ * The links are uninitialised until lgf_load_links or lgf_generate_links. */
+lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_buf,
+                      size_t buf_bytes, lgf_lattice **out);
+
+/* Release the handle and everything it owns (never a borrowed buffer).
+ * NULL is allowed and does nothing. */
+lgf_status lgf_destroy(lgf_lattice *h);
+
+/* Current storage format and dims of a handle. */
+lgf_status lgf_get_info(const lgf_lattice *h, int dims[4], int *format);
+
+/* Copy a canonical host array (n_doubles == 72*V) into the handle's layout and
+ * format (rounding to FP32 and dropping row 2 where the format says so).  The
+ * host pointer is read only during the call. */
+lgf_status lgf_load_links(lgf_lattice *h, const double *host_canon, size_t n_doubles);
+
+/* Copy the links out to a canonical host array (n_doubles == 72*V); _12
+ * formats have row 2 rebuilt. */
+lgf_status lgf_store_links(lgf_lattice *h, double *host_canon, size_t n_doubles);
+
+/* Gather the 4 links U_mu(s) of each listed site (host array of n_sites site
+ * indices, each in [0, V)) into host_out, n_sites*72 doubles in canonical
+ * order.  For spot checks of large lattices without copying the whole field. */
+lgf_status lgf_peek_links(lgf_lattice *h, const int64_t *sites, int64_t n_sites,
+                          double *host_out);
+
+/* Fill the field with the seeded synthetic links: for every link
+ * U = exp(i eps sum_j a_j lambda_j) with a_j ~ N(0,1) (Gell-Mann lambda_j,
+ * tr lambda_a lambda_b = 2 delta_ab), projected onto SU(3); if haar != 0 each
+ * link is then gauge transformed, U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag
+ * (Eq. (3)), by a Haar-random g(x).  Normals come from Philox4x32-10 keyed by
+ * the seed, counter (s, mu, call, 1) for a_j and (s, 0, call, 2) for g(s),
+ * through Box-Muller with uniforms (w + 1/2) 2^-32.  eps >= 0. */
+lgf_status lgf_generate_links(lgf_lattice *h, uint64_t seed, double eps, int haar);
+
+/* Change the storage format of the handle (allocates the new field, converts,
+ * frees the old one).  Conversions into an FP64 format reunitarize in FP64.
+ * LGF_ESTATE for a handle with a borrowed buffer. */
+lgf_status lgf_convert(lgf_lattice *h, int format);
+
+/* One half-sweep (parity 0 or 1) or a full sweep (parity 2: parity 0 then 1)
+ * of the relaxation (Sec. 3, Sec. 4): every site x of the parity gets
+ * K = sum_mu U_mu(x) + U_mu(x-mu)^dag (Eq. (8) with the neighbour g's already
+ * applied to the links), then for the subgroups (0,1), (0,2), (1,2) the SU(2)
+ * maximum of Eq. (9), overrelaxed to first order as N[(1-omega) + omega r]
+ * (Sec. 3.1), or squared with probability p_sr (Sec. 3.2), and finally
+ * U_mu(x) <- G U_mu(x), U_mu(x-mu) <- U_mu(x-mu) G^dag.
+ * The stochastic choices use Philox4x32-10 keyed by seed with counter
+ * (s, sweep_index, 0, 3); subgroup k squares when word k < floor(p_sr 2^32).
+ * omega in [1, 2], p_sr in [0, 1]. */
+lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint64_t seed,
+                     uint64_t sweep_index);
+
+/* Project every link back onto SU(3) in FP64: normalise row 0, orthogonalise
+ * and normalise row 1, row 2 = conj(row0 x row1). */
+lgf_status lgf_reunitarize(lgf_lattice *h);
+
+/* F = (1/(3*4*V)) sum_{x,mu} Re tr U_mu(x) (Eq. (2) at g = 1) and
+ * theta = (1/(3V)) sum_x tr[Delta(x) Delta(x)^dag] (Eq. (5)) with
+ * Delta(x) = sum_mu A_mu(x) - A_mu(x-mu) (Eq. (4)) and
+ * A_mu = [(U - U^dag)/(2i)]_traceless, accumulated in FP64 for every format.
+ * Either output pointer may be NULL.  Synchronises. */
+lgf_status lgf_measure(lgf_lattice *h, double *F, double *theta);
+
+/* Iterate full sweeps until theta < theta_target (Sec. 4).  Every
+ * check_every sweeps the links are reunitarized and F, theta measured (also
+ * once before the first sweep).  Mixed precision: when theta_switch > 0 and
+ * bulk_format differs from the handle's format, the sweeps run on an FP32 (or
+ * other) copy in bulk_format until a measurement gives theta < theta_switch;
+ * the copy is then converted back (reunitarized in FP64) and the sweeps go on
+ * in the handle's format.  history (may be NULL) receives up to history_cap
+ * (sweeps, F, theta) triples.  Returns LGF_OK when converged, LGF_ENOTCONV at
+ * max_sweeps, LGF_ENUMERIC when theta or F is not finite; the result struct is
+ * filled in every case. */
+lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
+                         double *history, int history_cap);
+
+/* Block until all work queued on the handle's stream has finished. */
+lgf_status lgf_synchronize(lgf_lattice *h);
+
+/* Kernel tuning of a handle, per storage format: lanes_per_site in {1, 2, 4}
+ * (lanes that share one site update), block (threads per workgroup: 64, 128,
+ * 256, 512 or 1024), xcd_remap (0/1: give each XCD a contiguous range of
+ * workgroups).  lgf_get_tuning reads the current values. */
+lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block,
+                          int xcd_remap);
+lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block,
+                          int *xcd_remap);
+
+/* Time the sweep kernel variants for a format on this handle's lattice (on a
+ * scratch copy of the links, which are left untouched) and keep the fastest.
+ * trials = timed half-sweeps per variant (>= 1). */
+lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
+
+/* Average duration in ms of the last n_launches sweep kernels enqueued through
+ * lgf_time_sweeps: runs n full sweeps (2n launches) with the given omega/p_sr
+ * and returns the per-launch mean measured with HIP events on the handle's
+ * stream. */
+lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed,
+                           uint64_t sweep_index, double *ms_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGF_H */

@@ -1,0 +1,723 @@
+// lgf_api.cpp -- the C ABI of include/lgf.h: handles, device memory, the
+// canonical-array boundary, and the gauge-fixing driver (Sec. 4 of Schroeck
+// and Vogt, arXiv:1305.3440: sweep the two parities in turn until theta
+// reaches the target), with the mixed FP32-bulk / FP64-finish policy,
+// hipGraph-captured sweep chunks and the sweep-kernel autotuner.
+#include "lgf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lgf_device.hpp"
+#include "lgf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lgf_status fail(lgf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define LGF_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(LGF_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),       \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+#define LGF_TRY(expr)                                                                          \
+    do {                                                                                       \
+        lgf_status s_ = (expr);                                                                \
+        if (s_ != LGF_OK) return s_;                                                           \
+    } while (0)
+
+bool valid_format(int f) { return f >= LGF_FP64_18 && f <= LGF_FP64_12; }
+
+bool valid_dims(const int dims[4])
+{
+    if (!dims) return false;
+    uint64_t V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 2 || (dims[d] & 1)) return false;
+        V *= (uint64_t)dims[d];
+    }
+    return V <= (1ull << 31);
+}
+
+struct GraphEntry {
+    int format;
+    void *field;
+    int n_sweeps;
+    double omega;
+    lgf::SweepTuning tune;
+    hipGraphExec_t exec;
+};
+
+constexpr int64_t kStageSites = 1 << 16;  // sites per canonical staging chunk (37.7 MB)
+
+}  // namespace
+
+struct lgf_lattice {
+    int dims[4];
+    int64_t V;
+    lgf::Geom geom;
+    int format;
+    void *field;
+    size_t field_bytes;
+    bool owned;
+    hipStream_t stream;
+    bool own_stream;
+    int device;
+    double *d_partials;
+    double *d_out;
+    double *h_out;  // pinned, 2 doubles
+    double *d_stage;
+    int64_t *d_sites;
+    int64_t sites_cap;
+    void *work[4];  // owned per-format copies for the mixed-precision bulk
+    size_t work_bytes[4];
+    lgf::SweepTuning tune[4];
+    std::vector<GraphEntry> graphs;
+    hipEvent_t ev0, ev1;
+};
+
+namespace {
+
+lgf_status use_device(const lgf_lattice *h)
+{
+    int cur = -1;
+    LGF_HIP(hipGetDevice(&cur));
+    if (cur != h->device) LGF_HIP(hipSetDevice(h->device));
+    return LGF_OK;
+}
+
+void drop_graphs(lgf_lattice *h)
+{
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
+lgf::Geom make_geom(const int dims[4])
+{
+    lgf::Geom g;
+    for (int d = 0; d < 4; ++d) g.L[d] = (uint32_t)dims[d];
+    g.hx = g.L[3] / 2;
+    g.Vh = g.L[0] * g.L[1] * g.L[2] * g.hx;
+    g.hs[0] = g.L[1] * g.L[2] * g.hx;
+    g.hs[1] = g.L[2] * g.hx;
+    g.hs[2] = g.hx;
+    return g;
+}
+
+lgf_status ensure_stage(lgf_lattice *h)
+{
+    if (!h->d_stage) {
+        const int64_t n = h->V < kStageSites ? h->V : kStageSites;
+        LGF_HIP(hipMalloc(&h->d_stage, (size_t)n * 72 * sizeof(double)));
+    }
+    return LGF_OK;
+}
+
+lgf_status ensure_sites(lgf_lattice *h, int64_t n)
+{
+    if (h->sites_cap < n) {
+        if (h->d_sites) LGF_HIP(hipFree(h->d_sites));
+        h->d_sites = nullptr;
+        h->sites_cap = 0;
+        LGF_HIP(hipMalloc(&h->d_sites, (size_t)n * sizeof(int64_t)));
+        h->sites_cap = n;
+    }
+    return LGF_OK;
+}
+
+lgf_status ensure_work(lgf_lattice *h, int format)
+{
+    if (!h->work[format]) {
+        const size_t bytes = (size_t)h->V * 4 * lgf::link_bytes(format);
+        hipError_t e = hipMalloc(&h->work[format], bytes);
+        if (e != hipSuccess) {
+            h->work[format] = nullptr;
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the %d-format copy", bytes, format);
+        }
+        h->work_bytes[format] = bytes;
+    }
+    return LGF_OK;
+}
+
+// F and theta of a field; with reunit the links are first projected onto
+// SU(3) in FP64 (fused: parity 0 reunitarizes its forward links and, in
+// registers, its backward links; parity 1 then reads the already stored ones).
+lgf_status measure_field(lgf_lattice *h, int format, void *field, bool reunit, double *F, double *theta)
+{
+    int n0 = 0, n1 = 0;
+    LGF_HIP(lgf::launch_measure(format, field, h->geom, 0, reunit, reunit, h->d_partials, &n0, h->stream));
+    LGF_HIP(lgf::launch_measure(format, field, h->geom, 1, reunit, false, h->d_partials + 2 * n0, &n1,
+                                h->stream));
+    LGF_HIP(lgf::launch_finish_measure(h->d_partials, n0 + n1, (double)h->V, h->d_out, h->stream));
+    LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    if (F) *F = h->h_out[0];
+    if (theta) *theta = h->h_out[1];
+    return LGF_OK;
+}
+
+lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, double omega, double p_sr,
+                        uint64_t seed, uint64_t sweep_index)
+{
+    lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
+    LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
+    return LGF_OK;
+}
+
+// n full sweeps on (format, field).  Overrelaxation chunks (no random
+// numbers, so every launch of the chunk has fixed arguments) are captured once
+// into a hipGraph and replayed; stochastic relaxation launches directly since
+// its counter changes every sweep.
+lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omega, double p_sr,
+                     uint64_t seed, uint64_t sweep0, bool use_graph)
+{
+    if (!use_graph || p_sr > 0.0) {
+        for (int k = 0; k < n; ++k)
+            for (int parity = 0; parity < 2; ++parity)
+                LGF_TRY(sweep_launch(h, format, field, parity, omega, p_sr, seed, sweep0 + (uint64_t)k));
+        return LGF_OK;
+    }
+    const lgf::SweepTuning &t = h->tune[format];
+    for (auto &g : h->graphs) {
+        if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
+            g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
+            g.tune.xcd_remap == t.xcd_remap) {
+            LGF_HIP(hipGraphLaunch(g.exec, h->stream));
+            return LGF_OK;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    lgf_status st = LGF_OK;
+    for (int k = 0; k < n && st == LGF_OK; ++k)
+        for (int parity = 0; parity < 2 && st == LGF_OK; ++parity)
+            st = sweep_launch(h, format, field, parity, omega, 0.0, seed, sweep0 + (uint64_t)k);
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (st != LGF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LGF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LGF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (h->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back(GraphEntry{format, field, n, omega, t, exec});
+    LGF_HIP(hipGraphLaunch(exec, h->stream));
+    return LGF_OK;
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lgf_last_error(void) { return g_last_error.c_str(); }
+
+const char *lgf_version(void) { return "lgf-mi355x 0.1 (gfx950)"; }
+
+lgf_status lgf_fix_params_default(lgf_fix_params *p)
+{
+    if (!p) return fail(LGF_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->omega = 1.7;
+    p->p_sr = 0.0;
+    p->theta_target = 1e-14;
+    p->theta_switch = 0.0;
+    p->bulk_format = -1;
+    p->check_every = 20;
+    p->use_graph = 1;
+    p->max_sweeps = 100000;
+    p->seed = 0;
+    p->sweep_offset = 0;
+    return LGF_OK;
+}
+
+size_t lgf_required_bytes(const int dims[4], int format)
+{
+    if (!valid_dims(dims) || !valid_format(format)) return 0;
+    size_t V = 1;
+    for (int d = 0; d < 4; ++d) V *= (size_t)dims[d];
+    return V * 4 * lgf::link_bytes(format);
+}
+
+lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_buf, size_t buf_bytes,
+                      lgf_lattice **out)
+{
+    if (!out) return fail(LGF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!dims) return fail(LGF_EINVAL, "dims is NULL");
+    if (!valid_dims(dims))
+        return fail(LGF_EINVAL, "dims {%d,%d,%d,%d}: every extent must be even and >= 2, V <= 2^31",
+                    dims[0], dims[1], dims[2], dims[3]);
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    const size_t need = lgf_required_bytes(dims, format);
+    if (device_buf && buf_bytes < need)
+        return fail(LGF_EINVAL, "borrowed buffer has %zu bytes, the field needs %zu", buf_bytes, need);
+
+    lgf_lattice *h = new (std::nothrow) lgf_lattice();
+    if (!h) return fail(LGF_ENOMEM, "host allocation of the handle failed");
+    for (int d = 0; d < 4; ++d) h->dims[d] = dims[d];
+    h->V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    h->geom = make_geom(dims);
+    h->format = format;
+    h->field_bytes = need;
+    for (int f = 0; f < 4; ++f) h->tune[f] = lgf::SweepTuning{};
+    // defaults chosen from the register footprint of one site's 8 links
+    h->tune[LGF_FP64_18].lanes_per_site = 2;
+    h->tune[LGF_FP64_12].lanes_per_site = 2;
+
+    auto bail = [&](lgf_status st) {
+        lgf_destroy(h);
+        return st;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(fail(LGF_EHIP, "hipGetDevice: %s", hipGetErrorString(e)));
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+        h->own_stream = false;
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) return bail(fail(LGF_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)));
+        h->own_stream = true;
+    }
+    if (device_buf) {
+        h->field = device_buf;
+        h->owned = false;
+    } else {
+        e = hipMalloc(&h->field, need);
+        if (e != hipSuccess) {
+            h->field = nullptr;
+            (void)hipGetLastError();
+            return bail(fail(LGF_ENOMEM, "cannot allocate %zu bytes for the link field", need));
+        }
+        h->owned = true;
+    }
+    const int nb = lgf::measure_blocks(h->geom);
+    if ((e = hipMalloc(&h->d_partials, (size_t)4 * nb * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->d_out, 2 * sizeof(double))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_out, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(LGF_ENOMEM, "handle scratch allocation failed: %s", hipGetErrorString(e)));
+    }
+    *out = h;
+    return LGF_OK;
+}
+
+lgf_status lgf_destroy(lgf_lattice *h)
+{
+    if (!h) return LGF_OK;
+    (void)use_device(h);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->owned && h->field) (void)hipFree(h->field);
+    for (int f = 0; f < 4; ++f)
+        if (h->work[f]) (void)hipFree(h->work[f]);
+    if (h->d_partials) (void)hipFree(h->d_partials);
+    if (h->d_out) (void)hipFree(h->d_out);
+    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->d_stage) (void)hipFree(h->d_stage);
+    if (h->d_sites) (void)hipFree(h->d_sites);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return LGF_OK;
+}
+
+lgf_status lgf_get_info(const lgf_lattice *h, int dims[4], int *format)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (dims)
+        for (int d = 0; d < 4; ++d) dims[d] = h->dims[d];
+    if (format) *format = h->format;
+    return LGF_OK;
+}
+
+lgf_status lgf_load_links(lgf_lattice *h, const double *host_canon, size_t n_doubles)
+{
+    if (!h || !host_canon) return fail(LGF_EINVAL, "NULL handle or host array");
+    if (n_doubles != (size_t)h->V * 72)
+        return fail(LGF_EINVAL, "host array has %zu doubles, the lattice needs %lld", n_doubles,
+                    (long long)h->V * 72);
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_stage(h));
+    for (int64_t s0 = 0; s0 < h->V; s0 += kStageSites) {
+        const int64_t n = (h->V - s0 < kStageSites) ? h->V - s0 : kStageSites;
+        LGF_HIP(hipMemcpyAsync(h->d_stage, host_canon + s0 * 72, (size_t)n * 72 * sizeof(double),
+                               hipMemcpyHostToDevice, h->stream));
+        LGF_HIP(lgf::launch_canon_to_field(h->format, h->d_stage, s0, n, h->field, h->geom, h->stream));
+    }
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    return LGF_OK;
+}
+
+lgf_status lgf_store_links(lgf_lattice *h, double *host_canon, size_t n_doubles)
+{
+    if (!h || !host_canon) return fail(LGF_EINVAL, "NULL handle or host array");
+    if (n_doubles != (size_t)h->V * 72)
+        return fail(LGF_EINVAL, "host array has %zu doubles, the lattice needs %lld", n_doubles,
+                    (long long)h->V * 72);
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_stage(h));
+    for (int64_t s0 = 0; s0 < h->V; s0 += kStageSites) {
+        const int64_t n = (h->V - s0 < kStageSites) ? h->V - s0 : kStageSites;
+        LGF_HIP(lgf::launch_field_to_canon(h->format, h->field, nullptr, s0, n, h->d_stage, h->geom,
+                                           h->stream));
+        LGF_HIP(hipMemcpyAsync(host_canon + s0 * 72, h->d_stage, (size_t)n * 72 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        LGF_HIP(hipStreamSynchronize(h->stream));
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_peek_links(lgf_lattice *h, const int64_t *sites, int64_t n_sites, double *host_out)
+{
+    if (!h || !sites || !host_out) return fail(LGF_EINVAL, "NULL handle, site list or output");
+    if (n_sites < 0) return fail(LGF_EINVAL, "negative site count");
+    if (n_sites == 0) return LGF_OK;
+    for (int64_t i = 0; i < n_sites; ++i)
+        if (sites[i] < 0 || sites[i] >= h->V)
+            return fail(LGF_EINVAL, "site %lld is outside [0, %lld)", (long long)sites[i], (long long)h->V);
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_stage(h));
+    for (int64_t i0 = 0; i0 < n_sites; i0 += kStageSites) {
+        const int64_t n = (n_sites - i0 < kStageSites) ? n_sites - i0 : kStageSites;
+        LGF_TRY(ensure_sites(h, n));
+        LGF_HIP(hipMemcpyAsync(h->d_sites, sites + i0, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice,
+                               h->stream));
+        LGF_HIP(lgf::launch_field_to_canon(h->format, h->field, h->d_sites, 0, n, h->d_stage, h->geom,
+                                           h->stream));
+        LGF_HIP(hipMemcpyAsync(host_out + i0 * 72, h->d_stage, (size_t)n * 72 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        LGF_HIP(hipStreamSynchronize(h->stream));
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_generate_links(lgf_lattice *h, uint64_t seed, double eps, int haar)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(LGF_EINVAL, "eps must be finite and >= 0");
+    LGF_TRY(use_device(h));
+    LGF_HIP(lgf::launch_generate(h->format, h->field, h->geom, seed, eps, haar != 0, h->stream));
+    return LGF_OK;
+}
+
+lgf_status lgf_convert(lgf_lattice *h, int format)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (format == h->format) return LGF_OK;
+    if (!h->owned) return fail(LGF_ESTATE, "cannot change the format of a borrowed buffer");
+    LGF_TRY(use_device(h));
+    const size_t bytes = (size_t)h->V * 4 * lgf::link_bytes(format);
+    void *nf = nullptr;
+    if (hipMalloc(&nf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the converted field", bytes);
+    }
+    const bool to_fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12);
+    hipError_t e = lgf::launch_convert(h->format, h->field, format, nf, h->geom, to_fp64, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(nf);
+        return fail(LGF_EHIP, "format conversion: %s", hipGetErrorString(e));
+    }
+    drop_graphs(h);
+    (void)hipFree(h->field);
+    h->field = nf;
+    h->field_bytes = bytes;
+    h->format = format;
+    return LGF_OK;
+}
+
+lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint64_t seed,
+                     uint64_t sweep_index)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(use_device(h));
+    if (parity == 2) {
+        LGF_TRY(sweep_launch(h, h->format, h->field, 0, omega, p_sr, seed, sweep_index));
+        LGF_TRY(sweep_launch(h, h->format, h->field, 1, omega, p_sr, seed, sweep_index));
+    } else {
+        LGF_TRY(sweep_launch(h, h->format, h->field, parity, omega, p_sr, seed, sweep_index));
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_reunitarize(lgf_lattice *h)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    LGF_TRY(use_device(h));
+    LGF_HIP(lgf::launch_convert(h->format, h->field, h->format, h->field, h->geom, true, h->stream));
+    return LGF_OK;
+}
+
+lgf_status lgf_measure(lgf_lattice *h, double *F, double *theta)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    LGF_TRY(use_device(h));
+    return measure_field(h, h->format, h->field, false, F, theta);
+}
+
+lgf_status lgf_synchronize(lgf_lattice *h)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    LGF_TRY(use_device(h));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    return LGF_OK;
+}
+
+lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_result *res, double *history,
+                         int history_cap)
+{
+    if (!h || !pp || !res) return fail(LGF_EINVAL, "NULL handle, params or result");
+    const lgf_fix_params p = *pp;
+    if (!(p.omega >= 1.0 && p.omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", p.omega);
+    if (!(p.p_sr >= 0.0 && p.p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p.p_sr);
+    if (!(p.theta_target > 0.0)) return fail(LGF_EINVAL, "theta_target must be > 0");
+    if (p.check_every < 1) return fail(LGF_EINVAL, "check_every must be >= 1");
+    if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
+    if (history_cap < 0 || (history_cap > 0 && !history)) return fail(LGF_EINVAL, "bad history buffer");
+    const int bulk = (p.bulk_format < 0) ? h->format : p.bulk_format;
+    if (!valid_format(bulk)) return fail(LGF_EINVAL, "unknown bulk format %d", bulk);
+    const bool mixed = (bulk != h->format);
+    if (mixed && !(p.theta_switch > 0.0))
+        return fail(LGF_EINVAL, "a bulk format other than the handle's needs theta_switch > 0");
+    LGF_TRY(use_device(h));
+
+    std::memset(res, 0, sizeof *res);
+    const auto t_start = std::chrono::steady_clock::now();
+    int nh = 0;
+    auto record = [&](int64_t sweeps, double F, double th) {
+        if (history && nh < history_cap) {
+            history[3 * nh] = (double)sweeps;
+            history[3 * nh + 1] = F;
+            history[3 * nh + 2] = th;
+            ++nh;
+        }
+    };
+
+    double F = 0.0, theta = 0.0;
+    LGF_HIP(hipEventRecord(h->ev0, h->stream));
+    LGF_TRY(measure_field(h, h->format, h->field, false, &F, &theta));
+    LGF_HIP(hipEventRecord(h->ev1, h->stream));
+    LGF_HIP(hipEventSynchronize(h->ev1));
+    res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+    record(0, F, theta);
+
+    int64_t sweeps = 0, sweeps_bulk = 0;
+    uint64_t ctr = p.sweep_offset;
+    lgf_status status = LGF_ENOTCONV;
+    if (!std::isfinite(F) || !std::isfinite(theta)) status = LGF_ENUMERIC;
+    else if (theta < p.theta_target) status = LGF_OK;
+
+    bool in_bulk = false;
+    int cur_fmt = h->format;
+    void *cur = h->field;
+    if (status == LGF_ENOTCONV && mixed && p.max_sweeps > 0) {
+        LGF_TRY(ensure_work(h, bulk));
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_HIP(lgf::launch_convert(h->format, h->field, bulk, h->work[bulk], h->geom, false, h->stream));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+        in_bulk = true;
+        cur_fmt = bulk;
+        cur = h->work[bulk];
+    }
+
+    while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(run_chunk(h, cur_fmt, cur, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        const double ms = elapsed_ms(h->ev0, h->ev1);
+        if (in_bulk) {
+            res->t_sweep_bulk_ms += ms;
+            sweeps_bulk += n;
+        } else {
+            res->t_sweep_finish_ms += ms;
+        }
+        sweeps += n;
+        ctr += (uint64_t)n;
+
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(measure_field(h, cur_fmt, cur, true, &F, &theta));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+        record(sweeps, F, theta);
+        if (!std::isfinite(F) || !std::isfinite(theta)) {
+            status = LGF_ENUMERIC;
+            break;
+        }
+        if (in_bulk && (theta < p.theta_switch || theta < p.theta_target || sweeps >= p.max_sweeps)) {
+            // leave the bulk precision: back to the handle's format, reunitarized in FP64
+            LGF_HIP(hipEventRecord(h->ev0, h->stream));
+            LGF_HIP(lgf::launch_convert(bulk, h->work[bulk], h->format, h->field, h->geom, true, h->stream));
+            LGF_HIP(hipEventRecord(h->ev1, h->stream));
+            LGF_HIP(hipEventSynchronize(h->ev1));
+            res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+            in_bulk = false;
+            cur_fmt = h->format;
+            cur = h->field;
+            if (theta < p.theta_target) {
+                LGF_TRY(measure_field(h, cur_fmt, cur, false, &F, &theta));
+                record(sweeps, F, theta);
+                if (theta < p.theta_target) status = LGF_OK;
+            }
+            continue;
+        }
+        if (!in_bulk && theta < p.theta_target) status = LGF_OK;
+    }
+    if (in_bulk) {
+        // max_sweeps == 0 with a converted copy: nothing ran, nothing to copy back
+        in_bulk = false;
+    }
+
+    res->sweeps = sweeps;
+    res->sweeps_bulk = sweeps_bulk;
+    res->theta = theta;
+    res->F = F;
+    res->status = status;
+    res->n_history = nh;
+    res->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (status == LGF_ENOTCONV)
+        return fail(LGF_ENOTCONV, "theta %g after %lld sweeps has not reached %g", theta, (long long)sweeps,
+                    p.theta_target);
+    if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", F, theta);
+    return LGF_OK;
+}
+
+lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (lanes_per_site != 1 && lanes_per_site != 2 && lanes_per_site != 4)
+        return fail(LGF_EINVAL, "lanes_per_site must be 1, 2 or 4");
+    if (block != 64 && block != 128 && block != 256)
+        return fail(LGF_EINVAL, "block must be 64, 128 or 256");
+    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0};
+    drop_graphs(h);
+    return LGF_OK;
+}
+
+lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (lanes_per_site) *lanes_per_site = h->tune[format].lanes_per_site;
+    if (block) *block = h->tune[format].block;
+    if (xcd_remap) *xcd_remap = h->tune[format].xcd_remap;
+    return LGF_OK;
+}
+
+lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
+    LGF_TRY(use_device(h));
+    // a scratch copy of the current links in the format being tuned
+    const size_t bytes = (size_t)h->V * 4 * lgf::link_bytes(format);
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the tuning copy", bytes);
+    }
+    hipError_t e = lgf::launch_convert(h->format, h->field, format, scratch, h->geom, false, h->stream);
+    const lgf::SweepTuning saved = h->tune[format];
+    lgf::SweepTuning best = saved;
+    double best_ms = 1e300;
+    const int lps_list[3] = {1, 2, 4};
+    const int block_list[3] = {64, 128, 256};
+    for (int li = 0; li < 3 && e == hipSuccess; ++li)
+        for (int bi = 0; bi < 3 && e == hipSuccess; ++bi)
+            for (int xr = 0; xr < 2 && e == hipSuccess; ++xr) {
+                const lgf::SweepTuning t{lps_list[li], block_list[bi], xr};
+                lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};
+                e = lgf::launch_sweep(format, scratch, h->geom, a, t, h->stream);  // warm-up
+                if (e != hipSuccess) break;
+                e = hipEventRecord(h->ev0, h->stream);
+                for (int k = 0; k < trials && e == hipSuccess; ++k) {
+                    a.parity = k & 1;
+                    e = lgf::launch_sweep(format, scratch, h->geom, a, t, h->stream);
+                }
+                if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+                if (e != hipSuccess) break;
+                const double ms = elapsed_ms(h->ev0, h->ev1) / trials;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return fail(LGF_EHIP, "autotune: %s", hipGetErrorString(e));
+    h->tune[format] = best;
+    drop_graphs(h);
+    return LGF_OK;
+}
+
+lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed,
+                           uint64_t sweep_index, double *ms_per_launch)
+{
+    if (!h || !ms_per_launch) return fail(LGF_EINVAL, "NULL handle or output");
+    if (n < 1) return fail(LGF_EINVAL, "n must be >= 1");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(use_device(h));
+    LGF_HIP(hipEventRecord(h->ev0, h->stream));
+    for (int k = 0; k < n; ++k)
+        for (int parity = 0; parity < 2; ++parity)
+            LGF_TRY(sweep_launch(h, h->format, h->field, parity, omega, p_sr, seed, sweep_index + (uint64_t)k));
+    LGF_HIP(hipEventRecord(h->ev1, h->stream));
+    LGF_HIP(hipEventSynchronize(h->ev1));
+    *ms_per_launch = elapsed_ms(h->ev0, h->ev1) / (2.0 * n);
+    return LGF_OK;
+}
+
+}  // extern "C"

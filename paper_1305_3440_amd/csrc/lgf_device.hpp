@@ -1,0 +1,266 @@
+// lgf_device.hpp -- device-side building blocks of the gfx950 gauge-fixing
+// kernels: complex 3x3 algebra in registers, the storage formats and their
+// parity-split structure-of-arrays layout, lattice geometry, Philox4x32-10.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lgf {
+
+// ----------------------------------------------------------------------------
+// Complex numbers and 3x3 complex matrices held in registers.
+// ----------------------------------------------------------------------------
+
+template <typename T> struct cpx { T re, im; };
+
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cpx<T> mul_conj(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T> __device__ __forceinline__ T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename T> struct mat3 { cpx<T> e[3][3]; };
+
+template <typename T> __device__ __forceinline__ void set_identity(mat3<T> &a)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.e[i][j] = {T(i == j ? 1 : 0), T(0)};
+}
+
+template <typename T> __device__ __forceinline__ void set_zero(mat3<T> &a)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.e[i][j] = {T(0), T(0)};
+}
+
+// acc += u + v^dag
+template <typename T>
+__device__ __forceinline__ void add_fwd_bwd(mat3<T> &acc, const mat3<T> &u, const mat3<T> &v)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            acc.e[i][j].re += u.e[i][j].re + v.e[j][i].re;
+            acc.e[i][j].im += u.e[i][j].im - v.e[j][i].im;
+        }
+}
+
+// row 2 = conj(row0 x row1): the last row of a unitary matrix with det 1
+template <typename T> __device__ __forceinline__ void rebuild_row2(mat3<T> &u)
+{
+    u.e[2][0] = conj(u.e[0][1] * u.e[1][2] - u.e[0][2] * u.e[1][1]);
+    u.e[2][1] = conj(u.e[0][2] * u.e[1][0] - u.e[0][0] * u.e[1][2]);
+    u.e[2][2] = conj(u.e[0][0] * u.e[1][1] - u.e[0][1] * u.e[1][0]);
+}
+
+// r = g * u, rows [0, R) only
+template <int R, typename T>
+__device__ __forceinline__ void left_mul(mat3<T> &r, const mat3<T> &g, const mat3<T> &u)
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.e[i][j] = g.e[i][0] * u.e[0][j] + g.e[i][1] * u.e[1][j] + g.e[i][2] * u.e[2][j];
+}
+
+// r = u * g^dag, rows [0, R) only
+template <int R, typename T>
+__device__ __forceinline__ void right_mul_dag(mat3<T> &r, const mat3<T> &u, const mat3<T> &g)
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.e[i][j] = mul_conj(u.e[i][0], g.e[j][0]) + mul_conj(u.e[i][1], g.e[j][1]) +
+                        mul_conj(u.e[i][2], g.e[j][2]);
+}
+
+template <typename T> __device__ __forceinline__ T fast_rsqrt(T x);
+template <> __device__ __forceinline__ float fast_rsqrt<float>(float x) { return __frsqrt_rn(x); }
+template <> __device__ __forceinline__ double fast_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
+
+// Project a 3x3 matrix onto SU(3) in FP64: normalise row 0, orthogonalise
+// and normalise row 1, row 2 = conj(row0 x row1).
+__device__ __forceinline__ void reunitarize(mat3<double> &u)
+{
+    double n0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n0 += norm2(u.e[0][k]);
+    const double i0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { u.e[0][k].re *= i0; u.e[0][k].im *= i0; }
+    cpx<double> d = {0.0, 0.0};  // <row0, row1> = sum_k conj(row0_k) row1_k
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d = d + conj(u.e[0][k]) * u.e[1][k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u.e[1][k] = u.e[1][k] - d * u.e[0][k];
+    double n1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n1 += norm2(u.e[1][k]);
+    const double i1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { u.e[1][k].re *= i1; u.e[1][k].im *= i1; }
+    rebuild_row2(u);
+}
+
+template <typename A, typename B>
+__device__ __forceinline__ void convert(mat3<B> &dst, const mat3<A> &src)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dst.e[i][j] = {B(src.e[i][j].re), B(src.e[i][j].im)};
+}
+
+// ----------------------------------------------------------------------------
+// Storage formats.  A field is split by parity; within a parity, direction
+// and vector slot, the Vh = V/2 sites form one contiguous stream of 8- or
+// 16-byte vectors ("planes"), so a wavefront's 64 consecutive sites load
+// 512 B - 1 KB contiguous per instruction:
+//     vector index = ((parity*4 + mu)*NV + slot)*Vh + h
+// A link is stored row-major, (row, column, re/im), rows 0..R-1.
+// ----------------------------------------------------------------------------
+
+enum : int { kF64_18 = 0, kF32_18 = 1, kF32_12 = 2, kF64_12 = 3 };
+
+template <int F> struct Fmt;
+template <> struct Fmt<kF64_18> { using T = double; using V = double2; static constexpr int R = 3, NV = 9, CPV = 1; };
+template <> struct Fmt<kF64_12> { using T = double; using V = double2; static constexpr int R = 2, NV = 6, CPV = 1; };
+template <> struct Fmt<kF32_18> { using T = float;  using V = float2;  static constexpr int R = 3, NV = 9, CPV = 1; };
+template <> struct Fmt<kF32_12> { using T = float;  using V = float4;  static constexpr int R = 2, NV = 3, CPV = 2; };
+
+// base pointer of the (parity, mu) block
+template <int F>
+__device__ __forceinline__ typename Fmt<F>::V *block_ptr(void *field, uint32_t Vh, int parity, int mu)
+{
+    return reinterpret_cast<typename Fmt<F>::V *>(field) +
+           (size_t)((parity * 4 + mu) * Fmt<F>::NV) * Vh;
+}
+
+template <int F>
+__device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *blk,
+                                          uint32_t Vh, uint32_t h)
+{
+    using S = Fmt<F>;
+    typename S::V v[S::NV];
+#pragma unroll
+    for (int k = 0; k < S::NV; ++k) v[k] = blk[(size_t)k * Vh + h];
+    if constexpr (S::CPV == 1) {
+#pragma unroll
+        for (int k = 0; k < S::NV; ++k) u.e[k / 3][k % 3] = {v[k].x, v[k].y};
+    } else {
+#pragma unroll
+        for (int k = 0; k < S::NV; ++k) {
+            u.e[(2 * k) / 3][(2 * k) % 3] = {v[k].x, v[k].y};
+            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v[k].z, v[k].w};
+        }
+    }
+    if constexpr (S::R == 2) rebuild_row2(u);
+}
+
+template <int F>
+__device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh, uint32_t h,
+                                           const mat3<typename Fmt<F>::T> &u)
+{
+    using S = Fmt<F>;
+#pragma unroll
+    for (int k = 0; k < S::NV; ++k) {
+        typename S::V v;
+        if constexpr (S::CPV == 1) {
+            v.x = u.e[k / 3][k % 3].re;
+            v.y = u.e[k / 3][k % 3].im;
+        } else {
+            v.x = u.e[(2 * k) / 3][(2 * k) % 3].re;
+            v.y = u.e[(2 * k) / 3][(2 * k) % 3].im;
+            v.z = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].re;
+            v.w = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].im;
+        }
+        blk[(size_t)k * Vh + h] = v;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Lattice geometry.  Half index h of a site of parity p is floor(s/2) with
+// s the lexicographic index (Lx even, so each x-row holds Lx/2 sites of each
+// parity); the parity-(1-p) neighbours of x in the t, z, y directions sit at
+// h -/+ the half strides, the x neighbours at the same row position or one off.
+// ----------------------------------------------------------------------------
+
+struct Geom {
+    uint32_t L[4];   // Lt, Lz, Ly, Lx
+    uint32_t hx;     // Lx / 2
+    uint32_t Vh;     // V / 2
+    uint32_t hs[3];  // half strides of t, z, y: Lz*Ly*hx, Ly*hx, hx
+};
+
+struct Site {
+    uint32_t t, z, y, x;
+    uint32_t row;  // (t*Lz + z)*Ly + y
+};
+
+__device__ __forceinline__ Site decode(const Geom &g, int parity, uint32_t h)
+{
+    Site c;
+    c.row = h / g.hx;
+    const uint32_t xh = h - c.row * g.hx;
+    uint32_t r = c.row;
+    c.y = r % g.L[2];
+    r /= g.L[2];
+    c.z = r % g.L[1];
+    c.t = r / g.L[1];
+    c.x = 2 * xh + ((parity + c.t + c.z + c.y) & 1u);
+    return c;
+}
+
+// half index (in the other parity) of the site x - mu
+__device__ __forceinline__ uint32_t back_half(const Geom &g, const Site &c, uint32_t h, int mu)
+{
+    if (mu == 3) {
+        const uint32_t xb = (c.x == 0) ? g.L[3] - 1 : c.x - 1;
+        return c.row * g.hx + (xb >> 1);
+    }
+    const uint32_t coord = (mu == 0) ? c.t : (mu == 1) ? c.z : c.y;
+    const uint32_t ext = g.L[mu];
+    const uint32_t hs = g.hs[mu];
+    return (coord == 0) ? h + (ext - 1) * hs : h - hs;
+}
+
+__device__ __forceinline__ uint32_t lex_index(const Geom &g, const Site &c) { return c.row * g.L[3] + c.x; }
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (x0, x1, x2, x3) -> (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1,
+// lo(M0 x0)) with the key bumped by the Weyl increments between rounds.
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = M0 * c.x, hi0 = __umulhi(M0, c.x);
+        const uint32_t lo1 = M1 * c.z, hi1 = __umulhi(M1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += W0;
+        k1 += W1;
+    }
+    return c;
+}
+
+}  // namespace lgf

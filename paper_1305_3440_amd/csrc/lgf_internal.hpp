@@ -1,0 +1,62 @@
+// lgf_internal.hpp -- host-side launchers of the gfx950 kernels (defined in
+// lgf_kernels.hip) as seen by the C-ABI runtime (lgf_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lgf {
+
+struct Geom;
+
+// bytes of one link in a storage format, and vector slots per link
+size_t link_bytes(int format);
+
+struct SweepTuning {
+    int lanes_per_site = 1;  // 1, 2 or 4
+    int block = 256;         // threads per workgroup
+    int xcd_remap = 0;       // contiguous workgroup ranges per XCD
+};
+
+struct SweepArgs {
+    int parity;
+    double omega;
+    double p_sr;
+    uint64_t seed;
+    uint64_t sweep_index;
+    uint32_t instance;
+};
+
+hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,
+                        const SweepTuning &t, hipStream_t s);
+
+// Reunitarize (optional) + per-block partial sums of (sum Re tr U, sum |Delta|^2)
+// over the sites of one parity.  reunit_fwd: reunitarize the 4 forward links
+// of every site and store them; reunit_bwd: reunitarize the backward links in
+// registers only (for the first parity pass, whose backward links are the
+// other parity's not yet reunitarized forward links).
+// Returns the number of partial pairs written in *n_partials.
+hipError_t launch_measure(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
+                          bool reunit_bwd, double *partials, int *n_partials, hipStream_t s);
+int measure_blocks(const Geom &g);
+
+// out[0] = F, out[1] = theta from n partial pairs
+hipError_t launch_finish_measure(const double *partials, int n, double V, double *out,
+                                 hipStream_t s);
+
+// dst (format fd) <- src (format fs), optionally reunitarized in FP64; src may
+// equal dst when the formats are equal (element-wise in place).
+hipError_t launch_convert(int fs, const void *src, int fd, void *dst, const Geom &g, bool reunit,
+                          hipStream_t s);
+
+hipError_t launch_generate(int format, void *field, const Geom &g, uint64_t seed, double eps,
+                           bool haar, hipStream_t s);
+
+// canonical double[n][4][18] chunk for sites [s0, s0+n) <-> field
+hipError_t launch_canon_to_field(int format, const double *canon, int64_t s0, int64_t n,
+                                 void *field, const Geom &g, hipStream_t s);
+hipError_t launch_field_to_canon(int format, const void *field, const int64_t *sites, int64_t s0,
+                                 int64_t n, double *canon, const Geom &g, hipStream_t s);
+
+}  // namespace lgf

@@ -1,0 +1,655 @@
+// lgf_kernels.hip -- gfx950 (CDNA4) kernels of the checkerboard SU(3) Landau
+// gauge fixing of Schroeck and Vogt (arXiv:1305.3440): the relaxation sweep
+// (Sec. 3, Eqs. (7)-(9), OR Sec. 3.1, SR Sec. 3.2), the F / theta reductions
+// (Eqs. (2), (4), (5)) fused with FP64 reunitarization, format conversion,
+// the seeded synthetic-field generator and canonical-array I/O.
+//
+// The sweep is bound by HBM bandwidth: a site update must read and write the
+// 8 links that touch the site and does ~3k flops on them, far below the
+// machine balance of either precision.  There is no dense contraction, so no
+// MFMA; the design work is in the memory stream: a parity-split structure of
+// arrays (lgf_device.hpp) so that every load and store of a wavefront is a
+// contiguous 512 B - 1 KB run, all 8 links of a site held in registers
+// between the gather and the store (no re-reads), and 1, 2 or 4 lanes per
+// site to trade registers (occupancy) against redundant SU(2) arithmetic.
+#include "lgf_device.hpp"
+#include "lgf_internal.hpp"
+
+namespace lgf {
+
+size_t link_bytes(int format)
+{
+    switch (format) {
+    case kF64_18: return 18 * sizeof(double);
+    case kF32_18: return 18 * sizeof(float);
+    case kF32_12: return 12 * sizeof(float);
+    case kF64_12: return 12 * sizeof(double);
+    default: return 0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Relaxation sweep
+// ----------------------------------------------------------------------------
+
+// One Cabibbo-Marinari SU(2) step on rows/columns (I, J) of W = G K.
+// Quaternion projection a of the 2x2 block (a scaled by 2, which the
+// normalisation removes); maximum of Re tr[s(b) w] at b = (a0, -a)/|a|
+// (Eq. (9)); OR: N[(1 - omega) + omega b] (first-order b^omega, Sec. 3.1);
+// SR: b^2 (Sec. 3.2).  Then W <- R W and G <- R G on rows I, J.
+template <int I, int J, bool UPDATE_W, typename T>
+__device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool overrelax, bool square)
+{
+    const T a0 = W.e[I][I].re + W.e[J][J].re;
+    const T a3 = W.e[I][I].im - W.e[J][J].im;
+    const T a1 = W.e[I][J].im + W.e[J][I].im;
+    const T a2 = W.e[I][J].re - W.e[J][I].re;
+    const T n2 = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+    T r0 = T(1), r1 = T(0), r2 = T(0), r3 = T(0);
+    if (n2 > T(0)) {
+        const T inv = fast_rsqrt<T>(n2);
+        const T b0 = a0 * inv, b1 = -a1 * inv, b2 = -a2 * inv, b3 = -a3 * inv;
+        if (square) {
+            r0 = b0 * b0 - (b1 * b1 + b2 * b2 + b3 * b3);
+            r1 = T(2) * b0 * b1;
+            r2 = T(2) * b0 * b2;
+            r3 = T(2) * b0 * b3;
+        } else if (overrelax) {
+            const T c0 = (T(1) - omega) + omega * b0;
+            const T c1 = omega * b1, c2 = omega * b2, c3 = omega * b3;
+            const T ic = fast_rsqrt<T>(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
+            r0 = c0 * ic; r1 = c1 * ic; r2 = c2 * ic; r3 = c3 * ic;
+        } else {
+            r0 = b0; r1 = b1; r2 = b2; r3 = b3;
+        }
+    }
+    // s(r) = [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]]
+    const cpx<T> s00 = {r0, r3}, s01 = {r2, r1}, s10 = {-r2, r1}, s11 = {r0, -r3};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> gi = G.e[I][c], gj = G.e[J][c];
+        G.e[I][c] = s00 * gi + s01 * gj;
+        G.e[J][c] = s10 * gi + s11 * gj;
+        if constexpr (UPDATE_W) {
+            const cpx<T> wi = W.e[I][c], wj = W.e[J][c];
+            W.e[I][c] = s00 * wi + s01 * wj;
+            W.e[J][c] = s10 * wi + s11 * wj;
+        }
+    }
+}
+
+template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
+
+template <int F, int LPS, bool SR>
+__global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
+                                                     typename Fmt<F>::T omega, int overrelax,
+                                                     uint64_t sr_threshold, uint32_t key0,
+                                                     uint32_t key1, uint32_t sweep, uint32_t instance,
+                                                     int xcd_remap, uint32_t n_blocks)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    constexpr int NL = 4 / LPS;  // directions handled per lane
+
+    uint32_t b = blockIdx.x;
+    if (xcd_remap) {
+        // workgroups are dealt to the 8 XCDs round-robin; give XCD k the
+        // contiguous range [k*per, (k+1)*per) of tiles so that neighbouring
+        // tiles share its L2
+        const uint32_t per = gridDim.x >> 3;
+        b = (b & 7u) * per + (b >> 3);
+        if (b >= n_blocks) return;
+    }
+    const uint32_t tid = b * blockDim.x + threadIdx.x;
+    const uint32_t grp = tid / LPS;
+    const int lane = (int)(tid % LPS);
+    const bool active = grp < g.Vh;
+    const uint32_t h = active ? grp : g.Vh - 1;
+    const Site c = decode(g, parity, h);
+
+    mat3<T> uf[NL], ub[NL];
+    uint32_t hb[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int mu = lane + k * LPS;
+        hb[k] = back_half(g, c, h, mu);
+        load_link<F>(uf[k], block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+        load_link<F>(ub[k], block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k]);
+    }
+
+    // K(x) = sum_mu U_mu(x) + U_mu(x - mu)^dag (Eq. (8), neighbours' g applied)
+    mat3<T> K;
+    set_zero(K);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) add_fwd_bwd(K, uf[k], ub[k]);
+#pragma unroll
+    for (int m = 1; m < LPS; m <<= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                K.e[i][j].re += shfl_xor_t(K.e[i][j].re, m);
+                K.e[i][j].im += shfl_xor_t(K.e[i][j].im, m);
+            }
+
+    bool sq0 = false, sq1 = false, sq2 = false;
+    if constexpr (SR) {
+        const uint4 w = philox4x32_10(make_uint4(lex_index(g, c), sweep, instance, 3u), key0, key1);
+        sq0 = (uint64_t)w.x < sr_threshold;
+        sq1 = (uint64_t)w.y < sr_threshold;
+        sq2 = (uint64_t)w.z < sr_threshold;
+    }
+
+    mat3<T> G;
+    set_identity(G);
+    const bool orl = overrelax != 0;
+    su2_step<0, 1, true>(K, G, omega, orl, sq0);
+    su2_step<0, 2, true>(K, G, omega, orl, sq1);
+    su2_step<1, 2, false>(K, G, omega, orl, sq2);
+
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int mu = lane + k * LPS;
+        mat3<T> r;
+        left_mul<S::R>(r, G, uf[k]);
+        store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, r);
+        right_mul_dag<S::R>(r, ub[k], G);
+        store_link<F>(block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
+    }
+}
+
+template <int F, int LPS>
+static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
+                                 hipStream_t s)
+{
+    using T = typename Fmt<F>::T;
+    const uint64_t threads = (uint64_t)g.Vh * LPS;
+    const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);
+    const uint32_t grid = t.xcd_remap ? ((nb + 7u) / 8u) * 8u : nb;
+    const int overrelax = (a.omega != 1.0) ? 1 : 0;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    if (a.p_sr > 0.0) {
+        const uint64_t thr = (uint64_t)floor(a.p_sr * 4294967296.0);
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, true>), dim3(grid), dim3(t.block), 0, s, field, g,
+                           a.parity, (T)a.omega, overrelax, thr, k0, k1, (uint32_t)a.sweep_index,
+                           a.instance, t.xcd_remap, nb);
+    } else {
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, false>), dim3(grid), dim3(t.block), 0, s, field, g,
+                           a.parity, (T)a.omega, overrelax, (uint64_t)0, k0, k1,
+                           (uint32_t)a.sweep_index, a.instance, t.xcd_remap, nb);
+    }
+    return hipGetLastError();
+}
+
+template <int F>
+static hipError_t launch_sweep_f(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
+                                 hipStream_t s)
+{
+    switch (t.lanes_per_site) {
+    case 1: return launch_sweep_t<F, 1>(field, g, a, t, s);
+    case 2: return launch_sweep_t<F, 2>(field, g, a, t, s);
+    case 4: return launch_sweep_t<F, 4>(field, g, a, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,
+                        const SweepTuning &t, hipStream_t s)
+{
+    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0) return hipErrorInvalidValue;
+    switch (format) {
+    case kF64_18: return launch_sweep_f<kF64_18>(field, g, a, t, s);
+    case kF32_18: return launch_sweep_f<kF32_18>(field, g, a, t, s);
+    case kF32_12: return launch_sweep_f<kF32_12>(field, g, a, t, s);
+    case kF64_12: return launch_sweep_f<kF64_12>(field, g, a, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// F and theta (Eqs. (2), (4), (5)), optionally fused with reunitarization.
+// Delta(x) = [(K - K^dag)/(2i)]_traceless, which equals sum_mu A_mu(x) -
+// A_mu(x - mu) for A_mu = [(U - U^dag)/(2i)]_traceless.  All in FP64.
+// ----------------------------------------------------------------------------
+
+constexpr int kMeasureBlock = 256;
+
+// u <- u as stored in format F and read back; o receives the stored value
+template <int F>
+__device__ __forceinline__ void round_to_format(mat3<double> &u, mat3<typename Fmt<F>::T> &o)
+{
+    convert(o, u);
+    if constexpr (Fmt<F>::R == 2) rebuild_row2(o);
+    convert(u, o);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void block_sum2(double a, double b, double *out)
+{
+    __shared__ double sa[BLOCK / 64], sb[BLOCK / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int i = 0; i < BLOCK / 64; ++i) { ta += sa[i]; tb += sb[i]; }
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
+template <int F>
+__global__ void __launch_bounds__(kMeasureBlock) measure_kernel(void *__restrict__ field, Geom g,
+                                                                int parity, int reunit_fwd,
+                                                                int reunit_bwd, double *partials)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    const uint32_t h0 = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const bool active = h0 < g.Vh;
+    const uint32_t h = active ? h0 : g.Vh - 1;
+    const Site c = decode(g, parity, h);
+
+    double f = 0.0;
+    mat3<double> K;
+    set_zero(K);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3<T> ut, vt;
+        load_link<F>(ut, block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+        load_link<F>(vt, block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, back_half(g, c, h, mu));
+        mat3<double> u, v;
+        convert(u, ut);
+        convert(v, vt);
+        // Reunitarized links are measured exactly as they will be stored and
+        // read back (rounded to the storage precision, row 2 rebuilt for the
+        // 12-real formats), so the two parity passes agree bit for bit.
+        if (reunit_fwd) {
+            reunitarize(u);
+            mat3<T> o;
+            round_to_format<F>(u, o);
+            if (active) store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, o);
+        }
+        if (reunit_bwd) {
+            reunitarize(v);
+            mat3<T> o;
+            round_to_format<F>(v, o);
+        }
+        f += u.e[0][0].re + u.e[1][1].re + u.e[2][2].re;
+        add_fwd_bwd(K, u, v);
+    }
+    // |[(K - K^dag)/(2i)]_traceless|^2
+    const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
+    const double tr3 = (d0 + d1 + d2) * (1.0 / 3.0);
+    double th = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            // entries (i,j) and (j,i) have equal modulus |K_ij - conj(K_ji)| / 2
+            const cpx<double> z = K.e[i][j] - conj(K.e[j][i]);
+            th += 0.5 * norm2(z);
+        }
+    if (!active) { f = 0.0; th = 0.0; }
+    block_sum2<kMeasureBlock>(f, th, partials + 2 * blockIdx.x);
+}
+
+int measure_blocks(const Geom &g) { return (int)((g.Vh + kMeasureBlock - 1) / kMeasureBlock); }
+
+hipError_t launch_measure(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
+                          bool reunit_bwd, double *partials, int *n_partials, hipStream_t s)
+{
+    const int nb = measure_blocks(g);
+    *n_partials = nb;
+    const int rf = reunit_fwd ? 1 : 0, rb = reunit_bwd ? 1 : 0;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((measure_kernel<kF64_18>), dim3(nb), dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF32_18: hipLaunchKernelGGL((measure_kernel<kF32_18>), dim3(nb), dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF32_12: hipLaunchKernelGGL((measure_kernel<kF32_12>), dim3(nb), dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF64_12: hipLaunchKernelGGL((measure_kernel<kF64_12>), dim3(nb), dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Deterministic final sum: thread t adds partials t, t+256, ... in order,
+// then a fixed tree over the block.
+__global__ void __launch_bounds__(256) finish_measure_kernel(const double *partials, int n, double V,
+                                                             double *out)
+{
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    __shared__ double r[2];
+    block_sum2<256>(a, b, r);
+    if (threadIdx.x == 0) {
+        out[0] = r[0] / (12.0 * V);
+        out[1] = r[1] / (3.0 * V);
+    }
+}
+
+hipError_t launch_finish_measure(const double *partials, int n, double V, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_measure_kernel, dim3(1), dim3(256), 0, s, partials, n, V, out);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Format conversion / reunitarization (element-wise over all 4V links)
+// ----------------------------------------------------------------------------
+
+template <int FS, int FD>
+__global__ void __launch_bounds__(256) convert_kernel(const void *__restrict__ src, void *__restrict__ dst,
+                                                      uint32_t Vh, int reunit)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= Vh) return;
+    const int plane = blockIdx.y;  // parity*4 + mu
+    mat3<typename Fmt<FS>::T> a;
+    load_link<FS>(a, block_ptr<FS>(const_cast<void *>(src), Vh, plane >> 2, plane & 3), Vh, h);
+    mat3<double> d;
+    convert(d, a);
+    if (reunit) reunitarize(d);
+    mat3<typename Fmt<FD>::T> o;
+    convert(o, d);
+    store_link<FD>(block_ptr<FD>(dst, Vh, plane >> 2, plane & 3), Vh, h, o);
+}
+
+template <int FS>
+static hipError_t launch_convert_s(const void *src, int fd, void *dst, uint32_t Vh, int reunit, hipStream_t s)
+{
+    const dim3 grid((Vh + 255) / 256, 8);
+    switch (fd) {
+    case kF64_18: hipLaunchKernelGGL((convert_kernel<FS, kF64_18>), grid, dim3(256), 0, s, src, dst, Vh, reunit); break;
+    case kF32_18: hipLaunchKernelGGL((convert_kernel<FS, kF32_18>), grid, dim3(256), 0, s, src, dst, Vh, reunit); break;
+    case kF32_12: hipLaunchKernelGGL((convert_kernel<FS, kF32_12>), grid, dim3(256), 0, s, src, dst, Vh, reunit); break;
+    case kF64_12: hipLaunchKernelGGL((convert_kernel<FS, kF64_12>), grid, dim3(256), 0, s, src, dst, Vh, reunit); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int fs, const void *src, int fd, void *dst, const Geom &g, bool reunit,
+                          hipStream_t s)
+{
+    const int r = reunit ? 1 : 0;
+    switch (fs) {
+    case kF64_18: return launch_convert_s<kF64_18>(src, fd, dst, g.Vh, r, s);
+    case kF32_18: return launch_convert_s<kF32_18>(src, fd, dst, g.Vh, r, s);
+    case kF32_12: return launch_convert_s<kF32_12>(src, fd, dst, g.Vh, r, s);
+    case kF64_12: return launch_convert_s<kF64_12>(src, fd, dst, g.Vh, r, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Seeded synthetic gauge field: U = exp(i eps sum_j a_j lambda_j), a_j normal,
+// projected on SU(3), then U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag with Haar g.
+// ----------------------------------------------------------------------------
+
+// four standard normals: Box-Muller on Philox words (0,1) and (2,3)
+__device__ __forceinline__ void normals4(uint32_t k0, uint32_t k1, uint4 ctr, double n[4])
+{
+    const uint4 w = philox4x32_10(ctr, k0, k1);
+    const double scale = 2.3283064365386963e-10;  // 2^-32
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double u1 = ((double)ws[2 * p] + 0.5) * scale;
+        const double u2 = ((double)ws[2 * p + 1] + 0.5) * scale;
+        const double r = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(6.283185307179586 * u2, &sn, &cs);
+        n[2 * p] = r * cs;
+        n[2 * p + 1] = r * sn;
+    }
+}
+
+__device__ __forceinline__ void matmul(mat3<double> &r, const mat3<double> &a, const mat3<double> &b)
+{
+    left_mul<3>(r, a, b);
+}
+
+// exp(i eps H(a)) by scaling and squaring with a 16-term Taylor series
+__device__ void su3_exp(mat3<double> &out, const double a[8], double eps)
+{
+    const double s3 = 0.57735026918962576;  // 1/sqrt(3)
+    // X = i eps H with H = sum_j a_j lambda_j
+    cpx<double> H[3][3];
+    H[0][0] = {a[2] + a[7] * s3, 0.0};
+    H[1][1] = {-a[2] + a[7] * s3, 0.0};
+    H[2][2] = {-2.0 * a[7] * s3, 0.0};
+    H[0][1] = {a[0], -a[1]};
+    H[1][0] = {a[0], a[1]};
+    H[0][2] = {a[3], -a[4]};
+    H[2][0] = {a[3], a[4]};
+    H[1][2] = {a[5], -a[6]};
+    H[2][1] = {a[5], a[6]};
+    mat3<double> X;
+    double nrm = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            X.e[i][j] = {-eps * H[i][j].im, eps * H[i][j].re};
+            nrm += norm2(X.e[i][j]);
+        }
+    nrm = sqrt(nrm);
+    int k = 0;
+    while (nrm >= 0.5 * ldexp(1.0, k)) ++k;
+    const double sc = ldexp(1.0, -k);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X.e[i][j] = {X.e[i][j].re * sc, X.e[i][j].im * sc};
+    mat3<double> S, term, tmp;
+    set_identity(S);
+    set_identity(term);
+    for (int n = 1; n <= 16; ++n) {
+        matmul(tmp, term, X);
+        const double inv = 1.0 / n;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                term.e[i][j] = {tmp.e[i][j].re * inv, tmp.e[i][j].im * inv};
+                S.e[i][j] = S.e[i][j] + term.e[i][j];
+            }
+    }
+    for (int q = 0; q < k; ++q) {
+        matmul(tmp, S, S);
+        S = tmp;
+    }
+    out = S;
+}
+
+// Haar SU(3): Ginibre matrix from 18 normals, Gram-Schmidt on the columns
+// (positive real R diagonal), divided by the principal cube root of det.
+__device__ void haar_su3(mat3<double> &g, uint32_t k0, uint32_t k1, uint32_t s)
+{
+    double n[20];
+    for (int call = 0; call < 5; ++call) normals4(k0, k1, make_uint4(s, 0u, (uint32_t)call, 2u), n + 4 * call);
+    const double r2 = 0.70710678118654752;
+    mat3<double> Z;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Z.e[i][j] = {n[2 * (3 * i + j)] * r2, n[2 * (3 * i + j) + 1] * r2};
+    for (int j = 0; j < 3; ++j) {
+        cpx<double> v[3] = {Z.e[0][j], Z.e[1][j], Z.e[2][j]};
+        for (int q = 0; q < j; ++q) {
+            cpx<double> pr = {0.0, 0.0};
+            for (int i = 0; i < 3; ++i) pr = pr + conj(g.e[i][q]) * v[i];
+            for (int i = 0; i < 3; ++i) v[i] = v[i] - pr * g.e[i][q];
+        }
+        double nv = 0.0;
+        for (int i = 0; i < 3; ++i) nv += norm2(v[i]);
+        const double iv = 1.0 / sqrt(nv);
+        for (int i = 0; i < 3; ++i) g.e[i][j] = {v[i].re * iv, v[i].im * iv};
+    }
+    const cpx<double> det =
+        g.e[0][0] * (g.e[1][1] * g.e[2][2] - g.e[1][2] * g.e[2][1]) -
+        g.e[0][1] * (g.e[1][0] * g.e[2][2] - g.e[1][2] * g.e[2][0]) +
+        g.e[0][2] * (g.e[1][0] * g.e[2][1] - g.e[1][1] * g.e[2][0]);
+    const double phi = atan2(det.im, det.re);
+    double sn, cs;
+    sincos(-phi / 3.0, &sn, &cs);
+    const cpx<double> f = {cs, sn};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) g.e[i][j] = g.e[i][j] * f;
+}
+
+template <int F>
+__global__ void __launch_bounds__(128) generate_kernel(void *__restrict__ field, Geom g, uint32_t k0,
+                                                       uint32_t k1, double eps, int haar)
+{
+    const uint32_t s = blockIdx.x * 128 + threadIdx.x;
+    if (s >= 2 * g.Vh) return;
+    uint32_t r = s / g.L[3];
+    const uint32_t x = s - r * g.L[3];
+    const uint32_t row = r;
+    const uint32_t y = r % g.L[2];
+    r /= g.L[2];
+    const uint32_t z = r % g.L[1];
+    const uint32_t t = r / g.L[1];
+    const int parity = (int)((t + z + y + x) & 1u);
+    const uint32_t h = s >> 1;
+    mat3<double> gx;
+    if (haar) haar_su3(gx, k0, k1, s);
+    for (int mu = 0; mu < 4; ++mu) {
+        double a[8];
+        normals4(k0, k1, make_uint4(s, (uint32_t)mu, 0u, 1u), a);
+        normals4(k0, k1, make_uint4(s, (uint32_t)mu, 1u, 1u), a + 4);
+        mat3<double> u;
+        su3_exp(u, a, eps);
+        reunitarize(u);
+        if (haar) {
+            // forward neighbour s + mu
+            uint32_t sn;
+            if (mu == 3) sn = row * g.L[3] + ((x + 1 == g.L[3]) ? 0 : x + 1);
+            else {
+                const uint32_t coord = (mu == 0) ? t : (mu == 1) ? z : y;
+                const uint32_t stride = 2 * g.hs[mu];
+                sn = (coord + 1 == g.L[mu]) ? s - (g.L[mu] - 1) * stride : s + stride;
+            }
+            mat3<double> gy, tmp;
+            haar_su3(gy, k0, k1, sn);
+            left_mul<3>(tmp, gx, u);
+            right_mul_dag<3>(u, tmp, gy);
+        }
+        mat3<typename Fmt<F>::T> o;
+        convert(o, u);
+        store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, o);
+    }
+}
+
+hipError_t launch_generate(int format, void *field, const Geom &g, uint64_t seed, double eps, bool haar,
+                           hipStream_t s)
+{
+    const uint32_t V = 2 * g.Vh;
+    const dim3 grid((V + 127) / 128);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const int hr = haar ? 1 : 0;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((generate_kernel<kF64_18>), grid, dim3(128), 0, s, field, g, k0, k1, eps, hr); break;
+    case kF32_18: hipLaunchKernelGGL((generate_kernel<kF32_18>), grid, dim3(128), 0, s, field, g, k0, k1, eps, hr); break;
+    case kF32_12: hipLaunchKernelGGL((generate_kernel<kF32_12>), grid, dim3(128), 0, s, field, g, k0, k1, eps, hr); break;
+    case kF64_12: hipLaunchKernelGGL((generate_kernel<kF64_12>), grid, dim3(128), 0, s, field, g, k0, k1, eps, hr); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Canonical double[site][mu][3][3][2] <-> private layout
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ void lex_parity_half(const Geom &g, uint32_t s, int &parity, uint32_t &h)
+{
+    uint32_t r = s / g.L[3];
+    const uint32_t x = s - r * g.L[3];
+    const uint32_t y = r % g.L[2];
+    r /= g.L[2];
+    const uint32_t z = r % g.L[1];
+    const uint32_t t = r / g.L[1];
+    parity = (int)((t + z + y + x) & 1u);
+    h = s >> 1;
+}
+
+template <int F>
+__global__ void __launch_bounds__(256) canon_to_field_kernel(const double *__restrict__ canon, uint32_t s0,
+                                                             uint32_t n, void *__restrict__ field, Geom g)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 4 * n) return;
+    const uint32_t s = s0 + (i >> 2);
+    const int mu = (int)(i & 3);
+    int parity;
+    uint32_t h;
+    lex_parity_half(g, s, parity, h);
+    const double *p = canon + (size_t)i * 18;
+    mat3<typename Fmt<F>::T> u;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            u.e[a][b] = {(typename Fmt<F>::T)p[2 * (3 * a + b)], (typename Fmt<F>::T)p[2 * (3 * a + b) + 1]};
+    store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, u);
+}
+
+template <int F>
+__global__ void __launch_bounds__(256) field_to_canon_kernel(const void *__restrict__ field,
+                                                             const int64_t *__restrict__ sites, uint32_t s0,
+                                                             uint32_t n, double *__restrict__ canon, Geom g)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 4 * n) return;
+    const uint32_t s = sites ? (uint32_t)sites[i >> 2] : s0 + (i >> 2);
+    const int mu = (int)(i & 3);
+    int parity;
+    uint32_t h;
+    lex_parity_half(g, s, parity, h);
+    mat3<typename Fmt<F>::T> u;
+    load_link<F>(u, block_ptr<F>(const_cast<void *>(field), g.Vh, parity, mu), g.Vh, h);
+    double *p = canon + (size_t)i * 18;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            p[2 * (3 * a + b)] = (double)u.e[a][b].re;
+            p[2 * (3 * a + b) + 1] = (double)u.e[a][b].im;
+        }
+}
+
+hipError_t launch_canon_to_field(int format, const double *canon, int64_t s0, int64_t n, void *field,
+                                 const Geom &g, hipStream_t s)
+{
+    const dim3 grid((uint32_t)((4 * n + 255) / 256));
+    const uint32_t a = (uint32_t)s0, b = (uint32_t)n;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((canon_to_field_kernel<kF64_18>), grid, dim3(256), 0, s, canon, a, b, field, g); break;
+    case kF32_18: hipLaunchKernelGGL((canon_to_field_kernel<kF32_18>), grid, dim3(256), 0, s, canon, a, b, field, g); break;
+    case kF32_12: hipLaunchKernelGGL((canon_to_field_kernel<kF32_12>), grid, dim3(256), 0, s, canon, a, b, field, g); break;
+    case kF64_12: hipLaunchKernelGGL((canon_to_field_kernel<kF64_12>), grid, dim3(256), 0, s, canon, a, b, field, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_field_to_canon(int format, const void *field, const int64_t *sites, int64_t s0, int64_t n,
+                                 double *canon, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((uint32_t)((4 * n + 255) / 256));
+    const uint32_t a = (uint32_t)s0, b = (uint32_t)n;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((field_to_canon_kernel<kF64_18>), grid, dim3(256), 0, s, field, sites, a, b, canon, g); break;
+    case kF32_18: hipLaunchKernelGGL((field_to_canon_kernel<kF32_18>), grid, dim3(256), 0, s, field, sites, a, b, canon, g); break;
+    case kF32_12: hipLaunchKernelGGL((field_to_canon_kernel<kF32_12>), grid, dim3(256), 0, s, field, sites, a, b, canon, g); break;
+    case kF64_12: hipLaunchKernelGGL((field_to_canon_kernel<kF64_12>), grid, dim3(256), 0, s, field, sites, a, b, canon, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lgf

@@ -1,0 +1,311 @@
+"""ctypes binding of the C ABI in include/lgf.h (argument marshalling only).
+
+Every function keeps its C name and arguments; numpy arrays stand for host
+pointers, and a torch tensor may be passed as a borrowed device buffer and a
+torch stream as the handle's stream.  All arithmetic happens in the gfx950
+library ``liblgf.so``; importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblgf.so")
+
+LGF_OK, LGF_EINVAL, LGF_ENOMEM, LGF_EHIP, LGF_ENOTCONV, LGF_ENUMERIC, LGF_ESTATE = range(7)
+STATUS_NAMES = {0: "LGF_OK", 1: "LGF_EINVAL", 2: "LGF_ENOMEM", 3: "LGF_EHIP", 4: "LGF_ENOTCONV",
+                5: "LGF_ENUMERIC", 6: "LGF_ESTATE"}
+LGF_FP64_18, LGF_FP32_18, LGF_FP32_12, LGF_FP64_12 = range(4)
+FORMAT_NAMES = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12"}
+LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
+
+
+class lgf_fix_params(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("p_sr", ctypes.c_double),
+                ("theta_target", ctypes.c_double), ("theta_switch", ctypes.c_double),
+                ("bulk_format", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("sweep_offset", ctypes.c_uint64)]
+
+
+class lgf_fix_result(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("sweeps_bulk", ctypes.c_int64),
+                ("theta", ctypes.c_double), ("F", ctypes.c_double), ("status", ctypes.c_int),
+                ("n_history", ctypes.c_int), ("t_total_ms", ctypes.c_double),
+                ("t_sweep_bulk_ms", ctypes.c_double), ("t_sweep_finish_ms", ctypes.c_double),
+                ("t_measure_ms", ctypes.c_double), ("t_convert_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class LgfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+EXPORTS = [
+    "lgf_last_error", "lgf_version", "lgf_fix_params_default", "lgf_required_bytes", "lgf_create",
+    "lgf_destroy", "lgf_get_info", "lgf_load_links", "lgf_store_links", "lgf_peek_links",
+    "lgf_generate_links", "lgf_convert", "lgf_sweep", "lgf_reunitarize", "lgf_measure",
+    "lgf_gauge_fix", "lgf_synchronize", "lgf_set_tuning", "lgf_get_tuning", "lgf_autotune",
+    "lgf_time_sweeps",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblgf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1305_3440_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I, I64, U64, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                             ctypes.c_double, ctypes.c_size_t)
+    sig = {
+        "lgf_last_error": (ctypes.c_char_p, []),
+        "lgf_version": (ctypes.c_char_p, []),
+        "lgf_fix_params_default": (I, [P]),
+        "lgf_required_bytes": (SZ, [P, I]),
+        "lgf_create": (I, [P, I, P, P, SZ, P]),
+        "lgf_destroy": (I, [P]),
+        "lgf_get_info": (I, [P, P, P]),
+        "lgf_load_links": (I, [P, P, SZ]),
+        "lgf_store_links": (I, [P, P, SZ]),
+        "lgf_peek_links": (I, [P, P, I64, P]),
+        "lgf_generate_links": (I, [P, U64, D, I]),
+        "lgf_convert": (I, [P, I]),
+        "lgf_sweep": (I, [P, I, D, D, U64, U64]),
+        "lgf_reunitarize": (I, [P]),
+        "lgf_measure": (I, [P, P, P]),
+        "lgf_gauge_fix": (I, [P, P, P, P, I]),
+        "lgf_synchronize": (I, [P]),
+        "lgf_set_tuning": (I, [P, I, I, I, I]),
+        "lgf_get_tuning": (I, [P, I, P, P, P]),
+        "lgf_autotune": (I, [P, I, I]),
+        "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=()):
+    if status != LGF_OK and status not in allow:
+        raise LgfError(status, lgf_last_error())
+    return status
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(dims):
+    return np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(4))
+
+
+def _canon(U: np.ndarray) -> np.ndarray:
+    if U.dtype != np.complex128 or not U.flags.c_contiguous or U.shape[1:] != (4, 3, 3):
+        raise ValueError("links must be a C-contiguous complex128 array of shape (V, 4, 3, 3)")
+    return U
+
+
+# ------------------------------------------------------------------ entry points
+
+def lgf_last_error() -> str:
+    return load_library().lgf_last_error().decode()
+
+
+def lgf_version() -> str:
+    return load_library().lgf_version().decode()
+
+
+def lgf_fix_params_default() -> lgf_fix_params:
+    p = lgf_fix_params()
+    _check(load_library().lgf_fix_params_default(ctypes.byref(p)))
+    return p
+
+
+def lgf_required_bytes(dims, fmt: int) -> int:
+    return int(load_library().lgf_required_bytes(_p(_dims(dims)), fmt))
+
+
+def _ptr_of(obj):
+    if obj is None:
+        return None
+    if isinstance(obj, int):
+        return obj
+    if hasattr(obj, "data_ptr"):        # torch tensor
+        return obj.data_ptr()
+    if hasattr(obj, "cuda_stream"):     # torch stream
+        return obj.cuda_stream
+    raise TypeError(f"cannot take a device pointer of {type(obj)}")
+
+
+def lgf_create(dims, fmt: int = LGF_FP64_18, stream=None, device_buf=None, buf_bytes: int = 0):
+    """Returns the opaque handle (a c_void_p)."""
+    h = ctypes.c_void_p()
+    if device_buf is not None and hasattr(device_buf, "numel") and not buf_bytes:
+        buf_bytes = device_buf.numel() * device_buf.element_size()
+    _check(load_library().lgf_create(_p(_dims(dims)), fmt, _ptr_of(stream), _ptr_of(device_buf),
+                                     buf_bytes, ctypes.byref(h)))
+    return h
+
+
+def lgf_destroy(h) -> None:
+    _check(load_library().lgf_destroy(h))
+
+
+def lgf_get_info(h):
+    d = np.zeros(4, dtype=np.int32)
+    f = ctypes.c_int()
+    _check(load_library().lgf_get_info(h, _p(d), ctypes.byref(f)))
+    return tuple(int(x) for x in d), int(f.value)
+
+
+def lgf_load_links(h, U: np.ndarray) -> None:
+    _canon(U)
+    _check(load_library().lgf_load_links(h, _p(U), U.size * 2))
+
+
+def lgf_store_links(h, V: int) -> np.ndarray:
+    U = np.empty((V, 4, 3, 3), dtype=np.complex128)
+    _check(load_library().lgf_store_links(h, _p(U), U.size * 2))
+    return U
+
+
+def lgf_peek_links(h, sites) -> np.ndarray:
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64).reshape(-1))
+    out = np.empty((s.size, 4, 3, 3), dtype=np.complex128)
+    _check(load_library().lgf_peek_links(h, _p(s), s.size, _p(out)))
+    return out
+
+
+def lgf_generate_links(h, seed: int, eps: float, haar: bool = True) -> None:
+    _check(load_library().lgf_generate_links(h, seed, eps, int(haar)))
+
+
+def lgf_convert(h, fmt: int) -> None:
+    _check(load_library().lgf_convert(h, fmt))
+
+
+def lgf_sweep(h, parity: int, omega: float, p_sr: float = 0.0, seed: int = 0,
+              sweep_index: int = 0) -> None:
+    _check(load_library().lgf_sweep(h, parity, omega, p_sr, seed, sweep_index))
+
+
+def lgf_reunitarize(h) -> None:
+    _check(load_library().lgf_reunitarize(h))
+
+
+def lgf_measure(h):
+    F = ctypes.c_double()
+    th = ctypes.c_double()
+    _check(load_library().lgf_measure(h, ctypes.byref(F), ctypes.byref(th)))
+    return F.value, th.value
+
+
+def lgf_gauge_fix(h, params: lgf_fix_params, history_cap: int = 4096):
+    """Returns (status, result dict, history array of (sweeps, F, theta))."""
+    res = lgf_fix_result()
+    hist = np.zeros((max(history_cap, 1), 3))
+    st = load_library().lgf_gauge_fix(h, ctypes.byref(params), ctypes.byref(res), _p(hist),
+                                      history_cap)
+    _check(st, allow=(LGF_ENOTCONV, LGF_ENUMERIC))
+    return st, res.as_dict(), hist[: res.n_history].copy()
+
+
+def lgf_synchronize(h) -> None:
+    _check(load_library().lgf_synchronize(h))
+
+
+def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0) -> None:
+    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap))
+
+
+def lgf_get_tuning(h, fmt: int):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def lgf_autotune(h, fmt: int, trials: int = 4) -> None:
+    _check(load_library().lgf_autotune(h, fmt, trials))
+
+
+def lgf_time_sweeps(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0,
+                    sweep_index: int = 0) -> float:
+    ms = ctypes.c_double()
+    _check(load_library().lgf_time_sweeps(h, n, omega, p_sr, seed, sweep_index, ctypes.byref(ms)))
+    return ms.value
+
+
+class Lattice:
+    """Owns one handle; a convenience around the entry points above."""
+
+    def __init__(self, dims, fmt: int = LGF_FP64_18, stream=None, device_buf=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.h = lgf_create(self.dims, fmt, stream, device_buf)
+
+    @property
+    def format(self) -> int:
+        return lgf_get_info(self.h)[1]
+
+    def close(self):
+        if self.h is not None:
+            lgf_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, U):
+        lgf_load_links(self.h, U)
+
+    def store(self):
+        return lgf_store_links(self.h, self.V)
+
+    def peek(self, sites):
+        return lgf_peek_links(self.h, sites)
+
+    def generate(self, seed, eps, haar=True):
+        lgf_generate_links(self.h, seed, eps, haar)
+
+    def convert(self, fmt):
+        lgf_convert(self.h, fmt)
+
+    def sweep(self, parity, omega, p_sr=0.0, seed=0, sweep_index=0):
+        lgf_sweep(self.h, parity, omega, p_sr, seed, sweep_index)
+
+    def reunitarize(self):
+        lgf_reunitarize(self.h)
+
+    def measure(self):
+        return lgf_measure(self.h)
+
+    def gauge_fix(self, **kw):
+        p = lgf_fix_params_default()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return lgf_gauge_fix(self.h, p)

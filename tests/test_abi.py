@@ -1,0 +1,110 @@
+"""The C-ABI library loads, exports every symbol include/lgf.h declares, and
+validates arguments on the host before touching a GPU (CPU only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lgf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lgf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    import paper_1305_3440_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def test_library_exports_every_declared_symbol(lgf):
+    names = declared_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", lgf.lgf.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = lgf.load_library()
+    for n in names:
+        assert hasattr(lib, n)
+    assert sorted(lgf.lgf.EXPORTS) == names
+
+
+def test_struct_layouts_match_header(lgf):
+    """The ctypes mirrors have the C structs' sizes (checked by compiling a
+    probe against the header)."""
+    src = ('#include "lgf.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu\\n",'
+           ' sizeof(lgf_fix_params), sizeof(lgf_fix_result));return 0;}\n')
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        a, b = (int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split())
+    assert ctypes.sizeof(lgf.lgf_fix_params) == a
+    assert ctypes.sizeof(lgf.lgf_fix_result) == b
+
+
+def test_required_bytes(lgf):
+    V = 8 * 8 * 8 * 8
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), lgf.LGF_FP64_18) == V * 4 * 144
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), lgf.LGF_FP32_18) == V * 4 * 72
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), lgf.LGF_FP32_12) == V * 4 * 48
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), lgf.LGF_FP64_12) == V * 4 * 96
+    assert lgf.lgf_required_bytes((64, 64, 64, 64), lgf.LGF_FP64_18) == 9663676416
+    assert lgf.lgf_required_bytes((8, 8, 8, 7), lgf.LGF_FP64_18) == 0
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), 9) == 0
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 7), (0, 8, 8, 8), (8, 8, 8, -2), (2, 2, 2, 1),
+                                  (65536, 65536, 2, 2)])
+def test_create_rejects_bad_dims_without_gpu(lgf, dims):
+    with pytest.raises(lgf.LgfError) as e:
+        lgf.lgf_create(dims, lgf.LGF_FP64_18)
+    assert e.value.status == lgf.LGF_EINVAL
+    assert "even" in lgf.lgf_last_error()
+
+
+def test_create_rejects_bad_format_and_small_buffer(lgf):
+    with pytest.raises(lgf.LgfError) as e:
+        lgf.lgf_create((4, 4, 4, 4), 7)
+    assert e.value.status == lgf.LGF_EINVAL
+    with pytest.raises(lgf.LgfError) as e:
+        lgf.lgf_create((4, 4, 4, 4), lgf.LGF_FP64_18, device_buf=0x1000, buf_bytes=100)
+    assert e.value.status == lgf.LGF_EINVAL
+
+
+def test_null_handles(lgf):
+    lib = lgf.load_library()
+    assert lib.lgf_destroy(None) == lgf.LGF_OK
+    assert lib.lgf_sweep(None, 0, 1.5, 0.0, 0, 0) == lgf.LGF_EINVAL
+    assert lib.lgf_measure(None, None, None) == lgf.LGF_EINVAL
+    assert lib.lgf_create(None, 0, None, None, 0, None) == lgf.LGF_EINVAL
+    assert lib.lgf_gauge_fix(None, None, None, None, 0) == lgf.LGF_EINVAL
+
+
+def test_fix_params_default(lgf):
+    p = lgf.lgf_fix_params_default()
+    assert p.omega == 1.7 and p.p_sr == 0.0 and p.theta_target == 1e-14
+    assert p.check_every == 20 and p.max_sweeps == 100000 and p.bulk_format == -1
+    assert p.use_graph == 1 and p.theta_switch == 0.0
+
+
+def test_binding_holds_no_arithmetic():
+    """The Python binding only marshals arguments: no numpy arithmetic on links."""
+    src = open(os.path.join(ROOT, "paper_1305_3440_amd", "lgf.py")).read()
+    for forbidden in ("np.linalg", "np.einsum", "@ ", "np.exp", "import oracle", "from oracle"):
+        assert forbidden not in src, forbidden

@@ -1,0 +1,377 @@
+"""Parity of the gfx950 library with the FP64 oracle, through the C ABI.
+
+Small lattices (several workgroups and a ragged tail) are compared element by
+element on identical input links; the full 64^4 workload is compared on
+sampled sites, which the oracle rebuilds from its own generator.  Tolerances:
+1e-12 absolute per entry for FP64 formats; 2e-6 relative (Frobenius) per link
+for FP32 formats, against the oracle run on the FP32-rounded input."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from lattice_np import dag, parity_grid, unitarity_error
+
+pytestmark = pytest.mark.gpu
+
+FP64 = (0, 3)      # LGF_FP64_18, LGF_FP64_12
+ALL_FORMATS = (0, 1, 2, 3)
+SMALL_DIMS = [(2, 2, 2, 2), (4, 4, 6, 10), (8, 6, 4, 12)]
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    if not gpu_available():
+        pytest.skip("no GPU visible")
+    import paper_1305_3440_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def announce(*args):
+    print("[gpu-case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def link_rel_err(A, B):
+    """max over links of ||A - B||_F / ||B||_F"""
+    d = np.linalg.norm((A - B).reshape(-1, 9), axis=1)
+    n = np.linalg.norm(B.reshape(-1, 9), axis=1)
+    return float((d / n).max())
+
+
+def tol_ok(fmt, got, ref):
+    if fmt in FP64:
+        return float(np.abs(got - ref).max()) <= 1e-12
+    return link_rel_err(got, ref) <= 2e-6
+
+
+# ------------------------------------------------------------ boundary
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+def test_load_store_round_trip(lgf, orc, fmt):
+    dims = (4, 4, 6, 10)
+    announce("load_store", fmt, dims)
+    U = orc.generate_links(dims, 5, 0.3)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(U)
+        got = lat.store()
+    if fmt == 0:
+        assert np.array_equal(got, U)
+    elif fmt == 3:
+        assert np.abs(got - U).max() < 1e-15
+    else:
+        assert np.abs(got - U).max() < 2e-7
+        assert unitarity_error(got) < 2e-6
+
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+@pytest.mark.parametrize("haar", [False, True])
+def test_generator_matches_oracle(lgf, orc, fmt, haar):
+    dims = (4, 4, 6, 10)
+    announce("generate", fmt, haar, dims)
+    ref = orc.generate_links(dims, 11, 0.27, haar=haar)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.generate(11, 0.27, haar)
+        got = lat.store()
+    if fmt in FP64:
+        assert np.abs(got - ref).max() < 1e-13
+    else:
+        assert np.abs(got - ref).max() < 2e-7
+
+
+def test_peek_matches_store(lgf, orc):
+    dims = (8, 6, 4, 12)
+    announce("peek", dims)
+    with lgf.Lattice(dims, 0) as lat:
+        lat.generate(4, 0.3)
+        full = lat.store()
+        sites = [0, 1, 17, 1151, 600, 3]
+        assert np.array_equal(lat.peek(sites), full[sites])
+        with pytest.raises(lgf.LgfError):
+            lat.peek([len(full)])
+
+
+# ------------------------------------------------------------ one sweep
+
+def gpu_input(lgf, dims, fmt, U):
+    """the links as the GPU holds them after loading U in format fmt"""
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(U)
+        return lat.store()
+
+
+TUNINGS = [(1, 256, 0), (2, 128, 1), (4, 64, 0), (4, 256, 1), (1, 64, 1), (2, 256, 0)]
+
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+@pytest.mark.parametrize("dims", SMALL_DIMS)
+@pytest.mark.parametrize("omega,p_sr", [(1.0, 0.0), (1.7, 0.0), (1.0, 0.5), (1.8, 0.3)])
+def test_half_and_full_sweep_match_oracle(lgf, orc, fmt, dims, omega, p_sr):
+    announce("sweep", fmt, dims, omega, p_sr)
+    U = orc.generate_links(dims, 7, 0.35)
+    U0 = gpu_input(lgf, dims, fmt, U)
+    for tune in TUNINGS:
+        with lgf.Lattice(dims, fmt) as lat:
+            lgf.lgf_set_tuning(lat.h, fmt, *tune)
+            lat.load(U)
+            ref = U0.copy()
+            lat.sweep(0, omega, p_sr, seed=9, sweep_index=3)
+            orc.half_sweep(dims, ref, 0, omega, p_sr, seed=9, sweep=3)
+            got = lat.store()
+            assert tol_ok(fmt, got, ref), (tune, np.abs(got - ref).max(), link_rel_err(got, ref))
+            lat.sweep(1, omega, p_sr, seed=9, sweep_index=3)
+            orc.half_sweep(dims, ref, 1, omega, p_sr, seed=9, sweep=3)
+            got = lat.store()
+            assert tol_ok(fmt, got, ref), (tune, np.abs(got - ref).max(), link_rel_err(got, ref))
+            lat.sweep(2, omega, p_sr, seed=9, sweep_index=4)
+            orc.sweep(dims, ref, omega, p_sr, seed=9, sweep_index=4)
+            got = lat.store()
+            assert tol_ok(fmt, got, ref), (tune, np.abs(got - ref).max(), link_rel_err(got, ref))
+
+
+def test_sr_decisions_bitwise(lgf, orc):
+    """p = 1 squares every subgroup: after one half-sweep at omega = 1 the GPU
+    and the oracle agree to rounding, which they could not if any coin differed;
+    with p = 0.5 the per-site updates agree only when every coin matches."""
+    dims = (8, 6, 4, 12)
+    announce("sr_bits", dims)
+    U = orc.generate_links(dims, 13, 0.4)
+    for p in (0.5, 0.25, 1.0):
+        ref = U.copy()
+        with lgf.Lattice(dims, 0) as lat:
+            lat.load(U)
+            lat.sweep(0, 1.0, p, seed=2**40 + 77, sweep_index=123456)
+            got = lat.store()
+        orc.half_sweep(dims, ref, 0, 1.0, p, seed=2**40 + 77, sweep=123456)
+        assert np.abs(got - ref).max() < 1e-12
+
+
+# ------------------------------------------------------------ reunitarize, measure
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+def test_measure_matches_oracle(lgf, orc, fmt):
+    dims = (8, 6, 4, 12)
+    announce("measure", fmt, dims)
+    U = orc.generate_links(dims, 3, 0.4)
+    U0 = gpu_input(lgf, dims, fmt, U)
+    F_ref, th_ref = orc.measure(dims, U0)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(U)
+        F, th = lat.measure()
+    assert abs(F - F_ref) < 1e-14 * abs(F_ref) + 1e-15
+    assert abs(th - th_ref) < 1e-12 * th_ref
+
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+def test_reunitarize_matches_oracle(lgf, orc, fmt):
+    dims = (4, 4, 6, 10)
+    announce("reunit", fmt, dims)
+    rng = np.random.default_rng(0)
+    U = orc.generate_links(dims, 3, 0.4)
+    noisy = U + 1e-4 * (rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape))
+    U0 = gpu_input(lgf, dims, fmt, noisy)
+    ref = U0.copy()
+    orc.reunitarize(ref)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(noisy)
+        lat.reunitarize()
+        got = lat.store()
+    if fmt in FP64:
+        assert np.abs(got - ref).max() < 1e-14
+    else:
+        assert np.abs(got - ref).max() < 2e-7
+
+
+# ------------------------------------------------------------ gauge fixing
+
+def test_gauge_fix_8x4_matches_oracle_history(lgf, orc):
+    """8^4, seed 0, eps 0.25, Haar gauge, omega 1.7 to theta < 1e-12: the GPU
+    FP64 run has the oracle's theta history (1e-8 relative while theta >
+    1e-10) and the same number of sweeps."""
+    dims = (8, 8, 8, 8)
+    announce("gauge_fix_8x4")
+    U = orc.generate_links(dims, 0, 0.25)
+    ref = U.copy()
+    r_orc = orc.gauge_fix(dims, ref, 1.7, 1e-12)
+    with lgf.Lattice(dims, 0) as lat:
+        lat.load(U)
+        st, res, hist = lat.gauge_fix(omega=1.7, theta_target=1e-12)
+        got = lat.store()
+    assert st == 0 and res["theta"] < 1e-12
+    h_orc = r_orc["history"]
+    assert res["sweeps"] == r_orc["sweeps"]
+    n = min(len(hist), len(h_orc))
+    for k in range(n):
+        if h_orc[k, 2] > 1e-10:
+            assert abs(hist[k, 2] - h_orc[k, 2]) <= 1e-8 * h_orc[k, 2], k
+            assert abs(hist[k, 1] - h_orc[k, 1]) <= 1e-12
+    assert abs(res["F"] - r_orc["F"]) < 1e-12
+    assert np.abs(got - ref).max() < 1e-9
+
+
+@pytest.mark.parametrize("bulk", [1, 2])
+def test_mixed_gauge_fix_reaches_target(lgf, orc, bulk):
+    """FP32 bulk sweeps, FP64 reunitarization every 20 sweeps, switch below
+    theta = 1e-8, FP64 finish: converges to theta < 1e-14 like the plain run,
+    to the same F within the FP32 orbit drift."""
+    dims = (8, 8, 8, 8)
+    announce("mixed", bulk)
+    U = orc.generate_links(dims, 1, 0.25)
+    ref = U.copy()
+    r_orc = orc.gauge_fix(dims, ref, 1.7, 1e-14)
+    with lgf.Lattice(dims, 0) as lat:
+        lat.load(U)
+        st, res, hist = lat.gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                      bulk_format=bulk)
+        got = lat.store()
+    assert st == 0 and res["theta"] < 1e-14
+    assert 0 < res["sweeps_bulk"] < res["sweeps"]
+    assert abs(res["F"] - r_orc["F"]) < 1e-5
+    assert unitarity_error(got) < 1e-12
+    # the FP64 finish: theta recomputed by the oracle on the returned links
+    assert orc.measure(dims, got)[1] < 1e-14
+
+
+def test_gauge_fix_graph_equals_direct(lgf, orc):
+    dims = (8, 6, 4, 12)
+    announce("graph_vs_direct")
+    U = orc.generate_links(dims, 2, 0.3)
+    outs = []
+    for use_graph in (0, 1, 1):
+        with lgf.Lattice(dims, 0) as lat:
+            lat.load(U)
+            st, res, _ = lat.gauge_fix(omega=1.6, theta_target=1e-12, use_graph=use_graph)
+            outs.append(lat.store())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+def test_sr_gauge_fix_converges(lgf, orc):
+    dims = (8, 6, 4, 12)
+    announce("sr_fix")
+    U = orc.generate_links(dims, 2, 0.3)
+    ref = U.copy()
+    r_orc = orc.gauge_fix(dims, ref, 1.0, 1e-12, p=0.5, seed=5)
+    with lgf.Lattice(dims, 0) as lat:
+        lat.load(U)
+        st, res, _ = lat.gauge_fix(omega=1.0, p_sr=0.5, seed=5, theta_target=1e-12)
+        got = lat.store()
+    assert st == 0 and res["sweeps"] == r_orc["sweeps"]
+    assert np.abs(got - ref).max() < 1e-9
+
+
+def test_status_codes(lgf, orc):
+    dims = (4, 4, 4, 4)
+    announce("status")
+    with lgf.Lattice(dims, 0) as lat:
+        lat.generate(0, 0.3)
+        with pytest.raises(lgf.LgfError) as e:
+            lat.sweep(0, 2.5)
+        assert e.value.status == lgf.LGF_EINVAL
+        with pytest.raises(lgf.LgfError) as e:
+            lat.sweep(3, 1.5)
+        assert e.value.status == lgf.LGF_EINVAL
+        with pytest.raises(lgf.LgfError) as e:
+            lat.sweep(0, 1.5, p_sr=1.5)
+        assert e.value.status == lgf.LGF_EINVAL
+        st, res, hist = lat.gauge_fix(omega=1.7, theta_target=1e-30, max_sweeps=40)
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 40 and len(hist) == 3
+        U = lat.store()
+        U[5, 2, 1, 1] = np.nan
+        lat.load(U)
+        st, res, hist = lat.gauge_fix(omega=1.7, theta_target=1e-12)
+        assert st == lgf.LGF_ENUMERIC
+
+
+def test_determinism(lgf, orc):
+    dims = (8, 8, 8, 8)
+    announce("determinism")
+    outs = []
+    for _ in range(2):
+        with lgf.Lattice(dims, 2) as lat:
+            lat.generate(3, 0.3)
+            for k in range(5):
+                lat.sweep(2, 1.8, 0.0, 0, k)
+                lat.sweep(2, 1.0, 0.5, 1, k)
+            outs.append((lat.store(), lat.measure()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+# ------------------------------------------------------------ full size, sampled
+
+def oracle_links8(orc, dims, seed, eps, s):
+    fw = [orc.generated_link(dims, seed, eps, True, s, mu) for mu in range(4)]
+    bw = [orc.generated_link(dims, seed, eps, True, orc.neighbor(dims, s, mu, -1), mu)
+          for mu in range(4)]
+    return np.array(fw + bw)
+
+
+def gpu_links8(lat, orc, dims, s):
+    nb = [orc.neighbor(dims, s, mu, -1) for mu in range(4)]
+    P = lat.peek([s] + nb)
+    return np.array([P[0, mu] for mu in range(4)] + [P[1 + mu, mu] for mu in range(4)])
+
+
+def sample_sites(orc, dims, parity, n, rng):
+    V = int(np.prod(dims))
+    Lt, Lz, Ly, Lx = dims
+    edge = [0, 1, Lx - 1, Lx, V - 1, V - 2, V - Lx, (Lt - 1) * Lz * Ly * Lx, Lz * Ly * Lx - 1]
+    cand = list(edge) + list(rng.integers(0, V, 4 * n))
+    out = []
+    for s in cand:
+        if orc.parity(dims, int(s)) == parity and int(s) not in out:
+            out.append(int(s))
+        if len(out) >= n:
+            break
+    return out
+
+
+@pytest.mark.parametrize("fmt,omega,p_sr", [(0, 1.8, 0.0), (2, 1.8, 0.0), (0, 1.0, 0.5)])
+def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
+    """The 64^4 workload (seed 3, eps 0.3, Haar gauge) in the launch
+    configuration the benchmark times: one half-sweep of parity 0 and one of
+    parity 1, compared on sampled sites (edges and wrap-arounds included)
+    with the oracle rebuilding every input link from its own generator."""
+    dims = (64, 64, 64, 64)
+    seed, eps, sr_seed, sweep = 3, 0.3, 17, 5
+    announce("64^4 sampled", fmt, omega, p_sr)
+    rng = np.random.default_rng(0)
+    tol = 1e-12 if fmt in FP64 else 2e-6
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.generate(seed, eps, True)
+        sites0 = sample_sites(orc, dims, 0, 24, rng)
+        for s in sites0[:6]:
+            got = gpu_links8(lat, orc, dims, s)
+            ref = oracle_links8(orc, dims, seed, eps, s)
+            assert (np.abs(got - ref).max() < 1e-13) if fmt in FP64 else (link_rel_err(got, ref) < 2e-7)
+        lat.sweep(0, omega, p_sr, sr_seed, sweep)
+        for s in sites0:
+            ref, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), omega,
+                                      orc.sr_decisions(sr_seed, s, sweep, 0, p_sr))
+            got = gpu_links8(lat, orc, dims, s)
+            err = np.abs(got - ref).max() if fmt in FP64 else link_rel_err(got, ref)
+            assert err < tol, (s, err)
+        # parity 1: each of its 8 links was last changed by the parity-0 site
+        # at its other end; the oracle redoes those 8 updates first
+        sites1 = sample_sites(orc, dims, 1, 8, rng)
+        lat.sweep(1, omega, p_sr, sr_seed, sweep)
+        for y in sites1:
+            links = np.zeros((8, 3, 3), dtype=np.complex128)
+            for mu in range(4):
+                z = orc.neighbor(dims, y, mu, +1)           # U_mu(y) is z's backward link mu
+                upd, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, z), omega,
+                                          orc.sr_decisions(sr_seed, z, sweep, 0, p_sr))
+                links[mu] = upd[4 + mu]
+                zb = orc.neighbor(dims, y, mu, -1)          # U_mu(y - mu) is zb's forward link mu
+                upd, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, zb), omega,
+                                          orc.sr_decisions(sr_seed, zb, sweep, 0, p_sr))
+                links[4 + mu] = upd[mu]
+            ref, _ = orc.local_update(links, omega, orc.sr_decisions(sr_seed, y, sweep, 0, p_sr))
+            got = gpu_links8(lat, orc, dims, y)
+            err = np.abs(got - ref).max() if fmt in FP64 else link_rel_err(got, ref)
+            assert err < tol, (y, err)
+        F, th = lat.measure()
+        assert np.isfinite(F) and np.isfinite(th) and 0 < F < 1
