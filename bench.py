@@ -5,7 +5,7 @@ One step = one complete gauge fixing of the 64^4 workload (seeded synthetic
 links: seed 3, eps 0.3, Haar-random gauge) from its stored start to
 theta < 1e-14 with overrelaxation omega = 1.8, in the mixed form: FP32 12-real
 bulk sweeps, FP64 reunitarization + F/theta every 20 sweeps, switch to FP64
-18-real below theta = 1e-8.  The start configuration stays resident in HBM
+(12-real storage) below theta = 1e-8, result handed back as FP64 18-real.  The start configuration stays resident in HBM
 (a device-to-device copy opens each step).  value = site updates per second
 over the whole step (V x sweeps / step time).
 
@@ -27,8 +27,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
-KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_device.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_device.hpp",
+                  "paper_1305_3440_amd/csrc/lgf_internal.hpp", "paper_1305_3440_amd/csrc/lgf_api.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_64x4_hbm_traffic.json")
 
 
 def log(*a):
@@ -82,16 +83,98 @@ def cpu_baseline(dims, seed, eps, omega, seconds):
                       f"Haar), FP64, {el:.1f} s"}
 
 
+def traffic_run(lgf, torch, dims, seed, eps, omega):
+    """Workload for the rocprofv3 counter passes: a copy of known size (to
+    calibrate FETCH_SIZE / WRITE_SIZE), then 4 sweep launches per format on
+    the benchmark's 64^4 field."""
+    n = 1 << 30
+    a = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    stream = torch.cuda.current_stream()
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_18):
+        h = lgf.lgf_create(dims, fmt, stream)
+        lgf.lgf_generate_links(h, seed, eps, True)
+        ms = lgf.lgf_time_sweeps(h, 2, omega)
+        log(f"[traffic] {lgf.FORMAT_NAMES[fmt]}: {ms:.3f} ms per launch")
+        lgf.lgf_destroy(h)
+    torch.cuda.synchronize()
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+
+
+def summarize_traffic(fetch_dir, write_dir, dims, command):
+    """Per-launch HBM bytes of the sweep kernels from two rocprofv3 --pmc
+    passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the
+    counter's reading for the 1 GiB copy; written next to the kernel-source
+    hash so a stale figure is never reported."""
+    import csv
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        with open(_find(d, "counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                per.setdefault((counter, row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+    copy_bytes = float(1 << 30)
+    out = {"source_sha": kernel_source_sha(), "command": command, "kernels": {}, "calibration": {}}
+    scale = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [v for (c, k), vs in per.items() if c == counter and "copyBuffer" in k for v in vs]
+        kib = max(vals)  # the 1 GiB copy is the largest copy-kernel dispatch
+        scale[counter] = copy_bytes / kib
+        out["calibration"][counter] = {"copy_bytes": copy_bytes, "counter_kib": kib,
+                                       "bytes_per_counter_unit": scale[counter]}
+    names = {"<2,": "fp32-12", "<3,": "fp64-12", "<0,": "fp64-18"}
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    for (counter, kname), vals in per.items():
+        if "sweep_kernel" not in kname:
+            continue
+        fmt = next(v for k, v in names.items() if k in kname.replace(" ", ""))
+        key = f"sweep:{fmt}:{'x'.join(map(str, dims))}"
+        e = out["kernels"].setdefault(key, {"kernel": kname})
+        e[counter.lower() + "_bytes_per_launch"] = sum(vals) / len(vals) * scale[counter]
+    for key, e in out["kernels"].items():
+        fmt = key.split(":")[1]
+        alg = Vh * 16 * {"fp32-12": 48, "fp64-12": 96, "fp64-18": 144}[fmt]
+        e["algorithmic_bytes_per_launch"] = alg
+        e["hbm_bytes_per_launch"] = e.get("fetch_size_bytes_per_launch", 0) + e.get(
+            "write_size_bytes_per_launch", 0)
+        e["hbm_over_algorithmic"] = e["hbm_bytes_per_launch"] / alg
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--dims", default="64,64,64,64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and SR reference runs")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="only the short workload of the rocprofv3 counter passes")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
+    ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        dims = tuple(int(x) for x in args.dims.split(","))
+        summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], dims,
+                          args.traffic_command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
@@ -112,24 +195,29 @@ def main():
     V = dims[0] * dims[1] * dims[2] * dims[3]
     seed, eps, omega = 3, 0.3, 1.8
     theta_target, theta_switch = 1e-14, 1e-8
-    bulk, finish = lgf.LGF_FP32_12, lgf.LGF_FP64_18
+    bulk, finish, home = lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_18
     stream = torch.cuda.current_stream()
+    if args.traffic_run:
+        traffic_run(lgf, torch, dims, seed, eps, omega)
+        return
 
-    nbytes = lgf.lgf_required_bytes(dims, finish)
+    nbytes = lgf.lgf_required_bytes(dims, home)
     pristine = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     work = torch.empty_like(pristine)
-    hp = lgf.lgf_create(dims, finish, stream, pristine)
+    hp = lgf.lgf_create(dims, home, stream, pristine)
     lgf.lgf_generate_links(hp, seed, eps, True)
-    hw = lgf.lgf_create(dims, finish, stream, work)
+    hw = lgf.lgf_create(dims, home, stream, work)
     torch.cuda.synchronize()
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; tuning fp32-12 "
-        f"{lgf.lgf_get_tuning(hw, bulk)} fp64-18 {lgf.lgf_get_tuning(hw, finish)}")
+        f"{lgf.lgf_get_tuning(hw, bulk)} fp64-12 {lgf.lgf_get_tuning(hw, finish)} fp64-18 "
+        f"{lgf.lgf_get_tuning(hw, home)}")
 
     params = lgf.lgf_fix_params_default()
     params.omega = omega
     params.theta_target = theta_target
     params.theta_switch = theta_switch
     params.bulk_format = bulk
+    params.finish_format = finish
     params.check_every = 20
     params.use_graph = 1
 
@@ -162,7 +250,7 @@ def main():
     tb = sum(r["t_sweep_bulk_ms"] for r in results)
     tf = sum(r["t_sweep_finish_ms"] for r in results)
     kernels = {}
-    for name, fmt, nsw, tms in (("sweep_fp32_12", bulk, sb, tb), ("sweep_fp64_18", finish, sf, tf)):
+    for name, fmt, nsw, tms in (("sweep_fp32_12", bulk, sb, tb), ("sweep_fp64_12", finish, sf, tf)):
         if nsw > 0:
             launch_ms = tms / (2 * nsw)
             by = Vh * 2 * 8 * LINK_BYTES[fmt]
@@ -172,7 +260,7 @@ def main():
                              "site_updates_per_s": Vh / (launch_ms * 1e-3), "total_ms": tms}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
-    fmt_name = "fp32-12" if dom == "sweep_fp32_12" else "fp64-18"
+    fmt_name = "fp32-12" if dom == "sweep_fp32_12" else "fp64-12"
     traffic = measured_traffic("sweep", dims, fmt_name)
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
@@ -238,7 +326,7 @@ def main():
         "dtype": "fp32+fp64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau OR gauge fixing, mixed "
-                               f"FP32-12 bulk / FP64-18 finish, theta<1e-14",
+                               f"FP32-12 bulk / FP64-12 finish, theta<1e-14",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
                    "sweeps_per_step": [r["sweeps"] for r in results]},

@@ -70,7 +70,7 @@ typedef struct {
     int bulk_format;       /* format of the bulk sweeps (lgf_format); the handle's own when equal */
     int check_every;       /* sweeps between reunitarize + measure, >= 1 (default 20) */
     int use_graph;         /* capture each chunk of check_every sweeps in a hipGraph (default 1) */
-    int reserved;
+    int finish_format;     /* format of the sweeps after the switch (-1 = the handle's own) */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
@@ -87,7 +87,7 @@ typedef struct {
     int n_history;         /* measurements written to the history buffer */
     double t_total_ms;     /* wall time of the whole call (host clock, links resident) */
     double t_sweep_bulk_ms;   /* sweep kernels in bulk_format */
-    double t_sweep_finish_ms; /* sweep kernels in the handle's format */
+    double t_sweep_finish_ms; /* sweep kernels in finish_format */
     double t_measure_ms;   /* reunitarize + measure */
     double t_convert_ms;   /* format conversions */
 } lgf_fix_result;
@@ -99,8 +99,8 @@ const char *lgf_last_error(void);
 const char *lgf_version(void);
 
 /* Fill *p with the defaults: omega 1.7, p_sr 0, theta_target 1e-14,
- * theta_switch 0, bulk_format -1 (= handle's format), check_every 20,
- * use_graph 1, max_sweeps 100000, seed 0, sweep_offset 0. */
+ * theta_switch 0, bulk_format -1 and finish_format -1 (= handle's format),
+ * check_every 20, use_graph 1, max_sweeps 100000, seed 0, sweep_offset 0. */
 lgf_status lgf_fix_params_default(lgf_fix_params *p);
 
 /* Device bytes of a link field of the given dims in the given format
@@ -180,14 +180,15 @@ lgf_status lgf_measure(lgf_lattice *h, double *F, double *theta);
 
 /* Iterate full sweeps until theta < theta_target (Sec. 4).  Every
  * check_every sweeps the links are reunitarized and F, theta measured (also
- * once before the first sweep).  Mixed precision: when theta_switch > 0 and
- * bulk_format differs from the handle's format, the sweeps run on an FP32 (or
- * other) copy in bulk_format until a measurement gives theta < theta_switch;
- * the copy is then converted back (reunitarized in FP64) and the sweeps go on
- * in the handle's format.  history (may be NULL) receives up to history_cap
- * (sweeps, F, theta) triples.  Returns LGF_OK when converged, LGF_ENOTCONV at
- * max_sweeps, LGF_ENUMERIC when theta or F is not finite; the result struct is
- * filled in every case. */
+ * once before the first sweep).  Mixed precision: when bulk_format differs
+ * from finish_format (theta_switch > 0 required), the sweeps run on a copy in
+ * bulk_format until a measurement gives theta < theta_switch; the copy is then
+ * converted to finish_format (reunitarized in FP64) and the sweeps go on
+ * until theta < theta_target.  The links end up in the handle's own format.
+ * history (may be NULL) receives up to history_cap (sweeps, F, theta)
+ * triples.  Returns LGF_OK when converged, LGF_ENOTCONV at max_sweeps,
+ * LGF_ENUMERIC when theta or F is not finite; the result struct is filled in
+ * every case. */
 lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
                          double *history, int history_cap);
 
@@ -195,13 +196,14 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_r
 lgf_status lgf_synchronize(lgf_lattice *h);
 
 /* Kernel tuning of a handle, per storage format: lanes_per_site in {1, 2, 4}
- * (lanes that share one site update), block (threads per workgroup: 64, 128,
- * 256, 512 or 1024), xcd_remap (0/1: give each XCD a contiguous range of
- * workgroups).  lgf_get_tuning reads the current values. */
+ * (lanes that share one site update), block (threads per workgroup: 64, 128
+ * or 256), xcd_remap (0/1: give each XCD a contiguous range of workgroups),
+ * nontemporal (0/1: stream the links past the caches).  lgf_get_tuning reads
+ * the current values (any output pointer may be NULL). */
 lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block,
-                          int xcd_remap);
+                          int xcd_remap, int nontemporal);
 lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block,
-                          int *xcd_remap);
+                          int *xcd_remap, int *nontemporal);
 
 /* Time the sweep kernel variants for a format on this handle's lattice (on a
  * scratch copy of the links, which are left untouched) and keep the fastest.

@@ -204,7 +204,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
             g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
-            g.tune.xcd_remap == t.xcd_remap) {
+            g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
         }
@@ -260,6 +260,7 @@ lgf_status lgf_fix_params_default(lgf_fix_params *p)
     p->bulk_format = -1;
     p->check_every = 20;
     p->use_graph = 1;
+    p->finish_format = -1;
     p->max_sweeps = 100000;
     p->seed = 0;
     p->sweep_offset = 0;
@@ -295,10 +296,9 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     h->geom = make_geom(dims);
     h->format = format;
     h->field_bytes = need;
+    // defaults: one lane per site, 128-thread workgroups (fastest measured
+    // at 64^4 for every format)
     for (int f = 0; f < 4; ++f) h->tune[f] = lgf::SweepTuning{};
-    // defaults chosen from the register footprint of one site's 8 links
-    h->tune[LGF_FP64_18].lanes_per_site = 2;
-    h->tune[LGF_FP64_12].lanes_per_site = 2;
 
     auto bail = [&](lgf_status st) {
         lgf_destroy(h);
@@ -518,10 +518,12 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
     if (history_cap < 0 || (history_cap > 0 && !history)) return fail(LGF_EINVAL, "bad history buffer");
     const int bulk = (p.bulk_format < 0) ? h->format : p.bulk_format;
+    const int finish = (p.finish_format < 0) ? h->format : p.finish_format;
     if (!valid_format(bulk)) return fail(LGF_EINVAL, "unknown bulk format %d", bulk);
-    const bool mixed = (bulk != h->format);
+    if (!valid_format(finish)) return fail(LGF_EINVAL, "unknown finish format %d", finish);
+    const bool mixed = (bulk != finish);
     if (mixed && !(p.theta_switch > 0.0))
-        return fail(LGF_EINVAL, "a bulk format other than the handle's needs theta_switch > 0");
+        return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
     LGF_TRY(use_device(h));
 
     std::memset(res, 0, sizeof *res);
@@ -535,13 +537,36 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
             ++nh;
         }
     };
+    // the field the sweeps run on, and a timed conversion between fields
+    int cur_fmt = h->format;
+    void *cur = h->field;
+    auto move_to = [&](int fmt, bool reunit) -> lgf_status {
+        void *dst = h->field;
+        if (fmt != h->format) {
+            LGF_TRY(ensure_work(h, fmt));
+            dst = h->work[fmt];
+        }
+        if (dst == cur) return LGF_OK;
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_HIP(lgf::launch_convert(cur_fmt, cur, fmt, dst, h->geom, reunit, h->stream));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+        cur = dst;
+        cur_fmt = fmt;
+        return LGF_OK;
+    };
+    auto measure_timed = [&](bool reunit, double *F, double *th) -> lgf_status {
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(measure_field(h, cur_fmt, cur, reunit, F, th));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+        return LGF_OK;
+    };
 
     double F = 0.0, theta = 0.0;
-    LGF_HIP(hipEventRecord(h->ev0, h->stream));
-    LGF_TRY(measure_field(h, h->format, h->field, false, &F, &theta));
-    LGF_HIP(hipEventRecord(h->ev1, h->stream));
-    LGF_HIP(hipEventSynchronize(h->ev1));
-    res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+    LGF_TRY(measure_timed(false, &F, &theta));
     record(0, F, theta);
 
     int64_t sweeps = 0, sweeps_bulk = 0;
@@ -550,21 +575,13 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     if (!std::isfinite(F) || !std::isfinite(theta)) status = LGF_ENUMERIC;
     else if (theta < p.theta_target) status = LGF_OK;
 
-    bool in_bulk = false;
-    int cur_fmt = h->format;
-    void *cur = h->field;
-    if (status == LGF_ENOTCONV && mixed && p.max_sweeps > 0) {
-        LGF_TRY(ensure_work(h, bulk));
-        LGF_HIP(hipEventRecord(h->ev0, h->stream));
-        LGF_HIP(lgf::launch_convert(h->format, h->field, bulk, h->work[bulk], h->geom, false, h->stream));
-        LGF_HIP(hipEventRecord(h->ev1, h->stream));
-        LGF_HIP(hipEventSynchronize(h->ev1));
-        res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
-        in_bulk = true;
-        cur_fmt = bulk;
-        cur = h->work[bulk];
+    bool in_bulk = mixed;
+    if (status == LGF_ENOTCONV && p.max_sweeps > 0) {
+        const int first = in_bulk ? bulk : finish;
+        const bool to_fp64 = (first == LGF_FP64_18 || first == LGF_FP64_12) &&
+                             !(h->format == LGF_FP64_18 || h->format == LGF_FP64_12);
+        LGF_TRY(move_to(first, to_fp64));
     }
-
     while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
         const int64_t left = p.max_sweeps - sweeps;
         const int n = (int)(left < p.check_every ? left : p.check_every);
@@ -582,39 +599,27 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         sweeps += n;
         ctr += (uint64_t)n;
 
-        LGF_HIP(hipEventRecord(h->ev0, h->stream));
-        LGF_TRY(measure_field(h, cur_fmt, cur, true, &F, &theta));
-        LGF_HIP(hipEventRecord(h->ev1, h->stream));
-        LGF_HIP(hipEventSynchronize(h->ev1));
-        res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+        LGF_TRY(measure_timed(true, &F, &theta));
         record(sweeps, F, theta);
         if (!std::isfinite(F) || !std::isfinite(theta)) {
             status = LGF_ENUMERIC;
             break;
         }
-        if (in_bulk && (theta < p.theta_switch || theta < p.theta_target || sweeps >= p.max_sweeps)) {
-            // leave the bulk precision: back to the handle's format, reunitarized in FP64
-            LGF_HIP(hipEventRecord(h->ev0, h->stream));
-            LGF_HIP(lgf::launch_convert(bulk, h->work[bulk], h->format, h->field, h->geom, true, h->stream));
-            LGF_HIP(hipEventRecord(h->ev1, h->stream));
-            LGF_HIP(hipEventSynchronize(h->ev1));
-            res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+        if (in_bulk && (theta < p.theta_switch || theta < p.theta_target)) {
+            // leave the bulk precision, reunitarizing in FP64 on the way
+            LGF_TRY(move_to(finish, true));
             in_bulk = false;
-            cur_fmt = h->format;
-            cur = h->field;
             if (theta < p.theta_target) {
-                LGF_TRY(measure_field(h, cur_fmt, cur, false, &F, &theta));
+                LGF_TRY(measure_timed(false, &F, &theta));
                 record(sweeps, F, theta);
-                if (theta < p.theta_target) status = LGF_OK;
+            } else {
+                continue;
             }
-            continue;
         }
         if (!in_bulk && theta < p.theta_target) status = LGF_OK;
     }
-    if (in_bulk) {
-        // max_sweeps == 0 with a converted copy: nothing ran, nothing to copy back
-        in_bulk = false;
-    }
+    // hand the links back in the handle's own format
+    LGF_TRY(move_to(h->format, false));
 
     res->sweeps = sweeps;
     res->sweeps_bulk = sweeps_bulk;
@@ -631,7 +636,8 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     return LGF_OK;
 }
 
-lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap)
+lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap,
+                          int nontemporal)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
@@ -639,18 +645,20 @@ lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int bl
         return fail(LGF_EINVAL, "lanes_per_site must be 1, 2 or 4");
     if (block != 64 && block != 128 && block != 256)
         return fail(LGF_EINVAL, "block must be 64, 128 or 256");
-    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0};
+    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0};
     drop_graphs(h);
     return LGF_OK;
 }
 
-lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap)
+lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap,
+                          int *nontemporal)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (lanes_per_site) *lanes_per_site = h->tune[format].lanes_per_site;
     if (block) *block = h->tune[format].block;
     if (xcd_remap) *xcd_remap = h->tune[format].xcd_remap;
+    if (nontemporal) *nontemporal = h->tune[format].nontemporal;
     return LGF_OK;
 }
 
@@ -675,8 +683,8 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     const int block_list[3] = {64, 128, 256};
     for (int li = 0; li < 3 && e == hipSuccess; ++li)
         for (int bi = 0; bi < 3 && e == hipSuccess; ++bi)
-            for (int xr = 0; xr < 2 && e == hipSuccess; ++xr) {
-                const lgf::SweepTuning t{lps_list[li], block_list[bi], xr};
+            for (int v = 0; v < 4 && e == hipSuccess; ++v) {
+                const lgf::SweepTuning t{lps_list[li], block_list[bi], v & 1, v >> 1};
                 lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};
                 e = lgf::launch_sweep(format, scratch, h->geom, a, t, h->stream);  // warm-up
                 if (e != hipSuccess) break;

@@ -90,9 +90,11 @@ __device__ __forceinline__ void right_mul_dag(mat3<T> &r, const mat3<T> &u, cons
                         mul_conj(u.e[i][2], g.e[j][2]);
 }
 
-template <typename T> __device__ __forceinline__ T fast_rsqrt(T x);
-template <> __device__ __forceinline__ float fast_rsqrt<float>(float x) { return __frsqrt_rn(x); }
-template <> __device__ __forceinline__ double fast_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
+template <typename T> __device__ __forceinline__ T exact_rsqrt(T x);
+// correctly rounded sqrt and division: the SU(2) normalisation amplifies
+// rounding errors on ill-conditioned sites, so no approximate rsqrt here
+template <> __device__ __forceinline__ float exact_rsqrt<float>(float x) { return 1.0f / sqrtf(x); }
+template <> __device__ __forceinline__ double exact_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
 
 // Project a 3x3 matrix onto SU(3) in FP64: normalise row 0, orthogonalise
 // and normalise row 1, row 2 = conj(row0 x row1).
@@ -138,11 +140,28 @@ __device__ __forceinline__ void convert(mat3<B> &dst, const mat3<A> &src)
 
 enum : int { kF64_18 = 0, kF32_18 = 1, kF32_12 = 2, kF64_12 = 3 };
 
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 template <int F> struct Fmt;
-template <> struct Fmt<kF64_18> { using T = double; using V = double2; static constexpr int R = 3, NV = 9, CPV = 1; };
-template <> struct Fmt<kF64_12> { using T = double; using V = double2; static constexpr int R = 2, NV = 6, CPV = 1; };
-template <> struct Fmt<kF32_18> { using T = float;  using V = float2;  static constexpr int R = 3, NV = 9, CPV = 1; };
-template <> struct Fmt<kF32_12> { using T = float;  using V = float4;  static constexpr int R = 2, NV = 3, CPV = 2; };
+template <> struct Fmt<kF64_18> { using T = double; using V = v2d; static constexpr int R = 3, NV = 9, CPV = 1; };
+template <> struct Fmt<kF64_12> { using T = double; using V = v2d; static constexpr int R = 2, NV = 6, CPV = 1; };
+template <> struct Fmt<kF32_18> { using T = float;  using V = v2f; static constexpr int R = 3, NV = 9, CPV = 1; };
+template <> struct Fmt<kF32_12> { using T = float;  using V = v4f; static constexpr int R = 2, NV = 3, CPV = 2; };
+
+// vector load / store, optionally marked non-temporal (streamed past the
+// caches: every link is read and written once per half-sweep)
+template <bool NT, typename V> __device__ __forceinline__ V vload(const V *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename V> __device__ __forceinline__ void vstore(V *p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // base pointer of the (parity, mu) block
 template <int F>
@@ -152,14 +171,14 @@ __device__ __forceinline__ typename Fmt<F>::V *block_ptr(void *field, uint32_t V
            (size_t)((parity * 4 + mu) * Fmt<F>::NV) * Vh;
 }
 
-template <int F>
+template <int F, bool NT = false>
 __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *blk,
                                           uint32_t Vh, uint32_t h)
 {
     using S = Fmt<F>;
     typename S::V v[S::NV];
 #pragma unroll
-    for (int k = 0; k < S::NV; ++k) v[k] = blk[(size_t)k * Vh + h];
+    for (int k = 0; k < S::NV; ++k) v[k] = vload<NT>(blk + (size_t)k * Vh + h);
     if constexpr (S::CPV == 1) {
 #pragma unroll
         for (int k = 0; k < S::NV; ++k) u.e[k / 3][k % 3] = {v[k].x, v[k].y};
@@ -173,7 +192,7 @@ __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typ
     if constexpr (S::R == 2) rebuild_row2(u);
 }
 
-template <int F>
+template <int F, bool NT = false>
 __device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh, uint32_t h,
                                            const mat3<typename Fmt<F>::T> &u)
 {
@@ -190,7 +209,7 @@ __device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh,
             v.z = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].re;
             v.w = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].im;
         }
-        blk[(size_t)k * Vh + h] = v;
+        vstore<NT>(blk + (size_t)k * Vh + h, v);
     }
 }
 

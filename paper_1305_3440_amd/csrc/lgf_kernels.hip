@@ -47,7 +47,7 @@ __device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool o
     const T n2 = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
     T r0 = T(1), r1 = T(0), r2 = T(0), r3 = T(0);
     if (n2 > T(0)) {
-        const T inv = fast_rsqrt<T>(n2);
+        const T inv = exact_rsqrt<T>(n2);
         const T b0 = a0 * inv, b1 = -a1 * inv, b2 = -a2 * inv, b3 = -a3 * inv;
         if (square) {
             r0 = b0 * b0 - (b1 * b1 + b2 * b2 + b3 * b3);
@@ -57,7 +57,7 @@ __device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool o
         } else if (overrelax) {
             const T c0 = (T(1) - omega) + omega * b0;
             const T c1 = omega * b1, c2 = omega * b2, c3 = omega * b3;
-            const T ic = fast_rsqrt<T>(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
+            const T ic = exact_rsqrt<T>(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
             r0 = c0 * ic; r1 = c1 * ic; r2 = c2 * ic; r3 = c3 * ic;
         } else {
             r0 = b0; r1 = b1; r2 = b2; r3 = b3;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool o
 
 template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
 
-template <int F, int LPS, bool SR>
+template <int F, int LPS, bool SR, bool NT>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      typename Fmt<F>::T omega, int overrelax,
                                                      uint64_t sr_threshold, uint32_t key0,
@@ -113,8 +113,8 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
     for (int k = 0; k < NL; ++k) {
         const int mu = lane + k * LPS;
         hb[k] = back_half(g, c, h, mu);
-        load_link<F>(uf[k], block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
-        load_link<F>(ub[k], block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k]);
+        load_link<F, NT>(uf[k], block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+        load_link<F, NT>(ub[k], block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k]);
     }
 
     // K(x) = sum_mu U_mu(x) + U_mu(x - mu)^dag (Eq. (8), neighbours' g applied)
@@ -153,13 +153,13 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
         const int mu = lane + k * LPS;
         mat3<T> r;
         left_mul<S::R>(r, G, uf[k]);
-        store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, r);
+        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, r);
         right_mul_dag<S::R>(r, ub[k], G);
-        store_link<F>(block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
+        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
     }
 }
 
-template <int F, int LPS>
+template <int F, int LPS, bool NT>
 static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  hipStream_t s)
 {
@@ -171,11 +171,11 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (a.p_sr > 0.0) {
         const uint64_t thr = (uint64_t)floor(a.p_sr * 4294967296.0);
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, true>), dim3(grid), dim3(t.block), 0, s, field, g,
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
                            a.parity, (T)a.omega, overrelax, thr, k0, k1, (uint32_t)a.sweep_index,
                            a.instance, t.xcd_remap, nb);
     } else {
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, false>), dim3(grid), dim3(t.block), 0, s, field, g,
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, false, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
                            a.parity, (T)a.omega, overrelax, (uint64_t)0, k0, k1,
                            (uint32_t)a.sweep_index, a.instance, t.xcd_remap, nb);
     }
@@ -186,10 +186,14 @@ template <int F>
 static hipError_t launch_sweep_f(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  hipStream_t s)
 {
-    switch (t.lanes_per_site) {
-    case 1: return launch_sweep_t<F, 1>(field, g, a, t, s);
-    case 2: return launch_sweep_t<F, 2>(field, g, a, t, s);
-    case 4: return launch_sweep_t<F, 4>(field, g, a, t, s);
+    const int key = t.lanes_per_site * 2 + (t.nontemporal ? 1 : 0);
+    switch (key) {
+    case 2: return launch_sweep_t<F, 1, false>(field, g, a, t, s);
+    case 3: return launch_sweep_t<F, 1, true>(field, g, a, t, s);
+    case 4: return launch_sweep_t<F, 2, false>(field, g, a, t, s);
+    case 5: return launch_sweep_t<F, 2, true>(field, g, a, t, s);
+    case 8: return launch_sweep_t<F, 4, false>(field, g, a, t, s);
+    case 9: return launch_sweep_t<F, 4, true>(field, g, a, t, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -27,7 +27,7 @@ class lgf_fix_params(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("p_sr", ctypes.c_double),
                 ("theta_target", ctypes.c_double), ("theta_switch", ctypes.c_double),
                 ("bulk_format", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("finish_format", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("sweep_offset", ctypes.c_uint64)]
 
@@ -88,8 +88,8 @@ def load_library(path: str = LIB_PATH):
         "lgf_measure": (I, [P, P, P]),
         "lgf_gauge_fix": (I, [P, P, P, P, I]),
         "lgf_synchronize": (I, [P]),
-        "lgf_set_tuning": (I, [P, I, I, I, I]),
-        "lgf_get_tuning": (I, [P, I, P, P, P]),
+        "lgf_set_tuning": (I, [P, I, I, I, I, I]),
+        "lgf_get_tuning": (I, [P, I, P, P, P, P]),
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
     }
@@ -230,14 +230,17 @@ def lgf_synchronize(h) -> None:
     _check(load_library().lgf_synchronize(h))
 
 
-def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0) -> None:
-    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap))
+def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0,
+                   nontemporal: int = 0) -> None:
+    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal))
 
 
 def lgf_get_tuning(h, fmt: int):
-    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+    """(lanes_per_site, block, xcd_remap, nontemporal)"""
+    a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                         ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
 
 
 def lgf_autotune(h, fmt: int, trials: int = 4) -> None:
