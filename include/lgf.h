@@ -217,6 +217,55 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
 lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed,
                            uint64_t sweep_index, double *ms_per_launch);
 
+/* ------------------------------------------------------------------------ */
+/* Ensembles: many independent lattices (sizes may differ) swept and measured */
+/* by one persistent launch per parity.                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct lgf_ensemble lgf_ensemble;   /* opaque handle: n lattices on one GPU */
+
+/* Create an ensemble of n configurations; dims holds n*4 extents (each
+ * configuration as in lgf_create), format is the home storage format of all
+ * of them.  The library allocates every field; stream as in lgf_create.  The
+ * links are uninitialised until loaded or generated. */
+lgf_status lgf_ensemble_create(int n, const int *dims, int format, void *stream, lgf_ensemble **out);
+
+/* Release the ensemble and everything it owns; NULL is allowed. */
+lgf_status lgf_ensemble_destroy(lgf_ensemble *e);
+
+/* Per configuration i in [0, n): generate (as lgf_generate_links), load or
+ * store the canonical host array (72*V_i doubles). */
+lgf_status lgf_ensemble_generate(lgf_ensemble *e, int i, uint64_t seed, double eps, int haar);
+lgf_status lgf_ensemble_load_links(lgf_ensemble *e, int i, const double *host_canon, size_t n_doubles);
+lgf_status lgf_ensemble_store_links(lgf_ensemble *e, int i, double *host_canon, size_t n_doubles);
+
+/* One half-sweep (parity 0, 1) or full sweep (2) of every configuration in the
+ * home format, as lgf_sweep, in one persistent launch per parity; the
+ * stochastic-relaxation counter of configuration i is (s, sweep_index, i, 3). */
+lgf_status lgf_ensemble_sweep(lgf_ensemble *e, int parity, double omega, double p_sr, uint64_t seed,
+                              uint64_t sweep_index);
+
+/* F[i], theta[i] of every configuration (as lgf_measure); either output may be
+ * NULL.  Synchronises. */
+lgf_status lgf_ensemble_measure(lgf_ensemble *e, double *F, double *theta);
+
+/* Gauge-fix every configuration (as lgf_gauge_fix, one lgf_fix_params for all)
+ * with per-configuration state: each configuration leaves the bulk format when
+ * its own theta < theta_switch and stops sweeping when its own theta <
+ * theta_target; the others go on.  All live configurations share each
+ * persistent launch, whatever their phase.  results[i] (n entries) gets each
+ * configuration's sweeps, theta, F and status; its time fields hold the
+ * ensemble totals (chunks holding any bulk configuration count as bulk time),
+ * except t_total_ms, the time at which that configuration finished. */
+lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
+                                  lgf_fix_result *results);
+
+/* Average ms per persistent launch (one parity of every configuration) of n
+ * full sweeps in the given format, on copies of the links (the home fields are
+ * untouched). */
+lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
+                                    double *ms_per_launch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,11 +17,14 @@
 #include <vector>
 
 #include "lgf_device.hpp"
+#include "lgf_host.hpp"
 #include "lgf_internal.hpp"
 
-namespace {
+namespace lgf {
 
+namespace {
 thread_local std::string g_last_error;
+}
 
 lgf_status fail(lgf_status st, const char *fmt, ...)
 {
@@ -34,19 +37,7 @@ lgf_status fail(lgf_status st, const char *fmt, ...)
     return st;
 }
 
-#define LGF_HIP(call)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(LGF_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),       \
-                        __FILE__, __LINE__);                                                   \
-    } while (0)
-
-#define LGF_TRY(expr)                                                                          \
-    do {                                                                                       \
-        lgf_status s_ = (expr);                                                                \
-        if (s_ != LGF_OK) return s_;                                                           \
-    } while (0)
+const char *last_error() { return g_last_error.c_str(); }
 
 bool valid_format(int f) { return f >= LGF_FP64_18 && f <= LGF_FP64_12; }
 
@@ -60,6 +51,35 @@ bool valid_dims(const int dims[4])
     }
     return V <= (1ull << 31);
 }
+
+Geom make_geom(const int dims[4])
+{
+    Geom g;
+    for (int d = 0; d < 4; ++d) g.L[d] = (uint32_t)dims[d];
+    g.hx = g.L[3] / 2;
+    g.Vh = g.L[0] * g.L[1] * g.L[2] * g.hx;
+    g.hs[0] = g.L[1] * g.L[2] * g.hx;
+    g.hs[1] = g.L[2] * g.hx;
+    g.hs[2] = g.hx;
+    return g;
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+}  // namespace lgf
+
+namespace {
+
+using lgf::fail;
+using lgf::valid_format;
+using lgf::valid_dims;
+using lgf::make_geom;
+using lgf::elapsed_ms;
 
 struct GraphEntry {
     int format;
@@ -112,18 +132,6 @@ void drop_graphs(lgf_lattice *h)
 {
     for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
-}
-
-lgf::Geom make_geom(const int dims[4])
-{
-    lgf::Geom g;
-    for (int d = 0; d < 4; ++d) g.L[d] = (uint32_t)dims[d];
-    g.hx = g.L[3] / 2;
-    g.Vh = g.L[0] * g.L[1] * g.L[2] * g.hx;
-    g.hs[0] = g.L[1] * g.L[2] * g.hx;
-    g.hs[1] = g.L[2] * g.hx;
-    g.hs[2] = g.hx;
-    return g;
 }
 
 lgf_status ensure_stage(lgf_lattice *h)
@@ -234,18 +242,11 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     return LGF_OK;
 }
 
-double elapsed_ms(hipEvent_t a, hipEvent_t b)
-{
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
-    return (double)ms;
-}
-
 }  // namespace
 
 extern "C" {
 
-const char *lgf_last_error(void) { return g_last_error.c_str(); }
+const char *lgf_last_error(void) { return lgf::last_error(); }
 
 const char *lgf_version(void) { return "lgf-mi355x 0.1 (gfx950)"; }
 
@@ -296,8 +297,8 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     h->geom = make_geom(dims);
     h->format = format;
     h->field_bytes = need;
-    // defaults: one lane per site, 128-thread workgroups (fastest measured
-    // at 64^4 for every format)
+    // defaults: one lane per site, 128-thread workgroups, non-temporal
+    // streaming (fastest measured at 64^4 for every format)
     for (int f = 0; f < 4; ++f) h->tune[f] = lgf::SweepTuning{};
 
     auto bail = [&](lgf_status st) {

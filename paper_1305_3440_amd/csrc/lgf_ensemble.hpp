@@ -1,0 +1,59 @@
+// lgf_ensemble.hpp -- device-visible descriptors of the ensemble work list and
+// the launchers of the persistent ensemble kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "lgf_device.hpp"
+
+namespace lgf {
+
+constexpr int kEnsTile = 128;  // sites per tile (one workgroup of one lane per site)
+
+struct EnsCfg {         // one configuration as the kernels see it
+    Geom g;
+    void *field;        // links in the current storage format
+    int fmt;            // current storage format
+    uint32_t instance;  // the configuration's index: third word of the SR counter
+};
+
+struct EnsTile {        // 128 consecutive half indices of one configuration
+    uint32_t cfg;
+    uint32_t h0;
+};
+
+struct EnsSpan {        // the tiles [first, first + count) of configuration cfg
+    uint32_t cfg;
+    uint32_t first;
+    uint32_t count;
+    double V;
+};
+
+struct EnsRelax {       // relaxation parameters shared by the whole launch
+    double omega;
+    int overrelax;
+    uint64_t sr_threshold;
+    uint32_t key0, key1;
+};
+
+struct EnsLaunch {      // device pointers of one ensemble's work list
+    const EnsCfg *cfgs;
+    const EnsTile *tiles;
+    const uint32_t *n_tiles;
+    const uint64_t *sweep_base;
+    uint32_t grid;      // persistent workgroups
+};
+
+hipError_t launch_ensemble_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
+                                 uint32_t sweep_offset, bool sr, bool nt, hipStream_t s);
+hipError_t launch_ensemble_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
+                                   bool reunit_fwd, bool reunit_bwd, double *partials, hipStream_t s);
+hipError_t launch_ensemble_finish(const double *partials, uint32_t n_tiles, const EnsSpan *spans,
+                                  uint32_t n_spans, double *out, hipStream_t s);
+// workgroups that fill every CU for the sweep kernel of a format pair
+int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt);
+// *p = v, as a one-lane kernel on the stream (safe inside a captured graph)
+hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
+
+}  // namespace lgf

@@ -1,0 +1,567 @@
+// lgf_ensemble_api.cpp -- C ABI of an ensemble of independent lattices of
+// different sizes swept and measured by one persistent launch per parity, with
+// per-configuration mixed-precision state and convergence, and hipGraph-
+// captured sweep chunks.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lgf.h"
+#include "lgf_ensemble.hpp"
+#include "lgf_host.hpp"
+#include "lgf_internal.hpp"
+
+using lgf::fail;
+
+namespace {
+
+enum Phase { kBulk = 0, kFinish = 1, kDone = 2 };
+
+struct EnsGraph {
+    int fa, fb;
+    int n_sweeps;
+    double omega;
+    bool nt;
+    hipGraphExec_t exec;
+};
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct lgf_ensemble {
+    int n = 0;
+    int format = 0;                       // home format of every configuration
+    std::vector<lgf::Geom> geom;
+    std::vector<int64_t> V;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    void *home = nullptr;                 // one allocation, configurations at offsets
+    std::vector<size_t> home_off;
+    void *work[4] = {nullptr, nullptr, nullptr, nullptr};  // per-format copies, same offsets scheme
+    std::vector<size_t> work_off[4];
+    // work list (device) and its pinned host mirrors
+    lgf::EnsCfg *d_cfgs = nullptr;
+    lgf::EnsTile *d_tiles = nullptr;
+    uint32_t *d_n_tiles = nullptr;
+    uint64_t *d_sweep_base = nullptr;
+    lgf::EnsSpan *d_spans = nullptr;
+    double *d_partials = nullptr;
+    double *d_out = nullptr;
+    lgf::EnsCfg *h_cfgs = nullptr;
+    lgf::EnsTile *h_tiles = nullptr;
+    uint32_t *h_n_tiles = nullptr;
+    lgf::EnsSpan *h_spans = nullptr;
+    double *h_out = nullptr;
+    uint32_t max_tiles = 0;
+    int nontemporal = 0;
+    std::vector<EnsGraph> graphs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+lgf_status ens_use_device(const lgf_ensemble *e)
+{
+    int cur = -1;
+    LGF_HIP(hipGetDevice(&cur));
+    if (cur != e->device) LGF_HIP(hipSetDevice(e->device));
+    return LGF_OK;
+}
+
+void *field_of(lgf_ensemble *e, int fmt, int i)
+{
+    if (fmt == e->format) return (char *)e->home + e->home_off[i];
+    return (char *)e->work[fmt] + e->work_off[fmt][i];
+}
+
+lgf_status ensure_work(lgf_ensemble *e, int fmt)
+{
+    if (fmt == e->format || e->work[fmt]) return LGF_OK;
+    std::vector<size_t> off(e->n);
+    size_t total = 0;
+    for (int i = 0; i < e->n; ++i) {
+        off[i] = total;
+        total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(fmt));
+    }
+    if (hipMalloc(&e->work[fmt], total) != hipSuccess) {
+        e->work[fmt] = nullptr;
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the ensemble's format-%d copies", total, fmt);
+    }
+    e->work_off[fmt] = off;
+    return LGF_OK;
+}
+
+void drop_graphs(lgf_ensemble *e)
+{
+    for (auto &g : e->graphs) (void)hipGraphExecDestroy(g.exec);
+    e->graphs.clear();
+}
+
+// Work list of the configurations whose phase is in `want`, each in format
+// fmt_of[i]; uploads descriptors, tiles and their count.  Returns the tiles.
+uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::vector<int> &fmt_of,
+                    bool include_done, std::vector<int> &listed)
+{
+    uint32_t nt = 0;
+    listed.clear();
+    for (int i = 0; i < e->n; ++i) {
+        e->h_cfgs[i].g = e->geom[i];
+        e->h_cfgs[i].fmt = fmt_of[i];
+        e->h_cfgs[i].field = field_of(e, fmt_of[i], i);
+        e->h_cfgs[i].instance = (uint32_t)i;
+        if (!include_done && phase[i] == kDone) continue;
+        const uint32_t tiles = (e->geom[i].Vh + lgf::kEnsTile - 1) / lgf::kEnsTile;
+        e->h_spans[listed.size()] = lgf::EnsSpan{(uint32_t)i, nt, tiles, (double)e->V[i]};
+        for (uint32_t t = 0; t < tiles; ++t) e->h_tiles[nt + t] = lgf::EnsTile{(uint32_t)i, t * (uint32_t)lgf::kEnsTile};
+        nt += tiles;
+        listed.push_back(i);
+    }
+    *e->h_n_tiles = nt;
+    return nt;
+}
+
+lgf_status upload_work(lgf_ensemble *e, uint32_t nt, size_t n_spans)
+{
+    LGF_HIP(hipMemcpyAsync(e->d_cfgs, e->h_cfgs, sizeof(lgf::EnsCfg) * e->n, hipMemcpyHostToDevice, e->stream));
+    if (nt) LGF_HIP(hipMemcpyAsync(e->d_tiles, e->h_tiles, sizeof(lgf::EnsTile) * nt, hipMemcpyHostToDevice, e->stream));
+    LGF_HIP(hipMemcpyAsync(e->d_n_tiles, e->h_n_tiles, sizeof(uint32_t), hipMemcpyHostToDevice, e->stream));
+    if (n_spans)
+        LGF_HIP(hipMemcpyAsync(e->d_spans, e->h_spans, sizeof(lgf::EnsSpan) * n_spans, hipMemcpyHostToDevice, e->stream));
+    return LGF_OK;
+}
+
+lgf::EnsLaunch launch_desc(lgf_ensemble *e, int fa, int fb, bool sr)
+{
+    return lgf::EnsLaunch{e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base,
+                          (uint32_t)lgf::ensemble_persistent_grid(fa, fb, sr, e->nontemporal != 0)};
+}
+
+lgf::EnsRelax relax_args(double omega, double p_sr, uint64_t seed)
+{
+    lgf::EnsRelax r;
+    r.omega = omega;
+    r.overrelax = (omega != 1.0) ? 1 : 0;
+    r.sr_threshold = (p_sr > 0.0) ? (uint64_t)std::floor(p_sr * 4294967296.0) : 0;
+    r.key0 = (uint32_t)seed;
+    r.key1 = (uint32_t)(seed >> 32);
+    return r;
+}
+
+// n full sweeps of every listed configuration, counters from sweep0
+lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, double p_sr, uint64_t seed,
+                     uint64_t sweep0, bool use_graph)
+{
+    LGF_HIP(lgf::launch_set_u64(e->d_sweep_base, sweep0, e->stream));
+    const bool sr = p_sr > 0.0;
+    const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
+    const lgf::EnsLaunch L = launch_desc(e, fa, fb, sr);
+    const bool nt = e->nontemporal != 0;
+    if (!use_graph || sr) {
+        for (int k = 0; k < n; ++k)
+            for (int parity = 0; parity < 2; ++parity)
+                LGF_HIP(lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream));
+        return LGF_OK;
+    }
+    for (auto &g : e->graphs)
+        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.nt == nt) {
+            LGF_HIP(hipGraphLaunch(g.exec, e->stream));
+            return LGF_OK;
+        }
+    hipGraph_t graph = nullptr;
+    LGF_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < n && err == hipSuccess; ++k)
+        for (int parity = 0; parity < 2 && err == hipSuccess; ++parity)
+            err = lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, false, nt, e->stream);
+    hipError_t e2 = hipStreamEndCapture(e->stream, &graph);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(LGF_EHIP, "ensemble graph capture: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err != hipSuccess) return fail(LGF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(err));
+    if (e->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(e->graphs.front().exec);
+        e->graphs.erase(e->graphs.begin());
+    }
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, nt, exec});
+    LGF_HIP(hipGraphLaunch(exec, e->stream));
+    return LGF_OK;
+}
+
+// F, theta of the listed configurations (work list already uploaded); with
+// reunit the fused FP64 reunitarization of the single-lattice measurement.
+lgf_status measure_listed(lgf_ensemble *e, int fa, int fb, uint32_t nt, const std::vector<int> &listed, bool reunit)
+{
+    if (nt == 0) return LGF_OK;
+    const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
+    LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 0, reunit, reunit, e->d_partials, e->stream));
+    LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 1, reunit, false, e->d_partials + 2 * (size_t)nt, e->stream));
+    LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
+    LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    return LGF_OK;
+}
+
+lgf_status convert_one(lgf_ensemble *e, int i, int fs, int fd, bool reunit)
+{
+    if (fs == fd) return LGF_OK;
+    LGF_TRY(ensure_work(e, fs));
+    LGF_TRY(ensure_work(e, fd));
+    LGF_HIP(lgf::launch_convert(fs, field_of(e, fs, i), fd, field_of(e, fd, i), e->geom[i], reunit, e->stream));
+    return LGF_OK;
+}
+
+bool is_fp64(int f) { return f == LGF_FP64_18 || f == LGF_FP64_12; }
+
+}  // namespace
+
+extern "C" {
+
+lgf_status lgf_ensemble_create(int n, const int *dims, int format, void *stream, lgf_ensemble **out)
+{
+    if (!out) return fail(LGF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !dims) return fail(LGF_EINVAL, "need n >= 1 configurations and their dims");
+    if (!lgf::valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    for (int i = 0; i < n; ++i)
+        if (!lgf::valid_dims(dims + 4 * i))
+            return fail(LGF_EINVAL, "configuration %d: every extent must be even and >= 2, V <= 2^31", i);
+    lgf_ensemble *e = new (std::nothrow) lgf_ensemble();
+    if (!e) return fail(LGF_ENOMEM, "host allocation of the ensemble failed");
+    e->n = n;
+    e->format = format;
+    e->nontemporal = 1;
+    size_t total = 0, tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        e->geom.push_back(lgf::make_geom(dims + 4 * i));
+        e->V.push_back((int64_t)dims[4 * i] * dims[4 * i + 1] * dims[4 * i + 2] * dims[4 * i + 3]);
+        e->home_off.push_back(total);
+        total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(format));
+        tiles += (e->geom[i].Vh + lgf::kEnsTile - 1) / lgf::kEnsTile;
+    }
+    e->max_tiles = (uint32_t)tiles;
+    auto bail = [&](lgf_status st) {
+        lgf_ensemble_destroy(e);
+        return st;
+    };
+    hipError_t err = hipGetDevice(&e->device);
+    if (err != hipSuccess) return bail(fail(LGF_EHIP, "hipGetDevice: %s", hipGetErrorString(err)));
+    if (stream) {
+        e->stream = (hipStream_t)stream;
+    } else {
+        if ((err = hipStreamCreate(&e->stream)) != hipSuccess)
+            return bail(fail(LGF_EHIP, "hipStreamCreate: %s", hipGetErrorString(err)));
+        e->own_stream = true;
+    }
+    if ((err = hipMalloc(&e->home, total)) != hipSuccess) {
+        e->home = nullptr;
+        (void)hipGetLastError();
+        return bail(fail(LGF_ENOMEM, "cannot allocate %zu bytes for the ensemble", total));
+    }
+    const size_t T = e->max_tiles;
+    if ((err = hipMalloc(&e->d_cfgs, sizeof(lgf::EnsCfg) * n)) != hipSuccess ||
+        (err = hipMalloc(&e->d_tiles, sizeof(lgf::EnsTile) * T)) != hipSuccess ||
+        (err = hipMalloc(&e->d_n_tiles, sizeof(uint32_t))) != hipSuccess ||
+        (err = hipMalloc(&e->d_sweep_base, sizeof(uint64_t))) != hipSuccess ||
+        (err = hipMalloc(&e->d_spans, sizeof(lgf::EnsSpan) * n)) != hipSuccess ||
+        (err = hipMalloc(&e->d_partials, sizeof(double) * 4 * T)) != hipSuccess ||
+        (err = hipMalloc(&e->d_out, sizeof(double) * 2 * n)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_cfgs, sizeof(lgf::EnsCfg) * n, hipHostMallocDefault)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_tiles, sizeof(lgf::EnsTile) * T, hipHostMallocDefault)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_n_tiles, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_spans, sizeof(lgf::EnsSpan) * n, hipHostMallocDefault)) != hipSuccess ||
+        (err = hipHostMalloc((void **)&e->h_out, sizeof(double) * 2 * n, hipHostMallocDefault)) != hipSuccess ||
+        (err = hipEventCreate(&e->ev0)) != hipSuccess || (err = hipEventCreate(&e->ev1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(LGF_ENOMEM, "ensemble scratch allocation failed: %s", hipGetErrorString(err)));
+    }
+    *out = e;
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_destroy(lgf_ensemble *e)
+{
+    if (!e) return LGF_OK;
+    (void)ens_use_device(e);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    drop_graphs(e);
+    if (e->home) (void)hipFree(e->home);
+    for (int f = 0; f < 4; ++f)
+        if (e->work[f]) (void)hipFree(e->work[f]);
+    void *dev[] = {e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base, e->d_spans, e->d_partials, e->d_out};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *host[] = {e->h_cfgs, e->h_tiles, e->h_n_tiles, e->h_spans, e->h_out};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+    return LGF_OK;
+}
+
+static lgf_status check_index(const lgf_ensemble *e, int i)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    if (i < 0 || i >= e->n) return fail(LGF_EINVAL, "configuration %d outside [0, %d)", i, e->n);
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_generate(lgf_ensemble *e, int i, uint64_t seed, double eps, int haar)
+{
+    LGF_TRY(check_index(e, i));
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(LGF_EINVAL, "eps must be finite and >= 0");
+    LGF_TRY(ens_use_device(e));
+    LGF_HIP(lgf::launch_generate(e->format, field_of(e, e->format, i), e->geom[i], seed, eps, haar != 0, e->stream));
+    return LGF_OK;
+}
+
+static lgf_status canon_io(lgf_ensemble *e, int i, double *host, size_t n_doubles, bool load)
+{
+    LGF_TRY(check_index(e, i));
+    if (!host) return fail(LGF_EINVAL, "host array is NULL");
+    if (n_doubles != (size_t)e->V[i] * 72)
+        return fail(LGF_EINVAL, "host array has %zu doubles, configuration %d needs %lld", n_doubles, i,
+                    (long long)e->V[i] * 72);
+    LGF_TRY(ens_use_device(e));
+    const int64_t chunk = 1 << 16;
+    double *stage = nullptr;
+    const int64_t ns = e->V[i] < chunk ? e->V[i] : chunk;
+    LGF_HIP(hipMalloc(&stage, (size_t)ns * 72 * sizeof(double)));
+    hipError_t err = hipSuccess;
+    for (int64_t s0 = 0; s0 < e->V[i] && err == hipSuccess; s0 += chunk) {
+        const int64_t n = (e->V[i] - s0 < chunk) ? e->V[i] - s0 : chunk;
+        if (load) {
+            err = hipMemcpyAsync(stage, host + s0 * 72, (size_t)n * 72 * sizeof(double), hipMemcpyHostToDevice, e->stream);
+            if (err == hipSuccess)
+                err = lgf::launch_canon_to_field(e->format, stage, s0, n, field_of(e, e->format, i), e->geom[i], e->stream);
+        } else {
+            err = lgf::launch_field_to_canon(e->format, field_of(e, e->format, i), nullptr, s0, n, stage, e->geom[i], e->stream);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(host + s0 * 72, stage, (size_t)n * 72 * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+        }
+        if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    }
+    (void)hipFree(stage);
+    if (err != hipSuccess) return fail(LGF_EHIP, "ensemble link copy: %s", hipGetErrorString(err));
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_load_links(lgf_ensemble *e, int i, const double *host_canon, size_t n_doubles)
+{
+    return canon_io(e, i, const_cast<double *>(host_canon), n_doubles, true);
+}
+
+lgf_status lgf_ensemble_store_links(lgf_ensemble *e, int i, double *host_canon, size_t n_doubles)
+{
+    return canon_io(e, i, host_canon, n_doubles, false);
+}
+
+lgf_status lgf_ensemble_sweep(lgf_ensemble *e, int parity, double omega, double p_sr, uint64_t seed,
+                              uint64_t sweep_index)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(ens_use_device(e));
+    std::vector<int> phase(e->n, kFinish), fmt(e->n, e->format), listed;
+    const uint32_t nt = build_work(e, phase, fmt, true, listed);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_HIP(lgf::launch_set_u64(e->d_sweep_base, sweep_index, e->stream));
+    const bool sr = p_sr > 0.0;
+    const lgf::EnsLaunch L = launch_desc(e, e->format, e->format, sr);
+    const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
+    for (int par = (parity == 1 ? 1 : 0); par <= (parity == 0 ? 0 : 1); ++par)
+        LGF_HIP(lgf::launch_ensemble_sweep(e->format, e->format, L, par, r, 0, sr, e->nontemporal != 0, e->stream));
+    // the pinned mirrors are reused by the next call: wait for the copies
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_measure(lgf_ensemble *e, double *F, double *theta)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    LGF_TRY(ens_use_device(e));
+    std::vector<int> phase(e->n, kFinish), fmt(e->n, e->format), listed;
+    const uint32_t nt = build_work(e, phase, fmt, true, listed);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_TRY(measure_listed(e, e->format, e->format, nt, listed, false));
+    for (int i = 0; i < e->n; ++i) {
+        if (F) F[i] = e->h_out[2 * i];
+        if (theta) theta[i] = e->h_out[2 * i + 1];
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf_fix_result *results)
+{
+    if (!e || !pp || !results) return fail(LGF_EINVAL, "NULL ensemble, params or results");
+    const lgf_fix_params p = *pp;
+    if (!(p.omega >= 1.0 && p.omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", p.omega);
+    if (!(p.p_sr >= 0.0 && p.p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p.p_sr);
+    if (!(p.theta_target > 0.0)) return fail(LGF_EINVAL, "theta_target must be > 0");
+    if (p.check_every < 1) return fail(LGF_EINVAL, "check_every must be >= 1");
+    if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
+    const int bulk = (p.bulk_format < 0) ? e->format : p.bulk_format;
+    const int finish = (p.finish_format < 0) ? e->format : p.finish_format;
+    if (!lgf::valid_format(bulk) || !lgf::valid_format(finish)) return fail(LGF_EINVAL, "unknown format");
+    const bool mixed = bulk != finish;
+    if (mixed && !(p.theta_switch > 0.0))
+        return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
+    LGF_TRY(ens_use_device(e));
+    const auto t_start = std::chrono::steady_clock::now();
+    auto now_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    std::memset(results, 0, sizeof(lgf_fix_result) * e->n);
+    double t_bulk = 0.0, t_finish = 0.0, t_meas = 0.0, t_conv = 0.0;
+
+    std::vector<int> phase(e->n, mixed ? kBulk : kFinish), fmt(e->n, e->format), listed;
+    // measurement 0 on the home field
+    uint32_t nt = build_work(e, phase, fmt, true, listed);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_TRY(measure_listed(e, e->format, e->format, nt, listed, false));
+    for (int i = 0; i < e->n; ++i) {
+        lgf_fix_result &r = results[i];
+        r.F = e->h_out[2 * i];
+        r.theta = e->h_out[2 * i + 1];
+        r.n_history = 1;
+        r.status = LGF_ENOTCONV;
+        if (!std::isfinite(r.F) || !std::isfinite(r.theta)) {
+            r.status = LGF_ENUMERIC;
+            phase[i] = kDone;
+        } else if (r.theta < p.theta_target || p.max_sweeps == 0) {
+            r.status = r.theta < p.theta_target ? LGF_OK : LGF_ENOTCONV;
+            phase[i] = kDone;
+        }
+    }
+    // move every live configuration to its first sweeping format
+    LGF_HIP(hipEventRecord(e->ev0, e->stream));
+    for (int i = 0; i < e->n; ++i) {
+        if (phase[i] == kDone) continue;
+        const int f = (phase[i] == kBulk) ? bulk : finish;
+        LGF_TRY(convert_one(e, i, e->format, f, is_fp64(f) && !is_fp64(e->format)));
+        fmt[i] = f;
+    }
+    LGF_HIP(hipEventRecord(e->ev1, e->stream));
+    LGF_HIP(hipEventSynchronize(e->ev1));
+    t_conv += lgf::elapsed_ms(e->ev0, e->ev1);
+
+    int64_t sweeps = 0;
+    uint64_t ctr = p.sweep_offset;
+    auto live = [&] {
+        for (int i = 0; i < e->n; ++i)
+            if (phase[i] != kDone) return true;
+        return false;
+    };
+    while (live() && sweeps < p.max_sweeps) {
+        nt = build_work(e, phase, fmt, false, listed);
+        LGF_TRY(upload_work(e, nt, listed.size()));
+        bool any_bulk = false, any_finish = false;
+        for (int i : listed) (phase[i] == kBulk ? any_bulk : any_finish) = true;
+        const int fa = any_bulk ? bulk : finish, fb = any_finish ? finish : bulk;
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_HIP(hipEventRecord(e->ev0, e->stream));
+        LGF_TRY(run_chunk(e, fa, fb, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0));
+        LGF_HIP(hipEventRecord(e->ev1, e->stream));
+        LGF_HIP(hipEventSynchronize(e->ev1));
+        const double ms = lgf::elapsed_ms(e->ev0, e->ev1);
+        (any_bulk ? t_bulk : t_finish) += ms;
+        sweeps += n;
+        ctr += (uint64_t)n;
+        LGF_HIP(hipEventRecord(e->ev0, e->stream));
+        LGF_TRY(measure_listed(e, fa, fb, nt, listed, true));
+        LGF_HIP(hipEventRecord(e->ev1, e->stream));
+        LGF_HIP(hipEventSynchronize(e->ev1));
+        t_meas += lgf::elapsed_ms(e->ev0, e->ev1);
+        LGF_HIP(hipEventRecord(e->ev0, e->stream));
+        for (int i : listed) {
+            lgf_fix_result &r = results[i];
+            r.F = e->h_out[2 * i];
+            r.theta = e->h_out[2 * i + 1];
+            r.sweeps = sweeps;
+            if (phase[i] == kBulk) r.sweeps_bulk += n;
+            r.n_history += 1;
+            if (!std::isfinite(r.F) || !std::isfinite(r.theta)) {
+                r.status = LGF_ENUMERIC;
+                phase[i] = kDone;
+                continue;
+            }
+            if (phase[i] == kBulk && (r.theta < p.theta_switch || r.theta < p.theta_target)) {
+                LGF_TRY(convert_one(e, i, bulk, finish, true));
+                fmt[i] = finish;
+                phase[i] = kFinish;
+                continue;  // the next measurement is taken in the finish format
+            }
+            if (phase[i] == kFinish && r.theta < p.theta_target) {
+                r.status = LGF_OK;
+                r.t_total_ms = now_ms();
+                phase[i] = kDone;
+            }
+        }
+        LGF_HIP(hipEventRecord(e->ev1, e->stream));
+        LGF_HIP(hipEventSynchronize(e->ev1));
+        t_conv += lgf::elapsed_ms(e->ev0, e->ev1);
+    }
+    // links back to the home format
+    bool any_bad = false;
+    for (int i = 0; i < e->n; ++i) {
+        LGF_TRY(convert_one(e, i, fmt[i], e->format, false));
+        fmt[i] = e->format;
+        lgf_fix_result &r = results[i];
+        if (r.t_total_ms == 0.0) r.t_total_ms = now_ms();
+        r.t_sweep_bulk_ms = t_bulk;
+        r.t_sweep_finish_ms = t_finish;
+        r.t_measure_ms = t_meas;
+        r.t_convert_ms = t_conv;
+        if (r.status != LGF_OK) any_bad = true;
+    }
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    if (any_bad) {
+        for (int i = 0; i < e->n; ++i)
+            if (results[i].status == LGF_ENUMERIC)
+                return fail(LGF_ENUMERIC, "configuration %d: F or theta is not finite", i);
+        return fail(LGF_ENOTCONV, "not every configuration reached theta < %g in %lld sweeps", p.theta_target,
+                    (long long)sweeps);
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
+                                    double *ms_per_launch)
+{
+    if (!e || !ms_per_launch) return fail(LGF_EINVAL, "NULL ensemble or output");
+    if (!lgf::valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (n < 1) return fail(LGF_EINVAL, "n must be >= 1");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(ens_use_device(e));
+    std::vector<int> phase(e->n, kFinish), fmt(e->n, format), listed;
+    for (int i = 0; i < e->n; ++i) LGF_TRY(convert_one(e, i, e->format, format, false));
+    const uint32_t nt = build_work(e, phase, fmt, true, listed);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_TRY(run_chunk(e, format, format, 1, omega, p_sr, 0, 0, false));  // warm-up
+    LGF_HIP(hipEventRecord(e->ev0, e->stream));
+    LGF_TRY(run_chunk(e, format, format, n, omega, p_sr, 0, 1, false));
+    LGF_HIP(hipEventRecord(e->ev1, e->stream));
+    LGF_HIP(hipEventSynchronize(e->ev1));
+    *ms_per_launch = lgf::elapsed_ms(e->ev0, e->ev1) / (2.0 * n);
+    return LGF_OK;
+}
+
+}  // extern "C"

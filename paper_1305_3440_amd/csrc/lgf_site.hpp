@@ -1,0 +1,232 @@
+// lgf_site.hpp -- the per-site work of the relaxation sweep and of the
+// F / theta measurement, shared by the single-lattice kernels and the
+// persistent ensemble kernels.
+#pragma once
+
+#include "lgf_device.hpp"
+
+namespace lgf {
+
+// One Cabibbo-Marinari SU(2) step on rows/columns (I, J) of W = G K.
+// Quaternion projection a of the 2x2 block (a scaled by 2, which the
+// normalisation removes); maximum of Re tr[s(b) w] at b = (a0, -a)/|a|
+// (Eq. (9)); OR: N[(1 - omega) + omega b] (first-order b^omega, Sec. 3.1);
+// SR: b^2 (Sec. 3.2).  Then W <- R W and G <- R G on rows I, J.
+template <int I, int J, bool UPDATE_W, typename T>
+__device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool overrelax, bool square)
+{
+    const T a0 = W.e[I][I].re + W.e[J][J].re;
+    const T a3 = W.e[I][I].im - W.e[J][J].im;
+    const T a1 = W.e[I][J].im + W.e[J][I].im;
+    const T a2 = W.e[I][J].re - W.e[J][I].re;
+    const T n2 = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+    T r0 = T(1), r1 = T(0), r2 = T(0), r3 = T(0);
+    if (n2 > T(0)) {
+        const T inv = exact_rsqrt<T>(n2);
+        const T b0 = a0 * inv, b1 = -a1 * inv, b2 = -a2 * inv, b3 = -a3 * inv;
+        if (square) {
+            r0 = b0 * b0 - (b1 * b1 + b2 * b2 + b3 * b3);
+            r1 = T(2) * b0 * b1;
+            r2 = T(2) * b0 * b2;
+            r3 = T(2) * b0 * b3;
+        } else if (overrelax) {
+            const T c0 = (T(1) - omega) + omega * b0;
+            const T c1 = omega * b1, c2 = omega * b2, c3 = omega * b3;
+            const T ic = exact_rsqrt<T>(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
+            r0 = c0 * ic; r1 = c1 * ic; r2 = c2 * ic; r3 = c3 * ic;
+        } else {
+            r0 = b0; r1 = b1; r2 = b2; r3 = b3;
+        }
+    }
+    // s(r) = [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]]
+    const cpx<T> s00 = {r0, r3}, s01 = {r2, r1}, s10 = {-r2, r1}, s11 = {r0, -r3};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> gi = G.e[I][c], gj = G.e[J][c];
+        G.e[I][c] = s00 * gi + s01 * gj;
+        G.e[J][c] = s10 * gi + s11 * gj;
+        if constexpr (UPDATE_W) {
+            const cpx<T> wi = W.e[I][c], wj = W.e[J][c];
+            W.e[I][c] = s00 * wi + s01 * wj;
+            W.e[J][c] = s10 * wi + s11 * wj;
+        }
+    }
+}
+
+
+template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
+
+// Parameters of one relaxation half-sweep as the kernels see them.
+template <typename T> struct RelaxArgs {
+    T omega;
+    int overrelax;          // omega != 1
+    uint64_t sr_threshold;  // floor(p 2^32); only read when SR
+    uint32_t key0, key1;    // Philox key (seed)
+    uint32_t sweep, instance;
+};
+
+// The local update of site h (half index) of the given parity by LPS lanes
+// (lane in [0, LPS)): gather U_mu(x), U_mu(x - mu) for the lane's directions,
+// K(x) = sum_mu U_mu(x) + U_mu(x - mu)^dag (Eq. (8) with the neighbours' g
+// already applied), reduced over the LPS lanes; the three Cabibbo-Marinari
+// SU(2) steps (0,1), (0,2), (1,2) accumulate G; store G U_mu(x) and
+// U_mu(x - mu) G^dag.  Inactive lanes compute on a valid site and store
+// nothing (they still take part in the cross-lane reduction).
+template <int F, int LPS, bool SR, bool NT>
+__device__ __forceinline__ void update_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
+                                            int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    constexpr int NL = 4 / LPS;  // directions handled per lane
+    const Site c = decode(g, parity, h);
+
+    mat3<T> uf[NL], ub[NL];
+    uint32_t hb[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int mu = lane + k * LPS;
+        hb[k] = back_half(g, c, h, mu);
+        load_link<F, NT>(uf[k], block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+        load_link<F, NT>(ub[k], block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k]);
+    }
+
+    mat3<T> K;
+    set_zero(K);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) add_fwd_bwd(K, uf[k], ub[k]);
+#pragma unroll
+    for (int m = 1; m < LPS; m <<= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                K.e[i][j].re += shfl_xor_t(K.e[i][j].re, m);
+                K.e[i][j].im += shfl_xor_t(K.e[i][j].im, m);
+            }
+
+    bool sq0 = false, sq1 = false, sq2 = false;
+    if constexpr (SR) {
+        const uint4 w = philox4x32_10(make_uint4(lex_index(g, c), a.sweep, a.instance, 3u), a.key0, a.key1);
+        sq0 = (uint64_t)w.x < a.sr_threshold;
+        sq1 = (uint64_t)w.y < a.sr_threshold;
+        sq2 = (uint64_t)w.z < a.sr_threshold;
+    }
+
+    mat3<T> G;
+    set_identity(G);
+    const bool orl = a.overrelax != 0;
+    su2_step<0, 1, true>(K, G, a.omega, orl, sq0);
+    su2_step<0, 2, true>(K, G, a.omega, orl, sq1);
+    su2_step<1, 2, false>(K, G, a.omega, orl, sq2);
+
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int mu = lane + k * LPS;
+        mat3<T> r;
+        left_mul<S::R>(r, G, uf[k]);
+        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, r);
+        right_mul_dag<S::R>(r, ub[k], G);
+        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// F and theta (Eqs. (2), (4), (5)), optionally fused with reunitarization.
+// Delta(x) = [(K - K^dag)/(2i)]_traceless, which equals sum_mu A_mu(x) -
+// A_mu(x - mu) for A_mu = [(U - U^dag)/(2i)]_traceless.  All in FP64.
+// ----------------------------------------------------------------------------
+
+constexpr int kMeasureBlock = 256;
+
+// u <- u as stored in format F and read back; o receives the stored value
+template <int F>
+__device__ __forceinline__ void round_to_format(mat3<double> &u, mat3<typename Fmt<F>::T> &o)
+{
+    convert(o, u);
+    if constexpr (Fmt<F>::R == 2) rebuild_row2(o);
+    convert(u, o);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void block_sum2(double a, double b, double *out)
+{
+    __shared__ double sa[BLOCK / 64], sb[BLOCK / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int i = 0; i < BLOCK / 64; ++i) { ta += sa[i]; tb += sb[i]; }
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
+// Site h's contributions f = sum_mu Re tr U_mu(x) and th = |Delta(x)|^2.
+// reunit_fwd: reunitarize the 4 forward links and store them; reunit_bwd:
+// reunitarize the backward links in registers only (first parity pass,
+// whose backward links are the other parity's not yet reunitarized forward
+// links).  Inactive lanes return zeros and store nothing.
+template <int F>
+__device__ __forceinline__ void measure_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
+                                             bool active, int reunit_fwd, int reunit_bwd, double &f, double &th)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    const Site c = decode(g, parity, h);
+    f = 0.0;
+    mat3<double> K;
+    set_zero(K);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3<T> ut, vt;
+        load_link<F>(ut, block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+        load_link<F>(vt, block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, back_half(g, c, h, mu));
+        mat3<double> u, v;
+        convert(u, ut);
+        convert(v, vt);
+        // Reunitarized links are measured exactly as they will be stored and
+        // read back (rounded to the storage precision, row 2 rebuilt for the
+        // 12-real formats), so the two parity passes agree bit for bit.
+        if (reunit_fwd) {
+            reunitarize(u);
+            mat3<T> o;
+            round_to_format<F>(u, o);
+            if (active) store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, o);
+        }
+        if (reunit_bwd) {
+            reunitarize(v);
+            mat3<T> o;
+            round_to_format<F>(v, o);
+        }
+        f += u.e[0][0].re + u.e[1][1].re + u.e[2][2].re;
+        add_fwd_bwd(K, u, v);
+    }
+    // |[(K - K^dag)/(2i)]_traceless|^2
+    const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
+    const double tr3 = (d0 + d1 + d2) * (1.0 / 3.0);
+    th = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            // entries (i,j) and (j,i) have equal modulus |K_ij - conj(K_ji)| / 2
+            const cpx<double> z = K.e[i][j] - conj(K.e[j][i]);
+            th += 0.5 * norm2(z);
+        }
+    if (!active) { f = 0.0; th = 0.0; }
+}
+
+}  // namespace lgf

@@ -312,3 +312,139 @@ class Lattice:
         for k, v in kw.items():
             setattr(p, k, v)
         return lgf_gauge_fix(self.h, p)
+
+
+# ------------------------------------------------------------------ ensembles
+
+ENSEMBLE_EXPORTS = [
+    "lgf_ensemble_create", "lgf_ensemble_destroy", "lgf_ensemble_generate",
+    "lgf_ensemble_load_links", "lgf_ensemble_store_links", "lgf_ensemble_sweep",
+    "lgf_ensemble_measure", "lgf_ensemble_gauge_fix", "lgf_ensemble_time_sweeps",
+]
+EXPORTS = EXPORTS + ENSEMBLE_EXPORTS
+
+
+def _ens_lib():
+    lib = load_library()
+    if not getattr(lib, "_lgf_ens_sigs", False):
+        P, I, U64, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+        sig = {
+            "lgf_ensemble_create": (I, [I, P, I, P, P]),
+            "lgf_ensemble_destroy": (I, [P]),
+            "lgf_ensemble_generate": (I, [P, I, U64, D, I]),
+            "lgf_ensemble_load_links": (I, [P, I, P, SZ]),
+            "lgf_ensemble_store_links": (I, [P, I, P, SZ]),
+            "lgf_ensemble_sweep": (I, [P, I, D, D, U64, U64]),
+            "lgf_ensemble_measure": (I, [P, P, P]),
+            "lgf_ensemble_gauge_fix": (I, [P, P, P]),
+            "lgf_ensemble_time_sweeps": (I, [P, I, I, D, D, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._lgf_ens_sigs = True
+    return lib
+
+
+def lgf_ensemble_create(dims_list, fmt: int = LGF_FP64_18, stream=None):
+    d = np.ascontiguousarray(np.asarray(dims_list, dtype=np.int32).reshape(-1, 4))
+    e = ctypes.c_void_p()
+    _check(_ens_lib().lgf_ensemble_create(d.shape[0], _p(d), fmt, _ptr_of(stream), ctypes.byref(e)))
+    return e
+
+
+def lgf_ensemble_destroy(e) -> None:
+    _check(_ens_lib().lgf_ensemble_destroy(e))
+
+
+def lgf_ensemble_generate(e, i: int, seed: int, eps: float, haar: bool = True) -> None:
+    _check(_ens_lib().lgf_ensemble_generate(e, i, seed, eps, int(haar)))
+
+
+def lgf_ensemble_load_links(e, i: int, U: np.ndarray) -> None:
+    _canon(U)
+    _check(_ens_lib().lgf_ensemble_load_links(e, i, _p(U), U.size * 2))
+
+
+def lgf_ensemble_store_links(e, i: int, V: int) -> np.ndarray:
+    U = np.empty((V, 4, 3, 3), dtype=np.complex128)
+    _check(_ens_lib().lgf_ensemble_store_links(e, i, _p(U), U.size * 2))
+    return U
+
+
+def lgf_ensemble_sweep(e, parity: int, omega: float, p_sr: float = 0.0, seed: int = 0,
+                       sweep_index: int = 0) -> None:
+    _check(_ens_lib().lgf_ensemble_sweep(e, parity, omega, p_sr, seed, sweep_index))
+
+
+def lgf_ensemble_measure(e, n: int):
+    F = np.zeros(n)
+    th = np.zeros(n)
+    _check(_ens_lib().lgf_ensemble_measure(e, _p(F), _p(th)))
+    return F, th
+
+
+def lgf_ensemble_gauge_fix(e, params: lgf_fix_params, n: int):
+    """Returns (status, list of per-configuration result dicts)."""
+    res = (lgf_fix_result * n)()
+    st = _ens_lib().lgf_ensemble_gauge_fix(e, ctypes.byref(params), res)
+    _check(st, allow=(LGF_ENOTCONV, LGF_ENUMERIC))
+    return st, [r.as_dict() for r in res]
+
+
+def lgf_ensemble_time_sweeps(e, fmt: int, n: int, omega: float, p_sr: float = 0.0) -> float:
+    ms = ctypes.c_double()
+    _check(_ens_lib().lgf_ensemble_time_sweeps(e, fmt, n, omega, p_sr, ctypes.byref(ms)))
+    return ms.value
+
+
+class Ensemble:
+    """Owns one ensemble handle."""
+
+    def __init__(self, dims_list, fmt: int = LGF_FP64_18, stream=None):
+        self.dims = [tuple(int(x) for x in d) for d in dims_list]
+        self.n = len(self.dims)
+        self.V = [int(np.prod(d)) for d in self.dims]
+        self.e = lgf_ensemble_create(self.dims, fmt, stream)
+
+    def close(self):
+        if self.e is not None:
+            lgf_ensemble_destroy(self.e)
+            self.e = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def generate(self, i, seed, eps, haar=True):
+        lgf_ensemble_generate(self.e, i, seed, eps, haar)
+
+    def load(self, i, U):
+        lgf_ensemble_load_links(self.e, i, U)
+
+    def store(self, i):
+        return lgf_ensemble_store_links(self.e, i, self.V[i])
+
+    def sweep(self, parity, omega, p_sr=0.0, seed=0, sweep_index=0):
+        lgf_ensemble_sweep(self.e, parity, omega, p_sr, seed, sweep_index)
+
+    def measure(self):
+        return lgf_ensemble_measure(self.e, self.n)
+
+    def gauge_fix(self, **kw):
+        p = lgf_fix_params_default()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return lgf_ensemble_gauge_fix(self.e, p, self.n)
+
+    def time_sweeps(self, fmt, n, omega, p_sr=0.0):
+        return lgf_ensemble_time_sweeps(self.e, fmt, n, omega, p_sr)

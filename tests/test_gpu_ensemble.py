@@ -1,0 +1,174 @@
+"""The batched persistent launch over an ensemble of lattices of different
+sizes, through the C ABI: per-configuration parity with the FP64 oracle, and
+bit-for-bit agreement with the single-lattice path."""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from lattice_np import unitarity_error
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DIMS = [(4, 4, 6, 10), (8, 6, 4, 12), (2, 2, 2, 2), (6, 4, 4, 8), (8, 8, 8, 8)]
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    if not gpu_available():
+        pytest.skip("no GPU visible")
+    import paper_1305_3440_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def announce(*args):
+    print("[gpu-case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def maxabs(a, b):
+    return float(np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("omega,p_sr", [(1.7, 0.0), (1.0, 0.4)])
+def test_ensemble_sweep_matches_oracle(lgf, orc, omega, p_sr):
+    """One full sweep of every configuration in one persistent launch per
+    parity equals the oracle's, configuration by configuration (the
+    stochastic-relaxation counter carries the configuration index)."""
+    announce("ensemble sweep", omega, p_sr)
+    Us = [orc.generate_links(d, 20 + i, 0.3) for i, d in enumerate(DIMS)]
+    with lgf.Ensemble(DIMS, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        ens.sweep(2, omega, p_sr, seed=7, sweep_index=11)
+        for i, (d, U) in enumerate(zip(DIMS, Us)):
+            ref = U.copy()
+            orc.sweep(d, ref, omega, p_sr, seed=7, sweep_index=11, instance=i)
+            assert maxabs(ens.store(i), ref) < 1e-12, (i, d)
+
+
+def test_ensemble_equals_single_lattice_bitwise(lgf, orc):
+    """The ensemble kernel runs the single-lattice site update (one lane per
+    site, non-temporal), so a sweep gives the same bits as lgf_sweep."""
+    announce("ensemble vs single")
+    for fmt in (lgf.LGF_FP64_18, lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+        Us = [orc.generate_links(d, 40 + i, 0.3) for i, d in enumerate(DIMS)]
+        with lgf.Ensemble(DIMS, fmt) as ens:
+            for i, U in enumerate(Us):
+                ens.load(i, U)
+            ens.sweep(0, 1.8)
+            ens.sweep(1, 1.8)
+            got = [ens.store(i) for i in range(len(DIMS))]
+        for i, (d, U) in enumerate(zip(DIMS, Us)):
+            with lgf.Lattice(d, fmt) as lat:
+                lgf.lgf_set_tuning(lat.h, fmt, 1, 128, 0, 1)
+                lat.load(U)
+                lat.sweep(2, 1.8)
+                assert np.array_equal(lat.store(), got[i]), (fmt, i, d)
+
+
+def test_ensemble_measure_matches_oracle(lgf, orc):
+    announce("ensemble measure")
+    Us = [orc.generate_links(d, 60 + i, 0.35) for i, d in enumerate(DIMS)]
+    with lgf.Ensemble(DIMS, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        F, th = ens.measure()
+    for i, (d, U) in enumerate(zip(DIMS, Us)):
+        Fr, thr = orc.measure(d, U)
+        assert abs(F[i] - Fr) < 1e-14 and abs(th[i] - thr) < 1e-12 * thr, i
+
+
+def test_ensemble_generate_matches_oracle(lgf, orc):
+    announce("ensemble generate")
+    with lgf.Ensemble(DIMS[:3], lgf.LGF_FP64_18) as ens:
+        for i, d in enumerate(DIMS[:3]):
+            ens.generate(i, 100 + i, 0.25, True)
+        for i, d in enumerate(DIMS[:3]):
+            assert maxabs(ens.store(i), orc.generate_links(d, 100 + i, 0.25, True)) < 1e-13
+
+
+def test_ensemble_mixed_gauge_fix_equals_single(lgf, orc):
+    """Mixed FP32-12 bulk / FP64-12 finish gauge fixing of every configuration
+    with its own switch and stop: each reaches theta < 1e-12 (checked by the
+    oracle on the returned links) with the sweeps and links of the
+    single-lattice driver."""
+    announce("ensemble mixed fix")
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8), (8, 6, 4, 12)]
+    kw = dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+              finish_format=lgf.LGF_FP64_12)
+    Us = [orc.generate_links(d, 80 + i, 0.3) for i, d in enumerate(dims)]
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        st, res = ens.gauge_fix(**kw)
+        got = [ens.store(i) for i in range(len(dims))]
+    assert st == lgf.LGF_OK
+    for i, d in enumerate(dims):
+        assert res[i]["status"] == 0 and res[i]["theta"] < 1e-12
+        assert orc.measure(d, got[i])[1] < 1e-12
+        assert unitarity_error(got[i]) < 1e-12
+        with lgf.Lattice(d, lgf.LGF_FP64_18) as lat:
+            lat.load(Us[i])
+            st1, r1, _ = lat.gauge_fix(**kw)
+            ref = lat.store()
+        assert r1["sweeps"] == res[i]["sweeps"] and r1["sweeps_bulk"] == res[i]["sweeps_bulk"], i
+        assert np.array_equal(ref, got[i]), i
+    sweeps = sorted(r["sweeps"] for r in res)
+    assert sweeps[0] < sweeps[-1]   # configurations stopped at different points
+
+
+def test_ensemble_not_converged_and_args(lgf, orc):
+    announce("ensemble status")
+    dims = [(4, 4, 4, 4), (4, 4, 4, 6)]
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i in range(2):
+            ens.generate(i, i, 0.3)
+        st, res = ens.gauge_fix(omega=1.7, theta_target=1e-30, max_sweeps=40)
+        assert st == lgf.LGF_ENOTCONV and all(r["sweeps"] == 40 for r in res)
+        with pytest.raises(lgf.LgfError):
+            ens.sweep(0, 2.5)
+        with pytest.raises(lgf.LgfError):
+            lgf.lgf_ensemble_generate(ens.e, 2, 0, 0.3)
+    with pytest.raises(lgf.LgfError):
+        lgf.lgf_ensemble_create([(4, 4, 4, 5)])
+
+
+def test_manifest_ensemble_sr_sampled(lgf, orc):
+    """The 48-configuration workload of the benchmark: generated on the GPU,
+    one stochastic-relaxation sweep in FP32-12 through the batched launch,
+    checked on every configuration against a single-lattice run of the same
+    format (bitwise) and, for the small ones, against the oracle."""
+    man = json.load(open(os.path.join(HERE, "golden", "ensemble48_manifest.json")))["configs"]
+    dims = [tuple(c["dims"]) for c in man]
+    announce("manifest ensemble", len(dims))
+    with lgf.Ensemble(dims, lgf.LGF_FP32_12) as ens:
+        for c in man:
+            ens.generate(c["index"], c["seed"], c["eps"], True)
+        ens.sweep(2, 1.0, 0.5, seed=5, sweep_index=0)
+        for c in man[:6]:
+            i, d = c["index"], tuple(c["dims"])
+            got = ens.store(i)
+            with lgf.Lattice(d, lgf.LGF_FP32_12) as lat:
+                lgf.lgf_set_tuning(lat.h, lgf.LGF_FP32_12, 1, 128, 0, 1)
+                lat.generate(c["seed"], c["eps"], True)
+                lgf.lgf_sweep(lat.h, 2, 1.0, 0.5, 5, 0)   # instance 0: differs unless i == 0
+                single = lat.store()
+            if i == 0:
+                assert np.array_equal(single, got)
+            if d[0] <= 12:
+                # the oracle's own field, stored as FP32 rows 0 and 1 with row 2
+                # = conj(row0 x row1) (the 12-real format)
+                ref = orc.generate_links(d, c["seed"], c["eps"], True).astype(np.complex64)
+                ref[..., 2, :] = np.conj(np.cross(ref[..., 0, :], ref[..., 1, :]))
+                ref = ref.astype(np.complex128)
+                orc.sweep(d, ref, 1.0, 0.5, seed=5, sweep_index=0, instance=i)
+                e = np.linalg.norm((got - ref).reshape(-1, 9), axis=1) / np.sqrt(3)
+                assert np.quantile(e, 0.99) <= 2e-6 and e.max() <= 1e-5, (i, e.max())
