@@ -155,6 +155,53 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     print(json.dumps(out, indent=1))
 
 
+def ensemble_bench(lgf, stream):
+    """The 48-configuration batched workload (manifest under tests/golden):
+    one persistent launch per parity over all lattices vs one launch per
+    lattice, and the whole ensemble gauge-fixed (mixed) to theta < 1e-14."""
+    man = json.load(open(os.path.join(ROOT, "tests", "golden", "ensemble48_manifest.json")))["configs"]
+    dims = [tuple(c["dims"]) for c in man]
+    Vtot = sum(d[0] * d[1] * d[2] * d[3] for d in dims)
+    out = {"configs": len(dims), "sites": Vtot, "sizes": sorted({d[0] for d in dims})}
+    e = lgf.lgf_ensemble_create(dims, lgf.LGF_FP64_18, stream)
+    for c in man:
+        lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+        lgf.lgf_ensemble_time_sweeps(e, fmt, 20, 1.7)
+        ms = lgf.lgf_ensemble_time_sweeps(e, fmt, 40, 1.7)
+        by = Vtot // 2 * 16 * LINK_BYTES[fmt]
+        out[f"batched_{lgf.FORMAT_NAMES[fmt]}"] = {"ms_per_launch": ms,
+                                                   "site_updates_per_s": Vtot / 2 / (ms * 1e-3),
+                                                   "GBs": by / (ms * 1e-3) / 1e9}
+    # the same sweeps as one launch per lattice (each lattice its own handle)
+    singles = []
+    for c in man:
+        h = lgf.lgf_create(tuple(c["dims"]), lgf.LGF_FP32_12, stream)
+        lgf.lgf_generate_links(h, c["seed"], c["eps"], True)
+        singles.append(h)
+    for h in singles:
+        lgf.lgf_time_sweeps(h, 2, 1.7)
+    ms_loop = sum(lgf.lgf_time_sweeps(h, 10, 1.7) for h in singles)
+    for h in singles:
+        lgf.lgf_destroy(h)
+    out["one_launch_per_lattice_fp32-12"] = {"ms_per_parity_sweep": ms_loop,
+                                             "site_updates_per_s": Vtot / 2 / (ms_loop * 1e-3)}
+    out["batched_speedup_fp32-12"] = ms_loop / out["batched_fp32-12"]["ms_per_launch"]
+    p = lgf.lgf_fix_params_default()
+    p.omega, p.theta_target, p.theta_switch = 1.7, 1e-14, 1e-8
+    p.bulk_format, p.finish_format = lgf.LGF_FP32_12, lgf.LGF_FP64_12
+    t0 = time.perf_counter()
+    st, res = lgf.lgf_ensemble_gauge_fix(e, p, len(dims))
+    wall = time.perf_counter() - t0
+    lgf.lgf_ensemble_destroy(e)
+    sw = [r["sweeps"] for r in res]
+    out["gauge_fix_mixed"] = {"status": int(st), "wall_s": wall, "all_below_1e-14": all(
+        r["theta"] < 1e-14 for r in res), "sweeps_min": min(sw), "sweeps_max": max(sw),
+        "site_updates": sum(r["sweeps"] * d[0] * d[1] * d[2] * d[3] for r, d in zip(res, dims)),
+        "site_updates_per_s": sum(r["sweeps"] * d[0] * d[1] * d[2] * d[3] for r, d in zip(res, dims)) / wall}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +353,10 @@ def main():
     lgf.lgf_destroy(hp)
     del work, pristine
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("[bench] 48-configuration ensemble")
+        extras["ensemble48"] = ensemble_bench(lgf, stream)
+        log(f"[bench] ensemble: {json.dumps(extras['ensemble48'])}")
 
     cpu = None
     if not args.no_cpu_baseline:
