@@ -76,6 +76,10 @@ def _load():
         "orc_plaquette": (D, [P, P]),
         "orc_gauge_fix": (I, [P, P, D, D, D, I, I, I64, U64, U32, P, P, P, P, I64, P]),
         "orc_num_threads": (I, []),
+        "orc_local_update_coulomb": (None, [P, D, P, P]),
+        "orc_half_sweep_coulomb": (None, [P, P, I, D, D, U64, U64, U32, P]),
+        "orc_measure_coulomb": (None, [P, P, P, P]),
+        "orc_coulomb_gauge_fix": (I, [P, P, D, D, D, I, I, I64, U64, U32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -263,6 +267,59 @@ def gauge_fix(dims, U: np.ndarray, omega: float, theta_target: float, p: float =
                                _ptr(th), _ptr(hist), history_cap, _ptr(nh))
     return {"status": int(st), "sweeps": int(sweeps[0]), "F": float(F[0]), "theta": float(th[0]),
             "history": hist[: int(nh[0])].copy()}
+
+
+# ---------------------------------------------------------------- Coulomb gauge
+
+def local_update_coulomb(links8: np.ndarray, omega: float, sr=(0, 0, 0)):
+    L = np.ascontiguousarray(np.array(links8, dtype=np.complex128).reshape(8, 3, 3))
+    srv = np.ascontiguousarray(np.asarray(sr, dtype=np.int32).reshape(3))
+    G = np.zeros((3, 3), dtype=np.complex128)
+    _load().orc_local_update_coulomb(_ptr(L), omega, _ptr(srv), _ptr(G))
+    return L, G
+
+
+def half_sweep_coulomb(dims, U: np.ndarray, parity: int, omega: float, p: float = 0.0,
+                       seed: int = 0, sweep: int = 0, instance: int = 0, slice_active=None) -> None:
+    _links_arg(U)
+    if slice_active is None:
+        act = None
+    else:
+        act = np.ascontiguousarray(np.asarray(slice_active, dtype=np.uint8).reshape(int(dims[0])))
+    _load().orc_half_sweep_coulomb(_ptr(_dims(dims)), _ptr(U), parity, omega, p, seed, sweep,
+                                   instance, None if act is None else _ptr(act))
+
+
+def sweep_coulomb(dims, U: np.ndarray, omega: float, p: float = 0.0, seed: int = 0,
+                  sweep_index: int = 0, instance: int = 0, slice_active=None) -> None:
+    for parity in (0, 1):
+        half_sweep_coulomb(dims, U, parity, omega, p, seed, sweep_index, instance, slice_active)
+
+
+def measure_coulomb(dims, U: np.ndarray):
+    """(F_C(t), theta_C(t)) per timeslice, arrays of length Lt."""
+    _links_arg(U)
+    Lt = int(dims[0])
+    F = np.zeros(Lt)
+    th = np.zeros(Lt)
+    _load().orc_measure_coulomb(_ptr(_dims(dims)), _ptr(U), _ptr(F), _ptr(th))
+    return F, th
+
+
+def coulomb_gauge_fix(dims, U: np.ndarray, omega: float, theta_target: float, p: float = 0.0,
+                      check_every: int = 20, reunitarize: bool = True, max_sweeps: int = 100000,
+                      seed: int = 0, instance: int = 0):
+    _links_arg(U)
+    Lt = int(dims[0])
+    sw = np.zeros(Lt)
+    F = np.zeros(Lt)
+    th = np.zeros(Lt)
+    tot = np.zeros(1, dtype=np.int64)
+    st = _load().orc_coulomb_gauge_fix(_ptr(_dims(dims)), _ptr(U), omega, p, theta_target,
+                                       check_every, int(reunitarize), max_sweeps, seed, instance,
+                                       _ptr(sw), _ptr(F), _ptr(th), _ptr(tot))
+    return {"status": int(st), "sweeps": int(tot[0]), "sweeps_t": sw.astype(np.int64), "F_t": F,
+            "theta_t": th}
 
 
 def num_threads() -> int:

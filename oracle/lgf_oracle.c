@@ -503,11 +503,12 @@ static mat3 su2_embed(const double r[4], int i, int j)
  * are replaced by G U_mu(x) and U_mu(x-mu) G^dag.  sr[k] != 0 makes subgroup k
  * take the stochastic-relaxation square.  G (18 doubles) is returned when
  * G_out is not NULL. */
-void orc_local_update(double *links, double omega, const int sr[3], double *G_out)
+static void local_update_from(double *links, double omega, const int sr[3], double *G_out,
+                              int mu_first)
 {
     static const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     mat3 K = mat_zero();
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int mu = mu_first; mu < 4; ++mu) {
         mat3 uf = mat_load(links + 18 * mu);
         mat3 ub = mat_load(links + 18 * (4 + mu));
         mat3 ubd = mat_dag(&ub);
@@ -537,6 +538,20 @@ void orc_local_update(double *links, double omega, const int sr[3], double *G_ou
     if (G_out) mat_store(&G, G_out);
 }
 
+void orc_local_update(double *links, double omega, const int sr[3], double *G_out)
+{
+    local_update_from(links, omega, sr, G_out, 0);
+}
+
+/* Coulomb gauge: the same local update with K(x) from the 6 spatial links only
+ * (the functional holds the spatial links of each timeslice), and G still
+ * applied to all 8 links, the temporal ones included (a gauge transformation
+ * acts on every link). */
+void orc_local_update_coulomb(double *links, double omega, const int sr[3], double *G_out)
+{
+    local_update_from(links, omega, sr, G_out, 1);
+}
+
 /* Stochastic-relaxation coin flips of one site update: Philox keyed by the
  * seed with counter (site, sweep, instance, 3); subgroup k squares when word k
  * is below floor(p 2^32) (both compared as 64-bit integers, so p = 1 always
@@ -550,8 +565,8 @@ void orc_sr_decisions(uint64_t seed, int64_t s, uint64_t sweep, uint32_t instanc
     for (int k = 0; k < 3; ++k) sr[k] = ((uint64_t)w[k] < thr) ? 1 : 0;
 }
 
-static void update_site(const lattice *lat, double *U, int64_t s, double omega, double p,
-                        uint64_t seed, uint64_t sweep, uint32_t instance)
+static void update_site_from(const lattice *lat, double *U, int64_t s, double omega, double p,
+                             uint64_t seed, uint64_t sweep, uint32_t instance, int mu_first)
 {
     double links[8 * 18];
     int64_t back[4];
@@ -562,11 +577,17 @@ static void update_site(const lattice *lat, double *U, int64_t s, double omega, 
     }
     int sr[3] = {0, 0, 0};
     if (p > 0.0) orc_sr_decisions(seed, s, sweep, instance, p, sr);
-    orc_local_update(links, omega, sr, NULL);
+    local_update_from(links, omega, sr, NULL, mu_first);
     for (int mu = 0; mu < 4; ++mu) {
         memcpy(link_ptr(U, s, mu), links + 18 * mu, 18 * sizeof(double));
         memcpy(link_ptr(U, back[mu], mu), links + 18 * (4 + mu), 18 * sizeof(double));
     }
+}
+
+static void update_site(const lattice *lat, double *U, int64_t s, double omega, double p,
+                        uint64_t seed, uint64_t sweep, uint32_t instance)
+{
+    update_site_from(lat, U, s, omega, p, seed, sweep, instance, 0);
 }
 
 /* One half-sweep: every site of the given parity gets its local update.  The
@@ -599,6 +620,22 @@ void orc_sweep(const int dims[4], double *U, double omega, double p, uint64_t se
 {
     orc_half_sweep(dims, U, 0, omega, p, seed, sweep, instance, NULL, 0);
     orc_half_sweep(dims, U, 1, omega, p, seed, sweep, instance, NULL, 0);
+}
+
+/* Coulomb-gauge half-sweep: every site of the 4-D parity whose timeslice is
+ * active (slice_active == NULL: all) gets the Coulomb local update.  Sites of
+ * one 4-D parity share no link, temporal links included, so the timeslices are
+ * relaxed together while their functionals stay independent. */
+void orc_half_sweep_coulomb(const int dims[4], double *U, int parity, double omega, double p,
+                            uint64_t seed, uint64_t sweep, uint32_t instance,
+                            const unsigned char *slice_active)
+{
+    lattice lat = make_lattice(dims);
+    const int64_t V3 = lat.V / lat.L[0];
+    #pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < lat.V; ++s)
+        if (site_parity(&lat, s) == parity && (!slice_active || slice_active[s / V3]))
+            update_site_from(&lat, U, s, omega, p, seed, sweep, instance, 1);
 }
 
 void orc_reunitarize(int64_t n_links, double *U)
@@ -655,6 +692,43 @@ void orc_measure(const int dims[4], const double *U, double *F, double *theta)
     free(t_site);
     *F = fsum / (3.0 * 4.0 * (double)lat.V);
     *theta = tsum / (3.0 * (double)lat.V);
+}
+
+/* Coulomb gauge, per timeslice t (spatial directions i = 1, 2, 3 only):
+ * F_C(t) = (1/(3*3*V3)) sum_{x in t, i} Re tr U_i(x) and
+ * theta_C(t) = (1/(3*V3)) sum_{x in t} tr[Delta_C Delta_C^dag] with
+ * Delta_C(x) = sum_i A_i(x) - A_i(x - i).  F and theta hold Lt values each. */
+void orc_measure_coulomb(const int dims[4], const double *U, double *F, double *theta)
+{
+    lattice lat = make_lattice(dims);
+    const int64_t V3 = lat.V / lat.L[0];
+    double *f_site = (double *)malloc(sizeof(double) * lat.V);
+    double *t_site = (double *)malloc(sizeof(double) * lat.V);
+    #pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < lat.V; ++s) {
+        double fs = 0.0;
+        mat3 Delta = mat_zero();
+        for (int mu = 1; mu < 4; ++mu) {
+            mat3 uf = mat_load(link_cptr(U, s, mu));
+            mat3 ub = mat_load(link_cptr(U, site_neighbor(&lat, s, mu, -1), mu));
+            fs += creal(mat_trace(&uf));
+            mat3 Af = gauge_potential(&uf), Ab = gauge_potential(&ub);
+            mat3 d = mat_sub(&Af, &Ab);
+            Delta = mat_add(&Delta, &d);
+        }
+        mat3 Dd = mat_dag(&Delta);
+        mat3 DDd = mat_mul(&Delta, &Dd);
+        f_site[s] = fs;
+        t_site[s] = creal(mat_trace(&DDd));
+    }
+    for (int t = 0; t < lat.L[0]; ++t) {
+        double fsum = 0.0, tsum = 0.0;
+        for (int64_t s = t * V3; s < (t + 1) * V3; ++s) { fsum += f_site[s]; tsum += t_site[s]; }
+        F[t] = fsum / (3.0 * 3.0 * (double)V3);
+        theta[t] = tsum / (3.0 * (double)V3);
+    }
+    free(f_site);
+    free(t_site);
 }
 
 /* Average of (1/3) Re tr of the R x T rectangular loop in the (mu, nu) plane:
@@ -749,6 +823,55 @@ int orc_gauge_fix(const int dims[4], double *U, double omega, double p, double t
     *theta_out = theta;
     if (n_history) *n_history = nh;
     return status;
+}
+
+/* Coulomb gauge fixing of every timeslice: full sweeps (parity 0 then 1) of
+ * the timeslices still active; every check_every sweeps reunitarize (all
+ * links) and measure theta_C(t); a timeslice stops (is frozen) at its first
+ * measurement with theta_C(t) < theta_target.  Outputs per timeslice: the
+ * sweeps it took (sweeps_t, as doubles), F_C(t), theta_C(t).  Returns 0 when
+ * every timeslice converged, 1 when max_sweeps was hit first. */
+int orc_coulomb_gauge_fix(const int dims[4], double *U, double omega, double p, double theta_target,
+                          int check_every, int reunitarize, int64_t max_sweeps, uint64_t seed,
+                          uint32_t instance, double *sweeps_t, double *F_t, double *theta_t,
+                          int64_t *sweeps_out)
+{
+    lattice lat = make_lattice(dims);
+    const int Lt = lat.L[0];
+    unsigned char *active = (unsigned char *)malloc((size_t)Lt);
+    orc_measure_coulomb(dims, U, F_t, theta_t);
+    int n_active = 0;
+    for (int t = 0; t < Lt; ++t) {
+        active[t] = theta_t[t] < theta_target ? 0 : 1;
+        sweeps_t[t] = 0.0;
+        n_active += active[t];
+    }
+    int64_t sweeps = 0;
+    while (n_active > 0 && sweeps < max_sweeps) {
+        for (int k = 0; k < check_every && sweeps < max_sweeps; ++k) {
+            orc_half_sweep_coulomb(dims, U, 0, omega, p, seed, (uint64_t)sweeps, instance, active);
+            orc_half_sweep_coulomb(dims, U, 1, omega, p, seed, (uint64_t)sweeps, instance, active);
+            ++sweeps;
+        }
+        if (reunitarize) orc_reunitarize(lat.V * 4, U);
+        double *F = (double *)malloc(sizeof(double) * Lt);
+        double *th = (double *)malloc(sizeof(double) * Lt);
+        orc_measure_coulomb(dims, U, F, th);
+        n_active = 0;
+        for (int t = 0; t < Lt; ++t) {
+            if (!active[t]) continue;
+            F_t[t] = F[t];
+            theta_t[t] = th[t];
+            sweeps_t[t] = (double)sweeps;
+            if (th[t] < theta_target) active[t] = 0;
+            n_active += active[t];
+        }
+        free(F);
+        free(th);
+    }
+    free(active);
+    *sweeps_out = sweeps;
+    return n_active > 0 ? 1 : 0;
 }
 
 /* Number of OpenMP threads a parallel region of the oracle uses. */
