@@ -218,6 +218,36 @@ lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uin
                            uint64_t sweep_index, double *ms_per_launch);
 
 /* ------------------------------------------------------------------------ */
+/* Coulomb gauge.  The paper names Coulomb gauge among the supported gauges   */
+/* (abstract, Sec. 1) without its definitions; the reading used here: each     */
+/* timeslice t has the functional F_C(t) = (1/(3*3*V3)) sum_{x in t, i=1..3}   */
+/* Re tr U_i(x) and precision theta_C(t) = (1/(3*V3)) sum_{x in t}             */
+/* tr[Delta_C Delta_C^dag] with Delta_C(x) = sum_i A_i(x) - A_i(x-i), so K(x)  */
+/* holds the 6 spatial links; the gauge transformation still acts on all 8     */
+/* links, temporal ones included.  All timeslices are relaxed by one launch   */
+/* per (4-D) parity.                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* One Coulomb half-sweep (parity 0, 1) or full sweep (2) of every timeslice
+ * whose flag in slice_active (host array of Lt bytes; NULL = all) is nonzero;
+ * other arguments as lgf_sweep. */
+lgf_status lgf_sweep_coulomb(lgf_lattice *h, int parity, double omega, double p_sr, uint64_t seed,
+                             uint64_t sweep_index, const unsigned char *slice_active);
+
+/* F_C(t) and theta_C(t) of every timeslice (host arrays of Lt doubles, either
+ * may be NULL), accumulated in FP64.  Synchronises. */
+lgf_status lgf_measure_coulomb(lgf_lattice *h, double *F_t, double *theta_t);
+
+/* Coulomb gauge fixing, as lgf_gauge_fix with per-timeslice convergence: a
+ * timeslice stops being updated at its first measurement with theta_C(t) <
+ * theta_target; the mixed-precision switch happens once every live timeslice
+ * is below theta_switch.  result: sweeps (total), theta = largest theta_C(t),
+ * F = mean F_C(t); sweeps_t, F_t, theta_t (host arrays of Lt doubles, may be
+ * NULL) receive per-timeslice sweeps, F_C and theta_C. */
+lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
+                                 double *sweeps_t, double *F_t, double *theta_t);
+
+/* ------------------------------------------------------------------------ */
 /* Ensembles: many independent lattices (sizes may differ) swept and measured */
 /* by one persistent launch per parity.                                       */
 /* ------------------------------------------------------------------------ */

@@ -87,6 +87,7 @@ struct GraphEntry {
     int n_sweeps;
     double omega;
     lgf::SweepTuning tune;
+    int coulomb;
     hipGraphExec_t exec;
 };
 
@@ -116,6 +117,12 @@ struct lgf_lattice {
     lgf::SweepTuning tune[4];
     std::vector<GraphEntry> graphs;
     hipEvent_t ev0, ev1;
+    // Coulomb gauge: timeslice flags and per-timeslice reductions (lazily)
+    uint8_t *d_mask;
+    uint8_t *h_mask;   // pinned, Lt flags
+    double *d_cpart;
+    double *d_cout;
+    double *h_cout;    // pinned, 2 Lt doubles
 };
 
 namespace {
@@ -188,10 +195,55 @@ lgf_status measure_field(lgf_lattice *h, int format, void *field, bool reunit, d
 }
 
 lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, double omega, double p_sr,
-                        uint64_t seed, uint64_t sweep_index)
+                        uint64_t seed, uint64_t sweep_index, bool coulomb = false)
 {
     lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
-    LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
+    if (coulomb)
+        LGF_HIP(lgf::launch_sweep_coulomb(format, field, h->geom, a, h->d_mask, h->tune[format].nontemporal != 0,
+                                          h->stream));
+    else
+        LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
+    return LGF_OK;
+}
+
+// Coulomb-gauge scratch: timeslice flags and per-timeslice partial sums
+lgf_status ensure_coulomb(lgf_lattice *h)
+{
+    if (h->d_mask) return LGF_OK;
+    const int Lt = h->dims[0];
+    const size_t parts = (size_t)4 * Lt * lgf::coulomb_blocks_per_slice(h->geom);
+    hipError_t e;
+    if ((e = hipMalloc(&h->d_mask, Lt)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_mask, Lt, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMalloc(&h->d_cpart, parts * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->d_cout, 2 * Lt * sizeof(double))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_cout, 2 * Lt * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "Coulomb scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    return LGF_OK;
+}
+
+// copy the host flags (NULL = all active) to the device mask; synchronises
+lgf_status upload_mask(lgf_lattice *h, const unsigned char *flags)
+{
+    for (int t = 0; t < h->dims[0]; ++t) h->h_mask[t] = flags ? (flags[t] ? 1 : 0) : 1;
+    LGF_HIP(hipMemcpyAsync(h->d_mask, h->h_mask, h->dims[0], hipMemcpyHostToDevice, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    return LGF_OK;
+}
+
+// per-timeslice F_C(t), theta_C(t) into h->h_cout (2 Lt doubles); with reunit
+// the fused FP64 reunitarization of every link first
+lgf_status measure_coulomb_field(lgf_lattice *h, int format, void *field, bool reunit)
+{
+    const size_t half = (size_t)2 * h->dims[0] * lgf::coulomb_blocks_per_slice(h->geom);
+    LGF_HIP(lgf::launch_measure_coulomb(format, field, h->geom, 0, reunit, reunit, h->d_cpart, h->stream));
+    LGF_HIP(lgf::launch_measure_coulomb(format, field, h->geom, 1, reunit, false, h->d_cpart + half, h->stream));
+    LGF_HIP(lgf::launch_finish_coulomb(h->d_cpart, h->geom, h->d_cout, h->stream));
+    LGF_HIP(hipMemcpyAsync(h->h_cout, h->d_cout, 2 * h->dims[0] * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
     return LGF_OK;
 }
 
@@ -200,17 +252,18 @@ lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, dou
 // into a hipGraph and replayed; stochastic relaxation launches directly since
 // its counter changes every sweep.
 lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omega, double p_sr,
-                     uint64_t seed, uint64_t sweep0, bool use_graph)
+                     uint64_t seed, uint64_t sweep0, bool use_graph, bool coulomb = false)
 {
     if (!use_graph || p_sr > 0.0) {
         for (int k = 0; k < n; ++k)
             for (int parity = 0; parity < 2; ++parity)
-                LGF_TRY(sweep_launch(h, format, field, parity, omega, p_sr, seed, sweep0 + (uint64_t)k));
+                LGF_TRY(sweep_launch(h, format, field, parity, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb));
         return LGF_OK;
     }
     const lgf::SweepTuning &t = h->tune[format];
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
+            g.coulomb == (coulomb ? 1 : 0) &&
             g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
             g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
@@ -222,7 +275,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     lgf_status st = LGF_OK;
     for (int k = 0; k < n && st == LGF_OK; ++k)
         for (int parity = 0; parity < 2 && st == LGF_OK; ++parity)
-            st = sweep_launch(h, format, field, parity, omega, 0.0, seed, sweep0 + (uint64_t)k);
+            st = sweep_launch(h, format, field, parity, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb);
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (st != LGF_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -237,7 +290,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
         (void)hipGraphExecDestroy(h->graphs.front().exec);
         h->graphs.erase(h->graphs.begin());
     }
-    h->graphs.push_back(GraphEntry{format, field, n, omega, t, exec});
+    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, exec});
     LGF_HIP(hipGraphLaunch(exec, h->stream));
     return LGF_OK;
 }
@@ -353,6 +406,11 @@ lgf_status lgf_destroy(lgf_lattice *h)
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->d_stage) (void)hipFree(h->d_stage);
     if (h->d_sites) (void)hipFree(h->d_sites);
+    if (h->d_mask) (void)hipFree(h->d_mask);
+    if (h->h_mask) (void)hipHostFree(h->h_mask);
+    if (h->d_cpart) (void)hipFree(h->d_cpart);
+    if (h->d_cout) (void)hipFree(h->d_cout);
+    if (h->h_cout) (void)hipHostFree(h->h_cout);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -634,6 +692,175 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         return fail(LGF_ENOTCONV, "theta %g after %lld sweeps has not reached %g", theta, (long long)sweeps,
                     p.theta_target);
     if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", F, theta);
+    return LGF_OK;
+}
+
+lgf_status lgf_sweep_coulomb(lgf_lattice *h, int parity, double omega, double p_sr, uint64_t seed,
+                             uint64_t sweep_index, const unsigned char *slice_active)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_coulomb(h));
+    LGF_TRY(upload_mask(h, slice_active));
+    for (int par = (parity == 1 ? 1 : 0); par <= (parity == 0 ? 0 : 1); ++par)
+        LGF_TRY(sweep_launch(h, h->format, h->field, par, omega, p_sr, seed, sweep_index, true));
+    return LGF_OK;
+}
+
+lgf_status lgf_measure_coulomb(lgf_lattice *h, double *F_t, double *theta_t)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_coulomb(h));
+    LGF_TRY(measure_coulomb_field(h, h->format, h->field, false));
+    for (int t = 0; t < h->dims[0]; ++t) {
+        if (F_t) F_t[t] = h->h_cout[2 * t];
+        if (theta_t) theta_t[t] = h->h_cout[2 * t + 1];
+    }
+    return LGF_OK;
+}
+
+lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_result *res, double *sweeps_t,
+                                 double *F_t, double *theta_t)
+{
+    if (!h || !pp || !res) return fail(LGF_EINVAL, "NULL handle, params or result");
+    const lgf_fix_params p = *pp;
+    if (!(p.omega >= 1.0 && p.omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", p.omega);
+    if (!(p.p_sr >= 0.0 && p.p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p.p_sr);
+    if (!(p.theta_target > 0.0)) return fail(LGF_EINVAL, "theta_target must be > 0");
+    if (p.check_every < 1) return fail(LGF_EINVAL, "check_every must be >= 1");
+    if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
+    const int bulk = (p.bulk_format < 0) ? h->format : p.bulk_format;
+    const int finish = (p.finish_format < 0) ? h->format : p.finish_format;
+    if (!valid_format(bulk) || !valid_format(finish)) return fail(LGF_EINVAL, "unknown format");
+    const bool mixed = bulk != finish;
+    if (mixed && !(p.theta_switch > 0.0))
+        return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
+    LGF_TRY(use_device(h));
+    LGF_TRY(ensure_coulomb(h));
+    const int Lt = h->dims[0];
+    std::memset(res, 0, sizeof *res);
+    const auto t_start = std::chrono::steady_clock::now();
+    std::vector<double> sw(Lt, 0.0), F(Lt), th(Lt);
+    std::vector<unsigned char> act(Lt, 1);
+    int cur_fmt = h->format;
+    void *cur = h->field;
+    auto move_to = [&](int fmt, bool reunit) -> lgf_status {
+        void *dst = h->field;
+        if (fmt != h->format) {
+            LGF_TRY(ensure_work(h, fmt));
+            dst = h->work[fmt];
+        }
+        if (dst == cur) return LGF_OK;
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_HIP(lgf::launch_convert(cur_fmt, cur, fmt, dst, h->geom, reunit, h->stream));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+        cur = dst;
+        cur_fmt = fmt;
+        return LGF_OK;
+    };
+    auto measure = [&](bool reunit, bool only_active) -> lgf_status {
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(measure_coulomb_field(h, cur_fmt, cur, reunit));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+        for (int t = 0; t < Lt; ++t)
+            if (!only_active || act[t]) {
+                F[t] = h->h_cout[2 * t];
+                th[t] = h->h_cout[2 * t + 1];
+            }
+        return LGF_OK;
+    };
+    auto n_live = [&] {
+        int n = 0;
+        for (int t = 0; t < Lt; ++t) n += act[t];
+        return n;
+    };
+    auto worst = [&] {
+        double m = 0.0;
+        for (int t = 0; t < Lt; ++t)
+            if (act[t] && th[t] > m) m = th[t];
+        return m;
+    };
+    lgf_status status = LGF_ENOTCONV;
+    LGF_TRY(measure(false, false));
+    int nh = 1;
+    for (int t = 0; t < Lt; ++t) {
+        if (!std::isfinite(F[t]) || !std::isfinite(th[t])) status = LGF_ENUMERIC;
+        if (th[t] < p.theta_target) act[t] = 0;
+    }
+    bool in_bulk = mixed;
+    int64_t sweeps = 0, sweeps_bulk = 0;
+    uint64_t ctr = p.sweep_offset;
+    if (status != LGF_ENUMERIC && n_live() > 0 && p.max_sweeps > 0) {
+        const int first = in_bulk ? bulk : finish;
+        LGF_TRY(move_to(first, (first == LGF_FP64_18 || first == LGF_FP64_12) &&
+                                   !(h->format == LGF_FP64_18 || h->format == LGF_FP64_12)));
+    }
+    while (status != LGF_ENUMERIC && n_live() > 0 && sweeps < p.max_sweeps) {
+        LGF_TRY(upload_mask(h, act.data()));
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(run_chunk(h, cur_fmt, cur, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0, true));
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        const double ms = elapsed_ms(h->ev0, h->ev1);
+        if (in_bulk) {
+            res->t_sweep_bulk_ms += ms;
+            sweeps_bulk += n;
+        } else {
+            res->t_sweep_finish_ms += ms;
+        }
+        sweeps += n;
+        ctr += (uint64_t)n;
+        LGF_TRY(measure(true, true));
+        ++nh;
+        for (int t = 0; t < Lt; ++t) {
+            if (!act[t]) continue;
+            sw[t] = (double)sweeps;
+            if (!std::isfinite(F[t]) || !std::isfinite(th[t])) status = LGF_ENUMERIC;
+        }
+        if (status == LGF_ENUMERIC) break;
+        if (in_bulk) {
+            // leave the bulk precision once every live timeslice is below the switch
+            if (worst() < p.theta_switch) {
+                LGF_TRY(move_to(finish, true));
+                in_bulk = false;
+            }
+            continue;
+        }
+        for (int t = 0; t < Lt; ++t)
+            if (act[t] && th[t] < p.theta_target) act[t] = 0;
+    }
+    if (status != LGF_ENUMERIC) status = n_live() == 0 ? LGF_OK : LGF_ENOTCONV;
+    LGF_TRY(move_to(h->format, false));
+    double tmax = 0.0, fsum = 0.0;
+    for (int t = 0; t < Lt; ++t) {
+        tmax = th[t] > tmax ? th[t] : tmax;
+        fsum += F[t];
+        if (sweeps_t) sweeps_t[t] = sw[t];
+        if (F_t) F_t[t] = F[t];
+        if (theta_t) theta_t[t] = th[t];
+    }
+    res->sweeps = sweeps;
+    res->sweeps_bulk = sweeps_bulk;
+    res->theta = tmax;
+    res->F = fsum / Lt;
+    res->status = status;
+    res->n_history = nh;
+    res->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (status == LGF_ENOTCONV)
+        return fail(LGF_ENOTCONV, "not every timeslice reached theta_C < %g in %lld sweeps", p.theta_target,
+                    (long long)sweeps);
+    if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F_C or theta_C is not finite");
     return LGF_OK;
 }
 

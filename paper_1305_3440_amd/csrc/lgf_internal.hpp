@@ -60,4 +60,16 @@ hipError_t launch_canon_to_field(int format, const double *canon, int64_t s0, in
 hipError_t launch_field_to_canon(int format, const void *field, const int64_t *sites, int64_t s0,
                                  int64_t n, double *canon, const Geom &g, hipStream_t s);
 
+// Coulomb gauge (K from the spatial links, per-timeslice masks and sums).
+// slice_active: device array of Lt flags (NULL = every timeslice).
+hipError_t launch_sweep_coulomb(int format, void *field, const Geom &g, const SweepArgs &a,
+                                const uint8_t *slice_active, bool nt, hipStream_t s);
+// partials must hold 4 * Lt * coulomb_blocks_per_slice(g) doubles; pass 0
+// writes the first half (parity 0 at partials, parity 1 at the second half is
+// the caller's offset 2 * Lt * blocks)
+int coulomb_blocks_per_slice(const Geom &g);
+hipError_t launch_measure_coulomb(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
+                                  bool reunit_bwd, double *partials, hipStream_t s);
+hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *out, hipStream_t s);
+
 }  // namespace lgf

@@ -468,3 +468,121 @@ hipError_t launch_field_to_canon(int format, const void *field, const int64_t *s
 }
 
 }  // namespace lgf
+
+// ----------------------------------------------------------------------------
+// Coulomb gauge: the functional of each timeslice holds its spatial links;
+// the sweep updates all timeslices at once (4-D checkerboard, so the temporal
+// links joining two timeslices are never written by two sites of a
+// half-sweep), frozen timeslices are skipped, and F_C, theta_C are reduced
+// per timeslice.
+// ----------------------------------------------------------------------------
+
+namespace lgf {
+
+template <int F, bool SR, bool NT>
+__global__ void __launch_bounds__(128) sweep_coulomb_kernel(void *__restrict__ field, Geom g, int parity,
+                                                            RelaxArgs<typename Fmt<F>::T> a,
+                                                            const uint8_t *__restrict__ slice_active)
+{
+    const uint32_t h0 = blockIdx.x * 128 + threadIdx.x;
+    const bool active = h0 < g.Vh;
+    update_site<F, 1, SR, NT, 1>(field, g, parity, active ? h0 : g.Vh - 1, 0, active, a, slice_active);
+}
+
+template <int F, bool NT>
+static hipError_t launch_sweep_coulomb_t(void *field, const Geom &g, const SweepArgs &a,
+                                         const uint8_t *slice_active, hipStream_t s)
+{
+    using T = typename Fmt<F>::T;
+    const dim3 grid((g.Vh + 127) / 128);
+    RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
+                    (uint32_t)a.sweep_index, a.instance};
+    if (a.p_sr > 0.0) {
+        ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+        hipLaunchKernelGGL((sweep_coulomb_kernel<F, true, NT>), grid, dim3(128), 0, s, field, g, a.parity, ra,
+                           slice_active);
+    } else {
+        hipLaunchKernelGGL((sweep_coulomb_kernel<F, false, NT>), grid, dim3(128), 0, s, field, g, a.parity, ra,
+                           slice_active);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_coulomb(int format, void *field, const Geom &g, const SweepArgs &a,
+                                const uint8_t *slice_active, bool nt, hipStream_t s)
+{
+    switch (format * 2 + (nt ? 1 : 0)) {
+    case 0: return launch_sweep_coulomb_t<kF64_18, false>(field, g, a, slice_active, s);
+    case 1: return launch_sweep_coulomb_t<kF64_18, true>(field, g, a, slice_active, s);
+    case 2: return launch_sweep_coulomb_t<kF32_18, false>(field, g, a, slice_active, s);
+    case 3: return launch_sweep_coulomb_t<kF32_18, true>(field, g, a, slice_active, s);
+    case 4: return launch_sweep_coulomb_t<kF32_12, false>(field, g, a, slice_active, s);
+    case 5: return launch_sweep_coulomb_t<kF32_12, true>(field, g, a, slice_active, s);
+    case 6: return launch_sweep_coulomb_t<kF64_12, false>(field, g, a, slice_active, s);
+    case 7: return launch_sweep_coulomb_t<kF64_12, true>(field, g, a, slice_active, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// grid (blocks per timeslice, Lt): every workgroup lies in one timeslice
+template <int F>
+__global__ void __launch_bounds__(kMeasureBlock) measure_coulomb_kernel(void *__restrict__ field, Geom g,
+                                                                        int parity, int reunit_fwd,
+                                                                        int reunit_bwd, double *partials)
+{
+    const uint32_t t = blockIdx.y;
+    const uint32_t i = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const bool active = i < g.hs[0];
+    const uint32_t h = t * g.hs[0] + (active ? i : g.hs[0] - 1);
+    double f, th;
+    measure_site<F, 1>(field, g, parity, h, active, reunit_fwd, reunit_bwd, f, th);
+    block_sum2<kMeasureBlock>(f, th, partials + 2 * ((size_t)t * gridDim.x + blockIdx.x));
+}
+
+int coulomb_blocks_per_slice(const Geom &g) { return (int)((g.hs[0] + kMeasureBlock - 1) / kMeasureBlock); }
+
+hipError_t launch_measure_coulomb(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
+                                  bool reunit_bwd, double *partials, hipStream_t s)
+{
+    const dim3 grid(coulomb_blocks_per_slice(g), g.L[0]);
+    const int rf = reunit_fwd ? 1 : 0, rb = reunit_bwd ? 1 : 0;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((measure_coulomb_kernel<kF64_18>), grid, dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF32_18: hipLaunchKernelGGL((measure_coulomb_kernel<kF32_18>), grid, dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF32_12: hipLaunchKernelGGL((measure_coulomb_kernel<kF32_12>), grid, dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    case kF64_12: hipLaunchKernelGGL((measure_coulomb_kernel<kF64_12>), grid, dim3(kMeasureBlock), 0, s, field, g, parity, rf, rb, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// one workgroup per timeslice: both parity passes' partials in a fixed order;
+// out[2t] = F_C(t), out[2t+1] = theta_C(t)
+__global__ void __launch_bounds__(256) finish_coulomb_kernel(const double *__restrict__ partials, int bps,
+                                                             double V3, double *__restrict__ out)
+{
+    const uint32_t t = blockIdx.x, Lt = gridDim.x;
+    double a = 0.0, b = 0.0;
+    for (uint32_t pass = 0; pass < 2; ++pass)
+        for (int i = threadIdx.x; i < bps; i += 256) {
+            const double *p = partials + 2 * (((size_t)pass * Lt + t) * bps + i);
+            a += p[0];
+            b += p[1];
+        }
+    __shared__ double r[2];
+    block_sum2<256>(a, b, r);
+    if (threadIdx.x == 0) {
+        out[2 * t] = r[0] / (9.0 * V3);
+        out[2 * t + 1] = r[1] / (3.0 * V3);
+    }
+}
+
+hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *out, hipStream_t s)
+{
+    const double V3 = 2.0 * (double)g.hs[0];
+    hipLaunchKernelGGL(finish_coulomb_kernel, dim3(g.L[0]), dim3(256), 0, s, partials,
+                       coulomb_blocks_per_slice(g), V3, out);
+    return hipGetLastError();
+}
+
+}  // namespace lgf

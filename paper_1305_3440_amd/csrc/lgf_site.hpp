@@ -72,14 +72,19 @@ template <typename T> struct RelaxArgs {
 // SU(2) steps (0,1), (0,2), (1,2) accumulate G; store G U_mu(x) and
 // U_mu(x - mu) G^dag.  Inactive lanes compute on a valid site and store
 // nothing (they still take part in the cross-lane reduction).
-template <int F, int LPS, bool SR, bool NT>
+// MU0 = 1 gives the Coulomb-gauge update: K from the spatial links only, G
+// still applied to all 8 links; slice_active (optional, one flag per
+// timeslice) leaves the sites of frozen timeslices untouched.
+template <int F, int LPS, bool SR, bool NT, int MU0 = 0>
 __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
-                                            int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a)
+                                            int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a,
+                                            const uint8_t *__restrict__ slice_active = nullptr)
 {
     using S = Fmt<F>;
     using T = typename S::T;
     constexpr int NL = 4 / LPS;  // directions handled per lane
     const Site c = decode(g, parity, h);
+    if (slice_active) active = active && slice_active[c.t];
 
     mat3<T> uf[NL], ub[NL];
     uint32_t hb[NL];
@@ -94,7 +99,8 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
     mat3<T> K;
     set_zero(K);
 #pragma unroll
-    for (int k = 0; k < NL; ++k) add_fwd_bwd(K, uf[k], ub[k]);
+    for (int k = 0; k < NL; ++k)
+        if (lane + k * LPS >= MU0) add_fwd_bwd(K, uf[k], ub[k]);
 #pragma unroll
     for (int m = 1; m < LPS; m <<= 1)
 #pragma unroll
@@ -178,8 +184,10 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out)
 // reunit_fwd: reunitarize the 4 forward links and store them; reunit_bwd:
 // reunitarize the backward links in registers only (first parity pass,
 // whose backward links are the other parity's not yet reunitarized forward
-// links).  Inactive lanes return zeros and store nothing.
-template <int F>
+// links).  Inactive lanes return zeros and store nothing.  MU0 = 1 measures
+// the Coulomb-gauge functional and precision (spatial links only), while the
+// temporal forward links are still reunitarized when asked.
+template <int F, int MU0 = 0>
 __device__ __forceinline__ void measure_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
                                              bool active, int reunit_fwd, int reunit_bwd, double &f, double &th)
 {
@@ -193,9 +201,18 @@ __device__ __forceinline__ void measure_site(void *__restrict__ field, const Geo
     for (int mu = 0; mu < 4; ++mu) {
         mat3<T> ut, vt;
         load_link<F>(ut, block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
-        load_link<F>(vt, block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, back_half(g, c, h, mu));
         mat3<double> u, v;
         convert(u, ut);
+        if (mu < MU0) {
+            if (reunit_fwd) {
+                reunitarize(u);
+                mat3<T> o;
+                round_to_format<F>(u, o);
+                if (active) store_link<F>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, o);
+            }
+            continue;
+        }
+        load_link<F>(vt, block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, back_half(g, c, h, mu));
         convert(v, vt);
         // Reunitarized links are measured exactly as they will be stored and
         // read back (rounded to the storage precision, row 2 rebuilt for the

@@ -313,6 +313,18 @@ class Lattice:
             setattr(p, k, v)
         return lgf_gauge_fix(self.h, p)
 
+    def sweep_coulomb(self, parity, omega, p_sr=0.0, seed=0, sweep_index=0, slice_active=None):
+        lgf_sweep_coulomb(self.h, parity, omega, p_sr, seed, sweep_index, slice_active)
+
+    def measure_coulomb(self):
+        return lgf_measure_coulomb(self.h, self.dims[0])
+
+    def coulomb_gauge_fix(self, **kw):
+        p = lgf_fix_params_default()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return lgf_coulomb_gauge_fix(self.h, p, self.dims[0])
+
 
 # ------------------------------------------------------------------ ensembles
 
@@ -321,7 +333,8 @@ ENSEMBLE_EXPORTS = [
     "lgf_ensemble_load_links", "lgf_ensemble_store_links", "lgf_ensemble_sweep",
     "lgf_ensemble_measure", "lgf_ensemble_gauge_fix", "lgf_ensemble_time_sweeps",
 ]
-EXPORTS = EXPORTS + ENSEMBLE_EXPORTS
+EXPORTS = EXPORTS + ENSEMBLE_EXPORTS + ["lgf_sweep_coulomb", "lgf_measure_coulomb",
+                                        "lgf_coulomb_gauge_fix"]
 
 
 def _ens_lib():
@@ -338,6 +351,9 @@ def _ens_lib():
             "lgf_ensemble_measure": (I, [P, P, P]),
             "lgf_ensemble_gauge_fix": (I, [P, P, P]),
             "lgf_ensemble_time_sweeps": (I, [P, I, I, D, D, P]),
+            "lgf_sweep_coulomb": (I, [P, I, D, D, U64, U64, P]),
+            "lgf_measure_coulomb": (I, [P, P, P]),
+            "lgf_coulomb_gauge_fix": (I, [P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -397,6 +413,29 @@ def lgf_ensemble_time_sweeps(e, fmt: int, n: int, omega: float, p_sr: float = 0.
     ms = ctypes.c_double()
     _check(_ens_lib().lgf_ensemble_time_sweeps(e, fmt, n, omega, p_sr, ctypes.byref(ms)))
     return ms.value
+
+
+def lgf_sweep_coulomb(h, parity: int, omega: float, p_sr: float = 0.0, seed: int = 0,
+                      sweep_index: int = 0, slice_active=None) -> None:
+    act = None if slice_active is None else np.ascontiguousarray(np.asarray(slice_active, dtype=np.uint8))
+    _check(_ens_lib().lgf_sweep_coulomb(h, parity, omega, p_sr, seed, sweep_index,
+                                        None if act is None else _p(act)))
+
+
+def lgf_measure_coulomb(h, Lt: int):
+    F = np.zeros(Lt)
+    th = np.zeros(Lt)
+    _check(_ens_lib().lgf_measure_coulomb(h, _p(F), _p(th)))
+    return F, th
+
+
+def lgf_coulomb_gauge_fix(h, params: lgf_fix_params, Lt: int):
+    """Returns (status, result dict, per-timeslice sweeps, F_C, theta_C)."""
+    res = lgf_fix_result()
+    sw, F, th = np.zeros(Lt), np.zeros(Lt), np.zeros(Lt)
+    st = _ens_lib().lgf_coulomb_gauge_fix(h, ctypes.byref(params), ctypes.byref(res), _p(sw), _p(F), _p(th))
+    _check(st, allow=(LGF_ENOTCONV, LGF_ENUMERIC))
+    return st, res.as_dict(), sw.astype(np.int64), F, th
 
 
 class Ensemble:

@@ -1,0 +1,102 @@
+"""Coulomb-gauge path of the library against the oracle (GPU): one sweep with
+and without frozen timeslices, per-timeslice F_C / theta_C, and the
+per-timeslice gauge fixing."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from lattice_np import unitarity_error
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 6, 10), (6, 4, 4, 8), (2, 2, 2, 2)]
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    if not gpu_available():
+        pytest.skip("no GPU visible")
+    import paper_1305_3440_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def announce(*args):
+    print("[gpu-case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def maxabs(a, b):
+    return float(np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("omega,p_sr", [(1.7, 0.0), (1.0, 0.5)])
+def test_coulomb_sweep_matches_oracle(lgf, orc, dims, omega, p_sr):
+    announce("coulomb sweep", dims, omega, p_sr)
+    U = orc.generate_links(dims, 31, 0.35)
+    Lt = dims[0]
+    masks = [None, [1 if t % 2 == 0 else 0 for t in range(Lt)]]
+    for mask in masks:
+        ref = U.copy()
+        orc.sweep_coulomb(dims, ref, omega, p_sr, seed=4, sweep_index=2, slice_active=mask)
+        with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+            lat.load(U)
+            lat.sweep_coulomb(2, omega, p_sr, seed=4, sweep_index=2, slice_active=mask)
+            assert maxabs(lat.store(), ref) < 1e-12, mask
+
+
+@pytest.mark.parametrize("fmt", [0, 2, 3])
+def test_coulomb_measure_matches_oracle(lgf, orc, fmt):
+    dims = (6, 4, 4, 8)
+    announce("coulomb measure", fmt)
+    U = orc.generate_links(dims, 32, 0.35)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(U)
+        U0 = lat.store()
+        F, th = lat.measure_coulomb()
+    Fr, thr = orc.measure_coulomb(dims, U0)
+    assert np.abs(F - Fr).max() < 1e-14
+    assert np.abs(th - thr).max() < 1e-12 * thr.max()
+
+
+def test_coulomb_gauge_fix_matches_oracle(lgf, orc):
+    """FP64 Coulomb gauge fixing with per-timeslice stopping: the same
+    per-timeslice sweep counts as the oracle, theta_C(t) below target, and the
+    links of the oracle's run."""
+    dims = (6, 6, 6, 6)
+    announce("coulomb fix")
+    U = orc.generate_links(dims, 33, 0.25)
+    ref = U.copy()
+    r = orc.coulomb_gauge_fix(dims, ref, 1.7, 1e-12)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-12)
+        got = lat.store()
+    assert st == lgf.LGF_OK and r["status"] == 0
+    assert np.array_equal(sw, r["sweeps_t"])
+    assert np.all(th < 1e-12)
+    assert maxabs(got, ref) < 1e-9
+    assert np.abs(F - r["F_t"]).max() < 1e-12
+
+
+def test_coulomb_mixed_gauge_fix(lgf, orc):
+    dims = (8, 6, 6, 6)
+    announce("coulomb mixed")
+    U = orc.generate_links(dims, 34, 0.3)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                                   bulk_format=lgf.LGF_FP32_12,
+                                                   finish_format=lgf.LGF_FP64_12)
+        got = lat.store()
+    assert st == lgf.LGF_OK and 0 < res["sweeps_bulk"] < res["sweeps"]
+    Fo, tho = orc.measure_coulomb(dims, got)
+    assert np.all(tho < 1e-14) and unitarity_error(got) < 1e-12
+    # gauge invariance: the temporal plaquettes are those of the input
+    for nu in (1, 2, 3):
+        assert abs(orc.wilson_loop(dims, got, 0, nu, 1, 1) - orc.wilson_loop(dims, U, 0, nu, 1, 1)) < 1e-5
