@@ -206,6 +206,41 @@ lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, dou
     return LGF_OK;
 }
 
+// One full sweep (parity 0, then parity 1).  With the pipeline tuning the
+// sweep is issued slice by slice in t: parity 0 of slice k, then parity 1 of
+// slice k-1, whose neighbours in slices k-2, k-1, k are all done by then;
+// parity 1 of slices Lt-1 and 0 (which needs slice Lt-1) close the sweep.
+// Every site update sees the same links as in the two-launch order, so the
+// result is the same bit for bit, while parity 1 finds the links parity 0
+// wrote one slice earlier still in the last-level cache.
+lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, double p_sr, uint64_t seed,
+                      uint64_t sweep_index, bool coulomb = false)
+{
+    const int Lt = h->dims[0];
+    if (coulomb || !h->tune[format].pipeline || Lt < 4) {
+        LGF_TRY(sweep_launch(h, format, field, 0, omega, p_sr, seed, sweep_index, coulomb));
+        LGF_TRY(sweep_launch(h, format, field, 1, omega, p_sr, seed, sweep_index, coulomb));
+        return LGF_OK;
+    }
+    const uint32_t hs = h->geom.hs[0];
+    auto slice = [&](int parity, int t) -> lgf_status {
+        lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
+        a.h_begin = (uint32_t)t * hs;
+        a.h_end = (uint32_t)(t + 1) * hs;
+        LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
+        return LGF_OK;
+    };
+    LGF_TRY(slice(0, 0));
+    LGF_TRY(slice(0, 1));
+    for (int k = 2; k < Lt; ++k) {
+        LGF_TRY(slice(0, k));
+        LGF_TRY(slice(1, k - 1));
+    }
+    LGF_TRY(slice(1, Lt - 1));
+    LGF_TRY(slice(1, 0));
+    return LGF_OK;
+}
+
 // Coulomb-gauge scratch: timeslice flags and per-timeslice partial sums
 lgf_status ensure_coulomb(lgf_lattice *h)
 {
@@ -256,8 +291,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
 {
     if (!use_graph || p_sr > 0.0) {
         for (int k = 0; k < n; ++k)
-            for (int parity = 0; parity < 2; ++parity)
-                LGF_TRY(sweep_launch(h, format, field, parity, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb));
+            LGF_TRY(full_sweep(h, format, field, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb));
         return LGF_OK;
     }
     const lgf::SweepTuning &t = h->tune[format];
@@ -265,7 +299,8 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
             g.coulomb == (coulomb ? 1 : 0) &&
             g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
-            g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal) {
+            g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal &&
+            g.tune.pipeline == t.pipeline) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
         }
@@ -274,8 +309,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     lgf_status st = LGF_OK;
     for (int k = 0; k < n && st == LGF_OK; ++k)
-        for (int parity = 0; parity < 2 && st == LGF_OK; ++parity)
-            st = sweep_launch(h, format, field, parity, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb);
+        st = full_sweep(h, format, field, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb);
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (st != LGF_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -534,8 +568,7 @@ lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
     LGF_TRY(use_device(h));
     if (parity == 2) {
-        LGF_TRY(sweep_launch(h, h->format, h->field, 0, omega, p_sr, seed, sweep_index));
-        LGF_TRY(sweep_launch(h, h->format, h->field, 1, omega, p_sr, seed, sweep_index));
+        LGF_TRY(full_sweep(h, h->format, h->field, omega, p_sr, seed, sweep_index));
     } else {
         LGF_TRY(sweep_launch(h, h->format, h->field, parity, omega, p_sr, seed, sweep_index));
     }
@@ -865,7 +898,7 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
 }
 
 lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap,
-                          int nontemporal)
+                          int nontemporal, int pipeline)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
@@ -873,13 +906,14 @@ lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int bl
         return fail(LGF_EINVAL, "lanes_per_site must be 1, 2 or 4");
     if (block != 64 && block != 128 && block != 256)
         return fail(LGF_EINVAL, "block must be 64, 128 or 256");
-    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0};
+    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0,
+                                       pipeline ? 1 : 0};
     drop_graphs(h);
     return LGF_OK;
 }
 
 lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap,
-                          int *nontemporal)
+                          int *nontemporal, int *pipeline)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
@@ -887,6 +921,7 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site,
     if (block) *block = h->tune[format].block;
     if (xcd_remap) *xcd_remap = h->tune[format].xcd_remap;
     if (nontemporal) *nontemporal = h->tune[format].nontemporal;
+    if (pipeline) *pipeline = h->tune[format].pipeline;
     return LGF_OK;
 }
 
@@ -907,31 +942,32 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     const lgf::SweepTuning saved = h->tune[format];
     lgf::SweepTuning best = saved;
     double best_ms = 1e300;
+    lgf_status st = LGF_OK;
     const int lps_list[3] = {1, 2, 4};
     const int block_list[3] = {64, 128, 256};
-    for (int li = 0; li < 3 && e == hipSuccess; ++li)
-        for (int bi = 0; bi < 3 && e == hipSuccess; ++bi)
-            for (int v = 0; v < 4 && e == hipSuccess; ++v) {
-                const lgf::SweepTuning t{lps_list[li], block_list[bi], v & 1, v >> 1};
-                lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};
-                e = lgf::launch_sweep(format, scratch, h->geom, a, t, h->stream);  // warm-up
-                if (e != hipSuccess) break;
+    // every variant times `trials` full sweeps after one untimed full sweep
+    for (int li = 0; li < 3 && e == hipSuccess && st == LGF_OK; ++li)
+        for (int bi = 0; bi < 3 && e == hipSuccess && st == LGF_OK; ++bi)
+            for (int v = 0; v < 8 && e == hipSuccess && st == LGF_OK; ++v) {
+                h->tune[format] = lgf::SweepTuning{lps_list[li], block_list[bi], v & 1, (v >> 1) & 1, v >> 2};
+                st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
+                if (st != LGF_OK) break;
                 e = hipEventRecord(h->ev0, h->stream);
-                for (int k = 0; k < trials && e == hipSuccess; ++k) {
-                    a.parity = k & 1;
-                    e = lgf::launch_sweep(format, scratch, h->geom, a, t, h->stream);
-                }
+                for (int k = 0; k < trials && e == hipSuccess && st == LGF_OK; ++k)
+                    st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
                 if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
-                if (e != hipSuccess) break;
+                if (e != hipSuccess || st != LGF_OK) break;
                 const double ms = elapsed_ms(h->ev0, h->ev1) / trials;
                 if (ms < best_ms) {
                     best_ms = ms;
-                    best = t;
+                    best = h->tune[format];
                 }
             }
+    h->tune[format] = saved;
     (void)hipStreamSynchronize(h->stream);
     (void)hipFree(scratch);
+    if (st != LGF_OK) return st;
     if (e != hipSuccess) return fail(LGF_EHIP, "autotune: %s", hipGetErrorString(e));
     h->tune[format] = best;
     drop_graphs(h);
@@ -948,8 +984,7 @@ lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uin
     LGF_TRY(use_device(h));
     LGF_HIP(hipEventRecord(h->ev0, h->stream));
     for (int k = 0; k < n; ++k)
-        for (int parity = 0; parity < 2; ++parity)
-            LGF_TRY(sweep_launch(h, h->format, h->field, parity, omega, p_sr, seed, sweep_index + (uint64_t)k));
+        LGF_TRY(full_sweep(h, h->format, h->field, omega, p_sr, seed, sweep_index + (uint64_t)k));
     LGF_HIP(hipEventRecord(h->ev1, h->stream));
     LGF_HIP(hipEventSynchronize(h->ev1));
     *ms_per_launch = elapsed_ms(h->ev0, h->ev1) / (2.0 * n);

@@ -18,6 +18,7 @@ struct SweepTuning {
     int block = 128;         // threads per workgroup (fastest measured at 64^4)
     int xcd_remap = 0;       // contiguous workgroup ranges per XCD
     int nontemporal = 1;     // stream links past the caches
+    int pipeline = 0;        // full sweeps as a t-slice pipeline (parity 1 one slice behind)
 };
 
 struct SweepArgs {
@@ -27,6 +28,8 @@ struct SweepArgs {
     uint64_t seed;
     uint64_t sweep_index;
     uint32_t instance;
+    uint32_t h_begin = 0;    // half-index range of the launch; h_end = 0: all Vh
+    uint32_t h_end = 0;
 };
 
 hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,

@@ -36,7 +36,7 @@ size_t link_bytes(int format)
 template <int F, int LPS, bool SR, bool NT>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      RelaxArgs<typename Fmt<F>::T> a, int xcd_remap,
-                                                     uint32_t n_blocks)
+                                                     uint32_t n_blocks, uint32_t h_begin, uint32_t h_end)
 {
     uint32_t b = blockIdx.x;
     if (xcd_remap) {
@@ -48,10 +48,10 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
         if (b >= n_blocks) return;
     }
     const uint32_t tid = b * blockDim.x + threadIdx.x;
-    const uint32_t grp = tid / LPS;
+    const uint32_t grp = h_begin + tid / LPS;
     const int lane = (int)(tid % LPS);
-    const bool active = grp < g.Vh;
-    update_site<F, LPS, SR, NT>(field, g, parity, active ? grp : g.Vh - 1, lane, active, a);
+    const bool active = grp < h_end;
+    update_site<F, LPS, SR, NT>(field, g, parity, active ? grp : h_end - 1, lane, active, a);
 }
 
 template <int F, int LPS, bool NT>
@@ -59,7 +59,8 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
                                  hipStream_t s)
 {
     using T = typename Fmt<F>::T;
-    const uint64_t threads = (uint64_t)g.Vh * LPS;
+    const uint32_t h_begin = a.h_end ? a.h_begin : 0, h_end = a.h_end ? a.h_end : g.Vh;
+    const uint64_t threads = (uint64_t)(h_end - h_begin) * LPS;
     const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);
     const uint32_t grid = t.xcd_remap ? ((nb + 7u) / 8u) * 8u : nb;
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
@@ -67,10 +68,10 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     if (a.p_sr > 0.0) {
         ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
         hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb);
+                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end);
     } else {
         hipLaunchKernelGGL((sweep_kernel<F, LPS, false, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb);
+                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end);
     }
     return hipGetLastError();
 }

@@ -88,8 +88,8 @@ def load_library(path: str = LIB_PATH):
         "lgf_measure": (I, [P, P, P]),
         "lgf_gauge_fix": (I, [P, P, P, P, I]),
         "lgf_synchronize": (I, [P]),
-        "lgf_set_tuning": (I, [P, I, I, I, I, I]),
-        "lgf_get_tuning": (I, [P, I, P, P, P, P]),
+        "lgf_set_tuning": (I, [P, I, I, I, I, I, I]),
+        "lgf_get_tuning": (I, [P, I, P, P, P, P, P]),
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
     }
@@ -231,16 +231,15 @@ def lgf_synchronize(h) -> None:
 
 
 def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0,
-                   nontemporal: int = 0) -> None:
-    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal))
+                   nontemporal: int = 1, pipeline: int = 0) -> None:
+    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal, pipeline))
 
 
 def lgf_get_tuning(h, fmt: int):
-    """(lanes_per_site, block, xcd_remap, nontemporal)"""
-    a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                         ctypes.byref(d)))
-    return a.value, b.value, c.value, d.value
+    """(lanes_per_site, block, xcd_remap, nontemporal, pipeline)"""
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(load_library().lgf_get_tuning(h, fmt, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def lgf_autotune(h, fmt: int, trials: int = 4) -> None:

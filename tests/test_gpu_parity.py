@@ -123,7 +123,9 @@ def gpu_input(lgf, dims, fmt, U):
         return lat.store()
 
 
-TUNINGS = [(1, 128, 0, 0), (2, 128, 1, 1), (4, 64, 0, 1), (4, 256, 1, 0), (1, 64, 1, 1), (2, 256, 0, 0)]
+# (lanes per site, block, XCD remap, non-temporal, t-slice pipeline)
+TUNINGS = [(1, 128, 0, 1, 0), (2, 128, 1, 1, 1), (4, 64, 0, 1, 0), (4, 256, 1, 0, 1), (1, 64, 1, 1, 1),
+           (2, 256, 0, 0, 0), (1, 128, 0, 1, 1)]
 
 
 @pytest.mark.parametrize("fmt", ALL_FORMATS)
@@ -273,6 +275,25 @@ def test_gauge_fix_graph_equals_direct(lgf, orc):
             st, res, _ = lat.gauge_fix(omega=1.6, theta_target=1e-12, use_graph=use_graph)
             outs.append(lat.store())
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+def test_pipelined_sweeps_are_bitwise_identical(lgf, orc):
+    """The t-slice pipelined full sweep performs every site update on the
+    same links as the two-launch order: identical bits after a gauge fixing."""
+    dims = (8, 6, 4, 12)
+    announce("pipeline")
+    U = orc.generate_links(dims, 21, 0.3)
+    outs = []
+    for fmt in (lgf.LGF_FP64_18, lgf.LGF_FP32_12):
+        for pipe in (0, 1):
+            with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+                lgf.lgf_set_tuning(lat.h, fmt, 1, 128, 0, 1, pipe)
+                lgf.lgf_set_tuning(lat.h, lgf.LGF_FP64_12, 1, 128, 0, 1, pipe)
+                lat.load(U)
+                st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-12, theta_switch=1e-8,
+                                           bulk_format=fmt, finish_format=lgf.LGF_FP64_12)
+                outs.append((lat.store(), res["sweeps"]))
+        assert np.array_equal(outs[-1][0], outs[-2][0]) and outs[-1][1] == outs[-2][1]
 
 
 def test_sr_gauge_fix_converges(lgf, orc):
