@@ -202,6 +202,30 @@ def ensemble_bench(lgf, stream):
     return out
 
 
+def coulomb_bench(lgf, stream):
+    """Coulomb gauge on 48^3 x 96 (seed 5, eps 0.3, Haar): the 96 timeslices
+    relaxed together by one launch per parity, mixed FP32-12 bulk / FP64-12
+    finish, omega 1.7, each timeslice stopping at its own theta_C < 1e-14."""
+    dims = (96, 48, 48, 48)
+    V3 = dims[1] * dims[2] * dims[3]
+    h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
+    lgf.lgf_generate_links(h, 5, 0.3, True)
+    p = lgf.lgf_fix_params_default()
+    p.omega, p.theta_target, p.theta_switch = 1.7, 1e-14, 1e-8
+    p.bulk_format, p.finish_format = lgf.LGF_FP32_12, lgf.LGF_FP64_12
+    lgf.lgf_synchronize(h)
+    t0 = time.perf_counter()
+    st, res, sw, F, th = lgf.lgf_coulomb_gauge_fix(h, p, dims[0])
+    wall = time.perf_counter() - t0
+    lgf.lgf_destroy(h)
+    su = float(sw.sum()) * V3
+    return {"dims": list(dims), "status": int(st), "wall_s": wall, "sweeps_total": res["sweeps"],
+            "sweeps_bulk": res["sweeps_bulk"], "timeslice_sweeps_min": int(sw.min()),
+            "timeslice_sweeps_max": int(sw.max()), "theta_max": float(th.max()),
+            "site_updates": su, "site_updates_per_s": su / wall,
+            "t_sweep_ms": res["t_sweep_bulk_ms"] + res["t_sweep_finish_ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +278,9 @@ def main():
     hp = lgf.lgf_create(dims, home, stream, pristine)
     lgf.lgf_generate_links(hp, seed, eps, True)
     hw = lgf.lgf_create(dims, home, stream, work)
+    # sweep variants picked by the autotuner on this lattice (scratch copies)
+    lgf.lgf_autotune(hw, bulk, 2)
+    lgf.lgf_autotune(hw, finish, 2)
     torch.cuda.synchronize()
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; tuning fp32-12 "
         f"{lgf.lgf_get_tuning(hw, bulk)} fp64-12 {lgf.lgf_get_tuning(hw, finish)} fp64-18 "
@@ -357,6 +384,9 @@ def main():
         log("[bench] 48-configuration ensemble")
         extras["ensemble48"] = ensemble_bench(lgf, stream)
         log(f"[bench] ensemble: {json.dumps(extras['ensemble48'])}")
+        log("[bench] Coulomb gauge 48^3 x 96")
+        extras["coulomb_48x3x96"] = coulomb_bench(lgf, stream)
+        log(f"[bench] coulomb: {json.dumps(extras['coulomb_48x3x96'])}")
 
     cpu = None
     if not args.no_cpu_baseline:

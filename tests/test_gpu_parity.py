@@ -376,12 +376,14 @@ def sample_sites(orc, dims, parity, n, rng):
     return out
 
 
-@pytest.mark.parametrize("fmt,omega,p_sr", [(0, 1.8, 0.0), (2, 1.8, 0.0), (0, 1.0, 0.5)])
+@pytest.mark.parametrize("fmt,omega,p_sr", [(0, 1.8, 0.0), (2, 1.8, 0.0), (3, 1.8, 0.0), (0, 1.0, 0.5)])
 def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
     """The 64^4 workload (seed 3, eps 0.3, Haar gauge) in the launch
-    configuration the benchmark times: one half-sweep of parity 0 and one of
-    parity 1, compared on sampled sites (edges and wrap-arounds included)
-    with the oracle rebuilding every input link from its own generator."""
+    configuration the benchmark times (the autotuner's pick): one half-sweep
+    of parity 0, checked on sampled parity-0 sites, and, on a fresh field, one
+    full sweep, checked on sampled parity-1 sites (edges and wrap-arounds
+    included), with the oracle rebuilding every input link from its own
+    generator."""
     dims = (64, 64, 64, 64)
     seed, eps, sr_seed, sweep = 3, 0.3, 17, 5
     announce("64^4 sampled", fmt, omega, p_sr)
@@ -393,8 +395,16 @@ def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
             assert maxabs(got, ref) < 1e-12, where
         else:
             errs.extend(link_errs(got, ref))
+
+    def upd(s):
+        out, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), omega,
+                                  orc.sr_decisions(sr_seed, s, sweep, 0, p_sr))
+        return out
+
     with lgf.Lattice(dims, fmt) as lat:
         lat.generate(seed, eps, True)
+        lgf.lgf_autotune(lat.h, fmt, 1)
+        announce("tuning", lgf.lgf_get_tuning(lat.h, fmt))
         sites0 = sample_sites(orc, dims, 0, 24, rng)
         for s in sites0[:6]:
             got = gpu_links8(lat, orc, dims, s)
@@ -402,24 +412,17 @@ def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
             assert (maxabs(got, ref) < 1e-13) if fmt in FP64 else (link_rel_err(got, ref) < 5e-7)
         lat.sweep(0, omega, p_sr, sr_seed, sweep)
         for s in sites0:
-            ref, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), omega,
-                                      orc.sr_decisions(sr_seed, s, sweep, 0, p_sr))
-            check(gpu_links8(lat, orc, dims, s), ref, s)
-        # parity 1: each of its 8 links was last changed by the parity-0 site
-        # at its other end; the oracle redoes those 8 updates first
+            check(gpu_links8(lat, orc, dims, s), upd(s), s)
+        # parity 1 after a full sweep: each of its 8 links was last changed by
+        # the parity-0 site at its other end; the oracle redoes those first
+        lat.generate(seed, eps, True)
+        lat.sweep(2, omega, p_sr, sr_seed, sweep)
         sites1 = sample_sites(orc, dims, 1, 8, rng)
-        lat.sweep(1, omega, p_sr, sr_seed, sweep)
         for y in sites1:
             links = np.zeros((8, 3, 3), dtype=np.complex128)
             for mu in range(4):
-                z = orc.neighbor(dims, y, mu, +1)           # U_mu(y) is z's backward link mu
-                upd, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, z), omega,
-                                          orc.sr_decisions(sr_seed, z, sweep, 0, p_sr))
-                links[mu] = upd[4 + mu]
-                zb = orc.neighbor(dims, y, mu, -1)          # U_mu(y - mu) is zb's forward link mu
-                upd, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, zb), omega,
-                                          orc.sr_decisions(sr_seed, zb, sweep, 0, p_sr))
-                links[4 + mu] = upd[mu]
+                links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]   # U_mu(y): backward link of y+mu
+                links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]   # U_mu(y-mu): forward link of y-mu
             ref, _ = orc.local_update(links, omega, orc.sr_decisions(sr_seed, y, sweep, 0, p_sr))
             check(gpu_links8(lat, orc, dims, y), ref, y)
         if fmt not in FP64:
