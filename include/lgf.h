@@ -71,6 +71,11 @@ typedef struct {
     int check_every;       /* sweeps between reunitarize + measure, >= 1 (default 20) */
     int use_graph;         /* capture each chunk of check_every sweeps in a hipGraph (default 1) */
     int finish_format;     /* format of the sweeps after the switch (-1 = the handle's own) */
+    int accumulate_g;      /* mixed precision without orbit drift: the FP32 bulk also accumulates
+                              g(x) and the FP64 links are rebuilt at the switch as
+                              g(x) U(x) g(x+mu)^dag from the untouched FP64 input (needs an FP32
+                              bulk, an FP64 finish and an FP64 handle) */
+    int reserved;
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
@@ -100,7 +105,8 @@ const char *lgf_version(void);
 
 /* Fill *p with the defaults: omega 1.7, p_sr 0, theta_target 1e-14,
  * theta_switch 0, bulk_format -1 and finish_format -1 (= handle's format),
- * check_every 20, use_graph 1, max_sweeps 100000, seed 0, sweep_offset 0. */
+ * accumulate_g 0, check_every 20, use_graph 1, max_sweeps 100000, seed 0,
+ * sweep_offset 0. */
 lgf_status lgf_fix_params_default(lgf_fix_params *p);
 
 /* Device bytes of a link field of the given dims in the given format
@@ -177,6 +183,11 @@ lgf_status lgf_reunitarize(lgf_lattice *h);
  * A_mu = [(U - U^dag)/(2i)]_traceless, accumulated in FP64 for every format.
  * Either output pointer may be NULL.  Synchronises. */
 lgf_status lgf_measure(lgf_lattice *h, double *F, double *theta);
+
+/* Average plaquette (1/(18 V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu)
+ * U_mu(x+nu)^dag U_nu(x)^dag], accumulated in FP64: gauge invariant, so it
+ * tracks how far a run has left the gauge orbit of its input.  Synchronises. */
+lgf_status lgf_plaquette(lgf_lattice *h, double *P);
 
 /* Iterate full sweeps until theta < theta_target (Sec. 4).  Every
  * check_every sweeps the links are reunitarized and F, theta measured (also

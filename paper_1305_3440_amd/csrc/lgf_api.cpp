@@ -88,6 +88,7 @@ struct GraphEntry {
     double omega;
     lgf::SweepTuning tune;
     int coulomb;
+    void *gacc;
     hipGraphExec_t exec;
 };
 
@@ -123,6 +124,10 @@ struct lgf_lattice {
     double *d_cpart;
     double *d_cout;
     double *h_cout;    // pinned, 2 Lt doubles
+    // accumulated gauge transformation of the mixed-precision bulk
+    void *gacc;        // site field in the bulk format (owned), or NULL
+    size_t gacc_bytes;
+    void *gacc_active; // passed to the sweeps while the bulk accumulates
 };
 
 namespace {
@@ -198,6 +203,7 @@ lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, dou
                         uint64_t seed, uint64_t sweep_index, bool coulomb = false)
 {
     lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
+    a.gacc = h->gacc_active;
     if (coulomb)
         LGF_HIP(lgf::launch_sweep_coulomb(format, field, h->geom, a, h->d_mask, h->tune[format].nontemporal != 0,
                                           h->stream));
@@ -225,6 +231,7 @@ lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, dou
     const uint32_t hs = h->geom.hs[0];
     auto slice = [&](int parity, int t) -> lgf_status {
         lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
+        a.gacc = h->gacc_active;
         a.h_begin = (uint32_t)t * hs;
         a.h_end = (uint32_t)(t + 1) * hs;
         LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
@@ -297,7 +304,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     const lgf::SweepTuning &t = h->tune[format];
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
-            g.coulomb == (coulomb ? 1 : 0) &&
+            g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active &&
             g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
             g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal &&
             g.tune.pipeline == t.pipeline) {
@@ -324,7 +331,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
         (void)hipGraphExecDestroy(h->graphs.front().exec);
         h->graphs.erase(h->graphs.begin());
     }
-    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, exec});
+    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, exec});
     LGF_HIP(hipGraphLaunch(exec, h->stream));
     return LGF_OK;
 }
@@ -349,6 +356,7 @@ lgf_status lgf_fix_params_default(lgf_fix_params *p)
     p->check_every = 20;
     p->use_graph = 1;
     p->finish_format = -1;
+    p->accumulate_g = 0;
     p->max_sweeps = 100000;
     p->seed = 0;
     p->sweep_offset = 0;
@@ -441,6 +449,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
     if (h->d_stage) (void)hipFree(h->d_stage);
     if (h->d_sites) (void)hipFree(h->d_sites);
     if (h->d_mask) (void)hipFree(h->d_mask);
+    if (h->gacc) (void)hipFree(h->gacc);
     if (h->h_mask) (void)hipHostFree(h->h_mask);
     if (h->d_cpart) (void)hipFree(h->d_cpart);
     if (h->d_cout) (void)hipFree(h->d_cout);
@@ -616,7 +625,31 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     const bool mixed = (bulk != finish);
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
+    auto is64 = [](int f) { return f == LGF_FP64_18 || f == LGF_FP64_12; };
+    const bool acc = p.accumulate_g != 0;
+    // the sweeps accumulate into g only inside this call, whatever way it ends
+    struct AccOff {
+        lgf_lattice *h;
+        ~AccOff() { h->gacc_active = nullptr; }
+    } acc_off{h};
+    if (acc && !(mixed && !is64(bulk) && is64(finish) && is64(h->format)))
+        return fail(LGF_EINVAL, "accumulate_g needs an FP32 bulk, an FP64 finish and an FP64 handle");
     LGF_TRY(use_device(h));
+    if (acc) {
+        const size_t gbytes = (size_t)h->V * lgf::link_bytes(bulk);
+        if (h->gacc && h->gacc_bytes != gbytes) {
+            (void)hipFree(h->gacc);
+            h->gacc = nullptr;
+        }
+        if (!h->gacc) {
+            if (hipMalloc(&h->gacc, gbytes) != hipSuccess) {
+                h->gacc = nullptr;
+                (void)hipGetLastError();
+                return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the accumulated gauge field", gbytes);
+            }
+            h->gacc_bytes = gbytes;
+        }
+    }
 
     std::memset(res, 0, sizeof *res);
     const auto t_start = std::chrono::steady_clock::now();
@@ -673,6 +706,10 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         const bool to_fp64 = (first == LGF_FP64_18 || first == LGF_FP64_12) &&
                              !(h->format == LGF_FP64_18 || h->format == LGF_FP64_12);
         LGF_TRY(move_to(first, to_fp64));
+        if (acc && in_bulk) {
+            LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 0, h->stream));
+            h->gacc_active = h->gacc;
+        }
     }
     while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
         const int64_t left = p.max_sweeps - sweeps;
@@ -691,6 +728,7 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         sweeps += n;
         ctr += (uint64_t)n;
 
+        if (h->gacc_active) LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 1, h->stream));
         LGF_TRY(measure_timed(true, &F, &theta));
         record(sweeps, F, theta);
         if (!std::isfinite(F) || !std::isfinite(theta)) {
@@ -698,8 +736,27 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
             break;
         }
         if (in_bulk && (theta < p.theta_switch || theta < p.theta_target)) {
-            // leave the bulk precision, reunitarizing in FP64 on the way
-            LGF_TRY(move_to(finish, true));
+            if (h->gacc_active) {
+                // rebuild the FP64 links from the untouched FP64 input: an exact
+                // gauge transformation by the accumulated g
+                void *dst = h->field;
+                if (finish != h->format) {
+                    LGF_TRY(ensure_work(h, finish));
+                    dst = h->work[finish];
+                }
+                LGF_HIP(hipEventRecord(h->ev0, h->stream));
+                LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, bulk, h->gacc, finish, dst, h->geom,
+                                                    h->stream));
+                LGF_HIP(hipEventRecord(h->ev1, h->stream));
+                LGF_HIP(hipEventSynchronize(h->ev1));
+                res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+                h->gacc_active = nullptr;
+                cur = dst;
+                cur_fmt = finish;
+            } else {
+                // leave the bulk precision, reunitarizing in FP64 on the way
+                LGF_TRY(move_to(finish, true));
+            }
             in_bulk = false;
             if (theta < p.theta_target) {
                 LGF_TRY(measure_timed(false, &F, &theta));
@@ -709,6 +766,14 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
             }
         }
         if (!in_bulk && theta < p.theta_target) status = LGF_OK;
+    }
+    if (h->gacc_active) {
+        // stopped inside the bulk (max_sweeps): hand back the exact transform
+        h->gacc_active = nullptr;
+        LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, bulk, h->gacc, h->format, h->field, h->geom,
+                                            h->stream));
+        cur = h->field;
+        cur_fmt = h->format;
     }
     // hand the links back in the handle's own format
     LGF_TRY(move_to(h->format, false));
@@ -725,6 +790,19 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         return fail(LGF_ENOTCONV, "theta %g after %lld sweeps has not reached %g", theta, (long long)sweeps,
                     p.theta_target);
     if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", F, theta);
+    return LGF_OK;
+}
+
+lgf_status lgf_plaquette(lgf_lattice *h, double *P)
+{
+    if (!h || !P) return fail(LGF_EINVAL, "NULL handle or output");
+    LGF_TRY(use_device(h));
+    int n = 0;
+    LGF_HIP(lgf::launch_plaquette(h->format, h->field, h->geom, h->d_partials, &n, h->stream));
+    LGF_HIP(lgf::launch_finish_measure(h->d_partials, n, (double)h->V, h->d_out, h->stream));
+    LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    *P = h->h_out[0] * 12.0 / 18.0;  // the final sum divides by 12 V; the plaquette by 18 V
     return LGF_OK;
 }
 
@@ -772,6 +850,7 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
+    if (p.accumulate_g) return fail(LGF_EINVAL, "accumulate_g is only supported by lgf_gauge_fix");
     LGF_TRY(use_device(h));
     LGF_TRY(ensure_coulomb(h));
     const int Lt = h->dims[0];

@@ -30,6 +30,7 @@ struct SweepArgs {
     uint32_t instance;
     uint32_t h_begin = 0;    // half-index range of the launch; h_end = 0: all Vh
     uint32_t h_end = 0;
+    void *gacc = nullptr;    // site field accumulating G (same format as the links), or none
 };
 
 hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,
@@ -74,5 +75,17 @@ int coulomb_blocks_per_slice(const Geom &g);
 hipError_t launch_measure_coulomb(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
                                   bool reunit_bwd, double *partials, hipStream_t s);
 hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *out, hipStream_t s);
+
+// site field (2 parities x one SU(3) per site, link-direction layout):
+// mode 0 sets the identity, mode 1 reunitarizes in FP64
+hipError_t launch_site_field(int format, void *gf, const Geom &g, int mode, hipStream_t s);
+// dst (format fd, FP64) <- g(x) src_mu(x) g(x+mu)^dag for src FP64 and g FP32
+hipError_t launch_gauge_transform(int fs, const void *src, int fg, const void *gf, int fd, void *dst,
+                                  const Geom &g, hipStream_t s);
+
+// per-block partial sums of Re tr over the 6 plaquettes of every site (first
+// entry of each pair); finish with launch_finish_measure (out[0] * 12 V / 18 V)
+hipError_t launch_plaquette(int format, void *field, const Geom &g, double *partials, int *n_partials,
+                            hipStream_t s);
 
 }  // namespace lgf

@@ -64,7 +64,7 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);
     const uint32_t grid = t.xcd_remap ? ((nb + 7u) / 8u) * 8u : nb;
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
-                    (uint32_t)a.sweep_index, a.instance};
+                    (uint32_t)a.sweep_index, a.instance, a.gacc};
     if (a.p_sr > 0.0) {
         ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
         hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
@@ -584,6 +584,170 @@ hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *
     hipLaunchKernelGGL(finish_coulomb_kernel, dim3(g.L[0]), dim3(256), 0, s, partials,
                        coulomb_blocks_per_slice(g), V3, out);
     return hipGetLastError();
+}
+
+}  // namespace lgf
+
+// ----------------------------------------------------------------------------
+// Plaquette: (1/(18 V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag
+// U_nu(x)^dag], a gauge-invariant observable used to watch the gauge orbit.
+// ----------------------------------------------------------------------------
+
+namespace lgf {
+
+// half index (in the other parity) of the site x + mu
+__device__ __forceinline__ uint32_t fwd_half(const Geom &g, const Site &c, uint32_t h, int mu)
+{
+    if (mu == 3) {
+        const uint32_t xf = (c.x + 1 == g.L[3]) ? 0 : c.x + 1;
+        return c.row * g.hx + (xf >> 1);
+    }
+    const uint32_t coord = (mu == 0) ? c.t : (mu == 1) ? c.z : c.y;
+    return (coord + 1 == g.L[mu]) ? h - (g.L[mu] - 1) * g.hs[mu] : h + g.hs[mu];
+}
+
+template <int F>
+__global__ void __launch_bounds__(kMeasureBlock) plaquette_kernel(void *__restrict__ field, Geom g,
+                                                                  double *partials)
+{
+    using T = typename Fmt<F>::T;
+    const int parity = blockIdx.y;
+    const uint32_t h0 = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const bool active = h0 < g.Vh;
+    const uint32_t h = active ? h0 : g.Vh - 1;
+    const Site c = decode(g, parity, h);
+    double sum = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            mat3<T> a, b, cc, d;
+            load_link<F>(a, block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
+            load_link<F>(b, block_ptr<F>(field, g.Vh, parity ^ 1, nu), g.Vh, fwd_half(g, c, h, mu));
+            load_link<F>(cc, block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, fwd_half(g, c, h, nu));
+            load_link<F>(d, block_ptr<F>(field, g.Vh, parity, nu), g.Vh, h);
+            mat3<double> A, B, C, D, AB, CD;
+            convert(A, a);
+            convert(B, b);
+            convert(C, cc);
+            convert(D, d);
+            left_mul<3>(AB, A, B);     // U_mu(x) U_nu(x+mu)
+            left_mul<3>(CD, D, C);     // U_nu(x) U_mu(x+nu); the loop is AB (CD)^dag
+            // Re tr[AB CD^dag] = sum_ij Re(AB_ij conj(CD_ij))
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    sum += AB.e[i][j].re * CD.e[i][j].re + AB.e[i][j].im * CD.e[i][j].im;
+        }
+    if (!active) sum = 0.0;
+    block_sum2<kMeasureBlock>(sum, 0.0, partials + 2 * ((size_t)parity * gridDim.x + blockIdx.x));
+}
+
+hipError_t launch_plaquette(int format, void *field, const Geom &g, double *partials, int *n_partials,
+                            hipStream_t s)
+{
+    const dim3 grid(measure_blocks(g), 2);
+    *n_partials = 2 * (int)grid.x;
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((plaquette_kernel<kF64_18>), grid, dim3(kMeasureBlock), 0, s, field, g, partials); break;
+    case kF32_18: hipLaunchKernelGGL((plaquette_kernel<kF32_18>), grid, dim3(kMeasureBlock), 0, s, field, g, partials); break;
+    case kF32_12: hipLaunchKernelGGL((plaquette_kernel<kF32_12>), grid, dim3(kMeasureBlock), 0, s, field, g, partials); break;
+    case kF64_12: hipLaunchKernelGGL((plaquette_kernel<kF64_12>), grid, dim3(kMeasureBlock), 0, s, field, g, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lgf
+
+// ----------------------------------------------------------------------------
+// Accumulated gauge transformation (mixed precision without orbit drift): the
+// FP32 bulk multiplies every site's G into g(x); at the switch the FP64 links
+// are rebuilt from the untouched FP64 input as g(x) U_mu(x) g(x+mu)^dag with
+// g projected on SU(3) in FP64, an exact gauge transformation (Eq. (3)).
+// ----------------------------------------------------------------------------
+
+namespace lgf {
+
+template <int F>
+__global__ void __launch_bounds__(256) site_field_kernel(void *__restrict__ gf, uint32_t Vh, int mode)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= Vh) return;
+    const int parity = blockIdx.y;
+    typename Fmt<F>::V *p = site_field_ptr<F>(gf, Vh, parity);
+    mat3<typename Fmt<F>::T> o;
+    if (mode == 0) {
+        set_identity(o);
+    } else {  // reunitarize in FP64
+        mat3<typename Fmt<F>::T> u;
+        load_link<F>(u, p, Vh, h);
+        mat3<double> d;
+        convert(d, u);
+        reunitarize(d);
+        convert(o, d);
+    }
+    store_link<F>(p, Vh, h, o);
+}
+
+hipError_t launch_site_field(int format, void *gf, const Geom &g, int mode, hipStream_t s)
+{
+    const dim3 grid((g.Vh + 255) / 256, 2);
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((site_field_kernel<kF64_18>), grid, dim3(256), 0, s, gf, g.Vh, mode); break;
+    case kF32_18: hipLaunchKernelGGL((site_field_kernel<kF32_18>), grid, dim3(256), 0, s, gf, g.Vh, mode); break;
+    case kF32_12: hipLaunchKernelGGL((site_field_kernel<kF32_12>), grid, dim3(256), 0, s, gf, g.Vh, mode); break;
+    case kF64_12: hipLaunchKernelGGL((site_field_kernel<kF64_12>), grid, dim3(256), 0, s, gf, g.Vh, mode); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// dst (format FD) <- g(x) src_mu(x) g(x+mu)^dag, src in format FS, g in FG;
+// element-wise per link, so dst may be src when FD == FS
+template <int FS, int FG, int FD>
+__global__ void __launch_bounds__(256) gauge_transform_kernel(const void *__restrict__ src,
+                                                              const void *__restrict__ gf, void *dst, Geom g)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= g.Vh) return;
+    const int parity = blockIdx.y >> 2, mu = blockIdx.y & 3;
+    const Site c = decode(g, parity, h);
+    mat3<typename Fmt<FS>::T> u;
+    mat3<typename Fmt<FG>::T> gx, gy;
+    load_link<FS>(u, block_ptr<FS>(const_cast<void *>(src), g.Vh, parity, mu), g.Vh, h);
+    load_link<FG>(gx, site_field_ptr<FG>(const_cast<void *>(gf), g.Vh, parity), g.Vh, h);
+    load_link<FG>(gy, site_field_ptr<FG>(const_cast<void *>(gf), g.Vh, parity ^ 1), g.Vh, fwd_half(g, c, h, mu));
+    mat3<double> U, X, Y, t, r;
+    convert(U, u);
+    convert(X, gx);
+    convert(Y, gy);
+    reunitarize(X);
+    reunitarize(Y);
+    left_mul<3>(t, X, U);
+    right_mul_dag<3>(r, t, Y);
+    mat3<typename Fmt<FD>::T> o;
+    convert(o, r);
+    store_link<FD>(block_ptr<FD>(dst, g.Vh, parity, mu), g.Vh, h, o);
+}
+
+template <int FS, int FG>
+static hipError_t launch_gt_d(int fd, const void *src, const void *gf, void *dst, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((g.Vh + 255) / 256, 8);
+    switch (fd) {
+    case kF64_18: hipLaunchKernelGGL((gauge_transform_kernel<FS, FG, kF64_18>), grid, dim3(256), 0, s, src, gf, dst, g); break;
+    case kF64_12: hipLaunchKernelGGL((gauge_transform_kernel<FS, FG, kF64_12>), grid, dim3(256), 0, s, src, gf, dst, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_transform(int fs, const void *src, int fg, const void *gf, int fd, void *dst, const Geom &g,
+                                  hipStream_t s)
+{
+    if (fs == kF64_18 && fg == kF32_12) return launch_gt_d<kF64_18, kF32_12>(fd, src, gf, dst, g, s);
+    if (fs == kF64_18 && fg == kF32_18) return launch_gt_d<kF64_18, kF32_18>(fd, src, gf, dst, g, s);
+    if (fs == kF64_12 && fg == kF32_12) return launch_gt_d<kF64_12, kF32_12>(fd, src, gf, dst, g, s);
+    if (fs == kF64_12 && fg == kF32_18) return launch_gt_d<kF64_12, kF32_18>(fd, src, gf, dst, g, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lgf

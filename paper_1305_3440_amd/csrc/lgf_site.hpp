@@ -63,7 +63,17 @@ template <typename T> struct RelaxArgs {
     uint64_t sr_threshold;  // floor(p 2^32); only read when SR
     uint32_t key0, key1;    // Philox key (seed)
     uint32_t sweep, instance;
+    void *gacc = nullptr;   // accumulated gauge transformation (site field) or none
 };
+
+// A site field (one SU(3) matrix per site, e.g. an accumulated gauge
+// transformation) in the same parity-split layout as one direction of a link
+// field: vector index = (parity*NV + slot)*Vh + h.
+template <int F>
+__device__ __forceinline__ typename Fmt<F>::V *site_field_ptr(void *field, uint32_t Vh, int parity)
+{
+    return reinterpret_cast<typename Fmt<F>::V *>(field) + (size_t)(parity * Fmt<F>::NV) * Vh;
+}
 
 // The local update of site h (half index) of the given parity by LPS lanes
 // (lane in [0, LPS)): gather U_mu(x), U_mu(x - mu) for the lane's directions,
@@ -127,6 +137,13 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
     su2_step<1, 2, false>(K, G, a.omega, orl, sq2);
 
     if (!active) return;
+    if (a.gacc && lane == 0) {
+        // g(x) <- G g(x): the product of every update applied to this site
+        mat3<T> gx, r;
+        load_link<F>(gx, site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h);
+        left_mul<S::R>(r, G, gx);
+        store_link<F>(site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h, r);
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int mu = lane + k * LPS;

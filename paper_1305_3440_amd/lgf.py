@@ -28,6 +28,7 @@ class lgf_fix_params(ctypes.Structure):
                 ("theta_target", ctypes.c_double), ("theta_switch", ctypes.c_double),
                 ("bulk_format", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("finish_format", ctypes.c_int),
+                ("accumulate_g", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("sweep_offset", ctypes.c_uint64)]
 
@@ -312,6 +313,9 @@ class Lattice:
             setattr(p, k, v)
         return lgf_gauge_fix(self.h, p)
 
+    def plaquette(self):
+        return lgf_plaquette(self.h)
+
     def sweep_coulomb(self, parity, omega, p_sr=0.0, seed=0, sweep_index=0, slice_active=None):
         lgf_sweep_coulomb(self.h, parity, omega, p_sr, seed, sweep_index, slice_active)
 
@@ -333,7 +337,7 @@ ENSEMBLE_EXPORTS = [
     "lgf_ensemble_measure", "lgf_ensemble_gauge_fix", "lgf_ensemble_time_sweeps",
 ]
 EXPORTS = EXPORTS + ENSEMBLE_EXPORTS + ["lgf_sweep_coulomb", "lgf_measure_coulomb",
-                                        "lgf_coulomb_gauge_fix"]
+                                        "lgf_coulomb_gauge_fix", "lgf_plaquette"]
 
 
 def _ens_lib():
@@ -353,6 +357,7 @@ def _ens_lib():
             "lgf_sweep_coulomb": (I, [P, I, D, D, U64, U64, P]),
             "lgf_measure_coulomb": (I, [P, P, P]),
             "lgf_coulomb_gauge_fix": (I, [P, P, P, P, P, P]),
+            "lgf_plaquette": (I, [P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -419,6 +424,12 @@ def lgf_sweep_coulomb(h, parity: int, omega: float, p_sr: float = 0.0, seed: int
     act = None if slice_active is None else np.ascontiguousarray(np.asarray(slice_active, dtype=np.uint8))
     _check(_ens_lib().lgf_sweep_coulomb(h, parity, omega, p_sr, seed, sweep_index,
                                         None if act is None else _p(act)))
+
+
+def lgf_plaquette(h) -> float:
+    P = ctypes.c_double()
+    _check(_ens_lib().lgf_plaquette(h, ctypes.byref(P)))
+    return P.value
 
 
 def lgf_measure_coulomb(h, Lt: int):

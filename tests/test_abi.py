@@ -101,6 +101,7 @@ def test_fix_params_default(lgf):
     assert p.omega == 1.7 and p.p_sr == 0.0 and p.theta_target == 1e-14
     assert p.check_every == 20 and p.max_sweeps == 100000 and p.bulk_format == -1
     assert p.use_graph == 1 and p.theta_switch == 0.0 and p.finish_format == -1
+    assert p.accumulate_g == 0
 
 
 def test_binding_holds_no_arithmetic():

@@ -431,3 +431,57 @@ def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
                 float(np.quantile(e, 0.99)), float(e.max()))
         F, th = lat.measure()
         assert np.isfinite(F) and np.isfinite(th) and 0 < F < 1
+
+
+# ------------------------------------------------------------ observables, exact mixed precision
+
+@pytest.mark.parametrize("fmt", ALL_FORMATS)
+def test_plaquette_matches_oracle(lgf, orc, fmt):
+    dims = (8, 6, 4, 12)
+    announce("plaquette", fmt)
+    U = orc.generate_links(dims, 14, 0.4)
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.load(U)
+        U0 = lat.store()
+        P = lat.plaquette()
+    assert abs(P - orc.plaquette(dims, U0)) < 1e-14
+
+
+def _loops(orc, dims, U):
+    return np.array([orc.wilson_loop(dims, U, mu, nu, R, T) for mu in range(4) for nu in range(mu + 1, 4)
+                     for (R, T) in [(1, 1), (1, 2), (2, 2)]])
+
+
+def test_accumulated_gauge_keeps_the_orbit(lgf, orc):
+    """Mixed FP32-12 bulk with the accumulated gauge transformation: the links
+    handed back are an FP64 gauge transformation of the input (plaquette and
+    Wilson loops unchanged to 1e-12, unlike the plain mixed run, whose FP32
+    bulk drifts off the orbit) and reach theta < 1e-14."""
+    dims = (8, 8, 8, 8)
+    announce("accumulate_g")
+    U = orc.generate_links(dims, 1, 0.25)
+    L0 = _loops(orc, dims, U)
+    out = {}
+    for acc in (0, 1):
+        with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+            lat.load(U)
+            st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                       bulk_format=lgf.LGF_FP32_12, finish_format=lgf.LGF_FP64_12,
+                                       accumulate_g=acc)
+            got = lat.store()
+        assert st == 0 and orc.measure(dims, got)[1] < 1e-14
+        out[acc] = float(np.abs(_loops(orc, dims, got) - L0).max())
+    assert out[1] < 1e-12
+    assert out[0] > 100 * out[1]
+    # stopped inside the bulk: the exact transformation is handed back too
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-30, max_sweeps=40,
+                                   bulk_format=lgf.LGF_FP32_12, finish_format=lgf.LGF_FP64_12,
+                                   accumulate_g=1)
+        got = lat.store()
+        assert st == lgf.LGF_ENOTCONV and res["sweeps_bulk"] == 40
+        assert float(np.abs(_loops(orc, dims, got) - L0).max()) < 1e-12
+        assert unitarity_error(got) < 1e-12
+        with pytest.raises(lgf.LgfError):
+            lat.gauge_fix(omega=1.7, accumulate_g=1)   # no FP32 bulk: rejected
