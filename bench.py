@@ -202,6 +202,46 @@ def ensemble_bench(lgf, stream):
     return out
 
 
+def gauge_32x4_bench(lgf, torch, stream):
+    """32^4 (seed 1, eps 0.25, Haar, omega 1.7, theta < 1e-14): time-to-theta of
+    plain FP64-18 and of the mixed runs (FP32-12 bulk, switch at 1e-8), and
+    how far each run's plaquette moved from the input's.  The plaquette is
+    gauge invariant, so an exact gauge transformation leaves it alone; the
+    FP32 bulk without the accumulated transformation does not."""
+    dims = (32, 32, 32, 32)
+    dev = torch.device("cuda:0")
+    home = lgf.LGF_FP64_18
+    nbytes = lgf.lgf_required_bytes(dims, home)
+    pristine = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    work = torch.empty_like(pristine)
+    hp = lgf.lgf_create(dims, home, stream, pristine)
+    lgf.lgf_generate_links(hp, 1, 0.25, True)
+    hw = lgf.lgf_create(dims, home, stream, work)
+    P0 = lgf.lgf_plaquette(hp)
+    runs = {"fp64_18": (-1, -1, 0), "mixed_fp32-12_to_fp64-18": (lgf.LGF_FP32_12, lgf.LGF_FP64_18, 0),
+            "mixed_fp32-12_to_fp64-12": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 0),
+            "mixed_fp32-12_to_fp64-12_accumulate_g": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 1)}
+    out = {"dims": list(dims), "plaquette_input": P0}
+    for name, (bulk, finish, acc) in runs.items():
+        p = lgf.lgf_fix_params_default()
+        p.omega, p.theta_target = 1.7, 1e-14
+        if bulk >= 0:
+            p.theta_switch, p.bulk_format, p.finish_format, p.accumulate_g = 1e-8, bulk, finish, acc
+        work.copy_(pristine)
+        st, res, _ = lgf.lgf_gauge_fix(hw, p)
+        out[name] = {"status": int(st), "time_to_theta_s": res["t_total_ms"] / 1e3, "sweeps": res["sweeps"],
+                     "sweeps_bulk": res["sweeps_bulk"], "theta": res["theta"], "F": res["F"],
+                     "plaquette_drift": lgf.lgf_plaquette(hw) - P0}
+    for name in runs:
+        if name != "fp64_18":
+            out[name]["speedup_vs_fp64"] = out["fp64_18"]["time_to_theta_s"] / out[name]["time_to_theta_s"]
+    lgf.lgf_destroy(hw)
+    lgf.lgf_destroy(hp)
+    del work, pristine
+    torch.cuda.empty_cache()
+    return out
+
+
 def coulomb_bench(lgf, stream):
     """Coulomb gauge on 48^3 x 96 (seed 5, eps 0.3, Haar): the 96 timeslices
     relaxed together by one launch per parity, mixed FP32-12 bulk / FP64-12
@@ -381,6 +421,9 @@ def main():
     del work, pristine
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("[bench] 32^4 plain vs mixed, plaquette drift")
+        extras["gauge_32x4"] = gauge_32x4_bench(lgf, torch, stream)
+        log(f"[bench] 32^4: {json.dumps(extras['gauge_32x4'])}")
         log("[bench] 48-configuration ensemble")
         extras["ensemble48"] = ensemble_bench(lgf, stream)
         log(f"[bench] ensemble: {json.dumps(extras['ensemble48'])}")

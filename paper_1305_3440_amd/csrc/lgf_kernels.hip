@@ -703,7 +703,7 @@ hipError_t launch_site_field(int format, void *gf, const Geom &g, int mode, hipS
 // dst (format FD) <- g(x) src_mu(x) g(x+mu)^dag, src in format FS, g in FG;
 // element-wise per link, so dst may be src when FD == FS
 template <int FS, int FG, int FD>
-__global__ void __launch_bounds__(256) gauge_transform_kernel(const void *__restrict__ src,
+__global__ void __launch_bounds__(256) gauge_transform_kernel(const void *src,
                                                               const void *__restrict__ gf, void *dst, Geom g)
 {
     const uint32_t h = blockIdx.x * 256 + threadIdx.x;

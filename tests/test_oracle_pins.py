@@ -292,6 +292,46 @@ def test_gauge_invariance(orc):
     assert np.abs(_loops(orc, dims, U) - L0).max() < 1e-12
 
 
+def test_wilson_loops_of_abelian_field(orc):
+    """For links diag(e^{i a}, e^{i b}, e^{-i(a+b)}) the path product of a loop
+    is diagonal with the phases summed around the rectangle, so (1/3) Re tr of
+    the R x T loop is (cos A + cos B + cos(A + B)) / 3 with A, B the circulations
+    of a and b: written with scalar phases and periodic shifts only."""
+    dims = (4, 6, 4, 8)
+    rng = np.random.default_rng(11)
+    a = rng.uniform(-np.pi, np.pi, (4,) + dims)
+    b = rng.uniform(-np.pi, np.pi, (4,) + dims)
+    U = np.zeros((int(np.prod(dims)), 4, 3, 3), dtype=np.complex128)
+    for mu in range(4):
+        U[:, mu, 0, 0] = np.exp(1j * a[mu]).ravel()
+        U[:, mu, 1, 1] = np.exp(1j * b[mu]).ravel()
+        U[:, mu, 2, 2] = np.exp(-1j * (a[mu] + b[mu])).ravel()
+
+    def shift(f, axis, n):            # f(x + n * axis-hat)
+        return np.roll(f, -n, axis=axis)
+
+    def circulation(ph, mu, nu, R, T):
+        c = np.zeros(dims)
+        for k in range(R):
+            c += shift(ph[mu], mu, k)
+            c -= shift(shift(ph[mu], nu, T), mu, k)
+        for l in range(T):
+            c += shift(shift(ph[nu], mu, R), nu, l)
+            c -= shift(ph[nu], nu, l)
+        return c
+
+    plaq = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            for (R, T) in [(1, 1), (2, 1), (1, 3), (3, 2)]:
+                A, B = circulation(a, mu, nu, R, T), circulation(b, mu, nu, R, T)
+                want = float(np.mean((np.cos(A) + np.cos(B) + np.cos(A + B)) / 3))
+                assert abs(orc.wilson_loop(dims, U, mu, nu, R, T) - want) < 1e-13, (mu, nu, R, T)
+                if (R, T) == (1, 1):
+                    plaq += want / 6
+    assert abs(orc.plaquette(dims, U) - plaq) < 1e-13
+
+
 @pytest.mark.parametrize("omega,p", [(1.0, 0.0), (1.3, 0.0), (1.7, 0.0), (2.0, 0.0),
                                      (1.0, 0.5), (1.8, 0.3)])
 def test_F_never_decreases(orc, omega, p):
