@@ -28,7 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
 KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_device.hpp",
-                  "paper_1305_3440_amd/csrc/lgf_internal.hpp", "paper_1305_3440_amd/csrc/lgf_api.cpp"]
+                  "paper_1305_3440_amd/csrc/lgf_site.hpp", "paper_1305_3440_amd/csrc/lgf_internal.hpp",
+                  "paper_1305_3440_amd/csrc/lgf_api.cpp"]
+# sweep variants the counter passes cover: (lanes per site, block, xcd remap, non-temporal, schedule)
+TRAFFIC_VARIANTS = [(1, 128, 0, 1, 0), (2, 128, 0, 1, 0), (4, 128, 0, 1, 0), (1, 128, 0, 1, 2),
+                    (2, 128, 0, 1, 2), (4, 128, 0, 1, 2), (1, 128, 0, 0, 0), (2, 128, 0, 0, 0)]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_64x4_hbm_traffic.json")
 
 
@@ -44,9 +48,16 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, dims, fmt_name: str):
+def traffic_key(fmt: int, lanes: int, nontemporal: int, schedule: int, dims) -> str:
+    """Key of one sweep-kernel instance (format, lanes per site, non-temporal,
+    out of place) on one lattice; the workgroup size does not change it."""
+    return (f"sweep:fmt{fmt}:lanes{lanes}:nt{int(bool(nontemporal))}:oop{int(schedule == 2)}:"
+            f"{'x'.join(map(str, dims))}")
+
+
+def measured_traffic(key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and this workload."""
+    was taken on the current kernel source and this kernel and workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +65,7 @@ def measured_traffic(kernel: str, dims, fmt_name: str):
         return None
     if t.get("source_sha") != kernel_source_sha():
         return None
-    e = t.get("kernels", {}).get(f"{kernel}:{fmt_name}:{'x'.join(map(str, dims))}")
+    e = t.get("kernels", {}).get(key)
     if not e:
         return None
     return e.get("hbm_bytes_per_launch")
@@ -85,8 +96,8 @@ def cpu_baseline(dims, seed, eps, omega, seconds):
 
 def traffic_run(lgf, torch, dims, seed, eps, omega):
     """Workload for the rocprofv3 counter passes: a copy of known size (to
-    calibrate FETCH_SIZE / WRITE_SIZE), then 4 sweep launches per format on
-    the benchmark's 64^4 field."""
+    calibrate FETCH_SIZE / WRITE_SIZE), then 4 sweep launches per format and
+    sweep variant on the benchmark's 64^4 field."""
     n = 1 << 30
     a = torch.zeros(n, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -98,8 +109,10 @@ def traffic_run(lgf, torch, dims, seed, eps, omega):
     for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_18):
         h = lgf.lgf_create(dims, fmt, stream)
         lgf.lgf_generate_links(h, seed, eps, True)
-        ms = lgf.lgf_time_sweeps(h, 2, omega)
-        log(f"[traffic] {lgf.FORMAT_NAMES[fmt]}: {ms:.3f} ms per launch")
+        for v in TRAFFIC_VARIANTS:
+            lgf.lgf_set_tuning(h, fmt, *v)
+            ms = lgf.lgf_time_sweeps(h, 2, omega)
+            log(f"[traffic] {lgf.FORMAT_NAMES[fmt]} {v}: {ms:.3f} ms per launch")
         lgf.lgf_destroy(h)
     torch.cuda.synchronize()
 
@@ -134,18 +147,20 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
         scale[counter] = copy_bytes / kib
         out["calibration"][counter] = {"copy_bytes": copy_bytes, "counter_kib": kib,
                                        "bytes_per_counter_unit": scale[counter]}
-    names = {"<2,": "fp32-12", "<3,": "fp64-12", "<0,": "fp64-18"}
+    import re
+    pat = re.compile(r"sweep_kernel<(\d+),\s*(\d+),\s*(true|false),\s*(true|false),\s*(true|false)>")
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     for (counter, kname), vals in per.items():
-        if "sweep_kernel" not in kname:
+        m = pat.search(kname)
+        if not m:
             continue
-        fmt = next(v for k, v in names.items() if k in kname.replace(" ", ""))
-        key = f"sweep:{fmt}:{'x'.join(map(str, dims))}"
-        e = out["kernels"].setdefault(key, {"kernel": kname})
+        fmt, lanes = int(m.group(1)), int(m.group(2))
+        key = traffic_key(fmt, lanes, m.group(4) == "true", 2 if m.group(5) == "true" else 0, dims)
+        e = out["kernels"].setdefault(key, {"kernel": kname, "format": fmt})
         e[counter.lower() + "_bytes_per_launch"] = sum(vals) / len(vals) * scale[counter]
+        e[counter.lower() + "_dispatches"] = len(vals)
     for key, e in out["kernels"].items():
-        fmt = key.split(":")[1]
-        alg = Vh * 16 * {"fp32-12": 48, "fp64-12": 96, "fp64-18": 144}[fmt]
+        alg = Vh * 16 * LINK_BYTES[e["format"]]
         e["algorithmic_bytes_per_launch"] = alg
         e["hbm_bytes_per_launch"] = e.get("fetch_size_bytes_per_launch", 0) + e.get(
             "write_size_bytes_per_launch", 0)
@@ -322,6 +337,7 @@ def main():
     lgf.lgf_autotune(hw, bulk, 2)
     lgf.lgf_autotune(hw, finish, 2)
     torch.cuda.synchronize()
+    tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish, home)}
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; tuning fp32-12 "
         f"{lgf.lgf_get_tuning(hw, bulk)} fp64-12 {lgf.lgf_get_tuning(hw, finish)} fp64-18 "
         f"{lgf.lgf_get_tuning(hw, home)}")
@@ -374,11 +390,17 @@ def main():
                              "site_updates_per_s": Vh / (launch_ms * 1e-3), "total_ms": tms}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
-    fmt_name = "fp32-12" if dom == "sweep_fp32_12" else "fp64-12"
-    traffic = measured_traffic("sweep", dims, fmt_name)
+    dfmt = bulk if dom == "sweep_fp32_12" else finish
+    fmt_name = lgf.FORMAT_NAMES[dfmt]
+    lanes, block, xcd, nt, sched = tuning[dfmt]
+    traffic = measured_traffic(traffic_key(dfmt, lanes, nt, sched, dims))
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": f"sweep_kernel<{fmt_name}>",
+                "traffic": traffic,
+                "kernel": f"sweep_kernel<{fmt_name}, lanes/site {lanes}, "
+                          f"{'non-temporal' if nt else 'cached'}, "
+                          f"{['in place', 't-slice pipeline', 'out of place'][sched]}> block {block}"
+                          f"{' xcd-remap' if xcd else ''}",
                 "avg_launch_ms": round(dk["avg_launch_ms"], 4),
                 "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
 
@@ -453,7 +475,10 @@ def main():
                                f"FP32-12 bulk / FP64-12 finish, theta<1e-14",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
-                   "sweeps_per_step": [r["sweeps"] for r in results]},
+                   "sweeps_per_step": [r["sweeps"] for r in results],
+                   "sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(
+                       ("lanes_per_site", "block", "xcd_remap", "nontemporal", "schedule"), t))
+                       for f, t in tuning.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -209,18 +209,23 @@ lgf_status lgf_synchronize(lgf_lattice *h);
 /* Kernel tuning of a handle, per storage format: lanes_per_site in {1, 2, 4}
  * (lanes that share one site update), block (threads per workgroup: 64, 128
  * or 256), xcd_remap (0/1: give each XCD a contiguous range of workgroups),
- * nontemporal (0/1: stream the links past the caches), pipeline (0/1: issue a
- * full sweep as a t-slice pipeline, parity 1 of slice k-1 right after parity 0
- * of slice k, so that parity 1 reads what parity 0 wrote from the last-level
- * cache; the result is bit-identical).  lgf_get_tuning reads the current
- * values (any output pointer may be NULL). */
+ * nontemporal (0/1: stream the links past the caches), schedule of a full
+ * sweep: 0 = parity 0 then parity 1, each updating the links in place;
+ * 1 = t-slice pipeline, parity 1 of slice k-1 right after parity 0 of slice k,
+ * so that parity 1 reads what parity 0 wrote from the last-level cache;
+ * 2 = out of place, parity 0 reads the field and writes every link into a
+ * second buffer of the same size, parity 1 writes them back (needs
+ * nontemporal = 1; the library allocates the buffer here, LGF_ENOMEM if it
+ * cannot).  Every schedule gives bit-identical links; single half-sweeps
+ * (lgf_sweep with parity 0 or 1) always run in place.  lgf_get_tuning reads
+ * the current values (any output pointer may be NULL). */
 lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block,
-                          int xcd_remap, int nontemporal, int pipeline);
+                          int xcd_remap, int nontemporal, int schedule);
 lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block,
-                          int *xcd_remap, int *nontemporal, int *pipeline);
+                          int *xcd_remap, int *nontemporal, int *schedule);
 
 /* Time the sweep variants (lanes per site, block, XCD remap, non-temporal,
- * pipeline) for a format on this handle's lattice, on a scratch copy of the
+ * schedule) for a format on this handle's lattice, on a scratch copy of the
  * links (which are left untouched), and keep the fastest.  trials = timed full
  * sweeps per variant (>= 1). */
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);

@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -115,6 +116,7 @@ struct lgf_lattice {
     int64_t sites_cap;
     void *work[4];  // owned per-format copies for the mixed-precision bulk
     size_t work_bytes[4];
+    void *partner[4];  // owned second buffer per format for the out-of-place schedule
     lgf::SweepTuning tune[4];
     std::vector<GraphEntry> graphs;
     hipEvent_t ev0, ev1;
@@ -182,6 +184,20 @@ lgf_status ensure_work(lgf_lattice *h, int format)
     return LGF_OK;
 }
 
+// the second buffer of a format's out-of-place sweep (a whole field's size)
+lgf_status ensure_partner(lgf_lattice *h, int format)
+{
+    if (!h->partner[format]) {
+        const size_t bytes = (size_t)h->V * 4 * lgf::link_bytes(format);
+        if (hipMalloc(&h->partner[format], bytes) != hipSuccess) {
+            h->partner[format] = nullptr;
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the out-of-place partner buffer", bytes);
+        }
+    }
+    return LGF_OK;
+}
+
 // F and theta of a field; with reunit the links are first projected onto
 // SU(3) in FP64 (fused: parity 0 reunitarizes its forward links and, in
 // registers, its backward links; parity 1 then reads the already stored ones).
@@ -223,7 +239,21 @@ lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, dou
                       uint64_t sweep_index, bool coulomb = false)
 {
     const int Lt = h->dims[0];
-    if (coulomb || !h->tune[format].pipeline || Lt < 4) {
+    const int sched = h->tune[format].schedule;
+    if (!coulomb && sched == lgf::kScheduleOutOfPlace) {
+        // parity 0 moves every link into the partner buffer, parity 1 moves them back
+        void *partner = h->partner[format];
+        if (!partner || partner == field) return fail(LGF_ESTATE, "no partner buffer for the out-of-place sweep");
+        lgf::SweepArgs a{0, omega, p_sr, seed, sweep_index, 0u};
+        a.gacc = h->gacc_active;
+        a.out = partner;
+        LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
+        a.parity = 1;
+        a.out = field;
+        LGF_HIP(lgf::launch_sweep(format, partner, h->geom, a, h->tune[format], h->stream));
+        return LGF_OK;
+    }
+    if (coulomb || sched != lgf::kSchedulePipeline || Lt < 4) {
         LGF_TRY(sweep_launch(h, format, field, 0, omega, p_sr, seed, sweep_index, coulomb));
         LGF_TRY(sweep_launch(h, format, field, 1, omega, p_sr, seed, sweep_index, coulomb));
         return LGF_OK;
@@ -307,7 +337,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
             g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active &&
             g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
             g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal &&
-            g.tune.pipeline == t.pipeline) {
+            g.tune.schedule == t.schedule) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
         }
@@ -441,8 +471,10 @@ lgf_status lgf_destroy(lgf_lattice *h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
     if (h->owned && h->field) (void)hipFree(h->field);
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 4; ++f) {
         if (h->work[f]) (void)hipFree(h->work[f]);
+        if (h->partner[f]) (void)hipFree(h->partner[f]);
+    }
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_out) (void)hipFree(h->d_out);
     if (h->h_out) (void)hipHostFree(h->h_out);
@@ -977,7 +1009,7 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
 }
 
 lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap,
-                          int nontemporal, int pipeline)
+                          int nontemporal, int schedule)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
@@ -985,14 +1017,21 @@ lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int bl
         return fail(LGF_EINVAL, "lanes_per_site must be 1, 2 or 4");
     if (block != 64 && block != 128 && block != 256)
         return fail(LGF_EINVAL, "block must be 64, 128 or 256");
-    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0,
-                                       pipeline ? 1 : 0};
+    if (schedule < lgf::kScheduleInPlace || schedule > lgf::kScheduleOutOfPlace)
+        return fail(LGF_EINVAL, "schedule must be 0 (in place), 1 (t-slice pipeline) or 2 (out of place)");
+    if (schedule == lgf::kScheduleOutOfPlace && !nontemporal)
+        return fail(LGF_EINVAL, "the out-of-place schedule needs nontemporal = 1");
+    if (schedule == lgf::kScheduleOutOfPlace) {
+        LGF_TRY(use_device(h));
+        LGF_TRY(ensure_partner(h, format));
+    }
+    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0, schedule};
     drop_graphs(h);
     return LGF_OK;
 }
 
 lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap,
-                          int *nontemporal, int *pipeline)
+                          int *nontemporal, int *schedule)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
@@ -1000,7 +1039,7 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site,
     if (block) *block = h->tune[format].block;
     if (xcd_remap) *xcd_remap = h->tune[format].xcd_remap;
     if (nontemporal) *nontemporal = h->tune[format].nontemporal;
-    if (pipeline) *pipeline = h->tune[format].pipeline;
+    if (schedule) *schedule = h->tune[format].schedule;
     return LGF_OK;
 }
 
@@ -1019,36 +1058,85 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     }
     hipError_t e = lgf::launch_convert(h->format, h->field, format, scratch, h->geom, false, h->stream);
     const lgf::SweepTuning saved = h->tune[format];
-    lgf::SweepTuning best = saved;
-    double best_ms = 1e300;
+    // the out-of-place variants need the partner buffer; without memory for it they are skipped
+    const bool had_partner = h->partner[format] != nullptr;
+    const bool can_oop = ensure_partner(h, format) == LGF_OK;
     lgf_status st = LGF_OK;
+    // time `trials` full sweeps of one variant after one untimed full sweep
+    auto time_variant = [&](const lgf::SweepTuning &t, double *ms) {
+        h->tune[format] = t;
+        st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
+        if (st != LGF_OK) return false;
+        e = hipEventRecord(h->ev0, h->stream);
+        for (int k = 0; k < trials && e == hipSuccess && st == LGF_OK; ++k)
+            st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
+        if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+        if (e != hipSuccess || st != LGF_OK) return false;
+        *ms = elapsed_ms(h->ev0, h->ev1) / trials;
+        return true;
+    };
+    // stage 1: every variant once
+    struct Cand {
+        lgf::SweepTuning t;
+        double ms;
+    };
+    std::vector<Cand> cands;
     const int lps_list[3] = {1, 2, 4};
     const int block_list[3] = {64, 128, 256};
-    // every variant times `trials` full sweeps after one untimed full sweep
-    for (int li = 0; li < 3 && e == hipSuccess && st == LGF_OK; ++li)
-        for (int bi = 0; bi < 3 && e == hipSuccess && st == LGF_OK; ++bi)
-            for (int v = 0; v < 8 && e == hipSuccess && st == LGF_OK; ++v) {
-                h->tune[format] = lgf::SweepTuning{lps_list[li], block_list[bi], v & 1, (v >> 1) & 1, v >> 2};
-                st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
-                if (st != LGF_OK) break;
-                e = hipEventRecord(h->ev0, h->stream);
-                for (int k = 0; k < trials && e == hipSuccess && st == LGF_OK; ++k)
-                    st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
-                if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
-                if (e != hipSuccess || st != LGF_OK) break;
-                const double ms = elapsed_ms(h->ev0, h->ev1) / trials;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = h->tune[format];
+    bool ok = (e == hipSuccess);
+    for (int li = 0; li < 3 && ok; ++li)
+        for (int bi = 0; bi < 3 && ok; ++bi)
+            for (int v = 0; v < 12 && ok; ++v) {
+                const int xcd = v & 1, nt = (v >> 1) & 1, sched = v >> 2;
+                if (sched == lgf::kScheduleOutOfPlace && (!nt || !can_oop)) continue;
+                Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched}, 0.0};
+                ok = time_variant(c.t, &c.ms);
+                if (ok) cands.push_back(c);
+            }
+    // stage 2: the four fastest and the default, timed again in three
+    // interleaved rounds; the smallest median wins (single timings of
+    // variants a few per cent apart are within the run-to-run noise)
+    lgf::SweepTuning best = saved;
+    if (ok) {
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        std::vector<lgf::SweepTuning> finals;
+        for (size_t i = 0; i < cands.size() && finals.size() < 4; ++i) finals.push_back(cands[i].t);
+        const lgf::SweepTuning dflt{};
+        bool have_default = false;
+        for (const auto &t : finals)
+            have_default = have_default || (t.lanes_per_site == dflt.lanes_per_site && t.block == dflt.block &&
+                                            t.xcd_remap == dflt.xcd_remap && t.nontemporal == dflt.nontemporal &&
+                                            t.schedule == dflt.schedule);
+        if (!have_default) finals.push_back(dflt);
+        std::vector<std::vector<double>> ms(finals.size());
+        for (int round = 0; round < 3 && ok; ++round)
+            for (size_t i = 0; i < finals.size() && ok; ++i) {
+                double m = 0.0;
+                ok = time_variant(finals[i], &m);
+                ms[i].push_back(m);
+            }
+        if (ok) {
+            double best_ms = 1e300;
+            for (size_t i = 0; i < finals.size(); ++i) {
+                std::sort(ms[i].begin(), ms[i].end());
+                if (ms[i][1] < best_ms) {
+                    best_ms = ms[i][1];
+                    best = finals[i];
                 }
             }
+        }
+    }
     h->tune[format] = saved;
     (void)hipStreamSynchronize(h->stream);
     (void)hipFree(scratch);
+    if (st == LGF_OK && e == hipSuccess) h->tune[format] = best;
+    if (!had_partner && h->partner[format] && h->tune[format].schedule != lgf::kScheduleOutOfPlace) {
+        (void)hipFree(h->partner[format]);
+        h->partner[format] = nullptr;
+    }
     if (st != LGF_OK) return st;
     if (e != hipSuccess) return fail(LGF_EHIP, "autotune: %s", hipGetErrorString(e));
-    h->tune[format] = best;
     drop_graphs(h);
     return LGF_OK;
 }

@@ -18,8 +18,12 @@ struct SweepTuning {
     int block = 128;         // threads per workgroup (fastest measured at 64^4)
     int xcd_remap = 0;       // contiguous workgroup ranges per XCD
     int nontemporal = 1;     // stream links past the caches
-    int pipeline = 0;        // full sweeps as a t-slice pipeline (parity 1 one slice behind)
+    int schedule = 0;        // full sweeps: 0 two in-place launches, 1 t-slice pipeline
+                             // (parity 1 one slice behind), 2 out of place (ping-pong
+                             // between the field and a second buffer of its format)
 };
+
+constexpr int kScheduleInPlace = 0, kSchedulePipeline = 1, kScheduleOutOfPlace = 2;
 
 struct SweepArgs {
     int parity;
@@ -31,6 +35,7 @@ struct SweepArgs {
     uint32_t h_begin = 0;    // half-index range of the launch; h_end = 0: all Vh
     uint32_t h_end = 0;
     void *gacc = nullptr;    // site field accumulating G (same format as the links), or none
+    void *out = nullptr;     // out-of-place target field (whole half-sweep only), or in place
 };
 
 hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,

@@ -33,10 +33,11 @@ size_t link_bytes(int format)
 // Relaxation sweep
 // ----------------------------------------------------------------------------
 
-template <int F, int LPS, bool SR, bool NT>
+template <int F, int LPS, bool SR, bool NT, bool OOP = false>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      RelaxArgs<typename Fmt<F>::T> a, int xcd_remap,
-                                                     uint32_t n_blocks, uint32_t h_begin, uint32_t h_end)
+                                                     uint32_t n_blocks, uint32_t h_begin, uint32_t h_end,
+                                                     void *__restrict__ out_field)
 {
     uint32_t b = blockIdx.x;
     if (xcd_remap) {
@@ -51,13 +52,15 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
     const uint32_t grp = h_begin + tid / LPS;
     const int lane = (int)(tid % LPS);
     const bool active = grp < h_end;
-    update_site<F, LPS, SR, NT>(field, g, parity, active ? grp : h_end - 1, lane, active, a);
+    update_site<F, LPS, SR, NT, 0, OOP>(field, g, parity, active ? grp : h_end - 1, lane, active, a, nullptr,
+                                        out_field);
 }
 
-template <int F, int LPS, bool NT>
+template <int F, int LPS, bool NT, bool OOP>
 static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  hipStream_t s)
 {
+    if (OOP && (a.out == nullptr || a.out == field || a.h_end != 0)) return hipErrorInvalidValue;
     using T = typename Fmt<F>::T;
     const uint32_t h_begin = a.h_end ? a.h_begin : 0, h_end = a.h_end ? a.h_end : g.Vh;
     const uint64_t threads = (uint64_t)(h_end - h_begin) * LPS;
@@ -67,11 +70,11 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
                     (uint32_t)a.sweep_index, a.instance, a.gacc};
     if (a.p_sr > 0.0) {
         ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end);
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT, OOP>), dim3(grid), dim3(t.block), 0, s, field, g,
+                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end, a.out);
     } else {
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, false, NT>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end);
+        hipLaunchKernelGGL((sweep_kernel<F, LPS, false, NT, OOP>), dim3(grid), dim3(t.block), 0, s, field, g,
+                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end, a.out);
     }
     return hipGetLastError();
 }
@@ -80,14 +83,20 @@ template <int F>
 static hipError_t launch_sweep_f(void *field, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  hipStream_t s)
 {
+    // out of place only with non-temporal access (the variant that can use it)
+    const bool oop = a.out != nullptr;
+    if (oop && !t.nontemporal) return hipErrorInvalidValue;
     const int key = t.lanes_per_site * 2 + (t.nontemporal ? 1 : 0);
     switch (key) {
-    case 2: return launch_sweep_t<F, 1, false>(field, g, a, t, s);
-    case 3: return launch_sweep_t<F, 1, true>(field, g, a, t, s);
-    case 4: return launch_sweep_t<F, 2, false>(field, g, a, t, s);
-    case 5: return launch_sweep_t<F, 2, true>(field, g, a, t, s);
-    case 8: return launch_sweep_t<F, 4, false>(field, g, a, t, s);
-    case 9: return launch_sweep_t<F, 4, true>(field, g, a, t, s);
+    case 2: return launch_sweep_t<F, 1, false, false>(field, g, a, t, s);
+    case 3: return oop ? launch_sweep_t<F, 1, true, true>(field, g, a, t, s)
+                       : launch_sweep_t<F, 1, true, false>(field, g, a, t, s);
+    case 4: return launch_sweep_t<F, 2, false, false>(field, g, a, t, s);
+    case 5: return oop ? launch_sweep_t<F, 2, true, true>(field, g, a, t, s)
+                       : launch_sweep_t<F, 2, true, false>(field, g, a, t, s);
+    case 8: return launch_sweep_t<F, 4, false, false>(field, g, a, t, s);
+    case 9: return oop ? launch_sweep_t<F, 4, true, true>(field, g, a, t, s)
+                       : launch_sweep_t<F, 4, true, false>(field, g, a, t, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -85,11 +85,16 @@ __device__ __forceinline__ typename Fmt<F>::V *site_field_ptr(void *field, uint3
 // MU0 = 1 gives the Coulomb-gauge update: K from the spatial links only, G
 // still applied to all 8 links; slice_active (optional, one flag per
 // timeslice) leaves the sites of frozen timeslices untouched.
-template <int F, int LPS, bool SR, bool NT, int MU0 = 0>
+// OOP: the updated links go to out_field instead of back into field (every
+// link has one end of each parity, so one half-sweep writes every link of
+// out_field exactly once and the next half-sweep reads them from there).
+template <int F, int LPS, bool SR, bool NT, int MU0 = 0, bool OOP = false>
 __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
                                             int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a,
-                                            const uint8_t *__restrict__ slice_active = nullptr)
+                                            const uint8_t *__restrict__ slice_active = nullptr,
+                                            void *__restrict__ out_field = nullptr)
 {
+    static_assert(!(OOP && MU0 != 0), "timeslice masks need the in-place update");
     using S = Fmt<F>;
     using T = typename S::T;
     constexpr int NL = 4 / LPS;  // directions handled per lane
@@ -149,9 +154,9 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
         const int mu = lane + k * LPS;
         mat3<T> r;
         left_mul<S::R>(r, G, uf[k]);
-        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h, r);
+        store_link<F, NT>(block_ptr<F>(OOP ? out_field : field, g.Vh, parity, mu), g.Vh, h, r);
         right_mul_dag<S::R>(r, ub[k], G);
-        store_link<F, NT>(block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
+        store_link<F, NT>(block_ptr<F>(OOP ? out_field : field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
     }
 }
 

@@ -232,12 +232,12 @@ def lgf_synchronize(h) -> None:
 
 
 def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0,
-                   nontemporal: int = 1, pipeline: int = 0) -> None:
-    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal, pipeline))
+                   nontemporal: int = 1, schedule: int = 0) -> None:
+    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal, schedule))
 
 
 def lgf_get_tuning(h, fmt: int):
-    """(lanes_per_site, block, xcd_remap, nontemporal, pipeline)"""
+    """(lanes_per_site, block, xcd_remap, nontemporal, schedule)"""
     v = [ctypes.c_int() for _ in range(5)]
     _check(load_library().lgf_get_tuning(h, fmt, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)

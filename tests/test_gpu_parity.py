@@ -123,9 +123,10 @@ def gpu_input(lgf, dims, fmt, U):
         return lat.store()
 
 
-# (lanes per site, block, XCD remap, non-temporal, t-slice pipeline)
+# (lanes per site, block, XCD remap, non-temporal, schedule: 0 in place,
+# 1 t-slice pipeline, 2 out of place)
 TUNINGS = [(1, 128, 0, 1, 0), (2, 128, 1, 1, 1), (4, 64, 0, 1, 0), (4, 256, 1, 0, 1), (1, 64, 1, 1, 1),
-           (2, 256, 0, 0, 0), (1, 128, 0, 1, 1)]
+           (2, 256, 0, 0, 0), (1, 128, 0, 1, 1), (1, 128, 0, 1, 2), (2, 64, 1, 1, 2), (4, 256, 0, 1, 2)]
 
 
 @pytest.mark.parametrize("fmt", ALL_FORMATS)
@@ -277,15 +278,16 @@ def test_gauge_fix_graph_equals_direct(lgf, orc):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
 
 
-def test_pipelined_sweeps_are_bitwise_identical(lgf, orc):
-    """The t-slice pipelined full sweep performs every site update on the
-    same links as the two-launch order: identical bits after a gauge fixing."""
+def test_sweep_schedules_are_bitwise_identical(lgf, orc):
+    """The t-slice pipelined and the out-of-place full sweeps perform every
+    site update on the same links as the two in-place launches: identical
+    bits after a gauge fixing (mixed, graph-captured chunks)."""
     dims = (8, 6, 4, 12)
-    announce("pipeline")
+    announce("schedules")
     U = orc.generate_links(dims, 21, 0.3)
     outs = []
     for fmt in (lgf.LGF_FP64_18, lgf.LGF_FP32_12):
-        for pipe in (0, 1):
+        for pipe in (0, 1, 2):
             with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
                 lgf.lgf_set_tuning(lat.h, fmt, 1, 128, 0, 1, pipe)
                 lgf.lgf_set_tuning(lat.h, lgf.LGF_FP64_12, 1, 128, 0, 1, pipe)
@@ -293,7 +295,8 @@ def test_pipelined_sweeps_are_bitwise_identical(lgf, orc):
                 st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-12, theta_switch=1e-8,
                                            bulk_format=fmt, finish_format=lgf.LGF_FP64_12)
                 outs.append((lat.store(), res["sweeps"]))
-        assert np.array_equal(outs[-1][0], outs[-2][0]) and outs[-1][1] == outs[-2][1]
+        for k in (-1, -2):
+            assert np.array_equal(outs[k][0], outs[-3][0]) and outs[k][1] == outs[-3][1]
 
 
 def test_sr_gauge_fix_converges(lgf, orc):
