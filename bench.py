@@ -27,9 +27,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
+# the sources that define the sweep kernels and their launch shape (the host
+# driver only picks among them)
 KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_device.hpp",
-                  "paper_1305_3440_amd/csrc/lgf_site.hpp", "paper_1305_3440_amd/csrc/lgf_internal.hpp",
-                  "paper_1305_3440_amd/csrc/lgf_api.cpp"]
+                  "paper_1305_3440_amd/csrc/lgf_site.hpp", "paper_1305_3440_amd/csrc/lgf_internal.hpp"]
 # sweep variants the counter passes cover: (lanes per site, block, xcd remap, non-temporal, schedule)
 TRAFFIC_VARIANTS = [(1, 128, 0, 1, 0), (2, 128, 0, 1, 0), (4, 128, 0, 1, 0), (1, 128, 0, 1, 2),
                     (2, 128, 0, 1, 2), (4, 128, 0, 1, 2), (1, 128, 0, 0, 0), (2, 128, 0, 0, 0)]
@@ -148,7 +149,9 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
         out["calibration"][counter] = {"copy_bytes": copy_bytes, "counter_kib": kib,
                                        "bytes_per_counter_unit": scale[counter]}
     import re
-    pat = re.compile(r"sweep_kernel<(\d+),\s*(\d+),\s*(true|false),\s*(true|false),\s*(true|false)>")
+    # sweep_kernel<format, lanes per site, SR, non-temporal, out of place, accumulate g>
+    pat = re.compile(r"sweep_kernel<(\d+),\s*(\d+),\s*(true|false),\s*(true|false),\s*(true|false),"
+                     r"\s*false>")
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     for (counter, kname), vals in per.items():
         m = pat.search(kname)
@@ -208,7 +211,18 @@ def ensemble_bench(lgf, stream):
     t0 = time.perf_counter()
     st, res = lgf.lgf_ensemble_gauge_fix(e, p, len(dims))
     wall = time.perf_counter() - t0
+    # the same 48 fields fixed in plain FP64 (18-real) for the per-configuration F difference
+    for c in man:
+        lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
+    p64 = lgf.lgf_fix_params_default()
+    p64.omega, p64.theta_target = 1.7, 1e-14
+    t0 = time.perf_counter()
+    st64, res64 = lgf.lgf_ensemble_gauge_fix(e, p64, len(dims))
+    wall64 = time.perf_counter() - t0
     lgf.lgf_ensemble_destroy(e)
+    out["gauge_fix_fp64"] = {"status": int(st64), "wall_s": wall64,
+                             "all_below_1e-14": all(r["theta"] < 1e-14 for r in res64)}
+    out["max_abs_dF_mixed_vs_fp64"] = max(abs(r["F"] - q["F"]) for r, q in zip(res, res64))
     sw = [r["sweeps"] for r in res]
     out["gauge_fix_mixed"] = {"status": int(st), "wall_s": wall, "all_below_1e-14": all(
         r["theta"] < 1e-14 for r in res), "sweeps_min": min(sw), "sweeps_max": max(sw),
@@ -274,7 +288,15 @@ def coulomb_bench(lgf, stream):
     wall = time.perf_counter() - t0
     lgf.lgf_destroy(h)
     su = float(sw.sum()) * V3
+    # algorithmic bytes: every site update moves its 8 links in and out once,
+    # 48 B per link in the FP32-12 bulk (all timeslices live), 96 B in the
+    # FP64-12 finish (live timeslices only)
+    V = V3 * dims[0]
+    su_bulk = float(res["sweeps_bulk"]) * V
+    alg_bytes = su_bulk * 16 * LINK_BYTES[lgf.LGF_FP32_12] + (su - su_bulk) * 16 * LINK_BYTES[lgf.LGF_FP64_12]
+    t_sweep_s = (res["t_sweep_bulk_ms"] + res["t_sweep_finish_ms"]) / 1e3
     return {"dims": list(dims), "status": int(st), "wall_s": wall, "sweeps_total": res["sweeps"],
+            "sweep_algorithmic_GBs": alg_bytes / t_sweep_s / 1e9,
             "sweeps_bulk": res["sweeps_bulk"], "timeslice_sweeps_min": int(sw.min()),
             "timeslice_sweeps_max": int(sw.max()), "theta_max": float(th.max()),
             "site_updates": su, "site_updates_per_s": su / wall,
@@ -403,6 +425,12 @@ def main():
                           f"{' xcd-remap' if xcd else ''}",
                 "avg_launch_ms": round(dk["avg_launch_ms"], 4),
                 "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
+
+    # the streaming ceiling on this GPU: a plain one-pass device copy of 4 GiB
+    copy_gbs = lgf.lgf_copy_bandwidth(4 << 30, 10, stream)
+    roofline["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy_ceiling"] = round(dk["achieved_GBs"] / copy_gbs, 4)
+    log(f"[bench] copy ceiling {copy_gbs:.1f} GB/s; dominant kernel at {dk['achieved_GBs']:.1f} GB/s")
 
     extras = {}
     if not args.no_extras:

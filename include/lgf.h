@@ -225,7 +225,8 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site,
                           int *xcd_remap, int *nontemporal, int *schedule);
 
 /* Time the sweep variants (lanes per site, block, XCD remap, non-temporal,
- * schedule) for a format on this handle's lattice, on a scratch copy of the
+ * schedule in place or out of place; the t-slice pipeline is left to
+ * lgf_set_tuning) for a format on this handle's lattice, on a scratch copy of the
  * links (which are left untouched), and keep the fastest.  trials = timed full
  * sweeps per variant (>= 1). */
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
@@ -236,6 +237,14 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
  * stream. */
 lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed,
                            uint64_t sweep_index, double *ms_per_launch);
+
+/* The bandwidth of a plain device copy, the practical ceiling of a streaming
+ * kernel: allocates two buffers of `bytes` (a multiple of 16) on the current
+ * device, copies one into the other reps times on hip_stream (NULL = default)
+ * with one 16-byte vector per lane and non-temporal access, and returns the
+ * read + write rate *GBs = 2 * bytes * reps / time (1e9 bytes/s).  Frees the
+ * buffers before returning.  LGF_ENOMEM if they cannot be allocated. */
+lgf_status lgf_copy_bandwidth(size_t bytes, int reps, void *hip_stream, double *GBs);
 
 /* ------------------------------------------------------------------------ */
 /* Coulomb gauge.  The paper names Coulomb gauge among the supported gauges   */

@@ -1089,6 +1089,9 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         for (int bi = 0; bi < 3 && ok; ++bi)
             for (int v = 0; v < 12 && ok; ++v) {
                 const int xcd = v & 1, nt = (v >> 1) & 1, sched = v >> 2;
+                // the t-slice pipeline is measured slower at every size it was
+                // tried on; it stays a manual option (lgf_set_tuning)
+                if (sched == lgf::kSchedulePipeline) continue;
                 if (sched == lgf::kScheduleOutOfPlace && (!nt || !can_oop)) continue;
                 Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched}, 0.0};
                 ok = time_variant(c.t, &c.ms);

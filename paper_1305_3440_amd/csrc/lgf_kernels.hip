@@ -33,7 +33,7 @@ size_t link_bytes(int format)
 // Relaxation sweep
 // ----------------------------------------------------------------------------
 
-template <int F, int LPS, bool SR, bool NT, bool OOP = false>
+template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      RelaxArgs<typename Fmt<F>::T> a, int xcd_remap,
                                                      uint32_t n_blocks, uint32_t h_begin, uint32_t h_end,
@@ -52,8 +52,17 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
     const uint32_t grp = h_begin + tid / LPS;
     const int lane = (int)(tid % LPS);
     const bool active = grp < h_end;
-    update_site<F, LPS, SR, NT, 0, OOP>(field, g, parity, active ? grp : h_end - 1, lane, active, a, nullptr,
-                                        out_field);
+    update_site<F, LPS, SR, NT, 0, OOP, ACC>(field, g, parity, active ? grp : h_end - 1, lane, active, a, nullptr,
+                                             out_field);
+}
+
+template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
+static void launch_sweep_kernel(dim3 grid, int block, hipStream_t s, void *field, const Geom &g, int parity,
+                                const RelaxArgs<typename Fmt<F>::T> &ra, int xcd_remap, uint32_t nb,
+                                uint32_t h_begin, uint32_t h_end, void *out)
+{
+    hipLaunchKernelGGL((sweep_kernel<F, LPS, SR, NT, OOP, ACC>), grid, dim3(block), 0, s, field, g, parity, ra,
+                       xcd_remap, nb, h_begin, h_end, out);
 }
 
 template <int F, int LPS, bool NT, bool OOP>
@@ -68,13 +77,26 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     const uint32_t grid = t.xcd_remap ? ((nb + 7u) / 8u) * 8u : nb;
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
                     (uint32_t)a.sweep_index, a.instance, a.gacc};
-    if (a.p_sr > 0.0) {
-        ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, true, NT, OOP>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end, a.out);
+    const bool sr = a.p_sr > 0.0;
+    if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+    if (a.gacc) {
+        // the accumulated gauge transformation belongs to the FP32 bulk only
+        if constexpr (F == kF32_12 || F == kF32_18) {
+            if (sr)
+                launch_sweep_kernel<F, LPS, true, NT, OOP, true>(grid, t.block, s, field, g, a.parity, ra,
+                                                                 t.xcd_remap, nb, h_begin, h_end, a.out);
+            else
+                launch_sweep_kernel<F, LPS, false, NT, OOP, true>(grid, t.block, s, field, g, a.parity, ra,
+                                                                  t.xcd_remap, nb, h_begin, h_end, a.out);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (sr) {
+        launch_sweep_kernel<F, LPS, true, NT, OOP, false>(grid, t.block, s, field, g, a.parity, ra, t.xcd_remap,
+                                                          nb, h_begin, h_end, a.out);
     } else {
-        hipLaunchKernelGGL((sweep_kernel<F, LPS, false, NT, OOP>), dim3(grid), dim3(t.block), 0, s, field, g,
-                           a.parity, ra, t.xcd_remap, nb, h_begin, h_end, a.out);
+        launch_sweep_kernel<F, LPS, false, NT, OOP, false>(grid, t.block, s, field, g, a.parity, ra, t.xcd_remap,
+                                                           nb, h_begin, h_end, a.out);
     }
     return hipGetLastError();
 }

@@ -88,7 +88,9 @@ __device__ __forceinline__ typename Fmt<F>::V *site_field_ptr(void *field, uint3
 // OOP: the updated links go to out_field instead of back into field (every
 // link has one end of each parity, so one half-sweep writes every link of
 // out_field exactly once and the next half-sweep reads them from there).
-template <int F, int LPS, bool SR, bool NT, int MU0 = 0, bool OOP = false>
+// ACC: also g(x) <- G g(x) in the site field a.gacc (the accumulated gauge
+// transformation of the mixed-precision bulk).
+template <int F, int LPS, bool SR, bool NT, int MU0 = 0, bool OOP = false, bool ACC = false>
 __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
                                             int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a,
                                             const uint8_t *__restrict__ slice_active = nullptr,
@@ -99,7 +101,12 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
     using T = typename S::T;
     constexpr int NL = 4 / LPS;  // directions handled per lane
     const Site c = decode(g, parity, h);
-    if (slice_active) active = active && slice_active[c.t];
+    if (slice_active) {
+        // a frozen timeslice is neither read nor written; with one lane per
+        // site no other lane waits on this one
+        if (LPS == 1 && !slice_active[c.t]) return;
+        active = active && slice_active[c.t];
+    }
 
     mat3<T> uf[NL], ub[NL];
     uint32_t hb[NL];
@@ -142,12 +149,14 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
     su2_step<1, 2, false>(K, G, a.omega, orl, sq2);
 
     if (!active) return;
-    if (a.gacc && lane == 0) {
-        // g(x) <- G g(x): the product of every update applied to this site
-        mat3<T> gx, r;
-        load_link<F>(gx, site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h);
-        left_mul<S::R>(r, G, gx);
-        store_link<F>(site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h, r);
+    if constexpr (ACC) {
+        if (lane == 0) {
+            // g(x) <- G g(x): the product of every update applied to this site
+            mat3<T> gx, r;
+            load_link<F>(gx, site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h);
+            left_mul<S::R>(r, G, gx);
+            store_link<F>(site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h, r);
+        }
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {

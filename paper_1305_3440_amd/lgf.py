@@ -55,7 +55,7 @@ EXPORTS = [
     "lgf_destroy", "lgf_get_info", "lgf_load_links", "lgf_store_links", "lgf_peek_links",
     "lgf_generate_links", "lgf_convert", "lgf_sweep", "lgf_reunitarize", "lgf_measure",
     "lgf_gauge_fix", "lgf_synchronize", "lgf_set_tuning", "lgf_get_tuning", "lgf_autotune",
-    "lgf_time_sweeps",
+    "lgf_time_sweeps", "lgf_copy_bandwidth",
 ]
 
 _lib = None
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "lgf_get_tuning": (I, [P, I, P, P, P, P, P]),
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
+        "lgf_copy_bandwidth": (I, [SZ, I, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -252,6 +253,13 @@ def lgf_time_sweeps(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0,
     ms = ctypes.c_double()
     _check(load_library().lgf_time_sweeps(h, n, omega, p_sr, seed, sweep_index, ctypes.byref(ms)))
     return ms.value
+
+
+def lgf_copy_bandwidth(nbytes: int, reps: int = 10, stream=None) -> float:
+    """Read + write GB/s of a plain device copy of nbytes (the streaming ceiling)."""
+    gbs = ctypes.c_double()
+    _check(load_library().lgf_copy_bandwidth(nbytes, reps, _ptr_of(stream), ctypes.byref(gbs)))
+    return gbs.value
 
 
 class Lattice:

@@ -96,6 +96,16 @@ def test_null_handles(lgf):
     assert lib.lgf_gauge_fix(None, None, None, None, 0) == lgf.LGF_EINVAL
 
 
+def test_copy_bandwidth_rejects_bad_arguments_without_gpu(lgf):
+    import ctypes
+    lib = lgf.load_library()
+    out = ctypes.c_double()
+    assert lib.lgf_copy_bandwidth(0, 1, None, ctypes.byref(out)) == lgf.LGF_EINVAL
+    assert lib.lgf_copy_bandwidth(17, 1, None, ctypes.byref(out)) == lgf.LGF_EINVAL
+    assert lib.lgf_copy_bandwidth(1 << 20, 0, None, ctypes.byref(out)) == lgf.LGF_EINVAL
+    assert lib.lgf_copy_bandwidth(1 << 20, 1, None, None) == lgf.LGF_EINVAL
+
+
 def test_fix_params_default(lgf):
     p = lgf.lgf_fix_params_default()
     assert p.omega == 1.7 and p.p_sr == 0.0 and p.theta_target == 1e-14

@@ -488,3 +488,10 @@ def test_accumulated_gauge_keeps_the_orbit(lgf, orc):
         assert unitarity_error(got) < 1e-12
         with pytest.raises(lgf.LgfError):
             lat.gauge_fix(omega=1.7, accumulate_g=1)   # no FP32 bulk: rejected
+
+
+def test_copy_bandwidth(lgf):
+    """The copy-ceiling utility runs and reports a plausible HBM rate."""
+    announce("copy bandwidth")
+    gbs = lgf.lgf_copy_bandwidth(256 << 20, 4)
+    assert 500.0 < gbs < 10000.0
