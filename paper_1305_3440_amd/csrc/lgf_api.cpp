@@ -1062,18 +1062,18 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     const bool had_partner = h->partner[format] != nullptr;
     const bool can_oop = ensure_partner(h, format) == LGF_OK;
     lgf_status st = LGF_OK;
-    // time `trials` full sweeps of one variant after one untimed full sweep
-    auto time_variant = [&](const lgf::SweepTuning &t, double *ms) {
+    // time n full sweeps of one variant after one untimed full sweep
+    auto time_variant = [&](const lgf::SweepTuning &t, int n, double *ms) {
         h->tune[format] = t;
         st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
         if (st != LGF_OK) return false;
         e = hipEventRecord(h->ev0, h->stream);
-        for (int k = 0; k < trials && e == hipSuccess && st == LGF_OK; ++k)
+        for (int k = 0; k < n && e == hipSuccess && st == LGF_OK; ++k)
             st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
         if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
         if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
         if (e != hipSuccess || st != LGF_OK) return false;
-        *ms = elapsed_ms(h->ev0, h->ev1) / trials;
+        *ms = elapsed_ms(h->ev0, h->ev1) / n;
         return true;
     };
     // stage 1: every variant once
@@ -1094,12 +1094,13 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
                 if (sched == lgf::kSchedulePipeline) continue;
                 if (sched == lgf::kScheduleOutOfPlace && (!nt || !can_oop)) continue;
                 Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched}, 0.0};
-                ok = time_variant(c.t, &c.ms);
+                ok = time_variant(c.t, trials, &c.ms);
                 if (ok) cands.push_back(c);
             }
-    // stage 2: the four fastest and the default, timed again in three
-    // interleaved rounds; the smallest median wins (single timings of
-    // variants a few per cent apart are within the run-to-run noise)
+    // stage 2: the four fastest and the default, timed again over three times
+    // as many sweeps in five interleaved rounds; the smallest median wins
+    // (single short timings of variants a few per cent apart are within the
+    // run-to-run noise)
     lgf::SweepTuning best = saved;
     if (ok) {
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
@@ -1113,18 +1114,19 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
                                             t.schedule == dflt.schedule);
         if (!have_default) finals.push_back(dflt);
         std::vector<std::vector<double>> ms(finals.size());
-        for (int round = 0; round < 3 && ok; ++round)
+        const int n2 = std::max(3 * trials, 6);
+        for (int round = 0; round < 5 && ok; ++round)
             for (size_t i = 0; i < finals.size() && ok; ++i) {
                 double m = 0.0;
-                ok = time_variant(finals[i], &m);
+                ok = time_variant(finals[i], n2, &m);
                 ms[i].push_back(m);
             }
         if (ok) {
             double best_ms = 1e300;
             for (size_t i = 0; i < finals.size(); ++i) {
                 std::sort(ms[i].begin(), ms[i].end());
-                if (ms[i][1] < best_ms) {
-                    best_ms = ms[i][1];
+                if (ms[i][2] < best_ms) {
+                    best_ms = ms[i][2];
                     best = finals[i];
                 }
             }
