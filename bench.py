@@ -414,7 +414,7 @@ def main():
     dk = kernels[dom]
     dfmt = bulk if dom == "sweep_fp32_12" else finish
     fmt_name = lgf.FORMAT_NAMES[dfmt]
-    lanes, block, xcd, nt, sched = tuning[dfmt]
+    lanes, block, xcd, nt, sched, spt = tuning[dfmt]
     traffic = measured_traffic(traffic_key(dfmt, lanes, nt, sched, dims))
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
@@ -422,7 +422,7 @@ def main():
                 "kernel": f"sweep_kernel<{fmt_name}, lanes/site {lanes}, "
                           f"{'non-temporal' if nt else 'cached'}, "
                           f"{['in place', 't-slice pipeline', 'out of place'][sched]}> block {block}"
-                          f"{' xcd-remap' if xcd else ''}",
+                          f", {spt} tile(s) per workgroup{', xcd-remap' if xcd else ''}",
                 "avg_launch_ms": round(dk["avg_launch_ms"], 4),
                 "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
 
@@ -504,9 +504,8 @@ def main():
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
                    "sweeps_per_step": [r["sweeps"] for r in results],
-                   "sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(
-                       ("lanes_per_site", "block", "xcd_remap", "nontemporal", "schedule"), t))
-                       for f, t in tuning.items()}},
+                   "sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, t))
+                                    for f, t in tuning.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

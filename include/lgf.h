@@ -206,9 +206,11 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_r
 /* Block until all work queued on the handle's stream has finished. */
 lgf_status lgf_synchronize(lgf_lattice *h);
 
-/* Kernel tuning of a handle, per storage format: lanes_per_site in {1, 2, 4}
- * (lanes that share one site update), block (threads per workgroup: 64, 128
- * or 256), xcd_remap (0/1: give each XCD a contiguous range of workgroups),
+/* Kernel tuning of a handle, per storage format (the autotuner sets it too):
+ * lanes_per_site in {1, 2, 4} (lanes that share one site update),
+ * sites_per_thread in {1, 2, 4} (tiles of `block` lanes per workgroup,
+ * strided over the launch), block (threads per workgroup: 64, 128 or 256),
+ * xcd_remap (0/1: give each XCD a contiguous range of workgroups),
  * nontemporal (0/1: stream the links past the caches), schedule of a full
  * sweep: 0 = parity 0 then parity 1, each updating the links in place;
  * 1 = t-slice pipeline, parity 1 of slice k-1 right after parity 0 of slice k,
@@ -217,12 +219,20 @@ lgf_status lgf_synchronize(lgf_lattice *h);
  * second buffer of the same size, parity 1 writes them back (needs
  * nontemporal = 1; the library allocates the buffer here, LGF_ENOMEM if it
  * cannot).  Every schedule gives bit-identical links; single half-sweeps
- * (lgf_sweep with parity 0 or 1) always run in place.  lgf_get_tuning reads
- * the current values (any output pointer may be NULL). */
-lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block,
-                          int xcd_remap, int nontemporal, int schedule);
-lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block,
-                          int *xcd_remap, int *nontemporal, int *schedule);
+ * (lgf_sweep with parity 0 or 1) always run in place.  lgf_set_tuning copies
+ * *tuning (LGF_EINVAL on a value outside these sets); lgf_get_tuning fills
+ * *tuning with the current values. */
+typedef struct {
+    int lanes_per_site;
+    int sites_per_thread;
+    int block;
+    int xcd_remap;
+    int nontemporal;
+    int schedule;
+} lgf_sweep_tuning;
+
+lgf_status lgf_set_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
+lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
 
 /* Time the sweep variants (lanes per site, block, XCD remap, non-temporal,
  * schedule in place or out of place; the t-slice pipeline is left to

@@ -335,9 +335,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
             g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active &&
-            g.tune.lanes_per_site == t.lanes_per_site && g.tune.block == t.block &&
-            g.tune.xcd_remap == t.xcd_remap && g.tune.nontemporal == t.nontemporal &&
-            g.tune.schedule == t.schedule) {
+            g.tune == t) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
         }
@@ -1008,38 +1006,42 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     return LGF_OK;
 }
 
-lgf_status lgf_set_tuning(lgf_lattice *h, int format, int lanes_per_site, int block, int xcd_remap,
-                          int nontemporal, int schedule)
+lgf_status lgf_set_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *t)
 {
-    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
-    if (lanes_per_site != 1 && lanes_per_site != 2 && lanes_per_site != 4)
+    const lgf_sweep_tuning u = *t;
+    if (u.lanes_per_site != 1 && u.lanes_per_site != 2 && u.lanes_per_site != 4)
         return fail(LGF_EINVAL, "lanes_per_site must be 1, 2 or 4");
-    if (block != 64 && block != 128 && block != 256)
+    if (u.sites_per_thread != 1 && u.sites_per_thread != 2 && u.sites_per_thread != 4)
+        return fail(LGF_EINVAL, "sites_per_thread must be 1, 2 or 4");
+    if (u.block != 64 && u.block != 128 && u.block != 256)
         return fail(LGF_EINVAL, "block must be 64, 128 or 256");
-    if (schedule < lgf::kScheduleInPlace || schedule > lgf::kScheduleOutOfPlace)
+    if (u.schedule < lgf::kScheduleInPlace || u.schedule > lgf::kScheduleOutOfPlace)
         return fail(LGF_EINVAL, "schedule must be 0 (in place), 1 (t-slice pipeline) or 2 (out of place)");
-    if (schedule == lgf::kScheduleOutOfPlace && !nontemporal)
+    if (u.schedule == lgf::kScheduleOutOfPlace && !u.nontemporal)
         return fail(LGF_EINVAL, "the out-of-place schedule needs nontemporal = 1");
-    if (schedule == lgf::kScheduleOutOfPlace) {
+    if (u.schedule == lgf::kScheduleOutOfPlace) {
         LGF_TRY(use_device(h));
         LGF_TRY(ensure_partner(h, format));
     }
-    h->tune[format] = lgf::SweepTuning{lanes_per_site, block, xcd_remap ? 1 : 0, nontemporal ? 1 : 0, schedule};
+    h->tune[format] = lgf::SweepTuning{u.lanes_per_site, u.block,      u.xcd_remap ? 1 : 0, u.nontemporal ? 1 : 0,
+                                       u.schedule,       u.sites_per_thread};
     drop_graphs(h);
     return LGF_OK;
 }
 
-lgf_status lgf_get_tuning(const lgf_lattice *h, int format, int *lanes_per_site, int *block, int *xcd_remap,
-                          int *nontemporal, int *schedule)
+lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *t)
 {
-    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
-    if (lanes_per_site) *lanes_per_site = h->tune[format].lanes_per_site;
-    if (block) *block = h->tune[format].block;
-    if (xcd_remap) *xcd_remap = h->tune[format].xcd_remap;
-    if (nontemporal) *nontemporal = h->tune[format].nontemporal;
-    if (schedule) *schedule = h->tune[format].schedule;
+    const lgf::SweepTuning &u = h->tune[format];
+    t->lanes_per_site = u.lanes_per_site;
+    t->sites_per_thread = u.sites_per_thread;
+    t->block = u.block;
+    t->xcd_remap = u.xcd_remap;
+    t->nontemporal = u.nontemporal;
+    t->schedule = u.schedule;
     return LGF_OK;
 }
 
@@ -1087,13 +1089,14 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     bool ok = (e == hipSuccess);
     for (int li = 0; li < 3 && ok; ++li)
         for (int bi = 0; bi < 3 && ok; ++bi)
-            for (int v = 0; v < 12 && ok; ++v) {
-                const int xcd = v & 1, nt = (v >> 1) & 1, sched = v >> 2;
+            for (int v = 0; v < 48 && ok; ++v) {
+                const int xcd = v & 1, nt = (v >> 1) & 1, sched = (v >> 2) % 3, spt = 1 << (v / 12);
                 // the t-slice pipeline is measured slower at every size it was
                 // tried on; it stays a manual option (lgf_set_tuning)
-                if (sched == lgf::kSchedulePipeline) continue;
+                if (sched == lgf::kSchedulePipeline || spt > 4) continue;
                 if (sched == lgf::kScheduleOutOfPlace && (!nt || !can_oop)) continue;
-                Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched}, 0.0};
+                if (spt > 1 && xcd) continue;
+                Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched, spt}, 0.0};
                 ok = time_variant(c.t, trials, &c.ms);
                 if (ok) cands.push_back(c);
             }
@@ -1109,9 +1112,7 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         const lgf::SweepTuning dflt{};
         bool have_default = false;
         for (const auto &t : finals)
-            have_default = have_default || (t.lanes_per_site == dflt.lanes_per_site && t.block == dflt.block &&
-                                            t.xcd_remap == dflt.xcd_remap && t.nontemporal == dflt.nontemporal &&
-                                            t.schedule == dflt.schedule);
+            have_default = have_default || t == dflt;
         if (!have_default) finals.push_back(dflt);
         std::vector<std::vector<double>> ms(finals.size());
         const int n2 = std::max(3 * trials, 6);

@@ -21,9 +21,16 @@ struct SweepTuning {
     int schedule = 0;        // full sweeps: 0 two in-place launches, 1 t-slice pipeline
                              // (parity 1 one slice behind), 2 out of place (ping-pong
                              // between the field and a second buffer of its format)
+    int sites_per_thread = 1;  // tiles per workgroup (1, 2 or 4), strided over the launch
 };
 
 constexpr int kScheduleInPlace = 0, kSchedulePipeline = 1, kScheduleOutOfPlace = 2;
+
+inline bool operator==(const SweepTuning &a, const SweepTuning &b)
+{
+    return a.lanes_per_site == b.lanes_per_site && a.block == b.block && a.xcd_remap == b.xcd_remap &&
+           a.nontemporal == b.nontemporal && a.schedule == b.schedule && a.sites_per_thread == b.sites_per_thread;
+}
 
 struct SweepArgs {
     int parity;

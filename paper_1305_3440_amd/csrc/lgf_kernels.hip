@@ -33,36 +33,45 @@ size_t link_bytes(int format)
 // Relaxation sweep
 // ----------------------------------------------------------------------------
 
+// One half-sweep: the sites [h_begin, h_end) of one parity, LPS lanes per
+// site, cut into n_tiles tiles of blockDim.x lanes.  Workgroup b takes the
+// tiles b, b + n_groups, b + 2 n_groups, ... (spt of them at most), so the
+// workgroups in flight always cover neighbouring tiles.
 template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      RelaxArgs<typename Fmt<F>::T> a, int xcd_remap,
-                                                     uint32_t n_blocks, uint32_t h_begin, uint32_t h_end,
+                                                     uint32_t n_groups, uint32_t n_tiles, uint32_t spt,
+                                                     uint32_t h_begin, uint32_t h_end,
                                                      void *__restrict__ out_field)
 {
     uint32_t b = blockIdx.x;
     if (xcd_remap) {
         // workgroups are dealt to the 8 XCDs round-robin; give XCD k the
-        // contiguous range [k*per, (k+1)*per) of tiles so that neighbouring
-        // tiles share its L2
+        // contiguous range [k*per, (k+1)*per) of workgroups so that
+        // neighbouring tiles share its L2
         const uint32_t per = gridDim.x >> 3;
         b = (b & 7u) * per + (b >> 3);
-        if (b >= n_blocks) return;
+        if (b >= n_groups) return;
     }
-    const uint32_t tid = b * blockDim.x + threadIdx.x;
-    const uint32_t grp = h_begin + tid / LPS;
-    const int lane = (int)(tid % LPS);
-    const bool active = grp < h_end;
-    update_site<F, LPS, SR, NT, 0, OOP, ACC>(field, g, parity, active ? grp : h_end - 1, lane, active, a, nullptr,
-                                             out_field);
+    for (uint32_t k = 0; k < spt; ++k) {
+        const uint32_t tile = b + k * n_groups;
+        if (tile >= n_tiles) return;
+        const uint64_t tid = (uint64_t)tile * blockDim.x + threadIdx.x;
+        const uint32_t grp = h_begin + (uint32_t)(tid / LPS);
+        const int lane = (int)(tid % LPS);
+        const bool active = grp < h_end;
+        update_site<F, LPS, SR, NT, 0, OOP, ACC>(field, g, parity, active ? grp : h_end - 1, lane, active, a,
+                                                 nullptr, out_field);
+    }
 }
 
 template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
 static void launch_sweep_kernel(dim3 grid, int block, hipStream_t s, void *field, const Geom &g, int parity,
-                                const RelaxArgs<typename Fmt<F>::T> &ra, int xcd_remap, uint32_t nb,
-                                uint32_t h_begin, uint32_t h_end, void *out)
+                                const RelaxArgs<typename Fmt<F>::T> &ra, int xcd_remap, uint32_t n_groups,
+                                uint32_t n_tiles, uint32_t spt, uint32_t h_begin, uint32_t h_end, void *out)
 {
     hipLaunchKernelGGL((sweep_kernel<F, LPS, SR, NT, OOP, ACC>), grid, dim3(block), 0, s, field, g, parity, ra,
-                       xcd_remap, nb, h_begin, h_end, out);
+                       xcd_remap, n_groups, n_tiles, spt, h_begin, h_end, out);
 }
 
 template <int F, int LPS, bool NT, bool OOP>
@@ -73,8 +82,10 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     using T = typename Fmt<F>::T;
     const uint32_t h_begin = a.h_end ? a.h_begin : 0, h_end = a.h_end ? a.h_end : g.Vh;
     const uint64_t threads = (uint64_t)(h_end - h_begin) * LPS;
-    const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);
-    const uint32_t grid = t.xcd_remap ? ((nb + 7u) / 8u) * 8u : nb;
+    const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);          // tiles
+    const uint32_t spt = (uint32_t)(t.sites_per_thread > 1 ? t.sites_per_thread : 1);
+    const uint32_t ng = (nb + spt - 1) / spt;                                     // workgroups
+    const uint32_t grid = t.xcd_remap ? ((ng + 7u) / 8u) * 8u : ng;
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
                     (uint32_t)a.sweep_index, a.instance, a.gacc};
     const bool sr = a.p_sr > 0.0;
@@ -84,19 +95,19 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
         if constexpr (F == kF32_12 || F == kF32_18) {
             if (sr)
                 launch_sweep_kernel<F, LPS, true, NT, OOP, true>(grid, t.block, s, field, g, a.parity, ra,
-                                                                 t.xcd_remap, nb, h_begin, h_end, a.out);
+                                                                 t.xcd_remap, ng, nb, spt, h_begin, h_end, a.out);
             else
                 launch_sweep_kernel<F, LPS, false, NT, OOP, true>(grid, t.block, s, field, g, a.parity, ra,
-                                                                  t.xcd_remap, nb, h_begin, h_end, a.out);
+                                                                  t.xcd_remap, ng, nb, spt, h_begin, h_end, a.out);
         } else {
             return hipErrorInvalidValue;
         }
     } else if (sr) {
         launch_sweep_kernel<F, LPS, true, NT, OOP, false>(grid, t.block, s, field, g, a.parity, ra, t.xcd_remap,
-                                                          nb, h_begin, h_end, a.out);
+                                                          ng, nb, spt, h_begin, h_end, a.out);
     } else {
         launch_sweep_kernel<F, LPS, false, NT, OOP, false>(grid, t.block, s, field, g, a.parity, ra, t.xcd_remap,
-                                                           nb, h_begin, h_end, a.out);
+                                                           ng, nb, spt, h_begin, h_end, a.out);
     }
     return hipGetLastError();
 }

@@ -89,8 +89,8 @@ def load_library(path: str = LIB_PATH):
         "lgf_measure": (I, [P, P, P]),
         "lgf_gauge_fix": (I, [P, P, P, P, I]),
         "lgf_synchronize": (I, [P]),
-        "lgf_set_tuning": (I, [P, I, I, I, I, I, I]),
-        "lgf_get_tuning": (I, [P, I, P, P, P, P, P]),
+        "lgf_set_tuning": (I, [P, I, P]),
+        "lgf_get_tuning": (I, [P, I, P]),
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
         "lgf_copy_bandwidth": (I, [SZ, I, P, P]),
@@ -232,16 +232,26 @@ def lgf_synchronize(h) -> None:
     _check(load_library().lgf_synchronize(h))
 
 
+class lgf_sweep_tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_site", ctypes.c_int), ("sites_per_thread", ctypes.c_int), ("block", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int), ("nontemporal", ctypes.c_int), ("schedule", ctypes.c_int)]
+
+
+TUNING_FIELDS = ("lanes_per_site", "block", "xcd_remap", "nontemporal", "schedule", "sites_per_thread")
+
+
 def lgf_set_tuning(h, fmt: int, lanes_per_site: int, block: int, xcd_remap: int = 0,
-                   nontemporal: int = 1, schedule: int = 0) -> None:
-    _check(load_library().lgf_set_tuning(h, fmt, lanes_per_site, block, xcd_remap, nontemporal, schedule))
+                   nontemporal: int = 1, schedule: int = 0, sites_per_thread: int = 1) -> None:
+    t = lgf_sweep_tuning(lanes_per_site=lanes_per_site, sites_per_thread=sites_per_thread, block=block,
+                         xcd_remap=xcd_remap, nontemporal=nontemporal, schedule=schedule)
+    _check(load_library().lgf_set_tuning(h, fmt, ctypes.byref(t)))
 
 
 def lgf_get_tuning(h, fmt: int):
-    """(lanes_per_site, block, xcd_remap, nontemporal, schedule)"""
-    v = [ctypes.c_int() for _ in range(5)]
-    _check(load_library().lgf_get_tuning(h, fmt, *[ctypes.byref(x) for x in v]))
-    return tuple(x.value for x in v)
+    """(lanes_per_site, block, xcd_remap, nontemporal, schedule, sites_per_thread)"""
+    t = lgf_sweep_tuning()
+    _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(t)))
+    return tuple(getattr(t, k) for k in TUNING_FIELDS)
 
 
 def lgf_autotune(h, fmt: int, trials: int = 4) -> None:

@@ -44,18 +44,21 @@ def test_library_exports_every_declared_symbol(lgf):
 def test_struct_layouts_match_header(lgf):
     """The ctypes mirrors have the C structs' sizes (checked by compiling a
     probe against the header)."""
-    src = ('#include "lgf.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu\\n",'
-           ' sizeof(lgf_fix_params), sizeof(lgf_fix_result));return 0;}\n')
+    src = ('#include "lgf.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
+           'printf("%zu %zu %zu %zu\\n", sizeof(lgf_fix_params), sizeof(lgf_fix_result),'
+           ' sizeof(lgf_sweep_tuning), offsetof(lgf_sweep_tuning, schedule));return 0;}\n')
     import tempfile
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "probe.c")
         exe = os.path.join(d, "probe")
         open(c, "w").write(src)
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
-        a, b = (int(x) for x in subprocess.run([exe], capture_output=True, text=True,
-                                               check=True).stdout.split())
+        a, b, c, d = (int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                                     check=True).stdout.split())
     assert ctypes.sizeof(lgf.lgf_fix_params) == a
     assert ctypes.sizeof(lgf.lgf_fix_result) == b
+    assert ctypes.sizeof(lgf.lgf_sweep_tuning) == c
+    assert lgf.lgf_sweep_tuning.schedule.offset == d
 
 
 def test_required_bytes(lgf):

@@ -124,9 +124,10 @@ def gpu_input(lgf, dims, fmt, U):
 
 
 # (lanes per site, block, XCD remap, non-temporal, schedule: 0 in place,
-# 1 t-slice pipeline, 2 out of place)
+# 1 t-slice pipeline, 2 out of place[, sites per thread])
 TUNINGS = [(1, 128, 0, 1, 0), (2, 128, 1, 1, 1), (4, 64, 0, 1, 0), (4, 256, 1, 0, 1), (1, 64, 1, 1, 1),
-           (2, 256, 0, 0, 0), (1, 128, 0, 1, 1), (1, 128, 0, 1, 2), (2, 64, 1, 1, 2), (4, 256, 0, 1, 2)]
+           (2, 256, 0, 0, 0), (1, 128, 0, 1, 1), (1, 128, 0, 1, 2), (2, 64, 1, 1, 2), (4, 256, 0, 1, 2),
+           (1, 128, 0, 1, 0, 2), (2, 64, 1, 1, 2, 4), (4, 64, 0, 0, 0, 2), (1, 64, 1, 1, 0, 4)]
 
 
 @pytest.mark.parametrize("fmt", ALL_FORMATS)
