@@ -184,6 +184,9 @@ def ensemble_bench(lgf, stream):
     e = lgf.lgf_ensemble_create(dims, lgf.LGF_FP64_18, stream)
     for c in man:
         lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
+    # tile width, persistent grid and non-temporal access picked on scratch copies
+    lgf.lgf_ensemble_autotune(e, lgf.LGF_FP32_12, 2)
+    out["tuning"] = dict(zip(("tile", "grid_mult", "nontemporal"), lgf.lgf_ensemble_get_tuning(e)))
     for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
         lgf.lgf_ensemble_time_sweeps(e, fmt, 20, 1.7)
         ms = lgf.lgf_ensemble_time_sweeps(e, fmt, 40, 1.7)

@@ -335,6 +335,17 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
 lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
                                     double *ms_per_launch);
 
+/* Tuning of the persistent ensemble launches: tile = sites per work-list tile
+ * and lanes per workgroup (64, 128 or 256), grid_mult = persistent workgroups
+ * as a multiple (1, 2 or 4) of what fits on the GPU at once, nontemporal
+ * (0/1) link access.  Results do not depend on it.  lgf_ensemble_autotune
+ * times the 12 variants for `format` on scratch copies of the links (trials =
+ * timed full sweeps per variant, >= 1), re-times the fastest, and keeps the
+ * winner; the links are untouched. */
+lgf_status lgf_ensemble_set_tuning(lgf_ensemble *e, int tile, int grid_mult, int nontemporal);
+lgf_status lgf_ensemble_get_tuning(const lgf_ensemble *e, int *tile, int *grid_mult, int *nontemporal);
+lgf_status lgf_ensemble_autotune(lgf_ensemble *e, int format, int trials);
+
 #ifdef __cplusplus
 }
 #endif

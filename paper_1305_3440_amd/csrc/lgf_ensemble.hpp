@@ -9,7 +9,9 @@
 
 namespace lgf {
 
-constexpr int kEnsTile = 128;  // sites per tile (one workgroup of one lane per site)
+constexpr int kEnsTile = 128;     // default sites per tile (one workgroup of one lane per site)
+constexpr int kEnsMinTile = 64;   // smallest tile width (sizes the work-list buffers)
+constexpr int kEnsMaxTile = 256;  // largest tile width (the kernels' launch bound)
 
 struct EnsCfg {         // one configuration as the kernels see it
     Geom g;
@@ -18,7 +20,7 @@ struct EnsCfg {         // one configuration as the kernels see it
     uint32_t instance;  // the configuration's index: third word of the SR counter
 };
 
-struct EnsTile {        // 128 consecutive half indices of one configuration
+struct EnsTile {        // `tile` consecutive half indices of one configuration
     uint32_t cfg;
     uint32_t h0;
 };
@@ -43,6 +45,7 @@ struct EnsLaunch {      // device pointers of one ensemble's work list
     const uint32_t *n_tiles;
     const uint64_t *sweep_base;
     uint32_t grid;      // persistent workgroups
+    uint32_t tile;      // sites per tile = lanes per workgroup (64, 128 or 256)
 };
 
 hipError_t launch_ensemble_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
@@ -51,8 +54,9 @@ hipError_t launch_ensemble_measure(int fa, int fb, const EnsLaunch &L, uint32_t 
                                    bool reunit_fwd, bool reunit_bwd, double *partials, hipStream_t s);
 hipError_t launch_ensemble_finish(const double *partials, uint32_t n_tiles, const EnsSpan *spans,
                                   uint32_t n_spans, double *out, hipStream_t s);
-// workgroups that fill every CU for the sweep kernel of a format pair
-int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt);
+// workgroups of `tile` lanes that fill every CU for the sweep kernel of a
+// format pair, times grid_mult
+int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt, int tile, int grid_mult);
 // *p = v, as a one-lane kernel on the stream (safe inside a captured graph)
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 

@@ -4,6 +4,7 @@
 // captured sweep chunks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -26,6 +27,7 @@ struct EnsGraph {
     int n_sweeps;
     double omega;
     bool nt;
+    int tile, grid_mult;
     hipGraphExec_t exec;
 };
 
@@ -61,7 +63,15 @@ struct lgf_ensemble {
     lgf::EnsSpan *h_spans = nullptr;
     double *h_out = nullptr;
     uint32_t max_tiles = 0;
+    // tuning: sites per tile (= lanes per workgroup), persistent workgroups
+    // per CU as a multiple of the occupancy limit, non-temporal link access
+    int tile = lgf::kEnsTile;
+    int grid_mult = 1;
     int nontemporal = 0;
+    // during a timing or tuning call: the fields of format scratch_fmt live in scratch
+    void *scratch = nullptr;
+    int scratch_fmt = -1;
+    std::vector<size_t> scratch_off;
     std::vector<EnsGraph> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -78,6 +88,7 @@ lgf_status ens_use_device(const lgf_ensemble *e)
 
 void *field_of(lgf_ensemble *e, int fmt, int i)
 {
+    if (fmt == e->scratch_fmt) return (char *)e->scratch + e->scratch_off[i];
     if (fmt == e->format) return (char *)e->home + e->home_off[i];
     return (char *)e->work[fmt] + e->work_off[fmt][i];
 }
@@ -119,9 +130,10 @@ uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::v
         e->h_cfgs[i].field = field_of(e, fmt_of[i], i);
         e->h_cfgs[i].instance = (uint32_t)i;
         if (!include_done && phase[i] == kDone) continue;
-        const uint32_t tiles = (e->geom[i].Vh + lgf::kEnsTile - 1) / lgf::kEnsTile;
+        const uint32_t w = (uint32_t)e->tile;
+        const uint32_t tiles = (e->geom[i].Vh + w - 1) / w;
         e->h_spans[listed.size()] = lgf::EnsSpan{(uint32_t)i, nt, tiles, (double)e->V[i]};
-        for (uint32_t t = 0; t < tiles; ++t) e->h_tiles[nt + t] = lgf::EnsTile{(uint32_t)i, t * (uint32_t)lgf::kEnsTile};
+        for (uint32_t t = 0; t < tiles; ++t) e->h_tiles[nt + t] = lgf::EnsTile{(uint32_t)i, t * w};
         nt += tiles;
         listed.push_back(i);
     }
@@ -142,7 +154,9 @@ lgf_status upload_work(lgf_ensemble *e, uint32_t nt, size_t n_spans)
 lgf::EnsLaunch launch_desc(lgf_ensemble *e, int fa, int fb, bool sr)
 {
     return lgf::EnsLaunch{e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base,
-                          (uint32_t)lgf::ensemble_persistent_grid(fa, fb, sr, e->nontemporal != 0)};
+                          (uint32_t)lgf::ensemble_persistent_grid(fa, fb, sr, e->nontemporal != 0, e->tile,
+                                                                  e->grid_mult),
+                          (uint32_t)e->tile};
 }
 
 lgf::EnsRelax relax_args(double omega, double p_sr, uint64_t seed)
@@ -172,7 +186,8 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         return LGF_OK;
     }
     for (auto &g : e->graphs)
-        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.nt == nt) {
+        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.nt == nt && g.tile == e->tile &&
+            g.grid_mult == e->grid_mult) {
             LGF_HIP(hipGraphLaunch(g.exec, e->stream));
             return LGF_OK;
         }
@@ -195,7 +210,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, nt, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, nt, e->tile, e->grid_mult, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }
@@ -225,6 +240,46 @@ lgf_status convert_one(lgf_ensemble *e, int i, int fs, int fd, bool reunit)
 
 bool is_fp64(int f) { return f == LGF_FP64_18 || f == LGF_FP64_12; }
 
+// Scratch copies of every configuration in `format` (converted from the home
+// fields); until drop_scratch, field_of(format, i) points at them, so timing
+// and tuning sweeps leave the links untouched.
+lgf_status make_scratch(lgf_ensemble *e, int format)
+{
+    std::vector<size_t> off(e->n);
+    size_t total = 0;
+    for (int i = 0; i < e->n; ++i) {
+        off[i] = total;
+        total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(format));
+    }
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the scratch copies", total);
+    }
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < e->n && err == hipSuccess; ++i)
+        err = lgf::launch_convert(e->format, field_of(e, e->format, i), format, (char *)scratch + off[i],
+                                  e->geom[i], false, e->stream);
+    if (err != hipSuccess) {
+        (void)hipStreamSynchronize(e->stream);
+        (void)hipFree(scratch);
+        return fail(LGF_EHIP, "scratch copies: %s", hipGetErrorString(err));
+    }
+    e->scratch = scratch;
+    e->scratch_off = off;
+    e->scratch_fmt = format;
+    return LGF_OK;
+}
+
+void drop_scratch(lgf_ensemble *e)
+{
+    (void)hipStreamSynchronize(e->stream);
+    if (e->scratch) (void)hipFree(e->scratch);
+    e->scratch = nullptr;
+    e->scratch_fmt = -1;
+    e->scratch_off.clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -249,7 +304,7 @@ lgf_status lgf_ensemble_create(int n, const int *dims, int format, void *stream,
         e->V.push_back((int64_t)dims[4 * i] * dims[4 * i + 1] * dims[4 * i + 2] * dims[4 * i + 3]);
         e->home_off.push_back(total);
         total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(format));
-        tiles += (e->geom[i].Vh + lgf::kEnsTile - 1) / lgf::kEnsTile;
+        tiles += (e->geom[i].Vh + lgf::kEnsMinTile - 1) / lgf::kEnsMinTile;
     }
     e->max_tiles = (uint32_t)tiles;
     auto bail = [&](lgf_status st) {
@@ -300,6 +355,7 @@ lgf_status lgf_ensemble_destroy(lgf_ensemble *e)
     if (e->home) (void)hipFree(e->home);
     for (int f = 0; f < 4; ++f)
         if (e->work[f]) (void)hipFree(e->work[f]);
+    if (e->scratch) (void)hipFree(e->scratch);
     void *dev[] = {e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base, e->d_spans, e->d_partials, e->d_out};
     for (void *p : dev)
         if (p) (void)hipFree(p);
@@ -552,16 +608,120 @@ lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double o
     if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
     LGF_TRY(ens_use_device(e));
+    LGF_TRY(make_scratch(e, format));
     std::vector<int> phase(e->n, kFinish), fmt(e->n, format), listed;
-    for (int i = 0; i < e->n; ++i) LGF_TRY(convert_one(e, i, e->format, format, false));
-    const uint32_t nt = build_work(e, phase, fmt, true, listed);
-    LGF_TRY(upload_work(e, nt, listed.size()));
-    LGF_TRY(run_chunk(e, format, format, 1, omega, p_sr, 0, 0, false));  // warm-up
-    LGF_HIP(hipEventRecord(e->ev0, e->stream));
-    LGF_TRY(run_chunk(e, format, format, n, omega, p_sr, 0, 1, false));
-    LGF_HIP(hipEventRecord(e->ev1, e->stream));
-    LGF_HIP(hipEventSynchronize(e->ev1));
-    *ms_per_launch = lgf::elapsed_ms(e->ev0, e->ev1) / (2.0 * n);
+    auto timed = [&]() -> lgf_status {
+        const uint32_t nt = build_work(e, phase, fmt, true, listed);
+        LGF_TRY(upload_work(e, nt, listed.size()));
+        LGF_TRY(run_chunk(e, format, format, 1, omega, p_sr, 0, 0, false));  // warm-up
+        LGF_HIP(hipEventRecord(e->ev0, e->stream));
+        LGF_TRY(run_chunk(e, format, format, n, omega, p_sr, 0, 1, false));
+        LGF_HIP(hipEventRecord(e->ev1, e->stream));
+        LGF_HIP(hipEventSynchronize(e->ev1));
+        *ms_per_launch = lgf::elapsed_ms(e->ev0, e->ev1) / (2.0 * n);
+        return LGF_OK;
+    };
+    const lgf_status st = timed();
+    drop_scratch(e);
+    return st;
+}
+
+lgf_status lgf_ensemble_set_tuning(lgf_ensemble *e, int tile, int grid_mult, int nontemporal)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    if (tile != 64 && tile != 128 && tile != 256) return fail(LGF_EINVAL, "tile must be 64, 128 or 256");
+    if (grid_mult != 1 && grid_mult != 2 && grid_mult != 4) return fail(LGF_EINVAL, "grid_mult must be 1, 2 or 4");
+    e->tile = tile;
+    e->grid_mult = grid_mult;
+    e->nontemporal = nontemporal ? 1 : 0;
+    drop_graphs(e);
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_get_tuning(const lgf_ensemble *e, int *tile, int *grid_mult, int *nontemporal)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    if (tile) *tile = e->tile;
+    if (grid_mult) *grid_mult = e->grid_mult;
+    if (nontemporal) *nontemporal = e->nontemporal;
+    return LGF_OK;
+}
+
+lgf_status lgf_ensemble_autotune(lgf_ensemble *e, int format, int trials)
+{
+    if (!e) return fail(LGF_EINVAL, "ensemble is NULL");
+    if (!lgf::valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
+    LGF_TRY(ens_use_device(e));
+    // scratch copies of every configuration in `format`; the links stay untouched
+    LGF_TRY(make_scratch(e, format));
+    hipError_t err = hipSuccess;
+    const int saved[3] = {e->tile, e->grid_mult, e->nontemporal};
+    struct Cand {
+        int tile, mult, nt;
+        double ms;
+    };
+    lgf_status st = LGF_OK;
+    std::vector<int> phase(e->n, kFinish), fmt(e->n, format), listed;
+    auto time_variant = [&](Cand &c, int n) -> bool {
+        e->tile = c.tile;
+        e->grid_mult = c.mult;
+        e->nontemporal = c.nt;
+        const uint32_t nt = build_work(e, phase, fmt, true, listed);
+        st = upload_work(e, nt, listed.size());
+        if (st == LGF_OK) st = run_chunk(e, format, format, 1, 1.7, 0.0, 0, 0, false);
+        if (st != LGF_OK) return false;
+        if ((err = hipEventRecord(e->ev0, e->stream)) != hipSuccess) return false;
+        st = run_chunk(e, format, format, n, 1.7, 0.0, 0, 1, false);
+        if (st != LGF_OK) return false;
+        if ((err = hipEventRecord(e->ev1, e->stream)) != hipSuccess ||
+            (err = hipEventSynchronize(e->ev1)) != hipSuccess)
+            return false;
+        c.ms = lgf::elapsed_ms(e->ev0, e->ev1) / n;
+        return true;
+    };
+    // stage 1: every variant once; stage 2: the three fastest and the default
+    // over three times as many sweeps in five interleaved rounds, smallest median
+    std::vector<Cand> cands;
+    bool ok = true;
+    for (int tile : {64, 128, 256})
+        for (int mult : {1, 2})
+            for (int nt : {0, 1}) {
+                Cand c{tile, mult, nt, 0.0};
+                if (!(ok = time_variant(c, trials))) break;
+                cands.push_back(c);
+            }
+    Cand best{saved[0], saved[1], saved[2], 0.0};
+    if (ok) {
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        std::vector<Cand> finals(cands.begin(), cands.begin() + std::min<size_t>(3, cands.size()));
+        bool have_default = false;
+        for (const Cand &c : finals) have_default = have_default || (c.tile == lgf::kEnsTile && c.mult == 1 && c.nt == 1);
+        if (!have_default) finals.push_back(Cand{lgf::kEnsTile, 1, 1, 0.0});
+        std::vector<std::vector<double>> ms(finals.size());
+        for (int round = 0; round < 5 && ok; ++round)
+            for (size_t i = 0; i < finals.size() && ok; ++i) {
+                ok = time_variant(finals[i], std::max(3 * trials, 6));
+                ms[i].push_back(finals[i].ms);
+            }
+        if (ok) {
+            double best_ms = 1e300;
+            for (size_t i = 0; i < finals.size(); ++i) {
+                std::sort(ms[i].begin(), ms[i].end());
+                if (ms[i][2] < best_ms) {
+                    best_ms = ms[i][2];
+                    best = finals[i];
+                }
+            }
+        }
+    }
+    drop_scratch(e);
+    e->tile = ok ? best.tile : saved[0];
+    e->grid_mult = ok ? best.mult : saved[1];
+    e->nontemporal = ok ? best.nt : saved[2];
+    drop_graphs(e);
+    if (st != LGF_OK) return st;
+    if (err != hipSuccess) return fail(LGF_EHIP, "ensemble autotune: %s", hipGetErrorString(err));
     return LGF_OK;
 }
 

@@ -2,9 +2,10 @@
 // ensemble of independent lattices of different sizes in one launch.
 //
 // The work list is a flat array of tiles (configuration, first half index):
-// every tile is 128 sites of one configuration, so a 24^4 lattice contributes
-// 1296 tiles per parity and an 8^4 one 16.  A fixed grid of workgroups (a few
-// per CU) walks the list; each tile reads its configuration's descriptor
+// every tile is `tile` sites of one configuration (64, 128 or 256, one lane per
+// site and one workgroup per tile; at 128 a 24^4 lattice contributes 1296 tiles
+// per parity and an 8^4 one 16).  A fixed grid of workgroups (a few per CU)
+// walks the list; each tile reads its configuration's descriptor
 // (geometry, field pointer, current storage format) and runs the same per-site
 // update as the single-lattice sweep.  Converged configurations are simply
 // left out of the list, and a configuration in its FP32 bulk phase and one in
@@ -28,7 +29,7 @@ __device__ __forceinline__ void ensemble_site(const EnsCfg &c, int parity, uint3
 
 // FA, FB: the (at most two) storage formats the launch may meet.
 template <int FA, int FB, bool SR, bool NT>
-__global__ void __launch_bounds__(kEnsTile) ensemble_sweep_kernel(const EnsCfg *__restrict__ cfgs,
+__global__ void __launch_bounds__(kEnsMaxTile) ensemble_sweep_kernel(const EnsCfg *__restrict__ cfgs,
                                                                    const EnsTile *__restrict__ tiles,
                                                                    const uint32_t *__restrict__ n_tiles,
                                                                    const uint64_t *__restrict__ sweep_base,
@@ -47,8 +48,26 @@ __global__ void __launch_bounds__(kEnsTile) ensemble_sweep_kernel(const EnsCfg *
     }
 }
 
+// sums of a and b over the workgroup (any multiple of 64 lanes up to 256)
+// into out[0], out[1], in a fixed order
+__device__ __forceinline__ void ens_block_sum2(double a, double b, double *out)
+{
+    __shared__ double sa[kEnsMaxTile / 64], sb[kEnsMaxTile / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { ta += sa[i]; tb += sb[i]; }
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
 template <int FA, int FB>
-__global__ void __launch_bounds__(kEnsTile) ensemble_measure_kernel(const EnsCfg *__restrict__ cfgs,
+__global__ void __launch_bounds__(kEnsMaxTile) ensemble_measure_kernel(const EnsCfg *__restrict__ cfgs,
                                                                      const EnsTile *__restrict__ tiles,
                                                                      int parity, int reunit_fwd, int reunit_bwd,
                                                                      double *partials)
@@ -61,7 +80,7 @@ __global__ void __launch_bounds__(kEnsTile) ensemble_measure_kernel(const EnsCfg
     double f = 0.0, th = 0.0;
     if (c.fmt == FA) measure_site<FA>(c.field, c.g, parity, h, active, reunit_fwd, reunit_bwd, f, th);
     else if (FB != FA && c.fmt == FB) measure_site<FB>(c.field, c.g, parity, h, active, reunit_fwd, reunit_bwd, f, th);
-    block_sum2<kEnsTile>(f, th, partials + 2 * blockIdx.x);
+    ens_block_sum2(f, th, partials + 2 * blockIdx.x);
 }
 
 // One workgroup per listed configuration: the sums of its tiles' partials
@@ -101,7 +120,7 @@ template <int FA, int FB>
 static hipError_t launch_ens_sweep_t(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
                                      bool sr, bool nt, hipStream_t s)
 {
-    const dim3 grid(L.grid), block(kEnsTile);
+    const dim3 grid(L.grid), block(L.tile);
     if (sr) {
         if (nt) hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
         else hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, false>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
@@ -133,7 +152,7 @@ hipError_t launch_ensemble_measure(int fa, int fb, const EnsLaunch &L, uint32_t 
     const int rf = reunit_fwd ? 1 : 0, rb = reunit_bwd ? 1 : 0;
 #define LGF_CASE(A, B)                                                                                  \
     if (fa == A && fb == B) {                                                                           \
-        hipLaunchKernelGGL((ensemble_measure_kernel<A, B>), dim3(n_tiles), dim3(kEnsTile), 0, s, L.cfgs, \
+        hipLaunchKernelGGL((ensemble_measure_kernel<A, B>), dim3(n_tiles), dim3(L.tile), 0, s, L.cfgs,   \
                            L.tiles, parity, rf, rb, partials);                                         \
         return hipGetLastError();                                                                       \
     }
@@ -161,7 +180,7 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt)
+int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt, int tile, int grid_mult)
 {
     if (fa > fb) { const int t = fa; fa = fb; fb = t; }
     const void *fn = nullptr;
@@ -173,9 +192,9 @@ int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt)
 #undef LGF_CASE
     int dev = 0, cus = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEnsTile, 0) != hipSuccess || per_cu < 1)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tile, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    return cus * per_cu;
+    return cus * per_cu * (grid_mult > 1 ? grid_mult : 1);
 }
 
 }  // namespace lgf

@@ -353,6 +353,7 @@ ENSEMBLE_EXPORTS = [
     "lgf_ensemble_create", "lgf_ensemble_destroy", "lgf_ensemble_generate",
     "lgf_ensemble_load_links", "lgf_ensemble_store_links", "lgf_ensemble_sweep",
     "lgf_ensemble_measure", "lgf_ensemble_gauge_fix", "lgf_ensemble_time_sweeps",
+    "lgf_ensemble_set_tuning", "lgf_ensemble_get_tuning", "lgf_ensemble_autotune",
 ]
 EXPORTS = EXPORTS + ENSEMBLE_EXPORTS + ["lgf_sweep_coulomb", "lgf_measure_coulomb",
                                         "lgf_coulomb_gauge_fix", "lgf_plaquette"]
@@ -372,6 +373,9 @@ def _ens_lib():
             "lgf_ensemble_measure": (I, [P, P, P]),
             "lgf_ensemble_gauge_fix": (I, [P, P, P]),
             "lgf_ensemble_time_sweeps": (I, [P, I, I, D, D, P]),
+            "lgf_ensemble_set_tuning": (I, [P, I, I, I]),
+            "lgf_ensemble_get_tuning": (I, [P, P, P, P]),
+            "lgf_ensemble_autotune": (I, [P, I, I]),
             "lgf_sweep_coulomb": (I, [P, I, D, D, U64, U64, P]),
             "lgf_measure_coulomb": (I, [P, P, P]),
             "lgf_coulomb_gauge_fix": (I, [P, P, P, P, P, P]),
@@ -383,6 +387,21 @@ def _ens_lib():
             fn.argtypes = args
         lib._lgf_ens_sigs = True
     return lib
+
+
+def lgf_ensemble_set_tuning(e, tile: int = 128, grid_mult: int = 1, nontemporal: int = 1) -> None:
+    _check(_ens_lib().lgf_ensemble_set_tuning(e, tile, grid_mult, nontemporal))
+
+
+def lgf_ensemble_get_tuning(e):
+    """(tile, grid_mult, nontemporal)"""
+    v = [ctypes.c_int() for _ in range(3)]
+    _check(_ens_lib().lgf_ensemble_get_tuning(e, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def lgf_ensemble_autotune(e, fmt: int, trials: int = 2) -> None:
+    _check(_ens_lib().lgf_ensemble_autotune(e, fmt, trials))
 
 
 def lgf_ensemble_create(dims_list, fmt: int = LGF_FP64_18, stream=None):

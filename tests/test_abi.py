@@ -109,6 +109,15 @@ def test_copy_bandwidth_rejects_bad_arguments_without_gpu(lgf):
     assert lib.lgf_copy_bandwidth(1 << 20, 1, None, None) == lgf.LGF_EINVAL
 
 
+def test_ensemble_tuning_null_and_bad_args_without_gpu(lgf):
+    lib = lgf.lgf._ens_lib()
+    assert lib.lgf_ensemble_set_tuning(None, 128, 1, 1) == lgf.LGF_EINVAL
+    assert lib.lgf_ensemble_get_tuning(None, None, None, None) == lgf.LGF_EINVAL
+    assert lib.lgf_ensemble_autotune(None, 0, 1) == lgf.LGF_EINVAL
+    assert lib.lgf_set_tuning(None, 0, None) == lgf.LGF_EINVAL
+    assert lib.lgf_get_tuning(None, 0, None) == lgf.LGF_EINVAL
+
+
 def test_fix_params_default(lgf):
     p = lgf.lgf_fix_params_default()
     assert p.omega == 1.7 and p.p_sr == 0.0 and p.theta_target == 1e-14

@@ -125,6 +125,44 @@ def test_ensemble_mixed_gauge_fix_equals_single(lgf, orc):
     assert sweeps[0] < sweeps[-1]   # configurations stopped at different points
 
 
+def test_ensemble_tunings_are_bitwise_identical(lgf, orc):
+    """Tile width, persistent grid size and non-temporal access change only
+    the schedule of independent site updates: every tuning gives the default
+    run's links and sweep counts bit for bit, and the autotuner and the timing
+    call leave the links untouched."""
+    announce("ensemble tunings")
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (2, 2, 2, 2), (6, 4, 4, 8)]
+    kw = dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+              finish_format=lgf.LGF_FP64_12)
+    Us = [orc.generate_links(d, 90 + i, 0.3) for i, d in enumerate(dims)]
+    outs = []
+    for tune in [(128, 1, 1), (64, 1, 0), (256, 2, 1), (64, 4, 1), (256, 1, 0)]:
+        with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+            lgf.lgf_ensemble_set_tuning(ens.e, *tune)
+            assert lgf.lgf_ensemble_get_tuning(ens.e) == tune
+            for i, U in enumerate(Us):
+                ens.load(i, U)
+            st, res = ens.gauge_fix(**kw)
+            assert st == lgf.LGF_OK
+            outs.append(([ens.store(i) for i in range(len(dims))], [r["sweeps"] for r in res]))
+    for got, sw in outs[1:]:
+        assert sw == outs[0][1]
+        for a, b in zip(got, outs[0][0]):
+            assert np.array_equal(a, b)
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        before = [ens.store(i) for i in range(len(dims))]
+        lgf.lgf_ensemble_autotune(ens.e, lgf.LGF_FP32_12, 1)
+        tile, mult, nt = lgf.lgf_ensemble_get_tuning(ens.e)
+        assert tile in (64, 128, 256) and mult in (1, 2) and nt in (0, 1)
+        assert lgf.lgf_ensemble_time_sweeps(ens.e, lgf.LGF_FP64_18, 2, 1.7) > 0.0
+        for i in range(len(dims)):
+            assert np.array_equal(ens.store(i), before[i])
+        with pytest.raises(lgf.LgfError):
+            lgf.lgf_ensemble_set_tuning(ens.e, 96, 1, 1)
+
+
 def test_ensemble_not_converged_and_args(lgf, orc):
     announce("ensemble status")
     dims = [(4, 4, 4, 4), (4, 4, 4, 6)]
