@@ -234,11 +234,14 @@ typedef struct {
 lgf_status lgf_set_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
 lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
 
-/* Time the sweep variants (lanes per site, block, XCD remap, non-temporal,
- * schedule in place or out of place; the t-slice pipeline is left to
- * lgf_set_tuning) for a format on this handle's lattice, on a scratch copy of the
- * links (which are left untouched), and keep the fastest.  trials = timed full
- * sweeps per variant (>= 1). */
+/* Time the sweep variants (lanes per site, sites per thread, block, XCD
+ * remap, non-temporal, schedule in place or out of place; the t-slice
+ * pipeline is left to lgf_set_tuning) for a format on this handle's lattice
+ * and keep the fastest.  The variants sweep the buffer that lgf_gauge_fix
+ * sweeps in that format (the handle's field, saved to a temporary copy first
+ * and restored afterwards, or the handle's working copy in another format), so
+ * the links are left as they were.  trials = timed full sweeps per variant in
+ * the first round (>= 1); the fastest few are re-timed over longer runs. */
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
 
 /* Average duration in ms of the last n_launches sweep kernels enqueued through

@@ -1051,14 +1051,31 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
     LGF_TRY(use_device(h));
-    // a scratch copy of the current links in the format being tuned
+    // The variants sweep the very buffer the gauge fixing sweeps in this
+    // format (the handle's field, or its working copy in another format):
+    // measured on one GPU the in-place and out-of-place rates depend on the
+    // buffer, by a few per cent either way.  The handle's own links are saved
+    // before and restored after; a working copy holds no state between calls.
     const size_t bytes = (size_t)h->V * 4 * lgf::link_bytes(format);
-    void *scratch = nullptr;
-    if (hipMalloc(&scratch, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the tuning copy", bytes);
+    void *scratch = nullptr, *backup = nullptr;
+    hipError_t e = hipSuccess;
+    if (format == h->format) {
+        scratch = h->field;
+        if (hipMalloc(&backup, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate %zu bytes to save the links while tuning", bytes);
+        }
+        e = hipMemcpyAsync(backup, h->field, bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(backup);
+            return fail(LGF_EHIP, "autotune: saving the links: %s", hipGetErrorString(e));
+        }
+    } else {
+        LGF_TRY(ensure_work(h, format));
+        scratch = h->work[format];
+        e = lgf::launch_convert(h->format, h->field, format, scratch, h->geom, false, h->stream);
     }
-    hipError_t e = lgf::launch_convert(h->format, h->field, format, scratch, h->geom, false, h->stream);
     const lgf::SweepTuning saved = h->tune[format];
     // the out-of-place variants need the partner buffer; without memory for it they are skipped
     const bool had_partner = h->partner[format] != nullptr;
@@ -1134,8 +1151,12 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         }
     }
     h->tune[format] = saved;
+    if (backup) {
+        const hipError_t e2 = hipMemcpyAsync(h->field, backup, bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = e2;
+    }
     (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(scratch);
+    if (backup) (void)hipFree(backup);
     if (st == LGF_OK && e == hipSuccess) h->tune[format] = best;
     if (!had_partner && h->partner[format] && h->tune[format].schedule != lgf::kScheduleOutOfPlace) {
         (void)hipFree(h->partner[format]);

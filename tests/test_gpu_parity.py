@@ -496,3 +496,23 @@ def test_copy_bandwidth(lgf):
     announce("copy bandwidth")
     gbs = lgf.lgf_copy_bandwidth(256 << 20, 4)
     assert 500.0 < gbs < 10000.0
+
+
+def test_autotune_leaves_links_untouched(lgf, orc):
+    """The autotuner sweeps the handle's own field (saved and restored) or its
+    working copy in another format: the links come back bit for bit, and the
+    picked variant is one the library accepts."""
+    dims = (8, 6, 4, 12)
+    announce("autotune restore")
+    U = orc.generate_links(dims, 44, 0.3)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        before = lat.store()
+        for fmt in (lgf.LGF_FP64_18, lgf.LGF_FP32_12):
+            lgf.lgf_autotune(lat.h, fmt, 1)
+            assert np.array_equal(lat.store(), before)
+            t = lgf.lgf_get_tuning(lat.h, fmt)
+            lgf.lgf_set_tuning(lat.h, fmt, *t)
+        st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-12, theta_switch=1e-8,
+                                   bulk_format=lgf.LGF_FP32_12, finish_format=lgf.LGF_FP64_12)
+        assert st == lgf.LGF_OK and orc.measure(dims, lat.store())[1] < 1e-12
