@@ -75,7 +75,11 @@ typedef struct {
                               g(x) and the FP64 links are rebuilt at the switch as
                               g(x) U(x) g(x+mu)^dag from the untouched FP64 input (needs an FP32
                               bulk, an FP64 finish and an FP64 handle) */
-    int reserved;
+    int separate_measure;  /* 1: reunitarize and measure in two passes of their own after each
+                              chunk; 0 (default): inside the chunk's last half-sweep plus one
+                              read-only pass over the other parity, where the sweep allows it
+                              (overrelaxation, non-temporal, not the t-slice pipeline).  The links
+                              are the same; F and theta differ only in the summation order */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */

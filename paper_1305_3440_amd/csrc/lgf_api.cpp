@@ -90,6 +90,7 @@ struct GraphEntry {
     lgf::SweepTuning tune;
     int coulomb;
     void *gacc;
+    int fused;
     hipGraphExec_t exec;
 };
 
@@ -117,6 +118,8 @@ struct lgf_lattice {
     void *work[4];  // owned per-format copies for the mixed-precision bulk
     size_t work_bytes[4];
     void *partner[4];  // owned second buffer per format for the out-of-place schedule
+    double *d_fused;   // partial sums of the measurement fused into a sweep
+    size_t fused_cap;  // (F, theta) pairs d_fused holds
     lgf::SweepTuning tune[4];
     std::vector<GraphEntry> graphs;
     hipEvent_t ev0, ev1;
@@ -216,10 +219,11 @@ lgf_status measure_field(lgf_lattice *h, int format, void *field, bool reunit, d
 }
 
 lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, double omega, double p_sr,
-                        uint64_t seed, uint64_t sweep_index, bool coulomb = false)
+                        uint64_t seed, uint64_t sweep_index, bool coulomb = false, double *meas = nullptr)
 {
     lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
     a.gacc = h->gacc_active;
+    a.meas = meas;
     if (coulomb)
         LGF_HIP(lgf::launch_sweep_coulomb(format, field, h->geom, a, h->d_mask, h->tune[format].nontemporal != 0,
                                           h->stream));
@@ -235,8 +239,10 @@ lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, dou
 // Every site update sees the same links as in the two-launch order, so the
 // result is the same bit for bit, while parity 1 finds the links parity 0
 // wrote one slice earlier still in the last-level cache.
+// meas: the parity-1 half-sweep also reunitarizes the links it writes and
+// leaves its (F, theta) partial sums there (see measure_fused).
 lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, double p_sr, uint64_t seed,
-                      uint64_t sweep_index, bool coulomb = false)
+                      uint64_t sweep_index, bool coulomb = false, double *meas = nullptr)
 {
     const int Lt = h->dims[0];
     const int sched = h->tune[format].schedule;
@@ -250,12 +256,15 @@ lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, dou
         LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
         a.parity = 1;
         a.out = field;
+        a.meas = meas;
         LGF_HIP(lgf::launch_sweep(format, partner, h->geom, a, h->tune[format], h->stream));
         return LGF_OK;
     }
-    if (coulomb || sched != lgf::kSchedulePipeline || Lt < 4) {
+    // (the pipeline gives the two-launch result bit for bit, so a sweep that
+    // carries the fused measurement simply runs as two launches)
+    if (coulomb || sched != lgf::kSchedulePipeline || Lt < 4 || meas) {
         LGF_TRY(sweep_launch(h, format, field, 0, omega, p_sr, seed, sweep_index, coulomb));
-        LGF_TRY(sweep_launch(h, format, field, 1, omega, p_sr, seed, sweep_index, coulomb));
+        LGF_TRY(sweep_launch(h, format, field, 1, omega, p_sr, seed, sweep_index, coulomb, meas));
         return LGF_OK;
     }
     const uint32_t hs = h->geom.hs[0];
@@ -323,18 +332,66 @@ lgf_status measure_coulomb_field(lgf_lattice *h, int format, void *field, bool r
 // numbers, so every launch of the chunk has fixed arguments) are captured once
 // into a hipGraph and replayed; stochastic relaxation launches directly since
 // its counter changes every sweep.
-lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omega, double p_sr,
-                     uint64_t seed, uint64_t sweep0, bool use_graph, bool coulomb = false)
+// Whether the chunk's last half-sweep can carry the reunitarization and the
+// measurement (kernel variants exist for overrelaxation with non-temporal
+// access, Landau gauge).
+bool can_fuse(const lgf_lattice *h, int format, double p_sr, bool coulomb)
 {
+    return !coulomb && p_sr == 0.0 && h->tune[format].nontemporal != 0;
+}
+
+// room for the fused sweep's partial sums followed by those of the parity-0
+// measurement pass; graphs that hold the old buffer are dropped on growth
+lgf_status ensure_fused(lgf_lattice *h, int format)
+{
+    const size_t need = (size_t)lgf::sweep_groups(h->geom, h->tune[format]) + (size_t)lgf::measure_blocks(h->geom);
+    if (h->fused_cap >= need) return LGF_OK;
+    drop_graphs(h);
+    if (h->d_fused) LGF_HIP(hipFree(h->d_fused));
+    h->d_fused = nullptr;
+    h->fused_cap = 0;
+    if (hipMalloc(&h->d_fused, need * 2 * sizeof(double)) != hipSuccess) {
+        h->d_fused = nullptr;
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate the fused measurement's partial sums");
+    }
+    h->fused_cap = need;
+    return LGF_OK;
+}
+
+// F and theta after a chunk whose last half-sweep was fused: its partial sums
+// (parity-1 sites' theta, parity-1 forward links' Re tr, from the links as
+// reunitarized and stored) plus a read-only pass over the parity-0 sites.
+lgf_status measure_fused(lgf_lattice *h, int format, void *field, double *F, double *theta)
+{
+    const int ng = (int)lgf::sweep_groups(h->geom, h->tune[format]);
+    int n0 = 0;
+    LGF_HIP(lgf::launch_measure(format, field, h->geom, 0, false, false, h->d_fused + 2 * (size_t)ng, &n0,
+                                h->stream));
+    LGF_HIP(lgf::launch_finish_measure(h->d_fused, ng + n0, (double)h->V, h->d_out, h->stream));
+    LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    if (F) *F = h->h_out[0];
+    if (theta) *theta = h->h_out[1];
+    return LGF_OK;
+}
+
+// fused: the last sweep reunitarizes and measures (see measure_fused); the
+// caller checked can_fuse
+lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omega, double p_sr,
+                     uint64_t seed, uint64_t sweep0, bool use_graph, bool coulomb = false, bool fused = false)
+{
+    if (fused) LGF_TRY(ensure_fused(h, format));
+    auto meas_of = [&](int k) { return (fused && k == n - 1) ? h->d_fused : nullptr; };
     if (!use_graph || p_sr > 0.0) {
         for (int k = 0; k < n; ++k)
-            LGF_TRY(full_sweep(h, format, field, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb));
+            LGF_TRY(full_sweep(h, format, field, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb, meas_of(k)));
         return LGF_OK;
     }
     const lgf::SweepTuning &t = h->tune[format];
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
-            g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active &&
+            g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active && g.fused == (fused ? 1 : 0) &&
             g.tune == t) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
@@ -344,7 +401,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     lgf_status st = LGF_OK;
     for (int k = 0; k < n && st == LGF_OK; ++k)
-        st = full_sweep(h, format, field, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb);
+        st = full_sweep(h, format, field, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb, meas_of(k));
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (st != LGF_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -359,7 +416,7 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
         (void)hipGraphExecDestroy(h->graphs.front().exec);
         h->graphs.erase(h->graphs.begin());
     }
-    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, exec});
+    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, fused ? 1 : 0, exec});
     LGF_HIP(hipGraphLaunch(exec, h->stream));
     return LGF_OK;
 }
@@ -474,6 +531,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
         if (h->partner[f]) (void)hipFree(h->partner[f]);
     }
     if (h->d_partials) (void)hipFree(h->d_partials);
+    if (h->d_fused) (void)hipFree(h->d_fused);
     if (h->d_out) (void)hipFree(h->d_out);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->d_stage) (void)hipFree(h->d_stage);
@@ -744,8 +802,10 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
         const int64_t left = p.max_sweeps - sweeps;
         const int n = (int)(left < p.check_every ? left : p.check_every);
+        // reunitarize + measure inside the chunk's last half-sweep where possible
+        const bool fuse = !p.separate_measure && can_fuse(h, cur_fmt, p.p_sr, false);
         LGF_HIP(hipEventRecord(h->ev0, h->stream));
-        LGF_TRY(run_chunk(h, cur_fmt, cur, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0));
+        LGF_TRY(run_chunk(h, cur_fmt, cur, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0, false, fuse));
         LGF_HIP(hipEventRecord(h->ev1, h->stream));
         LGF_HIP(hipEventSynchronize(h->ev1));
         const double ms = elapsed_ms(h->ev0, h->ev1);
@@ -759,7 +819,15 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         ctr += (uint64_t)n;
 
         if (h->gacc_active) LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 1, h->stream));
-        LGF_TRY(measure_timed(true, &F, &theta));
+        if (fuse) {
+            LGF_HIP(hipEventRecord(h->ev0, h->stream));
+            LGF_TRY(measure_fused(h, cur_fmt, cur, &F, &theta));
+            LGF_HIP(hipEventRecord(h->ev1, h->stream));
+            LGF_HIP(hipEventSynchronize(h->ev1));
+            res->t_measure_ms += elapsed_ms(h->ev0, h->ev1);
+        } else {
+            LGF_TRY(measure_timed(true, &F, &theta));
+        }
         record(sweeps, F, theta);
         if (!std::isfinite(F) || !std::isfinite(theta)) {
             status = LGF_ENUMERIC;

@@ -48,24 +48,6 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_sweep_kernel(const EnsCf
     }
 }
 
-// sums of a and b over the workgroup (any multiple of 64 lanes up to 256)
-// into out[0], out[1], in a fixed order
-__device__ __forceinline__ void ens_block_sum2(double a, double b, double *out)
-{
-    __shared__ double sa[kEnsMaxTile / 64], sb[kEnsMaxTile / 64];
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) { sa[w] = a; sb[w] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0.0, tb = 0.0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { ta += sa[i]; tb += sb[i]; }
-        out[0] = ta;
-        out[1] = tb;
-    }
-}
-
 template <int FA, int FB>
 __global__ void __launch_bounds__(kEnsMaxTile) ensemble_measure_kernel(const EnsCfg *__restrict__ cfgs,
                                                                      const EnsTile *__restrict__ tiles,
@@ -80,7 +62,7 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_measure_kernel(const Ens
     double f = 0.0, th = 0.0;
     if (c.fmt == FA) measure_site<FA>(c.field, c.g, parity, h, active, reunit_fwd, reunit_bwd, f, th);
     else if (FB != FA && c.fmt == FB) measure_site<FB>(c.field, c.g, parity, h, active, reunit_fwd, reunit_bwd, f, th);
-    ens_block_sum2(f, th, partials + 2 * blockIdx.x);
+    block_sum2_any(f, th, partials + 2 * blockIdx.x);
 }
 
 // One workgroup per listed configuration: the sums of its tiles' partials

@@ -43,7 +43,12 @@ struct SweepArgs {
     uint32_t h_end = 0;
     void *gacc = nullptr;    // site field accumulating G (same format as the links), or none
     void *out = nullptr;     // out-of-place target field (whole half-sweep only), or in place
+    double *meas = nullptr;  // fused reunitarize + measure: per-workgroup (F, theta) partial sums
 };
+
+// workgroups of a whole half-sweep with tuning t (the partial sums a fused
+// measurement writes)
+uint32_t sweep_groups(const Geom &g, const SweepTuning &t);
 
 hipError_t launch_sweep(int format, void *field, const Geom &g, const SweepArgs &a,
                         const SweepTuning &t, hipStream_t s);

@@ -36,13 +36,15 @@ size_t link_bytes(int format)
 // One half-sweep: the sites [h_begin, h_end) of one parity, LPS lanes per
 // site, cut into n_tiles tiles of blockDim.x lanes.  Workgroup b takes the
 // tiles b, b + n_groups, b + 2 n_groups, ... (spt of them at most), so the
-// workgroups in flight always cover neighbouring tiles.
-template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
+// workgroups in flight always cover neighbouring tiles.  MEAS: the links are
+// reunitarized as they are written and workgroup b leaves the sums of its
+// sites' F and theta contributions in partials[2b], partials[2b + 1].
+template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC, bool MEAS>
 __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Geom g, int parity,
                                                      RelaxArgs<typename Fmt<F>::T> a, int xcd_remap,
                                                      uint32_t n_groups, uint32_t n_tiles, uint32_t spt,
                                                      uint32_t h_begin, uint32_t h_end,
-                                                     void *__restrict__ out_field)
+                                                     void *__restrict__ out_field, double *__restrict__ partials)
 {
     uint32_t b = blockIdx.x;
     if (xcd_remap) {
@@ -51,27 +53,46 @@ __global__ void __launch_bounds__(256) sweep_kernel(void *__restrict__ field, Ge
         // neighbouring tiles share its L2
         const uint32_t per = gridDim.x >> 3;
         b = (b & 7u) * per + (b >> 3);
-        if (b >= n_groups) return;
+        if (b >= n_groups) return;  // the whole workgroup: no partials slot
     }
-    for (uint32_t k = 0; k < spt; ++k) {
-        const uint32_t tile = b + k * n_groups;
-        if (tile >= n_tiles) return;
-        const uint64_t tid = (uint64_t)tile * blockDim.x + threadIdx.x;
-        const uint32_t grp = h_begin + (uint32_t)(tid / LPS);
+    MeasAcc acc;
+    auto one_tile = [&](uint32_t tile) {
+        // Vh <= 2^30 and LPS <= 4, so tile * blockDim + lane < 2^32
+        const uint32_t tid = tile * blockDim.x + threadIdx.x;
+        const uint32_t grp = h_begin + tid / LPS;
         const int lane = (int)(tid % LPS);
         const bool active = grp < h_end;
-        update_site<F, LPS, SR, NT, 0, OOP, ACC>(field, g, parity, active ? grp : h_end - 1, lane, active, a,
-                                                 nullptr, out_field);
+        update_site<F, LPS, SR, NT, 0, OOP, ACC, MEAS>(field, g, parity, active ? grp : h_end - 1, lane, active,
+                                                       a, nullptr, out_field, &acc);
+    };
+    if (spt == 1) {
+        one_tile(b);  // the common case without a loop around the register-heavy update
+    } else {
+        for (uint32_t k = 0; k < spt; ++k) {
+            const uint32_t tile = b + k * n_groups;
+            if (tile >= n_tiles) break;  // uniform over the workgroup
+            one_tile(tile);
+        }
     }
+    if constexpr (MEAS) block_sum2_any(acc.f, acc.th, partials + 2 * b);
 }
 
-template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC>
+template <int F, int LPS, bool SR, bool NT, bool OOP, bool ACC, bool MEAS = false>
 static void launch_sweep_kernel(dim3 grid, int block, hipStream_t s, void *field, const Geom &g, int parity,
                                 const RelaxArgs<typename Fmt<F>::T> &ra, int xcd_remap, uint32_t n_groups,
-                                uint32_t n_tiles, uint32_t spt, uint32_t h_begin, uint32_t h_end, void *out)
+                                uint32_t n_tiles, uint32_t spt, uint32_t h_begin, uint32_t h_end, void *out,
+                                double *partials = nullptr)
 {
-    hipLaunchKernelGGL((sweep_kernel<F, LPS, SR, NT, OOP, ACC>), grid, dim3(block), 0, s, field, g, parity, ra,
-                       xcd_remap, n_groups, n_tiles, spt, h_begin, h_end, out);
+    hipLaunchKernelGGL((sweep_kernel<F, LPS, SR, NT, OOP, ACC, MEAS>), grid, dim3(block), 0, s, field, g, parity,
+                       ra, xcd_remap, n_groups, n_tiles, spt, h_begin, h_end, out, partials);
+}
+
+uint32_t sweep_groups(const Geom &g, const SweepTuning &t)
+{
+    const uint64_t threads = (uint64_t)g.Vh * (uint64_t)t.lanes_per_site;
+    const uint32_t nb = (uint32_t)((threads + t.block - 1) / t.block);
+    const uint32_t spt = (uint32_t)(t.sites_per_thread > 1 ? t.sites_per_thread : 1);
+    return (nb + spt - 1) / spt;
 }
 
 template <int F, int LPS, bool NT, bool OOP>
@@ -90,6 +111,27 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
                     (uint32_t)a.sweep_index, a.instance, a.gacc};
     const bool sr = a.p_sr > 0.0;
     if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+    if (a.meas) {
+        // the fused reunitarize + measure: overrelaxation, non-temporal, whole half-sweeps
+        if (sr || a.h_end != 0) return hipErrorInvalidValue;
+        if constexpr (NT) {
+            if (a.gacc) {
+                if constexpr (F == kF32_12 || F == kF32_18)
+                    launch_sweep_kernel<F, LPS, false, NT, OOP, true, true>(grid, t.block, s, field, g, a.parity,
+                                                                            ra, t.xcd_remap, ng, nb, spt, h_begin,
+                                                                            h_end, a.out, a.meas);
+                else
+                    return hipErrorInvalidValue;
+            } else {
+                launch_sweep_kernel<F, LPS, false, NT, OOP, false, true>(grid, t.block, s, field, g, a.parity, ra,
+                                                                         t.xcd_remap, ng, nb, spt, h_begin, h_end,
+                                                                         a.out, a.meas);
+            }
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (a.gacc) {
         // the accumulated gauge transformation belongs to the FP32 bulk only
         if constexpr (F == kF32_12 || F == kF32_18) {

@@ -56,6 +56,38 @@ __device__ __forceinline__ void su2_step(mat3<T> &W, mat3<T> &G, T omega, bool o
 
 template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
 
+// u <- u as stored in format F and read back; o receives the stored value
+template <int F>
+__device__ __forceinline__ void round_to_format(mat3<double> &u, mat3<typename Fmt<F>::T> &o)
+{
+    convert(o, u);
+    if constexpr (Fmt<F>::R == 2) rebuild_row2(o);
+    convert(u, o);
+}
+
+// |[(K - K^dag)/(2i)]_traceless|^2 = tr[Delta Delta^dag] of one site
+__device__ __forceinline__ double theta_of_K(const mat3<double> &K)
+{
+    const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
+    const double tr3 = (d0 + d1 + d2) * (1.0 / 3.0);
+    double th = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            // entries (i,j) and (j,i) have equal modulus |K_ij - conj(K_ji)| / 2
+            const cpx<double> z = K.e[i][j] - conj(K.e[j][i]);
+            th += 0.5 * norm2(z);
+        }
+    return th;
+}
+
+// Per-thread sums of the measurement fused into a half-sweep
+struct MeasAcc {
+    double f = 0.0;   // sum of Re tr of the forward links written
+    double th = 0.0;  // sum of tr[Delta Delta^dag] of the sites updated
+};
+
 // Parameters of one relaxation half-sweep as the kernels see them.
 template <typename T> struct RelaxArgs {
     T omega;
@@ -90,13 +122,19 @@ __device__ __forceinline__ typename Fmt<F>::V *site_field_ptr(void *field, uint3
 // out_field exactly once and the next half-sweep reads them from there).
 // ACC: also g(x) <- G g(x) in the site field a.gacc (the accumulated gauge
 // transformation of the mixed-precision bulk).
-template <int F, int LPS, bool SR, bool NT, int MU0 = 0, bool OOP = false, bool ACC = false>
+// MEAS: the written links are first reunitarized in FP64 and rounded to the
+// storage format -- the values a separate reunitarization pass would store --
+// and the site's F and theta contributions are taken from them: the forward
+// links' Re tr into acc->f and tr[Delta Delta^dag] of x, from the new links
+// around it (every one of them written by this update), into acc->th.
+template <int F, int LPS, bool SR, bool NT, int MU0 = 0, bool OOP = false, bool ACC = false, bool MEAS = false>
 __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom &g, int parity, uint32_t h,
                                             int lane, bool active, const RelaxArgs<typename Fmt<F>::T> &a,
                                             const uint8_t *__restrict__ slice_active = nullptr,
-                                            void *__restrict__ out_field = nullptr)
+                                            void *__restrict__ out_field = nullptr, MeasAcc *acc = nullptr)
 {
     static_assert(!(OOP && MU0 != 0), "timeslice masks need the in-place update");
+    static_assert(!(MEAS && MU0 != 0), "the fused measurement is the Landau one");
     using S = Fmt<F>;
     using T = typename S::T;
     constexpr int NL = 4 / LPS;  // directions handled per lane
@@ -158,14 +196,41 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
             store_link<F>(site_field_ptr<F>(a.gacc, g.Vh, parity), g.Vh, h, r);
         }
     }
+    mat3<double> Kn;
+    if constexpr (MEAS) set_zero(Kn);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int mu = lane + k * LPS;
-        mat3<T> r;
+        mat3<T> r, rb;
         left_mul<S::R>(r, G, uf[k]);
+        right_mul_dag<S::R>(rb, ub[k], G);
+        if constexpr (MEAS) {
+            // only rows 0 and 1 enter the reunitarization, so the 12-real
+            // products (rows 0 and 1) need no row 2 here
+            mat3<double> df, db;
+            convert(df, r);
+            convert(db, rb);
+            reunitarize(df);
+            reunitarize(db);
+            round_to_format<F>(df, r);
+            round_to_format<F>(db, rb);
+            acc->f += df.e[0][0].re + df.e[1][1].re + df.e[2][2].re;
+            add_fwd_bwd(Kn, df, db);
+        }
         store_link<F, NT>(block_ptr<F>(OOP ? out_field : field, g.Vh, parity, mu), g.Vh, h, r);
-        right_mul_dag<S::R>(r, ub[k], G);
-        store_link<F, NT>(block_ptr<F>(OOP ? out_field : field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], r);
+        store_link<F, NT>(block_ptr<F>(OOP ? out_field : field, g.Vh, parity ^ 1, mu), g.Vh, hb[k], rb);
+    }
+    if constexpr (MEAS) {
+#pragma unroll
+        for (int m = 1; m < LPS; m <<= 1)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    Kn.e[i][j].re += shfl_xor_t(Kn.e[i][j].re, m);
+                    Kn.e[i][j].im += shfl_xor_t(Kn.e[i][j].im, m);
+                }
+        if (lane == 0) acc->th += theta_of_K(Kn);
     }
 }
 
@@ -177,20 +242,29 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
 
 constexpr int kMeasureBlock = 256;
 
-// u <- u as stored in format F and read back; o receives the stored value
-template <int F>
-__device__ __forceinline__ void round_to_format(mat3<double> &u, mat3<typename Fmt<F>::T> &o)
-{
-    convert(o, u);
-    if constexpr (Fmt<F>::R == 2) rebuild_row2(o);
-    convert(u, o);
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
     return v;
+}
+
+// sums of a and b over a workgroup of any multiple of 64 lanes up to 256,
+// in a fixed order, into out[0], out[1] (written by lane 0)
+__device__ __forceinline__ void block_sum2_any(double a, double b, double *out)
+{
+    __shared__ double sa[4], sb[4];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { ta += sa[i]; tb += sb[i]; }
+        out[0] = ta;
+        out[1] = tb;
+    }
 }
 
 template <int BLOCK>
@@ -262,18 +336,7 @@ __device__ __forceinline__ void measure_site(void *__restrict__ field, const Geo
         f += u.e[0][0].re + u.e[1][1].re + u.e[2][2].re;
         add_fwd_bwd(K, u, v);
     }
-    // |[(K - K^dag)/(2i)]_traceless|^2
-    const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
-    const double tr3 = (d0 + d1 + d2) * (1.0 / 3.0);
-    th = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i + 1; j < 3; ++j) {
-            // entries (i,j) and (j,i) have equal modulus |K_ij - conj(K_ji)| / 2
-            const cpx<double> z = K.e[i][j] - conj(K.e[j][i]);
-            th += 0.5 * norm2(z);
-        }
+    th = theta_of_K(K);
     if (!active) { f = 0.0; th = 0.0; }
 }
 

@@ -28,7 +28,7 @@ class lgf_fix_params(ctypes.Structure):
                 ("theta_target", ctypes.c_double), ("theta_switch", ctypes.c_double),
                 ("bulk_format", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("finish_format", ctypes.c_int),
-                ("accumulate_g", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("accumulate_g", ctypes.c_int), ("separate_measure", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("sweep_offset", ctypes.c_uint64)]
 

@@ -516,3 +516,38 @@ def test_autotune_leaves_links_untouched(lgf, orc):
         st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-12, theta_switch=1e-8,
                                    bulk_format=lgf.LGF_FP32_12, finish_format=lgf.LGF_FP64_12)
         assert st == lgf.LGF_OK and orc.measure(dims, lat.store())[1] < 1e-12
+
+
+@pytest.mark.parametrize("tune", [(1, 128, 0, 1, 0, 1), (2, 64, 1, 1, 2, 1), (4, 256, 0, 1, 0, 2),
+                                  (1, 64, 0, 1, 2, 4)])
+def test_fused_measure_equals_separate_passes(lgf, orc, tune):
+    """Reunitarize + measure inside the chunk's last half-sweep (plus one
+    read-only pass over parity 0) against the separate passes: the same
+    sweeps, the same links, and F, theta equal up to the summation order --
+    plain FP64-18, mixed FP32-12 / FP64-12, and mixed with the accumulated
+    gauge transformation."""
+    dims = (8, 6, 4, 12)
+    announce("fused measure", tune)
+    U = orc.generate_links(dims, 51, 0.3)
+    runs = [dict(omega=1.7, theta_target=1e-12),
+            dict(omega=1.7, theta_target=1e-13, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                 finish_format=lgf.LGF_FP64_12),
+            dict(omega=1.7, theta_target=1e-13, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                 finish_format=lgf.LGF_FP64_12, accumulate_g=1)]
+    for kw in runs:
+        out = []
+        for sep in (1, 0):
+            with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+                for f in ALL_FORMATS:
+                    lgf.lgf_set_tuning(lat.h, f, *tune)
+                lat.load(U)
+                st, res, hist = lat.gauge_fix(separate_measure=sep, **kw)
+                out.append((st, res, hist, lat.store()))
+        (st1, r1, h1, U1), (st0, r0, h0, U0) = out
+        assert st1 == st0 == lgf.LGF_OK, kw
+        assert r1["sweeps"] == r0["sweeps"] and r1["sweeps_bulk"] == r0["sweeps_bulk"], kw
+        assert maxabs(U0, U1) < 1e-14, kw
+        assert np.array_equal(h0[:, 0], h1[:, 0])
+        assert np.allclose(h0[:, 1], h1[:, 1], rtol=1e-14, atol=0)
+        assert np.allclose(h0[:, 2], h1[:, 2], rtol=1e-10, atol=1e-28)
+        assert orc.measure(dims, U0)[1] < kw["theta_target"]
