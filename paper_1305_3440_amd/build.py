@@ -22,8 +22,13 @@ ARCH = "gfx950"
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 # (v_pk_*_f32); ordinary scalar FP32 code is generated instead.
+# -ffp-contract=on: multiply-adds are fused only within one source expression,
+# decided before inlining, so a helper (the site update, reunitarization, the
+# theta of a site) gives the same bits in every kernel it is inlined into -- the
+# sweep, its fused-measurement variant, the measurement and the ensemble
+# kernels agree bit for bit.
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

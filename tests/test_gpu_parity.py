@@ -546,8 +546,11 @@ def test_fused_measure_equals_separate_passes(lgf, orc, tune):
         (st1, r1, h1, U1), (st0, r0, h0, U0) = out
         assert st1 == st0 == lgf.LGF_OK, kw
         assert r1["sweeps"] == r0["sweeps"] and r1["sweeps_bulk"] == r0["sweeps_bulk"], kw
-        assert maxabs(U0, U1) < 1e-14, kw
+        assert np.array_equal(U0, U1), (kw, maxabs(U0, U1))
         assert np.array_equal(h0[:, 0], h1[:, 0])
-        assert np.allclose(h0[:, 1], h1[:, 1], rtol=1e-14, atol=0)
-        assert np.allclose(h0[:, 2], h1[:, 2], rtol=1e-10, atol=1e-28)
+        assert np.allclose(h0[:, 1], h1[:, 1], rtol=1e-13, atol=0), kw
+        # theta sums |Delta|^2 with Delta = (K - K^dag)/2i of O(1) entries: a
+        # different summation order of K moves theta by ~eps |K| |Delta| per site
+        dth = np.abs(h0[:, 2] - h1[:, 2])
+        assert np.all(dth <= 1e-14 * np.sqrt(h1[:, 2]) + 1e-12 * h1[:, 2]), (kw, float((dth / h1[:, 2]).max()))
         assert orc.measure(dims, U0)[1] < kw["theta_target"]
