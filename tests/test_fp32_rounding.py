@@ -8,7 +8,9 @@ the FP64 oracle on the FP32-rounded input links.  The worst links exceed
 projection |a| small against |W|, so the rounding of W is amplified by
 |W|/|a|), and the stochastic-relaxation square doubles the angle error.  The
 GPU parity tests therefore bound FP32 sweeps by 2e-6 on 99% of links and
-1e-5 on all, the distribution exact FP32 arithmetic itself produces."""
+2e-5 on all, the distribution exact FP32 arithmetic itself produces: its worst
+link grows with the number of links (2.4e-6..1e-5 on a 4x4x6x10 lattice, 9e-6
+on the 12^4 lattice of the 48-configuration workload, 82944 links)."""
 from __future__ import annotations
 
 import numpy as np
@@ -76,4 +78,35 @@ def test_fp32_tolerance_is_arithmetic(orc):
     e = np.linalg.norm((W.astype(np.complex128) - ref).reshape(-1, 9), axis=1) / np.sqrt(3)
     assert e.max() > 2e-6                        # exact FP32 misses 2e-6 on some links ...
     assert np.quantile(e, 0.99) <= 2e-6          # ... but not on 99% of them
-    assert e.max() <= 1e-5
+    assert e.max() <= 2e-5
+
+
+def test_fp32_tail_grows_with_the_lattice(orc):
+    """The same emulation on a 12^4 configuration of the 48-lattice workload
+    (index 2: seed 102, eps 0.332797, Haar gauge; FP32 12-real input), one full
+    stochastic-relaxation sweep: the worst of its 82944 links is near 1e-5."""
+    import json
+    import os
+    man = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "ensemble48_manifest.json")))["configs"]
+    c = man[2]
+    d, i = tuple(c["dims"]), c["index"]
+    U32 = orc.generate_links(d, c["seed"], c["eps"], True).astype(np.complex64)
+    U32[..., 2, :] = np.conj(np.cross(U32[..., 0, :], U32[..., 1, :]))
+    ref = U32.astype(np.complex128)
+    orc.sweep(d, ref, 1.0, 0.5, seed=5, sweep_index=0, instance=i)
+    W = U32.copy()
+    for par in (0, 1):
+        for s in range(W.shape[0]):
+            if orc.parity(d, s) != par:
+                continue
+            nb = [orc.neighbor(d, s, mu, -1) for mu in range(4)]
+            L = np.array([W[s, mu] for mu in range(4)] + [W[nb[mu], mu] for mu in range(4)])
+            out = _site_update_fp32(L, 1.0, orc.sr_decisions(5, s, 0, i, 0.5))
+            for mu in range(4):
+                W[s, mu] = out[mu]
+                W[nb[mu], mu] = out[4 + mu]
+    W[..., 2, :] = np.conj(np.cross(W[..., 0, :], W[..., 1, :]))
+    e = np.linalg.norm((W.astype(np.complex128) - ref).reshape(-1, 9), axis=1) / np.sqrt(3)
+    assert np.quantile(e, 0.99) <= 2e-6
+    assert 5e-6 < e.max() <= 2e-5

@@ -209,4 +209,4 @@ def test_manifest_ensemble_sr_sampled(lgf, orc):
                 ref = ref.astype(np.complex128)
                 orc.sweep(d, ref, 1.0, 0.5, seed=5, sweep_index=0, instance=i)
                 e = np.linalg.norm((got - ref).reshape(-1, 9), axis=1) / np.sqrt(3)
-                assert np.quantile(e, 0.99) <= 2e-6 and e.max() <= 1e-5, (i, e.max())
+                assert np.quantile(e, 0.99) <= 2e-6 and e.max() <= 2e-5, (i, e.max())
