@@ -149,9 +149,10 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
         out["calibration"][counter] = {"copy_bytes": copy_bytes, "counter_kib": kib,
                                        "bytes_per_counter_unit": scale[counter]}
     import re
-    # sweep_kernel<format, lanes per site, SR, non-temporal, out of place, accumulate g>
+    # sweep_kernel<format, lanes per site, SR, non-temporal, out of place,
+    # accumulate g, fused measurement>: the plain sweep instances
     pat = re.compile(r"sweep_kernel<(\d+),\s*(\d+),\s*(true|false),\s*(true|false),\s*(true|false),"
-                     r"\s*false>")
+                     r"\s*false,\s*false>")
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     for (counter, kname), vals in per.items():
         m = pat.search(kname)
