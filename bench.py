@@ -438,7 +438,9 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        # plain FP64 on the same input
+        # plain FP64 on the same input, its sweep variant autotuned the same way
+        lgf.lgf_autotune(hw, home, 2)
+        extras["fp64_plain_tuning"] = dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home)))
         p64 = lgf.lgf_fix_params_default()
         p64.omega = omega
         p64.theta_target = theta_target
