@@ -437,6 +437,28 @@ def test_64x4_sampled_sweep(lgf, orc, fmt, omega, p_sr):
         assert np.isfinite(F) and np.isfinite(th) and 0 < F < 1
 
 
+def test_large_lattice_beyond_32bit_vector_indices(lgf, orc):
+    """64 x 128^3 (134M sites) in FP64-18: 4.8e9 16-byte vectors, so link
+    addresses pass 2^32 vectors (and 2^36 bytes).  One half-sweep of parity 0
+    checked on sampled sites (the last planes included), then F and theta of
+    the whole field."""
+    dims = (64, 128, 128, 128)
+    seed, eps = 4, 0.3
+    announce("64x128^3 fp64-18")
+    rng = np.random.default_rng(1)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.generate(seed, eps, True)
+        sites = sample_sites(orc, dims, 0, 10, rng)
+        for s in sites[:3]:
+            assert maxabs(gpu_links8(lat, orc, dims, s), oracle_links8(orc, dims, seed, eps, s)) < 1e-13, s
+        lat.sweep(0, 1.8, 0.0, 0, 0)
+        for s in sites:
+            ref, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), 1.8, [0, 0, 0])
+            assert maxabs(gpu_links8(lat, orc, dims, s), ref) < 1e-12, s
+        F, th = lat.measure()
+        assert np.isfinite(F) and np.isfinite(th) and 0 < F < 1
+
+
 # ------------------------------------------------------------ observables, exact mixed precision
 
 @pytest.mark.parametrize("fmt", ALL_FORMATS)
