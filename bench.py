@@ -88,11 +88,18 @@ def cpu_baseline(dims, seed, eps, omega, seconds):
         if el >= seconds or n >= 1000:
             break
     Vs = Lt * dims[1] * dims[2] * dims[3]
+    # and the small 8^4 workload (seed 0, eps 0.25, Haar, omega 1.7) to theta < 1e-12
+    d8 = (8, 8, 8, 8)
+    U8 = oracle.generate_links(d8, 0, 0.25, True)
+    t8 = time.perf_counter()
+    r8 = oracle.gauge_fix(d8, U8, 1.7, 1e-12)
+    t8 = time.perf_counter() - t8
     return {"value": Vs * n / el, "unit": "site-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{n} full OR sweeps (omega {omega}) of a {'x'.join(map(str, sdims))} slab "
                       f"({Vs} sites) with the 64^4 workload's generator (seed {seed}, eps {eps}, "
-                      f"Haar), FP64, {el:.1f} s"}
+                      f"Haar), FP64, {el:.1f} s",
+            "time_to_theta_8x4_s": t8, "sweeps_8x4": r8["sweeps"]}
 
 
 def traffic_run(lgf, torch, dims, seed, eps, omega):
@@ -477,6 +484,16 @@ def main():
     del work, pristine
     torch.cuda.empty_cache()
     if not args.no_extras:
+        # the small 8^4 workload to theta < 1e-12, plain FP64-18 (its oracle time is in cpu_baseline)
+        h8 = lgf.lgf_create((8, 8, 8, 8), home, stream)
+        lgf.lgf_generate_links(h8, 0, 0.25, True)
+        p8 = lgf.lgf_fix_params_default()
+        p8.omega, p8.theta_target = 1.7, 1e-12
+        lgf.lgf_synchronize(h8)
+        st8, r8, _ = lgf.lgf_gauge_fix(h8, p8)
+        lgf.lgf_destroy(h8)
+        extras["gauge_8x4"] = {"status": int(st8), "sweeps": r8["sweeps"],
+                               "time_to_theta_s": r8["t_total_ms"] / 1e3, "theta": r8["theta"]}
         log("[bench] 32^4 plain vs mixed, plaquette drift")
         extras["gauge_32x4"] = gauge_32x4_bench(lgf, torch, stream)
         log(f"[bench] 32^4: {json.dumps(extras['gauge_32x4'])}")
