@@ -265,6 +265,17 @@ def lgf_time_sweeps(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0,
     return ms.value
 
 
+def fix_params(**kw) -> "lgf_fix_params":
+    """lgf_fix_params_default() with the named fields replaced (unknown names raise)."""
+    p = lgf_fix_params_default()
+    names = {f[0] for f in lgf_fix_params._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"lgf_fix_params has no field {k!r}")
+        setattr(p, k, v)
+    return p
+
+
 def lgf_copy_bandwidth(nbytes: int, reps: int = 10, stream=None) -> float:
     """Read + write GB/s of a plain device copy of nbytes (the streaming ceiling)."""
     gbs = ctypes.c_double()
@@ -326,9 +337,7 @@ class Lattice:
         return lgf_measure(self.h)
 
     def gauge_fix(self, **kw):
-        p = lgf_fix_params_default()
-        for k, v in kw.items():
-            setattr(p, k, v)
+        p = fix_params(**kw)
         return lgf_gauge_fix(self.h, p)
 
     def plaquette(self):
@@ -341,9 +350,7 @@ class Lattice:
         return lgf_measure_coulomb(self.h, self.dims[0])
 
     def coulomb_gauge_fix(self, **kw):
-        p = lgf_fix_params_default()
-        for k, v in kw.items():
-            setattr(p, k, v)
+        p = fix_params(**kw)
         return lgf_coulomb_gauge_fix(self.h, p, self.dims[0])
 
 
@@ -527,9 +534,7 @@ class Ensemble:
         return lgf_ensemble_measure(self.e, self.n)
 
     def gauge_fix(self, **kw):
-        p = lgf_fix_params_default()
-        for k, v in kw.items():
-            setattr(p, k, v)
+        p = fix_params(**kw)
         return lgf_ensemble_gauge_fix(self.e, p, self.n)
 
     def time_sweeps(self, fmt, n, omega, p_sr=0.0):

@@ -131,3 +131,10 @@ def test_binding_holds_no_arithmetic():
     src = open(os.path.join(ROOT, "paper_1305_3440_amd", "lgf.py")).read()
     for forbidden in ("np.linalg", "np.einsum", "@ ", "np.exp", "import oracle", "from oracle"):
         assert forbidden not in src, forbidden
+
+
+def test_fix_params_rejects_unknown_fields(lgf):
+    p = lgf.fix_params(omega=1.5, separate_measure=1)
+    assert p.omega == 1.5 and p.separate_measure == 1 and p.check_every == 20
+    with pytest.raises(TypeError):
+        lgf.fix_params(omgea=1.5)
