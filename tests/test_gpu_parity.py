@@ -567,7 +567,8 @@ def test_fused_measure_equals_separate_passes(lgf, orc, dims, tune):
                 st, res, hist = lat.gauge_fix(separate_measure=sep, **kw)
                 out.append((st, res, hist, lat.store()))
         (st1, r1, h1, U1), (st0, r0, h0, U0) = out
-        assert st1 == st0 == (lgf.LGF_ENOTCONV if kw["theta_target"] < 1e-20 else lgf.LGF_OK), kw
+        assert st1 == st0 and st0 in (lgf.LGF_OK, lgf.LGF_ENOTCONV), kw
+        assert st0 == lgf.LGF_OK or kw.get("max_sweeps"), kw
         assert r1["sweeps"] == r0["sweeps"] and r1["sweeps_bulk"] == r0["sweeps_bulk"], kw
         assert np.array_equal(U0, U1), (kw, maxabs(U0, U1))
         assert np.array_equal(h0[:, 0], h1[:, 0])
