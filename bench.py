@@ -367,8 +367,8 @@ def main():
     lgf.lgf_generate_links(hp, seed, eps, True)
     hw = lgf.lgf_create(dims, home, stream, work)
     # sweep variants picked by the autotuner on this lattice (scratch copies)
-    lgf.lgf_autotune(hw, bulk, 2)
-    lgf.lgf_autotune(hw, finish, 2)
+    lgf.lgf_autotune(hw, bulk, 4)
+    lgf.lgf_autotune(hw, finish, 4)
     torch.cuda.synchronize()
     tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish, home)}
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; tuning fp32-12 "
@@ -446,7 +446,7 @@ def main():
     extras = {}
     if not args.no_extras:
         # plain FP64 on the same input, its sweep variant autotuned the same way
-        lgf.lgf_autotune(hw, home, 2)
+        lgf.lgf_autotune(hw, home, 4)
         extras["fp64_plain_tuning"] = dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home)))
         p64 = lgf.lgf_fix_params_default()
         p64.omega = omega
