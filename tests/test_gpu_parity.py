@@ -267,16 +267,25 @@ def test_mixed_gauge_fix_reaches_target(lgf, orc, bulk, finish):
 
 
 def test_gauge_fix_graph_equals_direct(lgf, orc):
+    """Chunks replayed from captured graphs (each replay followed by the
+    eager measurement that reads the partial sums the graph's last launch
+    wrote) against direct launches: the same links and the same F, theta at
+    every check, plain and mixed."""
     dims = (8, 6, 4, 12)
     announce("graph_vs_direct")
     U = orc.generate_links(dims, 2, 0.3)
-    outs = []
-    for use_graph in (0, 1, 1):
-        with lgf.Lattice(dims, 0) as lat:
-            lat.load(U)
-            st, res, _ = lat.gauge_fix(omega=1.6, theta_target=1e-12, use_graph=use_graph)
-            outs.append(lat.store())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    for kw in (dict(omega=1.6, theta_target=1e-12),
+               dict(omega=1.6, theta_target=1e-13, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                    finish_format=lgf.LGF_FP64_12)):
+        outs = []
+        for use_graph in (0, 1, 1):
+            with lgf.Lattice(dims, 0) as lat:
+                lat.load(U)
+                st, res, hist = lat.gauge_fix(use_graph=use_graph, **kw)
+                assert st == lgf.LGF_OK and hist.shape[0] > 5
+                outs.append((lat.store(), hist))
+        for got, hist in outs[1:]:
+            assert np.array_equal(got, outs[0][0]) and np.array_equal(hist, outs[0][1]), kw
 
 
 def test_sweep_schedules_are_bitwise_identical(lgf, orc):
