@@ -91,3 +91,14 @@ def expm_hermitian(H, eps):
     """exp(i eps H) for Hermitian H via its eigendecomposition"""
     w, v = np.linalg.eigh(H)
     return (v * np.exp(1j * eps * w)[..., None, :]) @ dag(v)
+
+
+def stored_as(U, fmt):
+    """U as a field in storage format fmt holds it, computed on the host: the
+    FP32 formats (1 FP32-18, 2 FP32-12) round every entry to single precision,
+    the 12-real formats (2, 3 FP64-12) keep rows 0 and 1 and rebuild row 2 as
+    conj(row0 x row1) in the storage precision; format 0 (FP64-18) is U."""
+    W = U.astype(np.complex64) if fmt in (1, 2) else U.copy()
+    if fmt in (2, 3):
+        W[..., 2, :] = np.conj(np.cross(W[..., 0, :], W[..., 1, :]))
+    return W.astype(np.complex128)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import gpu_available
-from lattice_np import unitarity_error
+from lattice_np import stored_as, unitarity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -57,11 +57,12 @@ def test_coulomb_measure_matches_oracle(lgf, orc, fmt):
     U = orc.generate_links(dims, 32, 0.35)
     with lgf.Lattice(dims, fmt) as lat:
         lat.load(U)
-        U0 = lat.store()
         F, th = lat.measure_coulomb()
-    Fr, thr = orc.measure_coulomb(dims, U0)
-    assert np.abs(F - Fr).max() < 1e-14
-    assert np.abs(th - thr).max() < 1e-12 * thr.max()
+    Fr, thr = orc.measure_coulomb(dims, stored_as(U, fmt))
+    # FP32 12-real: row 2 rebuilt with fused multiply-adds on the GPU, without on the host
+    tol = 2e-7 if fmt == 2 else 1e-12
+    assert np.abs(F - Fr).max() < (2e-7 if fmt == 2 else 1e-14)
+    assert np.abs(th - thr).max() < tol * thr.max()
 
 
 def test_coulomb_gauge_fix_matches_oracle(lgf, orc):

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from conftest import gpu_available
-from lattice_np import dag, parity_grid, unitarity_error
+from lattice_np import dag, parity_grid, stored_as, unitarity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -116,13 +116,6 @@ def test_peek_matches_store(lgf, orc):
 
 # ------------------------------------------------------------ one sweep
 
-def gpu_input(lgf, dims, fmt, U):
-    """the links as the GPU holds them after loading U in format fmt"""
-    with lgf.Lattice(dims, fmt) as lat:
-        lat.load(U)
-        return lat.store()
-
-
 # (lanes per site, block, XCD remap, non-temporal, schedule: 0 in place,
 # 1 t-slice pipeline, 2 out of place[, sites per thread])
 TUNINGS = [(1, 128, 0, 1, 0), (2, 128, 1, 1, 1), (4, 64, 0, 1, 0), (4, 256, 1, 0, 1), (1, 64, 1, 1, 1),
@@ -138,7 +131,7 @@ def test_half_and_full_sweep_match_oracle(lgf, orc, fmt, dims, omega, p_sr):
     two calls or as one parity-2 call), on the same input links."""
     announce("sweep", fmt, dims, omega, p_sr)
     U = orc.generate_links(dims, 7, 0.35)
-    U0 = gpu_input(lgf, dims, fmt, U)
+    U0 = stored_as(U, fmt)   # the field a load of U in this format holds (up to its row-2 rounding)
     ref_half = U0.copy()
     orc.half_sweep(dims, ref_half, 0, omega, p_sr, seed=9, sweep=3)
     ref_full = ref_half.copy()
@@ -187,13 +180,15 @@ def test_measure_matches_oracle(lgf, orc, fmt):
     dims = (8, 6, 4, 12)
     announce("measure", fmt, dims)
     U = orc.generate_links(dims, 3, 0.4)
-    U0 = gpu_input(lgf, dims, fmt, U)
-    F_ref, th_ref = orc.measure(dims, U0)
+    F_ref, th_ref = orc.measure(dims, stored_as(U, fmt))
     with lgf.Lattice(dims, fmt) as lat:
         lat.load(U)
         F, th = lat.measure()
-    assert abs(F - F_ref) < 1e-14 * abs(F_ref) + 1e-15
-    assert abs(th - th_ref) < 1e-12 * th_ref
+    # FP32 12-real: the GPU rebuilds row 2 with fused multiply-adds, the host
+    # without, so its entries may differ by an FP32 rounding unit
+    ftol, thtol = (2e-7, 2e-7) if fmt == 2 else (1e-14, 1e-12)
+    assert abs(F - F_ref) < ftol * abs(F_ref) + 1e-15
+    assert abs(th - th_ref) < thtol * th_ref
 
 
 @pytest.mark.parametrize("fmt", ALL_FORMATS)
@@ -203,8 +198,7 @@ def test_reunitarize_matches_oracle(lgf, orc, fmt):
     rng = np.random.default_rng(0)
     U = orc.generate_links(dims, 3, 0.4)
     noisy = U + 1e-4 * (rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape))
-    U0 = gpu_input(lgf, dims, fmt, noisy)
-    ref = U0.copy()
+    ref = stored_as(noisy, fmt)
     orc.reunitarize(ref)
     with lgf.Lattice(dims, fmt) as lat:
         lat.load(noisy)
@@ -477,9 +471,9 @@ def test_plaquette_matches_oracle(lgf, orc, fmt):
     U = orc.generate_links(dims, 14, 0.4)
     with lgf.Lattice(dims, fmt) as lat:
         lat.load(U)
-        U0 = lat.store()
         P = lat.plaquette()
-    assert abs(P - orc.plaquette(dims, U0)) < 1e-14
+    # FP32 12-real: row 2 rebuilt with fused multiply-adds on the GPU, without on the host
+    assert abs(P - orc.plaquette(dims, stored_as(U, fmt))) < (2e-7 if fmt == 2 else 1e-14)
 
 
 def _loops(orc, dims, U):
