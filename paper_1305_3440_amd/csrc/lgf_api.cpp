@@ -91,6 +91,8 @@ struct GraphEntry {
     int coulomb;
     void *gacc;
     int fused;
+    double p_sr;
+    uint64_t seed;
     hipGraphExec_t exec;
 };
 
@@ -120,6 +122,8 @@ struct lgf_lattice {
     void *partner[4];  // owned second buffer per format for the out-of-place schedule
     double *d_fused;   // partial sums of the measurement fused into a sweep
     size_t fused_cap;  // (F, theta) pairs d_fused holds
+    uint64_t *d_sweep_base;               // device copy of a chunk's first SR counter
+    const uint64_t *sweep_base_active;    // passed to the sweeps while a chunk is captured
     lgf::SweepTuning tune[4];
     std::vector<GraphEntry> graphs;
     hipEvent_t ev0, ev1;
@@ -224,6 +228,7 @@ lgf_status sweep_launch(lgf_lattice *h, int format, void *field, int parity, dou
     lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
     a.gacc = h->gacc_active;
     a.meas = meas;
+    a.sweep_base = h->sweep_base_active;
     if (coulomb)
         LGF_HIP(lgf::launch_sweep_coulomb(format, field, h->geom, a, h->d_mask, h->tune[format].nontemporal != 0,
                                           h->stream));
@@ -252,6 +257,7 @@ lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, dou
         if (!partner || partner == field) return fail(LGF_ESTATE, "no partner buffer for the out-of-place sweep");
         lgf::SweepArgs a{0, omega, p_sr, seed, sweep_index, 0u};
         a.gacc = h->gacc_active;
+        a.sweep_base = h->sweep_base_active;
         a.out = partner;
         LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
         a.parity = 1;
@@ -271,6 +277,7 @@ lgf_status full_sweep(lgf_lattice *h, int format, void *field, double omega, dou
     auto slice = [&](int parity, int t) -> lgf_status {
         lgf::SweepArgs a{parity, omega, p_sr, seed, sweep_index, 0u};
         a.gacc = h->gacc_active;
+        a.sweep_base = h->sweep_base_active;
         a.h_begin = (uint32_t)t * hs;
         a.h_end = (uint32_t)(t + 1) * hs;
         LGF_HIP(lgf::launch_sweep(format, field, h->geom, a, h->tune[format], h->stream));
@@ -383,16 +390,21 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
 {
     if (fused) LGF_TRY(ensure_fused(h, format));
     auto meas_of = [&](int k) { return (fused && k == n - 1) ? h->d_fused : nullptr; };
-    if (!use_graph || p_sr > 0.0) {
+    if (!use_graph) {
         for (int k = 0; k < n; ++k)
             LGF_TRY(full_sweep(h, format, field, omega, p_sr, seed, sweep0 + (uint64_t)k, coulomb, meas_of(k)));
         return LGF_OK;
     }
+    // stochastic relaxation: the captured sweeps carry counter offsets 0..n-1
+    // and read the chunk's first counter from the device, set here outside
+    // the graph, so one graph serves every chunk
+    const bool sr = p_sr > 0.0;
+    if (sr) LGF_HIP(lgf::launch_set_u64(h->d_sweep_base, sweep0, h->stream));
     const lgf::SweepTuning &t = h->tune[format];
     for (auto &g : h->graphs) {
         if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
             g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active && g.fused == (fused ? 1 : 0) &&
-            g.tune == t) {
+            g.p_sr == p_sr && (!sr || g.seed == seed) && g.tune == t) {
             LGF_HIP(hipGraphLaunch(g.exec, h->stream));
             return LGF_OK;
         }
@@ -400,8 +412,11 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     hipGraph_t graph = nullptr;
     LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     lgf_status st = LGF_OK;
+    h->sweep_base_active = sr ? h->d_sweep_base : nullptr;
     for (int k = 0; k < n && st == LGF_OK; ++k)
-        st = full_sweep(h, format, field, omega, 0.0, seed, sweep0 + (uint64_t)k, coulomb, meas_of(k));
+        st = full_sweep(h, format, field, omega, p_sr, seed, sr ? (uint64_t)k : sweep0 + (uint64_t)k, coulomb,
+                        meas_of(k));
+    h->sweep_base_active = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (st != LGF_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -416,7 +431,8 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
         (void)hipGraphExecDestroy(h->graphs.front().exec);
         h->graphs.erase(h->graphs.begin());
     }
-    h->graphs.push_back(GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, fused ? 1 : 0, exec});
+    h->graphs.push_back(
+        GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, fused ? 1 : 0, p_sr, seed, exec});
     LGF_HIP(hipGraphLaunch(exec, h->stream));
     return LGF_OK;
 }
@@ -510,6 +526,7 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     const int nb = lgf::measure_blocks(h->geom);
     if ((e = hipMalloc(&h->d_partials, (size_t)4 * nb * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&h->d_out, 2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->d_sweep_base, sizeof(uint64_t))) != hipSuccess ||
         (e = hipHostMalloc((void **)&h->h_out, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess) {
         (void)hipGetLastError();
@@ -532,6 +549,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
     }
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_fused) (void)hipFree(h->d_fused);
+    if (h->d_sweep_base) (void)hipFree(h->d_sweep_base);
     if (h->d_out) (void)hipFree(h->d_out);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->d_stage) (void)hipFree(h->d_stage);

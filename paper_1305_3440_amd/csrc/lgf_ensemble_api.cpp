@@ -26,6 +26,8 @@ struct EnsGraph {
     int fa, fb;
     int n_sweeps;
     double omega;
+    double p_sr;
+    uint64_t seed;
     bool nt;
     int tile, grid_mult;
     hipGraphExec_t exec;
@@ -170,7 +172,10 @@ lgf::EnsRelax relax_args(double omega, double p_sr, uint64_t seed)
     return r;
 }
 
-// n full sweeps of every listed configuration, counters from sweep0
+// n full sweeps of every listed configuration, counters from sweep0.  The
+// kernels read the counter base from device memory (set here, outside any
+// graph), so a captured chunk replays for any sweep0, stochastic relaxation
+// included.
 lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, double p_sr, uint64_t seed,
                      uint64_t sweep0, bool use_graph)
 {
@@ -179,15 +184,15 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
     const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
     const lgf::EnsLaunch L = launch_desc(e, fa, fb, sr);
     const bool nt = e->nontemporal != 0;
-    if (!use_graph || sr) {
+    if (!use_graph) {
         for (int k = 0; k < n; ++k)
             for (int parity = 0; parity < 2; ++parity)
                 LGF_HIP(lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream));
         return LGF_OK;
     }
     for (auto &g : e->graphs)
-        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.nt == nt && g.tile == e->tile &&
-            g.grid_mult == e->grid_mult) {
+        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.p_sr == p_sr &&
+            (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult) {
             LGF_HIP(hipGraphLaunch(g.exec, e->stream));
             return LGF_OK;
         }
@@ -196,7 +201,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
     hipError_t err = hipSuccess;
     for (int k = 0; k < n && err == hipSuccess; ++k)
         for (int parity = 0; parity < 2 && err == hipSuccess; ++parity)
-            err = lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, false, nt, e->stream);
+            err = lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream);
     hipError_t e2 = hipStreamEndCapture(e->stream, &graph);
     if (err != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -210,7 +215,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, nt, e->tile, e->grid_mult, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }

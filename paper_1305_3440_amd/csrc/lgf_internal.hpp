@@ -44,7 +44,11 @@ struct SweepArgs {
     void *gacc = nullptr;    // site field accumulating G (same format as the links), or none
     void *out = nullptr;     // out-of-place target field (whole half-sweep only), or in place
     double *meas = nullptr;  // fused reunitarize + measure: per-workgroup (F, theta) partial sums
+    const uint64_t *sweep_base = nullptr;  // SR counter = *sweep_base + sweep_index when set
 };
+
+// *p = v, as a one-lane kernel on the stream (safe inside a captured graph)
+hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 
 // workgroups of a whole half-sweep with tuning t (the partial sums a fused
 // measurement writes)

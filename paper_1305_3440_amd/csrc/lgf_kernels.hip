@@ -108,7 +108,7 @@ static hipError_t launch_sweep_t(void *field, const Geom &g, const SweepArgs &a,
     const uint32_t ng = (nb + spt - 1) / spt;                                     // workgroups
     const uint32_t grid = t.xcd_remap ? ((ng + 7u) / 8u) * 8u : ng;
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
-                    (uint32_t)a.sweep_index, a.instance, a.gacc};
+                    (uint32_t)a.sweep_index, a.instance, a.gacc, a.sweep_base};
     const bool sr = a.p_sr > 0.0;
     if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
     if (a.meas) {
@@ -581,7 +581,7 @@ static hipError_t launch_sweep_coulomb_t(void *field, const Geom &g, const Sweep
     using T = typename Fmt<F>::T;
     const dim3 grid((g.Vh + 127) / 128);
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
-                    (uint32_t)a.sweep_index, a.instance};
+                    (uint32_t)a.sweep_index, a.instance, nullptr, a.sweep_base};
     if (a.p_sr > 0.0) {
         ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
         hipLaunchKernelGGL((sweep_coulomb_kernel<F, true, NT>), grid, dim3(128), 0, s, field, g, a.parity, ra,

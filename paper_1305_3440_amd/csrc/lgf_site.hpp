@@ -96,6 +96,9 @@ template <typename T> struct RelaxArgs {
     uint32_t key0, key1;    // Philox key (seed)
     uint32_t sweep, instance;
     void *gacc = nullptr;   // accumulated gauge transformation (site field) or none
+    // when set, the stochastic-relaxation counter is *sweep_base + sweep (read
+    // on the device, so a captured chunk replays for any starting counter)
+    const uint64_t *sweep_base = nullptr;
 };
 
 // A site field (one SU(3) matrix per site, e.g. an accumulated gauge
@@ -173,7 +176,8 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
 
     bool sq0 = false, sq1 = false, sq2 = false;
     if constexpr (SR) {
-        const uint4 w = philox4x32_10(make_uint4(lex_index(g, c), a.sweep, a.instance, 3u), a.key0, a.key1);
+        const uint32_t sweep = a.sweep_base ? (uint32_t)(*a.sweep_base + a.sweep) : a.sweep;
+        const uint4 w = philox4x32_10(make_uint4(lex_index(g, c), sweep, a.instance, 3u), a.key0, a.key1);
         sq0 = (uint64_t)w.x < a.sr_threshold;
         sq1 = (uint64_t)w.y < a.sr_threshold;
         sq2 = (uint64_t)w.z < a.sr_threshold;

@@ -163,6 +163,30 @@ def test_ensemble_tunings_are_bitwise_identical(lgf, orc):
             lgf.lgf_ensemble_set_tuning(ens.e, 96, 1, 1)
 
 
+def test_ensemble_sr_graph_equals_direct(lgf, orc):
+    """Stochastic relaxation chunks replayed from captured graphs read their
+    sweep counter from device memory: the same coins, hence the same links and
+    sweep counts, as direct launches."""
+    announce("ensemble sr graph")
+    dims = [(4, 4, 6, 10), (6, 4, 4, 8), (8, 8, 8, 8)]
+    Us = [orc.generate_links(d, 70 + i, 0.3) for i, d in enumerate(dims)]
+    outs = []
+    for use_graph in (0, 1):
+        with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+            for i, U in enumerate(Us):
+                ens.load(i, U)
+            st, res = ens.gauge_fix(omega=1.0, p_sr=0.5, seed=9, theta_target=1e-11, use_graph=use_graph)
+            assert st == lgf.LGF_OK
+            outs.append(([ens.store(i) for i in range(len(dims))], [r["sweeps"] for r in res]))
+    assert outs[0][1] == outs[1][1]
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    # and the oracle's stochastic relaxation (instance = configuration index) agrees
+    ref = Us[0].copy()
+    r = orc.gauge_fix(dims[0], ref, 1.0, 1e-11, p=0.5, seed=9, instance=0)
+    assert r["sweeps"] == outs[0][1][0] and maxabs(outs[0][0][0], ref) < 1e-9
+
+
 def test_ensemble_not_converged_and_args(lgf, orc):
     announce("ensemble status")
     dims = [(4, 4, 4, 4), (4, 4, 4, 6)]

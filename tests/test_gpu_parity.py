@@ -264,13 +264,15 @@ def test_gauge_fix_graph_equals_direct(lgf, orc):
     """Chunks replayed from captured graphs (each replay followed by the
     eager measurement that reads the partial sums the graph's last launch
     wrote) against direct launches: the same links and the same F, theta at
-    every check, plain and mixed."""
+    every check, plain, mixed, and stochastic relaxation (whose replays read
+    the chunk's first counter from the device)."""
     dims = (8, 6, 4, 12)
     announce("graph_vs_direct")
     U = orc.generate_links(dims, 2, 0.3)
     for kw in (dict(omega=1.6, theta_target=1e-12),
                dict(omega=1.6, theta_target=1e-13, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
-                    finish_format=lgf.LGF_FP64_12)):
+                    finish_format=lgf.LGF_FP64_12),
+               dict(omega=1.0, p_sr=0.5, seed=3, theta_target=1e-11, sweep_offset=1000)):
         outs = []
         for use_graph in (0, 1, 1):
             with lgf.Lattice(dims, 0) as lat:
