@@ -101,3 +101,63 @@ def test_coulomb_mixed_gauge_fix(lgf, orc):
     # gauge invariance: the temporal plaquettes are those of the input
     for nu in (1, 2, 3):
         assert abs(orc.wilson_loop(dims, got, 0, nu, 1, 1) - orc.wilson_loop(dims, U, 0, nu, 1, 1)) < 1e-5
+
+
+def _links8(orc, dims, seed, eps, s):
+    fw = [orc.generated_link(dims, seed, eps, True, s, mu) for mu in range(4)]
+    bw = [orc.generated_link(dims, seed, eps, True, orc.neighbor(dims, s, mu, -1), mu) for mu in range(4)]
+    return np.array(fw + bw)
+
+
+def _gpu_links8(lat, orc, dims, s):
+    nb = [orc.neighbor(dims, s, mu, -1) for mu in range(4)]
+    P = lat.peek([s] + nb)
+    return np.array([P[0, mu] for mu in range(4)] + [P[1 + mu, mu] for mu in range(4)])
+
+
+@pytest.mark.parametrize("fmt", [3, 2])
+def test_coulomb_48x3x96_sampled(lgf, orc, fmt):
+    """The Coulomb workload at its full size (48^3 x 96, seed 5, eps 0.3, Haar
+    gauge), in the formats of its mixed run: one parity-0 half-sweep with every
+    other timeslice frozen, checked on sampled sites against the oracle's local
+    update from its own generator (active timeslices) and against the
+    untouched links (frozen ones); then F_C(t), theta_C(t) of every timeslice
+    are finite, and only the relaxed timeslices gained in F_C."""
+    dims = (96, 48, 48, 48)
+    seed, eps, omega = 5, 0.3, 1.7
+    announce("coulomb 48^3x96 sampled", fmt)
+    V3 = 48 ** 3
+    mask = [1 if t % 2 == 0 else 0 for t in range(dims[0])]
+    rng = np.random.default_rng(3)
+    V = dims[0] * V3
+    cand = [0, 1, 47, V3 - 1, V3, V - 1, V - 2, 95 * V3 + 48] + [int(x) for x in rng.integers(0, V, 200)]
+    sites = [s for s in cand if orc.parity(dims, s) == 0][:24]
+    errs = []
+    with lgf.Lattice(dims, fmt) as lat:
+        lat.generate(seed, eps, True)
+        before = {s: _gpu_links8(lat, orc, dims, s) for s in sites}
+        lat.sweep_coulomb(0, omega, 0.0, 0, 0, slice_active=mask)
+        for s in sites:
+            got = _gpu_links8(lat, orc, dims, s)
+            if mask[s // V3]:
+                ref, _ = orc.local_update_coulomb(_links8(orc, dims, seed, eps, s), omega, [0, 0, 0])
+                if fmt == 3:
+                    assert maxabs(got, ref) < 1e-12, s
+                else:
+                    errs.extend(np.linalg.norm((got - ref).reshape(-1, 9), axis=1)
+                                / np.linalg.norm(ref.reshape(-1, 9), axis=1))
+            else:
+                # a frozen site's spatial links (forward and backward) are only
+                # ever written by sites of its own timeslice
+                for k in (1, 2, 3, 5, 6, 7):
+                    assert np.array_equal(got[k], before[s][k]), (s, k)
+        F, th = lat.measure_coulomb()
+    assert sum(mask[s // V3] for s in sites) >= 6 and sum(1 - mask[s // V3] for s in sites) >= 6
+    if errs:
+        e = np.array(errs)
+        assert float(np.quantile(e, 0.99)) <= 2e-6 and float(e.max()) <= 2e-5
+    # from a Haar-random gauge F_C(t) starts near 0 (either sign); the relaxed
+    # timeslices gained, the frozen ones did not
+    act = np.array(mask, dtype=bool)
+    assert np.all(np.isfinite(F)) and np.all(np.abs(F) < 1) and np.all(th > 0)
+    assert F[act].min() > 100 * np.abs(F[~act]).max()
