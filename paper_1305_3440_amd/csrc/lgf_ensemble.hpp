@@ -48,8 +48,10 @@ struct EnsLaunch {      // device pointers of one ensemble's work list
     uint32_t tile;      // sites per tile = lanes per workgroup (64, 128 or 256)
 };
 
+// meas (optional): the fused reunitarization + measurement, its per-tile
+// partial sums written to the second-pass slots of the measurement layout
 hipError_t launch_ensemble_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
-                                 uint32_t sweep_offset, bool sr, bool nt, hipStream_t s);
+                                 uint32_t sweep_offset, bool sr, bool nt, hipStream_t s, double *meas = nullptr);
 hipError_t launch_ensemble_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
                                    bool reunit_fwd, bool reunit_bwd, double *partials, hipStream_t s);
 hipError_t launch_ensemble_finish(const double *partials, uint32_t n_tiles, const EnsSpan *spans,

@@ -30,6 +30,7 @@ struct EnsGraph {
     uint64_t seed;
     bool nt;
     int tile, grid_mult;
+    bool fused;
     hipGraphExec_t exec;
 };
 
@@ -176,23 +177,29 @@ lgf::EnsRelax relax_args(double omega, double p_sr, uint64_t seed)
 // kernels read the counter base from device memory (set here, outside any
 // graph), so a captured chunk replays for any sweep0, stochastic relaxation
 // included.
+// fused: the chunk's last parity-1 launch also reunitarizes and leaves its
+// tiles' (F, theta) sums in the second-pass slots of d_partials (the caller
+// checked overrelaxation and non-temporal access; see measure_listed_fused)
 lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, double p_sr, uint64_t seed,
-                     uint64_t sweep0, bool use_graph)
+                     uint64_t sweep0, bool use_graph, bool fused = false)
 {
     LGF_HIP(lgf::launch_set_u64(e->d_sweep_base, sweep0, e->stream));
     const bool sr = p_sr > 0.0;
     const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
     const lgf::EnsLaunch L = launch_desc(e, fa, fb, sr);
     const bool nt = e->nontemporal != 0;
+    auto meas_of = [&](int k, int parity) { return (fused && k == n - 1 && parity == 1) ? e->d_partials : nullptr; };
     if (!use_graph) {
         for (int k = 0; k < n; ++k)
             for (int parity = 0; parity < 2; ++parity)
-                LGF_HIP(lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream));
+                LGF_HIP(lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream,
+                                                   meas_of(k, parity)));
         return LGF_OK;
     }
     for (auto &g : e->graphs)
         if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.p_sr == p_sr &&
-            (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult) {
+            (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult &&
+            g.fused == fused) {
             LGF_HIP(hipGraphLaunch(g.exec, e->stream));
             return LGF_OK;
         }
@@ -201,7 +208,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
     hipError_t err = hipSuccess;
     for (int k = 0; k < n && err == hipSuccess; ++k)
         for (int parity = 0; parity < 2 && err == hipSuccess; ++parity)
-            err = lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream);
+            err = lgf::launch_ensemble_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, nt, e->stream, meas_of(k, parity));
     hipError_t e2 = hipStreamEndCapture(e->stream, &graph);
     if (err != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -215,7 +222,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }
@@ -228,6 +235,20 @@ lgf_status measure_listed(lgf_ensemble *e, int fa, int fb, uint32_t nt, const st
     const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
     LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 0, reunit, reunit, e->d_partials, e->stream));
     LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 1, reunit, false, e->d_partials + 2 * (size_t)nt, e->stream));
+    LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
+    LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    return LGF_OK;
+}
+
+// F, theta after a chunk whose last parity-1 launch was fused: its per-tile
+// sums (second pass) plus a read-only parity-0 pass (first pass), then the
+// per-configuration finish, as in measure_listed
+lgf_status measure_listed_fused(lgf_ensemble *e, int fa, int fb, uint32_t nt, const std::vector<int> &listed)
+{
+    if (nt == 0) return LGF_OK;
+    const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
+    LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 0, false, false, e->d_partials, e->stream));
     LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
     LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
     LGF_HIP(hipStreamSynchronize(e->stream));
@@ -538,8 +559,10 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf
         const int fa = any_bulk ? bulk : finish, fb = any_finish ? finish : bulk;
         const int64_t left = p.max_sweeps - sweeps;
         const int n = (int)(left < p.check_every ? left : p.check_every);
+        // reunitarize + measure inside the chunk's last half-sweep where possible
+        const bool fuse = !p.separate_measure && p.p_sr == 0.0 && e->nontemporal != 0;
         LGF_HIP(hipEventRecord(e->ev0, e->stream));
-        LGF_TRY(run_chunk(e, fa, fb, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0));
+        LGF_TRY(run_chunk(e, fa, fb, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0, fuse));
         LGF_HIP(hipEventRecord(e->ev1, e->stream));
         LGF_HIP(hipEventSynchronize(e->ev1));
         const double ms = lgf::elapsed_ms(e->ev0, e->ev1);
@@ -547,7 +570,10 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf
         sweeps += n;
         ctr += (uint64_t)n;
         LGF_HIP(hipEventRecord(e->ev0, e->stream));
-        LGF_TRY(measure_listed(e, fa, fb, nt, listed, true));
+        if (fuse)
+            LGF_TRY(measure_listed_fused(e, fa, fb, nt, listed));
+        else
+            LGF_TRY(measure_listed(e, fa, fb, nt, listed, true));
         LGF_HIP(hipEventRecord(e->ev1, e->stream));
         LGF_HIP(hipEventSynchronize(e->ev1));
         t_meas += lgf::elapsed_ms(e->ev0, e->ev1);

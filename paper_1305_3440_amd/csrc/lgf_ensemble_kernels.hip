@@ -18,22 +18,26 @@
 
 namespace lgf {
 
-template <int F, bool SR, bool NT>
+template <int F, bool SR, bool NT, bool MEAS>
 __device__ __forceinline__ void ensemble_site(const EnsCfg &c, int parity, uint32_t h, bool active,
-                                              const EnsRelax &r, uint32_t sweep)
+                                              const EnsRelax &r, uint32_t sweep, MeasAcc *acc)
 {
     using T = typename Fmt<F>::T;
     const RelaxArgs<T> a{(T)r.omega, r.overrelax, r.sr_threshold, r.key0, r.key1, sweep, c.instance};
-    update_site<F, 1, SR, NT>(c.field, c.g, parity, h, 0, active, a);
+    update_site<F, 1, SR, NT, 0, false, false, MEAS>(c.field, c.g, parity, h, 0, active, a, nullptr, nullptr, acc);
 }
 
-// FA, FB: the (at most two) storage formats the launch may meet.
-template <int FA, int FB, bool SR, bool NT>
+// FA, FB: the (at most two) storage formats the launch may meet.  MEAS: the
+// links are reunitarized as they are written and each tile t leaves its
+// sites' (F, theta) sums in partials[2 (n + t)], the second-pass slots of the
+// ensemble measurement's layout (n = the listed tiles).
+template <int FA, int FB, bool SR, bool NT, bool MEAS = false>
 __global__ void __launch_bounds__(kEnsMaxTile) ensemble_sweep_kernel(const EnsCfg *__restrict__ cfgs,
                                                                    const EnsTile *__restrict__ tiles,
                                                                    const uint32_t *__restrict__ n_tiles,
                                                                    const uint64_t *__restrict__ sweep_base,
-                                                                   int parity, EnsRelax r, uint32_t sweep_offset)
+                                                                   int parity, EnsRelax r, uint32_t sweep_offset,
+                                                                   double *__restrict__ partials)
 {
     const uint32_t n = *n_tiles;
     const uint32_t sweep = (uint32_t)(*sweep_base + sweep_offset);
@@ -43,8 +47,13 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_sweep_kernel(const EnsCf
         const uint32_t h0 = w.h0 + threadIdx.x;
         const bool active = h0 < c.g.Vh;
         const uint32_t h = active ? h0 : c.g.Vh - 1;
-        if (c.fmt == FA) ensemble_site<FA, SR, NT>(c, parity, h, active, r, sweep);
-        else if (FB != FA && c.fmt == FB) ensemble_site<FB, SR, NT>(c, parity, h, active, r, sweep);
+        MeasAcc acc;
+        if (c.fmt == FA) ensemble_site<FA, SR, NT, MEAS>(c, parity, h, active, r, sweep, &acc);
+        else if (FB != FA && c.fmt == FB) ensemble_site<FB, SR, NT, MEAS>(c, parity, h, active, r, sweep, &acc);
+        if constexpr (MEAS) {
+            block_sum2_any(acc.f, acc.th, partials + 2 * ((size_t)n + t));
+            __syncthreads();  // the block sum's shared slots are reused by the next tile
+        }
     }
 }
 
@@ -100,15 +109,19 @@ static const void *sweep_symbol()
 
 template <int FA, int FB>
 static hipError_t launch_ens_sweep_t(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
-                                     bool sr, bool nt, hipStream_t s)
+                                     bool sr, bool nt, double *meas, hipStream_t s)
 {
     const dim3 grid(L.grid), block(L.tile);
-    if (sr) {
-        if (nt) hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
-        else hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, false>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
+    if (meas) {
+        // the fused measurement: overrelaxation with non-temporal access only
+        if (sr || !nt) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, false, true, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset, meas);
+    } else if (sr) {
+        if (nt) hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset, nullptr);
+        else hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, true, false>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset, nullptr);
     } else {
-        if (nt) hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, false, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
-        else hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, false, false>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset);
+        if (nt) hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, false, true>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset, nullptr);
+        else hipLaunchKernelGGL((ensemble_sweep_kernel<FA, FB, false, false>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, L.sweep_base, parity, r, sweep_offset, nullptr);
     }
     return hipGetLastError();
 }
@@ -117,10 +130,10 @@ static hipError_t launch_ens_sweep_t(const EnsLaunch &L, int parity, const EnsRe
 #define LGF_ENS_PAIRS(X) X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(1, 1) X(1, 2) X(1, 3) X(2, 2) X(2, 3) X(3, 3)
 
 hipError_t launch_ensemble_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
-                                 uint32_t sweep_offset, bool sr, bool nt, hipStream_t s)
+                                 uint32_t sweep_offset, bool sr, bool nt, hipStream_t s, double *meas)
 {
     if (fa > fb) { const int t = fa; fa = fb; fb = t; }
-#define LGF_CASE(A, B) if (fa == A && fb == B) return launch_ens_sweep_t<A, B>(L, parity, r, sweep_offset, sr, nt, s);
+#define LGF_CASE(A, B) if (fa == A && fb == B) return launch_ens_sweep_t<A, B>(L, parity, r, sweep_offset, sr, nt, meas, s);
     LGF_ENS_PAIRS(LGF_CASE)
 #undef LGF_CASE
     return hipErrorInvalidValue;

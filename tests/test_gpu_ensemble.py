@@ -163,6 +163,36 @@ def test_ensemble_tunings_are_bitwise_identical(lgf, orc):
             lgf.lgf_ensemble_set_tuning(ens.e, 96, 1, 1)
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_ensemble_fused_measure_equals_separate_passes(lgf, orc, tile):
+    """The ensemble's reunitarization + measurement inside each chunk's last
+    parity-1 launch (plus a read-only parity-0 pass) against the two separate
+    passes: the same sweeps and links for every configuration, and every F,
+    theta equal up to the summation order."""
+    announce("ensemble fused measure", tile)
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (2, 2, 2, 2), (6, 4, 4, 8)]
+    kw = dict(omega=1.7, theta_target=1e-13, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+              finish_format=lgf.LGF_FP64_12)
+    Us = [orc.generate_links(d, 110 + i, 0.3) for i, d in enumerate(dims)]
+    outs = []
+    for sep in (1, 0):
+        with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+            lgf.lgf_ensemble_set_tuning(ens.e, tile, 1, 1)
+            for i, U in enumerate(Us):
+                ens.load(i, U)
+            st, res = ens.gauge_fix(separate_measure=sep, **kw)
+            assert st == lgf.LGF_OK
+            outs.append((res, [ens.store(i) for i in range(len(dims))]))
+    (r1, U1), (r0, U0) = outs
+    for i, d in enumerate(dims):
+        assert r1[i]["sweeps"] == r0[i]["sweeps"] and r1[i]["sweeps_bulk"] == r0[i]["sweeps_bulk"], i
+        assert np.array_equal(U0[i], U1[i]), i
+        assert abs(r0[i]["F"] - r1[i]["F"]) <= 1e-13 * abs(r1[i]["F"])
+        th0, th1 = r0[i]["theta"], r1[i]["theta"]
+        assert abs(th0 - th1) <= 1e-14 * np.sqrt(th1) + 1e-12 * th1, i
+        assert orc.measure(d, U0[i])[1] < 1e-13
+
+
 def test_ensemble_sr_graph_equals_direct(lgf, orc):
     """Stochastic relaxation chunks replayed from captured graphs read their
     sweep counter from device memory: the same coins, hence the same links and
