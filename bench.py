@@ -532,6 +532,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "step_breakdown_ms": {k: sum(r[k] for r in results) / len(results)
+                              for k in ("t_sweep_bulk_ms", "t_sweep_finish_ms", "t_measure_ms", "t_convert_ms",
+                                        "t_total_ms")},
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
