@@ -191,6 +191,39 @@ lgf_status ensure_work(lgf_lattice *h, int format)
     return LGF_OK;
 }
 
+// The accumulated gauge transformation of an FP32 bulk (a site field in the
+// bulk format): allocated once, set to the identity here and handed to the
+// sweeps, which multiply in every update's G.
+lgf_status gacc_begin(lgf_lattice *h, int bulk)
+{
+    const size_t gbytes = (size_t)h->V * lgf::link_bytes(bulk);
+    if (h->gacc && h->gacc_bytes != gbytes) {
+        (void)hipFree(h->gacc);
+        h->gacc = nullptr;
+    }
+    if (!h->gacc) {
+        if (hipMalloc(&h->gacc, gbytes) != hipSuccess) {
+            h->gacc = nullptr;
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the accumulated gauge field", gbytes);
+        }
+        h->gacc_bytes = gbytes;
+    }
+    LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 0, h->stream));
+    h->gacc_active = h->gacc;
+    return LGF_OK;
+}
+
+// End the accumulation: dst (format fd) <- g(x) U(x) g(x+mu)^dag from the
+// handle's untouched FP64 field, each g reunitarized in FP64 first -- an exact
+// gauge transformation of the input.
+lgf_status gacc_apply(lgf_lattice *h, int bulk, int fd, void *dst)
+{
+    h->gacc_active = nullptr;
+    LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, bulk, h->gacc, fd, dst, h->geom, h->stream));
+    return LGF_OK;
+}
+
 // the second buffer of a format's out-of-place sweep (a whole field's size)
 lgf_status ensure_partner(lgf_lattice *h, int format)
 {
@@ -741,21 +774,6 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     if (acc && !(mixed && !is64(bulk) && is64(finish) && is64(h->format)))
         return fail(LGF_EINVAL, "accumulate_g needs an FP32 bulk, an FP64 finish and an FP64 handle");
     LGF_TRY(use_device(h));
-    if (acc) {
-        const size_t gbytes = (size_t)h->V * lgf::link_bytes(bulk);
-        if (h->gacc && h->gacc_bytes != gbytes) {
-            (void)hipFree(h->gacc);
-            h->gacc = nullptr;
-        }
-        if (!h->gacc) {
-            if (hipMalloc(&h->gacc, gbytes) != hipSuccess) {
-                h->gacc = nullptr;
-                (void)hipGetLastError();
-                return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the accumulated gauge field", gbytes);
-            }
-            h->gacc_bytes = gbytes;
-        }
-    }
 
     std::memset(res, 0, sizeof *res);
     const auto t_start = std::chrono::steady_clock::now();
@@ -812,10 +830,7 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         const bool to_fp64 = (first == LGF_FP64_18 || first == LGF_FP64_12) &&
                              !(h->format == LGF_FP64_18 || h->format == LGF_FP64_12);
         LGF_TRY(move_to(first, to_fp64));
-        if (acc && in_bulk) {
-            LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 0, h->stream));
-            h->gacc_active = h->gacc;
-        }
+        if (acc && in_bulk) LGF_TRY(gacc_begin(h, bulk));
     }
     while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
         const int64_t left = p.max_sweeps - sweeps;
@@ -861,12 +876,10 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
                     dst = h->work[finish];
                 }
                 LGF_HIP(hipEventRecord(h->ev0, h->stream));
-                LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, bulk, h->gacc, finish, dst, h->geom,
-                                                    h->stream));
+                LGF_TRY(gacc_apply(h, bulk, finish, dst));
                 LGF_HIP(hipEventRecord(h->ev1, h->stream));
                 LGF_HIP(hipEventSynchronize(h->ev1));
                 res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
-                h->gacc_active = nullptr;
                 cur = dst;
                 cur_fmt = finish;
             } else {
@@ -885,9 +898,7 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     }
     if (h->gacc_active) {
         // stopped inside the bulk (max_sweeps): hand back the exact transform
-        h->gacc_active = nullptr;
-        LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, bulk, h->gacc, h->format, h->field, h->geom,
-                                            h->stream));
+        LGF_TRY(gacc_apply(h, bulk, h->format, h->field));
         cur = h->field;
         cur_fmt = h->format;
     }
@@ -966,7 +977,15 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
-    if (p.accumulate_g) return fail(LGF_EINVAL, "accumulate_g is only supported by lgf_gauge_fix");
+    auto is64 = [](int f) { return f == LGF_FP64_18 || f == LGF_FP64_12; };
+    const bool acc = p.accumulate_g != 0;
+    if (acc && !(mixed && !is64(bulk) && is64(finish) && is64(h->format)))
+        return fail(LGF_EINVAL, "accumulate_g needs an FP32 bulk, an FP64 finish and an FP64 handle");
+    // the sweeps accumulate into g only inside this call, whatever way it ends
+    struct AccOff {
+        lgf_lattice *h;
+        ~AccOff() { h->gacc_active = nullptr; }
+    } acc_off{h};
     LGF_TRY(use_device(h));
     LGF_TRY(ensure_coulomb(h));
     const int Lt = h->dims[0];
@@ -1028,8 +1047,8 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     uint64_t ctr = p.sweep_offset;
     if (status != LGF_ENUMERIC && n_live() > 0 && p.max_sweeps > 0) {
         const int first = in_bulk ? bulk : finish;
-        LGF_TRY(move_to(first, (first == LGF_FP64_18 || first == LGF_FP64_12) &&
-                                   !(h->format == LGF_FP64_18 || h->format == LGF_FP64_12)));
+        LGF_TRY(move_to(first, is64(first) && !is64(h->format)));
+        if (acc && in_bulk) LGF_TRY(gacc_begin(h, bulk));
     }
     while (status != LGF_ENUMERIC && n_live() > 0 && sweeps < p.max_sweeps) {
         LGF_TRY(upload_mask(h, act.data()));
@@ -1048,6 +1067,7 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
         }
         sweeps += n;
         ctr += (uint64_t)n;
+        if (h->gacc_active) LGF_HIP(lgf::launch_site_field(bulk, h->gacc, h->geom, 1, h->stream));
         LGF_TRY(measure(true, true));
         ++nh;
         for (int t = 0; t < Lt; ++t) {
@@ -1059,7 +1079,23 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
         if (in_bulk) {
             // leave the bulk precision once every live timeslice is below the switch
             if (worst() < p.theta_switch) {
-                LGF_TRY(move_to(finish, true));
+                if (h->gacc_active) {
+                    // the FP64 links as an exact gauge transformation of the input
+                    void *dst = h->field;
+                    if (finish != h->format) {
+                        LGF_TRY(ensure_work(h, finish));
+                        dst = h->work[finish];
+                    }
+                    LGF_HIP(hipEventRecord(h->ev0, h->stream));
+                    LGF_TRY(gacc_apply(h, bulk, finish, dst));
+                    LGF_HIP(hipEventRecord(h->ev1, h->stream));
+                    LGF_HIP(hipEventSynchronize(h->ev1));
+                    res->t_convert_ms += elapsed_ms(h->ev0, h->ev1);
+                    cur = dst;
+                    cur_fmt = finish;
+                } else {
+                    LGF_TRY(move_to(finish, true));
+                }
                 in_bulk = false;
             }
             continue;
@@ -1068,6 +1104,12 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
             if (act[t] && th[t] < p.theta_target) act[t] = 0;
     }
     if (status != LGF_ENUMERIC) status = n_live() == 0 ? LGF_OK : LGF_ENOTCONV;
+    if (h->gacc_active) {
+        // stopped inside the bulk: hand back the exact transform of the input
+        LGF_TRY(gacc_apply(h, bulk, h->format, h->field));
+        cur = h->field;
+        cur_fmt = h->format;
+    }
     LGF_TRY(move_to(h->format, false));
     double tmax = 0.0, fsum = 0.0;
     for (int t = 0; t < Lt; ++t) {

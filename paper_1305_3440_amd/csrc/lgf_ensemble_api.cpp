@@ -504,7 +504,8 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
-    if (p.accumulate_g) return fail(LGF_EINVAL, "accumulate_g is only supported by lgf_gauge_fix");
+    if (p.accumulate_g)
+        return fail(LGF_EINVAL, "accumulate_g is supported by lgf_gauge_fix and lgf_coulomb_gauge_fix only");
     LGF_TRY(ens_use_device(e));
     const auto t_start = std::chrono::steady_clock::now();
     auto now_ms = [&] {

@@ -564,14 +564,14 @@ hipError_t launch_field_to_canon(int format, const void *field, const int64_t *s
 
 namespace lgf {
 
-template <int F, bool SR, bool NT>
+template <int F, bool SR, bool NT, bool ACC = false>
 __global__ void __launch_bounds__(128) sweep_coulomb_kernel(void *__restrict__ field, Geom g, int parity,
                                                             RelaxArgs<typename Fmt<F>::T> a,
                                                             const uint8_t *__restrict__ slice_active)
 {
     const uint32_t h0 = blockIdx.x * 128 + threadIdx.x;
     const bool active = h0 < g.Vh;
-    update_site<F, 1, SR, NT, 1>(field, g, parity, active ? h0 : g.Vh - 1, 0, active, a, slice_active);
+    update_site<F, 1, SR, NT, 1, false, ACC>(field, g, parity, active ? h0 : g.Vh - 1, 0, active, a, slice_active);
 }
 
 template <int F, bool NT>
@@ -581,9 +581,22 @@ static hipError_t launch_sweep_coulomb_t(void *field, const Geom &g, const Sweep
     using T = typename Fmt<F>::T;
     const dim3 grid((g.Vh + 127) / 128);
     RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
-                    (uint32_t)a.sweep_index, a.instance, nullptr, a.sweep_base};
-    if (a.p_sr > 0.0) {
-        ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+                    (uint32_t)a.sweep_index, a.instance, a.gacc, a.sweep_base};
+    const bool sr = a.p_sr > 0.0;
+    if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+    if (a.gacc) {
+        // the accumulated gauge transformation belongs to the FP32 bulk only
+        if constexpr (F == kF32_12 || F == kF32_18) {
+            if (sr)
+                hipLaunchKernelGGL((sweep_coulomb_kernel<F, true, NT, true>), grid, dim3(128), 0, s, field, g,
+                                   a.parity, ra, slice_active);
+            else
+                hipLaunchKernelGGL((sweep_coulomb_kernel<F, false, NT, true>), grid, dim3(128), 0, s, field, g,
+                                   a.parity, ra, slice_active);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (sr) {
         hipLaunchKernelGGL((sweep_coulomb_kernel<F, true, NT>), grid, dim3(128), 0, s, field, g, a.parity, ra,
                            slice_active);
     } else {

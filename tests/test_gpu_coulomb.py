@@ -103,6 +103,31 @@ def test_coulomb_mixed_gauge_fix(lgf, orc):
         assert abs(orc.wilson_loop(dims, got, 0, nu, 1, 1) - orc.wilson_loop(dims, U, 0, nu, 1, 1)) < 1e-5
 
 
+def test_coulomb_accumulated_gauge_keeps_the_orbit(lgf, orc):
+    """Mixed Coulomb gauge fixing with the accumulated gauge transformation:
+    every timeslice below theta_C < 1e-14, and the links an FP64 gauge
+    transformation of the input (temporal and spatial Wilson loops equal the
+    input's to 1e-12, where the plain mixed run drifts by far more)."""
+    dims = (8, 6, 6, 6)
+    announce("coulomb accumulate_g")
+    U = orc.generate_links(dims, 34, 0.3)
+    loops = lambda V: np.array([orc.wilson_loop(dims, V, mu, nu, R, T) for mu in range(4)
+                                for nu in range(mu + 1, 4) for (R, T) in [(1, 1), (1, 2)]])
+    L0 = loops(U)
+    drift = {}
+    for acc in (0, 1):
+        with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+            lat.load(U)
+            st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                                       bulk_format=lgf.LGF_FP32_12,
+                                                       finish_format=lgf.LGF_FP64_12, accumulate_g=acc)
+            got = lat.store()
+        assert st == lgf.LGF_OK and 0 < res["sweeps_bulk"] < res["sweeps"]
+        assert np.all(orc.measure_coulomb(dims, got)[1] < 1e-14) and unitarity_error(got) < 1e-12
+        drift[acc] = float(np.abs(loops(got) - L0).max())
+    assert drift[1] < 1e-12 and drift[0] > 100 * drift[1], drift
+
+
 def _links8(orc, dims, seed, eps, s):
     fw = [orc.generated_link(dims, seed, eps, True, s, mu) for mu in range(4)]
     bw = [orc.generated_link(dims, seed, eps, True, orc.neighbor(dims, s, mu, -1), mu) for mu in range(4)]
