@@ -1223,6 +1223,17 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         *ms = elapsed_ms(h->ev0, h->ev1) / n;
         return true;
     };
+    // warm-up: the GPU's clocks settle under a sustained streaming load within
+    // seconds, and the variants rank differently on a cold GPU (the ones with
+    // more arithmetic per byte look better) than in a long gauge fixing
+    if (e == hipSuccess) {
+        const auto w0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < 2000 && st == LGF_OK && e == hipSuccess; k += 20) {
+            for (int j = 0; j < 20 && st == LGF_OK; ++j) st = full_sweep(h, format, scratch, 1.7, 0.0, 0, 0);
+            e = hipStreamSynchronize(h->stream);
+            if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 3.0) break;
+        }
+    }
     // stage 1: every variant once
     struct Cand {
         lgf::SweepTuning t;
@@ -1231,7 +1242,7 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
     std::vector<Cand> cands;
     const int lps_list[3] = {1, 2, 4};
     const int block_list[3] = {64, 128, 256};
-    bool ok = (e == hipSuccess);
+    bool ok = (e == hipSuccess && st == LGF_OK);
     for (int li = 0; li < 3 && ok; ++li)
         for (int bi = 0; bi < 3 && ok; ++bi)
             for (int v = 0; v < 48 && ok; ++v) {
@@ -1245,7 +1256,7 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
                 ok = time_variant(c.t, trials, &c.ms);
                 if (ok) cands.push_back(c);
             }
-    // stage 2: the four fastest and the default, timed again over three times
+    // stage 2: the four fastest and the default, timed again over ten times
     // as many sweeps in five interleaved rounds; the smallest median wins
     // (single short timings of variants a few per cent apart are within the
     // run-to-run noise)
@@ -1260,7 +1271,7 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
             have_default = have_default || t == dflt;
         if (!have_default) finals.push_back(dflt);
         std::vector<std::vector<double>> ms(finals.size());
-        const int n2 = std::max(3 * trials, 6);
+        const int n2 = std::max(10 * trials, 20);
         for (int round = 0; round < 5 && ok; ++round)
             for (size_t i = 0; i < finals.size() && ok; ++i) {
                 double m = 0.0;

@@ -712,10 +712,20 @@ lgf_status lgf_ensemble_autotune(lgf_ensemble *e, int format, int trials)
         c.ms = lgf::elapsed_ms(e->ev0, e->ev1) / n;
         return true;
     };
+    // warm-up under a sustained load first (clocks settle within seconds, and
+    // a cold GPU ranks the variants differently), with the current tuning
+    {
+        Cand w{saved[0], saved[1], saved[2], 0.0};
+        const auto w0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < 50 && st == LGF_OK; ++k) {
+            if (!time_variant(w, 20)) break;
+            if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 2.0) break;
+        }
+    }
     // stage 1: every variant once; stage 2: the three fastest and the default
-    // over three times as many sweeps in five interleaved rounds, smallest median
+    // over ten times as many sweeps in five interleaved rounds, smallest median
     std::vector<Cand> cands;
-    bool ok = true;
+    bool ok = (st == LGF_OK && err == hipSuccess);
     for (int tile : {64, 128, 256})
         for (int mult : {1, 2})
             for (int nt : {0, 1}) {
@@ -733,7 +743,7 @@ lgf_status lgf_ensemble_autotune(lgf_ensemble *e, int format, int trials)
         std::vector<std::vector<double>> ms(finals.size());
         for (int round = 0; round < 5 && ok; ++round)
             for (size_t i = 0; i < finals.size() && ok; ++i) {
-                ok = time_variant(finals[i], std::max(3 * trials, 6));
+                ok = time_variant(finals[i], std::max(10 * trials, 20));
                 ms[i].push_back(finals[i].ms);
             }
         if (ok) {
