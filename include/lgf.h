@@ -223,9 +223,12 @@ lgf_status lgf_synchronize(lgf_lattice *h);
  * second buffer of the same size, parity 1 writes them back (needs
  * nontemporal = 1; the library allocates the buffer here, LGF_ENOMEM if it
  * cannot).  Every schedule gives bit-identical links; single half-sweeps
- * (lgf_sweep with parity 0 or 1) always run in place.  lgf_set_tuning copies
- * *tuning (LGF_EINVAL on a value outside these sets); lgf_get_tuning fills
- * *tuning with the current values. */
+ * (lgf_sweep with parity 0 or 1) always run in place.  A new handle starts at 1
+ * lane, 1 tile, 128 lanes, no remap, non-temporal, in place -- except FP64-12,
+ * which starts out of place (its second buffer allocated before its first full
+ * sweep; without memory for it the format falls back to in place).
+ * lgf_set_tuning copies *tuning (LGF_EINVAL on a value outside these sets);
+ * lgf_get_tuning fills *tuning with the current values. */
 typedef struct {
     int lanes_per_site;
     int sites_per_thread;

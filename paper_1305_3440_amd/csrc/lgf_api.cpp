@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -238,6 +239,29 @@ lgf_status ensure_partner(lgf_lattice *h, int format)
     return LGF_OK;
 }
 
+// The starting tuning of a format: one lane per site, 128-lane workgroups,
+// non-temporal access; the FP64 12-real sweep of the mixed finish out of place
+// (on every GPU measured within a few per cent of the fastest variant, often
+// the fastest), the others in place.
+lgf::SweepTuning default_tuning(int format)
+{
+    lgf::SweepTuning t{};
+    if (format == LGF_FP64_12) t.schedule = lgf::kScheduleOutOfPlace;
+    return t;
+}
+
+// Before sweeps in a format: the out-of-place schedule needs its partner
+// buffer (allocated here, never inside a graph capture); without memory for
+// it the format falls back to in place.
+void prepare_schedule(lgf_lattice *h, int format)
+{
+    if (h->tune[format].schedule != lgf::kScheduleOutOfPlace || h->partner[format]) return;
+    if (ensure_partner(h, format) != LGF_OK) {
+        h->tune[format].schedule = lgf::kScheduleInPlace;
+        drop_graphs(h);
+    }
+}
+
 // F and theta of a field; with reunit the links are first projected onto
 // SU(3) in FP64 (fused: parity 0 reunitarizes its forward links and, in
 // registers, its backward links; parity 1 then reads the already stored ones).
@@ -421,6 +445,7 @@ lgf_status measure_fused(lgf_lattice *h, int format, void *field, double *F, dou
 lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omega, double p_sr,
                      uint64_t seed, uint64_t sweep0, bool use_graph, bool coulomb = false, bool fused = false)
 {
+    if (!coulomb) prepare_schedule(h, format);
     if (fused) LGF_TRY(ensure_fused(h, format));
     auto meas_of = [&](int k) { return (fused && k == n - 1) ? h->d_fused : nullptr; };
     if (!use_graph) {
@@ -528,7 +553,7 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     h->field_bytes = need;
     // defaults: one lane per site, 128-thread workgroups, non-temporal
     // streaming (fastest measured at 64^4 for every format)
-    for (int f = 0; f < 4; ++f) h->tune[f] = lgf::SweepTuning{};
+    for (int f = 0; f < 4; ++f) h->tune[f] = default_tuning(f);
 
     auto bail = [&](lgf_status st) {
         lgf_destroy(h);
@@ -716,6 +741,7 @@ lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
     LGF_TRY(use_device(h));
     if (parity == 2) {
+        prepare_schedule(h, h->format);
         LGF_TRY(full_sweep(h, h->format, h->field, omega, p_sr, seed, sweep_index));
     } else {
         LGF_TRY(sweep_launch(h, h->format, h->field, parity, omega, p_sr, seed, sweep_index));
@@ -1204,10 +1230,13 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         scratch = h->work[format];
         e = lgf::launch_convert(h->format, h->field, format, scratch, h->geom, false, h->stream);
     }
-    const lgf::SweepTuning saved = h->tune[format];
-    // the out-of-place variants need the partner buffer; without memory for it they are skipped
+    // the out-of-place variants need the partner buffer; without memory for it
+    // they are skipped (and an out-of-place tuning falls back to in place)
     const bool had_partner = h->partner[format] != nullptr;
     const bool can_oop = ensure_partner(h, format) == LGF_OK;
+    if (!can_oop && h->tune[format].schedule == lgf::kScheduleOutOfPlace)
+        h->tune[format].schedule = lgf::kScheduleInPlace;
+    const lgf::SweepTuning saved = h->tune[format];
     lgf_status st = LGF_OK;
     // time n full sweeps of one variant after one untimed full sweep
     auto time_variant = [&](const lgf::SweepTuning &t, int n, double *ms) {
@@ -1265,7 +1294,7 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
         std::vector<lgf::SweepTuning> finals;
         for (size_t i = 0; i < cands.size() && finals.size() < 4; ++i) finals.push_back(cands[i].t);
-        const lgf::SweepTuning dflt{};
+        const lgf::SweepTuning dflt = default_tuning(format);
         bool have_default = false;
         for (const auto &t : finals)
             have_default = have_default || t == dflt;
@@ -1280,13 +1309,25 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
             }
         if (ok) {
             double best_ms = 1e300;
+            const bool log = std::getenv("LGF_AUTOTUNE_LOG") != nullptr;
             for (size_t i = 0; i < finals.size(); ++i) {
                 std::sort(ms[i].begin(), ms[i].end());
+                if (log) {
+                    const lgf::SweepTuning &t = finals[i];
+                    std::fprintf(stderr, "lgf_autotune format %d: lanes %d block %d xcd %d nt %d schedule %d spt %d: "
+                                 "median %.4f ms per full sweep (min %.4f, max %.4f)\n", format, t.lanes_per_site,
+                                 t.block, t.xcd_remap, t.nontemporal, t.schedule, t.sites_per_thread, ms[i][2],
+                                 ms[i][0], ms[i][4]);
+                }
                 if (ms[i][2] < best_ms) {
                     best_ms = ms[i][2];
                     best = finals[i];
                 }
             }
+            // a variant replaces the default only when clearly faster: near-ties
+            // are within what one GPU's timings drift over a long run
+            for (size_t i = 0; i < finals.size(); ++i)
+                if (finals[i] == dflt && best_ms > 0.99 * ms[i][2]) best = dflt;
         }
     }
     h->tune[format] = saved;
@@ -1315,6 +1356,7 @@ lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uin
     if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
     LGF_TRY(use_device(h));
+    prepare_schedule(h, h->format);
     LGF_HIP(hipEventRecord(h->ev0, h->stream));
     for (int k = 0; k < n; ++k)
         LGF_TRY(full_sweep(h, h->format, h->field, omega, p_sr, seed, sweep_index + (uint64_t)k));
