@@ -5,13 +5,17 @@ One step = one complete gauge fixing of the 64^4 workload (seeded synthetic
 links: seed 3, eps 0.3, Haar-random gauge) from its stored start to
 theta < 1e-14 with overrelaxation omega = 1.8, in the mixed form: FP32 12-real
 bulk sweeps, FP64 reunitarization + F/theta every 20 sweeps, switch to FP64
-(12-real storage) below theta = 1e-8, result handed back as FP64 18-real.  The start configuration stays resident in HBM
-(a device-to-device copy opens each step).  value = site updates per second
-over the whole step (V x sweeps / step time).
+(12-real storage) below theta = 1e-8, result handed back as FP64 18-real.  The
+sweeps run in the fixed-link form (the links stay as stored, the sweeps update
+the gauge transformation g and form g U g^dag in registers; the result is
+g U g^dag from the input).  The start configuration stays resident in HBM (a
+device-to-device copy opens each step).  value = site updates per second over
+the whole step (V x sweeps / step time).
 
-Also reported: the plain-FP64 time-to-theta on the same input, stochastic
-relaxation (p = 0.5) sweep throughput, per-kernel roofline figures from HIP
-events, and the FP64 CPU oracle timed on a bounded sample of the workload.
+Also reported: the same gauge fixing with sweeps that rewrite the links, the
+plain-FP64 time-to-theta on the same input, stochastic relaxation (p = 0.5)
+sweep throughput, per-kernel roofline figures from HIP events, and the FP64 CPU
+oracle timed on a bounded sample of the workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -29,11 +33,15 @@ HBM_PEAK_GBS = 8000.0
 LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
 # the sources that define the sweep kernels and their launch shape (the host
 # driver only picks among them)
-KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_device.hpp",
-                  "paper_1305_3440_amd/csrc/lgf_site.hpp", "paper_1305_3440_amd/csrc/lgf_internal.hpp"]
+KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_fixed.hip",
+                  "paper_1305_3440_amd/csrc/lgf_device.hpp", "paper_1305_3440_amd/csrc/lgf_site.hpp",
+                  "paper_1305_3440_amd/csrc/lgf_internal.hpp"]
 # sweep variants the counter passes cover: (lanes per site, block, xcd remap, non-temporal, schedule)
 TRAFFIC_VARIANTS = [(1, 128, 0, 1, 0), (2, 128, 0, 1, 0), (4, 128, 0, 1, 0), (1, 128, 0, 1, 2),
                     (2, 128, 0, 1, 2), (4, 128, 0, 1, 2), (1, 128, 0, 0, 0), (2, 128, 0, 0, 0)]
+# fixed-link sweep variants the counter passes cover: (lanes per site, block, tile order)
+TRAFFIC_FIXED_VARIANTS = [(lps, block, order) for lps in (2, 4) for block in (64, 128, 256) for order in (0, 1, 2)]
+TRAFFIC_FIXED_SWEEPS = 4   # full sweeps per variant: 2 x 3 plain launches + the chunk's last sweep
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_64x4_hbm_traffic.json")
 
 
@@ -54,6 +62,12 @@ def traffic_key(fmt: int, lanes: int, nontemporal: int, schedule: int, dims) -> 
     out of place) on one lattice; the workgroup size does not change it."""
     return (f"sweep:fmt{fmt}:lanes{lanes}:nt{int(bool(nontemporal))}:oop{int(schedule == 2)}:"
             f"{'x'.join(map(str, dims))}")
+
+
+def fixed_traffic_key(fmt: int, lanes: int, block: int, order: int, dims) -> str:
+    """Key of one fixed-link sweep variant on one lattice (the tile order and
+    the workgroup size set which neighbouring g come from the caches)."""
+    return f"fixed:fmt{fmt}:lanes{lanes}:block{block}:order{order}:{'x'.join(map(str, dims))}"
 
 
 def measured_traffic(key: str):
@@ -122,6 +136,20 @@ def traffic_run(lgf, torch, dims, seed, eps, omega):
             ms = lgf.lgf_time_sweeps(h, 2, omega)
             log(f"[traffic] {lgf.FORMAT_NAMES[fmt]} {v}: {ms:.3f} ms per launch")
         lgf.lgf_destroy(h)
+    # the fixed-link sweeps: TRAFFIC_FIXED_SWEEPS full sweeps per variant, in
+    # the order of TRAFFIC_FIXED_VARIANTS (the summary groups the dispatches by it)
+    h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
+    lgf.lgf_generate_links(h, seed, eps, True)
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+        for v in TRAFFIC_FIXED_VARIANTS:
+            lgf.lgf_set_fixed_tuning(h, fmt, *v)
+            p = lgf.fix_params(omega=omega, theta_target=1e-300, check_every=TRAFFIC_FIXED_SWEEPS,
+                               max_sweeps=TRAFFIC_FIXED_SWEEPS, fixed_links=1, use_graph=0, bulk_format=fmt,
+                               finish_format=fmt)
+            st, res, _ = lgf.lgf_gauge_fix(h, p)
+            log(f"[traffic] fixed {lgf.FORMAT_NAMES[fmt]} {v}: "
+                f"{res['t_sweep_finish_ms'] / (2 * TRAFFIC_FIXED_SWEEPS):.3f} ms per launch")
+    lgf.lgf_destroy(h)
     torch.cuda.synchronize()
 
 
@@ -134,18 +162,25 @@ def _find(dirpath, suffix):
 
 
 def summarize_traffic(fetch_dir, write_dir, dims, command):
+    import re
     """Per-launch HBM bytes of the sweep kernels from two rocprofv3 --pmc
     passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the
     counter's reading for the 1 GiB copy; written next to the kernel-source
     hash so a stale figure is never reported."""
     import csv
     per = {}
+    fixed_seq = {}  # (counter, format, lanes) -> plain fixed-sweep readings in dispatch order
+    fixed_pat = re.compile(r"fixed_sweep_kernel<(\d+),\s*(\d+),\s*false,\s*0>")
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         with open(_find(d, "counter_collection.csv")) as f:
-            for row in csv.DictReader(f):
-                if row.get("Counter_Name") != counter:
-                    continue
-                per.setdefault((counter, row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+            rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
+        rows.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
+        for row in rows:
+            per.setdefault((counter, row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+            m = fixed_pat.search(row["Kernel_Name"])
+            if m:
+                fixed_seq.setdefault((counter, int(m.group(1)), int(m.group(2))), []).append(
+                    float(row["Counter_Value"]))
     copy_bytes = float(1 << 30)
     out = {"source_sha": kernel_source_sha(), "command": command, "kernels": {}, "calibration": {}}
     scale = {}
@@ -155,7 +190,6 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
         scale[counter] = copy_bytes / kib
         out["calibration"][counter] = {"copy_bytes": copy_bytes, "counter_kib": kib,
                                        "bytes_per_counter_unit": scale[counter]}
-    import re
     # sweep_kernel<format, lanes per site, SR, non-temporal, out of place,
     # accumulate g, fused measurement>: the plain sweep instances
     pat = re.compile(r"sweep_kernel<(\d+),\s*(\d+),\s*(true|false),\s*(true|false),\s*(true|false),"
@@ -170,8 +204,24 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
         e = out["kernels"].setdefault(key, {"kernel": kname, "format": fmt})
         e[counter.lower() + "_bytes_per_launch"] = sum(vals) / len(vals) * scale[counter]
         e[counter.lower() + "_dispatches"] = len(vals)
+    # the fixed-link sweep: the plain (no reunitarization) launches of each
+    # variant, 2 (TRAFFIC_FIXED_SWEEPS - 1) per variant, in the traffic run's order
+    per_variant = 2 * (TRAFFIC_FIXED_SWEEPS - 1)
+    for (counter, fmt, lanes), vals in fixed_seq.items():
+        vs = [v for v in TRAFFIC_FIXED_VARIANTS if v[0] == lanes]
+        for i, v in enumerate(vs):
+            chunk = vals[i * per_variant:(i + 1) * per_variant]
+            if len(chunk) != per_variant:
+                continue
+            key = fixed_traffic_key(fmt, v[0], v[1], v[2], dims)
+            e = out["kernels"].setdefault(key, {"kernel": f"fixed_sweep_kernel<{fmt}, {lanes}, false, 0>",
+                                                "format": fmt, "fixed": True, "block": v[1], "order": v[2]})
+            e[counter.lower() + "_bytes_per_launch"] = sum(chunk) / len(chunk) * scale[counter]
+            e[counter.lower() + "_dispatches"] = len(chunk)
     for key, e in out["kernels"].items():
-        alg = Vh * 16 * LINK_BYTES[e["format"]]
+        # link sweep: 8 links in and out per site; fixed-link sweep: 8 links in,
+        # g(x) in and out, the neighbouring g of the other parity in once
+        alg = Vh * (11 if e.get("fixed") else 16) * LINK_BYTES[e["format"]]
         e["algorithmic_bytes_per_launch"] = alg
         e["hbm_bytes_per_launch"] = e.get("fetch_size_bytes_per_launch", 0) + e.get(
             "write_size_bytes_per_launch", 0)
@@ -247,7 +297,8 @@ def gauge_32x4_bench(lgf, torch, stream):
     plain FP64-18 and of the mixed runs (FP32-12 bulk, switch at 1e-8), and
     how far each run's plaquette moved from the input's.  The plaquette is
     gauge invariant, so an exact gauge transformation leaves it alone; the
-    FP32 bulk without the accumulated transformation does not."""
+    FP32 bulk without the accumulated transformation does not (the
+    fixed-link sweeps keep the input links, so they stay on the orbit too)."""
     dims = (32, 32, 32, 32)
     dev = torch.device("cuda:0")
     home = lgf.LGF_FP64_18
@@ -258,13 +309,16 @@ def gauge_32x4_bench(lgf, torch, stream):
     lgf.lgf_generate_links(hp, 1, 0.25, True)
     hw = lgf.lgf_create(dims, home, stream, work)
     P0 = lgf.lgf_plaquette(hp)
-    runs = {"fp64_18": (-1, -1, 0), "mixed_fp32-12_to_fp64-18": (lgf.LGF_FP32_12, lgf.LGF_FP64_18, 0),
-            "mixed_fp32-12_to_fp64-12": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 0),
-            "mixed_fp32-12_to_fp64-12_accumulate_g": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 1)}
+    # (bulk, finish, accumulate_g, fixed_links)
+    runs = {"fp64_18": (-1, -1, 0, 0), "mixed_fp32-12_to_fp64-18": (lgf.LGF_FP32_12, lgf.LGF_FP64_18, 0, 0),
+            "mixed_fp32-12_to_fp64-12": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 0, 0),
+            "mixed_fp32-12_to_fp64-12_accumulate_g": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 1, 0),
+            "fp64_18_fixed_links": (-1, -1, 0, 1),
+            "mixed_fp32-12_to_fp64-12_fixed_links": (lgf.LGF_FP32_12, lgf.LGF_FP64_12, 0, 1)}
     out = {"dims": list(dims), "plaquette_input": P0}
-    for name, (bulk, finish, acc) in runs.items():
+    for name, (bulk, finish, acc, fixed) in runs.items():
         p = lgf.lgf_fix_params_default()
-        p.omega, p.theta_target = 1.7, 1e-14
+        p.omega, p.theta_target, p.fixed_links = 1.7, 1e-14, fixed
         if bulk >= 0:
             p.theta_switch, p.bulk_format, p.finish_format, p.accumulate_g = 1e-8, bulk, finish, acc
         work.copy_(pristine)
@@ -366,14 +420,18 @@ def main():
     hp = lgf.lgf_create(dims, home, stream, pristine)
     lgf.lgf_generate_links(hp, seed, eps, True)
     hw = lgf.lgf_create(dims, home, stream, work)
-    # sweep variants picked by the autotuner on this lattice (scratch copies)
+    # sweep variants picked by the autotuners on this lattice: the fixed-link
+    # sweeps of the step, and the link-rewriting sweeps of the comparison run
+    lgf.lgf_autotune_fixed(hw, bulk, 4)
+    lgf.lgf_autotune_fixed(hw, finish, 4)
     lgf.lgf_autotune(hw, bulk, 4)
     lgf.lgf_autotune(hw, finish, 4)
     torch.cuda.synchronize()
+    fixed_tuning = {f: lgf.lgf_get_fixed_tuning(hw, f) for f in (bulk, finish)}
     tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish, home)}
-    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; tuning fp32-12 "
-        f"{lgf.lgf_get_tuning(hw, bulk)} fp64-12 {lgf.lgf_get_tuning(hw, finish)} fp64-18 "
-        f"{lgf.lgf_get_tuning(hw, home)}")
+    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, "
+        f"order) fp32-12 {fixed_tuning[bulk]} fp64-12 {fixed_tuning[finish]}; link-sweep tuning fp32-12 "
+        f"{tuning[bulk]} fp64-12 {tuning[finish]}")
 
     params = lgf.lgf_fix_params_default()
     params.omega = omega
@@ -383,10 +441,11 @@ def main():
     params.finish_format = finish
     params.check_every = 20
     params.use_graph = 1
+    params.fixed_links = 1
 
-    def step():
+    def step(p=params):
         work.copy_(pristine)
-        st, res, hist = lgf.lgf_gauge_fix(hw, params)
+        st, res, hist = lgf.lgf_gauge_fix(hw, p)
         if st != lgf.LGF_OK:
             raise RuntimeError(f"gauge fix did not converge: {res}")
         return res
@@ -413,27 +472,27 @@ def main():
     tb = sum(r["t_sweep_bulk_ms"] for r in results)
     tf = sum(r["t_sweep_finish_ms"] for r in results)
     kernels = {}
-    for name, fmt, nsw, tms in (("sweep_fp32_12", bulk, sb, tb), ("sweep_fp64_12", finish, sf, tf)):
+    for name, fmt, nsw, tms in (("fixed_sweep_fp32_12", bulk, sb, tb), ("fixed_sweep_fp64_12", finish, sf, tf)):
         if nsw > 0:
             launch_ms = tms / (2 * nsw)
-            by = Vh * 2 * 8 * LINK_BYTES[fmt]
+            # 8 links in, g(x) in and out, the 8 neighbouring g (each shared by
+            # 8 sites of the half-sweep) in once: 11 matrices per site
+            by = Vh * 11 * LINK_BYTES[fmt]
             kernels[name] = {"launches": 2 * nsw, "avg_launch_ms": launch_ms,
                              "algorithmic_bytes_per_launch": by,
                              "achieved_GBs": by / (launch_ms * 1e-3) / 1e9,
                              "site_updates_per_s": Vh / (launch_ms * 1e-3), "total_ms": tms}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
-    dfmt = bulk if dom == "sweep_fp32_12" else finish
+    dfmt = bulk if dom == "fixed_sweep_fp32_12" else finish
     fmt_name = lgf.FORMAT_NAMES[dfmt]
-    lanes, block, xcd, nt, sched, spt = tuning[dfmt]
-    traffic = measured_traffic(traffic_key(dfmt, lanes, nt, sched, dims))
+    lanes, block, order = fixed_tuning[dfmt]
+    traffic = measured_traffic(fixed_traffic_key(dfmt, lanes, block, order, dims))
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"sweep_kernel<{fmt_name}, lanes/site {lanes}, "
-                          f"{'non-temporal' if nt else 'cached'}, "
-                          f"{['in place', 't-slice pipeline', 'out of place'][sched]}> block {block}"
-                          f", {spt} tile(s) per workgroup{', xcd-remap' if xcd else ''}",
+                "kernel": f"fixed_sweep_kernel<{fmt_name}, lanes/site {lanes}> block {block}, tile order "
+                          f"{['lexicographic', 'XCD ranges', 't-z blocks per XCD'][order]}",
                 "avg_launch_ms": round(dk["avg_launch_ms"], 4),
                 "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
 
@@ -445,6 +504,18 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # the same mixed gauge fixing with sweeps that rewrite the links
+        plink = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch,
+                               bulk_format=bulk, finish_format=finish, check_every=20, use_graph=1)
+        rl = step(plink)
+        extras["link_sweeps_mixed"] = {
+            "time_to_theta_s": rl["t_total_ms"] / 1e3, "sweeps": rl["sweeps"], "sweeps_bulk": rl["sweeps_bulk"],
+            "theta": rl["theta"], "F": rl["F"],
+            "site_updates_per_s": V * rl["sweeps"] / (rl["t_total_ms"] / 1e3),
+            "sweep_ms_per_launch": {"fp32-12": rl["t_sweep_bulk_ms"] / (2 * rl["sweeps_bulk"]),
+                                    "fp64-12": rl["t_sweep_finish_ms"] / (2 * (rl["sweeps"] - rl["sweeps_bulk"]))},
+            "tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, tuning[f])) for f in (bulk, finish)}}
+        log(f"[bench] link sweeps, mixed: {rl['sweeps']} sweeps, {rl['t_total_ms']:.0f} ms, F {rl['F']:.12f}")
         # plain FP64 on the same input, its sweep variant autotuned the same way
         lgf.lgf_autotune(hw, home, 4)
         extras["fp64_plain_tuning"] = dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home)))
@@ -477,6 +548,8 @@ def main():
         extras["time_to_theta_mixed_s"] = mixed_s
         extras["mixed_speedup_vs_fp64"] = extras["time_to_theta_fp64_s"] / mixed_s
         extras["dF_mixed_vs_fp64"] = results[-1]["F"] - r64["F"]
+        extras["dF_link_sweeps_mixed_vs_fp64"] = rl["F"] - r64["F"]
+        extras["fixed_speedup_vs_link_sweeps"] = extras["link_sweeps_mixed"]["time_to_theta_s"] / mixed_s
         log(f"[bench] fp64 plain: {r64['sweeps']} sweeps, {r64['t_total_ms']:.0f} ms; "
             f"SR fp64 {ms_sr64:.3f} ms/launch, SR fp32-12 {ms_sr32:.3f}, OR fp32-12 {ms_or32:.3f}")
     lgf.lgf_destroy(hw)
@@ -523,12 +596,12 @@ def main():
         "dtype": "fp32+fp64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau OR gauge fixing, mixed "
-                               f"FP32-12 bulk / FP64-12 finish, theta<1e-14",
+                               f"FP32-12 bulk / FP64-12 finish, theta<1e-14, fixed-link sweeps",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
                    "sweeps_per_step": [r["sweeps"] for r in results],
-                   "sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, t))
-                                    for f, t in tuning.items()}},
+                   "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(("lanes_per_site", "block", "order"), t))
+                                          for f, t in fixed_tuning.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -80,6 +80,18 @@ typedef struct {
                               read-only pass over the other parity, where the sweep allows it
                               (overrelaxation, non-temporal, not the t-slice pipeline).  The links
                               are the same; F and theta differ only in the summation order */
+    int fixed_links;       /* 1: the sweeps keep the links at their input values and update the
+                              gauge transformation g instead (a site field in the sweep format),
+                              forming each link g(x) U_mu(x) g(x+mu)^dag (Eq. (3)) in registers;
+                              K(x) = g(x) M(x) with M(x) = sum_mu U_mu(x) g(x+mu)^dag +
+                              [g(x-mu) U_mu(x-mu)]^dag gives the update of Sec. 3 unchanged.  A
+                              half-sweep reads the 8 links and writes only g(x).  Every check_every
+                              sweeps each g is reunitarized as it is stored; at the precision switch
+                              g is handed over (reunitarized in FP64) and the finish runs on the
+                              FP64 links; at the end the handle's links become g U g^dag from the
+                              untouched input, an exact gauge transformation of it.  Needs an FP64
+                              handle; accumulate_g is implied.  0 (default): the sweeps rewrite
+                              the links. */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
@@ -250,6 +262,29 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tu
  * the links are left as they were.  trials = timed full sweeps per variant in
  * the first round (>= 1); the fastest few are re-timed over longer runs. */
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
+
+/* Tuning of the fixed-link sweep (lgf_fix_params.fixed_links) per format:
+ * lanes_per_site 2 or 4 (one lane per site does not fit the registers),
+ * block 64, 128 or 256, xcd_remap 0 (lexicographic tiles), 1 (contiguous
+ * ranges per XCD) or 2 (each XCD takes blocks of 8, 4 or 2 t-slices x z-planes,
+ * walked z, t, then y, so that the neighbouring g a site update reads were
+ * read by a nearby workgroup of the same XCD; lexicographic where the lattice
+ * does not divide into a multiple of 8 such blocks); sites_per_thread must be 1,
+ * nontemporal 1 (links and g(x) are streamed, the neighbouring g go through
+ * the caches) and schedule 0.  Default: 2 lanes; FP64 formats 64-lane
+ * workgroups, order 2; FP32 formats 256-lane workgroups, order 0.  LGF_EINVAL
+ * on other values. */
+lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
+lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
+
+/* Pick the fastest fixed-link sweep variant for `format` on this lattice
+ * (lanes 2/4 x block 64/128/256 x tile order 0/1/2): each timed over `trials`
+ * full sweeps, the fastest again over ten times as many in five interleaved
+ * rounds; the default stays unless another is 1 % faster.  The sweeps read the
+ * handle's links (or their copy in `format`) and write only the gauge
+ * transformation, which lgf_gauge_fix resets: the links are untouched.  Needs
+ * an FP64 handle.  Synchronises. */
+lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials);
 
 /* Average duration in ms of the last n_launches sweep kernels enqueued through
  * lgf_time_sweeps: runs n full sweeps (2n launches) with the given omega/p_sr

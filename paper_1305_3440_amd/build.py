@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblgf.so")
 
-SOURCES = ["lgf_kernels.hip", "lgf_ensemble_kernels.hip", "lgf_util.hip", "lgf_api.cpp", "lgf_ensemble_api.cpp"]
+SOURCES = ["lgf_kernels.hip", "lgf_fixed.hip", "lgf_ensemble_kernels.hip", "lgf_util.hip", "lgf_api.cpp", "lgf_ensemble_api.cpp"]
 
 ARCH = "gfx950"
 

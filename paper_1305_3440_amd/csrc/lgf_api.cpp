@@ -94,8 +94,16 @@ struct GraphEntry {
     int fused;
     double p_sr;
     uint64_t seed;
+    int fixed;  // fixed-link form: field holds the links, gacc the gauge transformation
     hipGraphExec_t exec;
 };
+
+bool same_chunk(const GraphEntry &a, const GraphEntry &b, bool sr)
+{
+    return a.format == b.format && a.field == b.field && a.n_sweeps == b.n_sweeps && a.omega == b.omega &&
+           a.tune == b.tune && a.coulomb == b.coulomb && a.gacc == b.gacc && a.fused == b.fused &&
+           a.p_sr == b.p_sr && (!sr || a.seed == b.seed) && a.fixed == b.fixed;
+}
 
 constexpr int64_t kStageSites = 1 << 16;  // sites per canonical staging chunk (37.7 MB)
 
@@ -138,6 +146,10 @@ struct lgf_lattice {
     void *gacc;        // site field in the bulk format (owned), or NULL
     size_t gacc_bytes;
     void *gacc_active; // passed to the sweeps while the bulk accumulates
+    // fixed-link form: the gauge transformation per sweep format (owned site
+    // fields) and the tuning of its sweep
+    void *gfix[4];
+    lgf::SweepTuning tune_fixed[4];
 };
 
 namespace {
@@ -406,9 +418,8 @@ bool can_fuse(const lgf_lattice *h, int format, double p_sr, bool coulomb)
 
 // room for the fused sweep's partial sums followed by those of the parity-0
 // measurement pass; graphs that hold the old buffer are dropped on growth
-lgf_status ensure_fused(lgf_lattice *h, int format)
+lgf_status ensure_fused_cap(lgf_lattice *h, size_t need)
 {
-    const size_t need = (size_t)lgf::sweep_groups(h->geom, h->tune[format]) + (size_t)lgf::measure_blocks(h->geom);
     if (h->fused_cap >= need) return LGF_OK;
     drop_graphs(h);
     if (h->d_fused) LGF_HIP(hipFree(h->d_fused));
@@ -421,6 +432,12 @@ lgf_status ensure_fused(lgf_lattice *h, int format)
     }
     h->fused_cap = need;
     return LGF_OK;
+}
+
+lgf_status ensure_fused(lgf_lattice *h, int format)
+{
+    return ensure_fused_cap(h, (size_t)lgf::sweep_groups(h->geom, h->tune[format]) +
+                                   (size_t)lgf::measure_blocks(h->geom));
 }
 
 // F and theta after a chunk whose last half-sweep was fused: its partial sums
@@ -437,6 +454,48 @@ lgf_status measure_fused(lgf_lattice *h, int format, void *field, double *F, dou
     LGF_HIP(hipStreamSynchronize(h->stream));
     if (F) *F = h->h_out[0];
     if (theta) *theta = h->h_out[1];
+    return LGF_OK;
+}
+
+// Launch the chunk of sweeps that issue() enqueues through a hipGraph: the
+// cached graph with the same key is replayed, otherwise issue() is captured
+// into a new one (at most 8 kept).  For stochastic relaxation the captured
+// launches carry counter offsets and read the chunk's first counter from
+// h->d_sweep_base, written here before the replay.
+template <class Issue>
+lgf_status run_captured(lgf_lattice *h, const GraphEntry &key, uint64_t sweep0, Issue issue)
+{
+    const bool sr = key.p_sr > 0.0;
+    if (sr) LGF_HIP(lgf::launch_set_u64(h->d_sweep_base, sweep0, h->stream));
+    for (auto &g : h->graphs) {
+        if (same_chunk(g, key, sr)) {
+            LGF_HIP(hipGraphLaunch(g.exec, h->stream));
+            return LGF_OK;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    h->sweep_base_active = sr ? h->d_sweep_base : nullptr;
+    const lgf_status st = issue();
+    h->sweep_base_active = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (st != LGF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LGF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LGF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (h->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+    }
+    GraphEntry entry = key;
+    entry.exec = exec;
+    h->graphs.push_back(entry);
+    LGF_HIP(hipGraphLaunch(exec, h->stream));
     return LGF_OK;
 }
 
@@ -457,41 +516,282 @@ lgf_status run_chunk(lgf_lattice *h, int format, void *field, int n, double omeg
     // and read the chunk's first counter from the device, set here outside
     // the graph, so one graph serves every chunk
     const bool sr = p_sr > 0.0;
-    if (sr) LGF_HIP(lgf::launch_set_u64(h->d_sweep_base, sweep0, h->stream));
-    const lgf::SweepTuning &t = h->tune[format];
-    for (auto &g : h->graphs) {
-        if (g.format == format && g.field == field && g.n_sweeps == n && g.omega == omega &&
-            g.coulomb == (coulomb ? 1 : 0) && g.gacc == h->gacc_active && g.fused == (fused ? 1 : 0) &&
-            g.p_sr == p_sr && (!sr || g.seed == seed) && g.tune == t) {
-            LGF_HIP(hipGraphLaunch(g.exec, h->stream));
-            return LGF_OK;
+    GraphEntry key{format, field, n, omega, h->tune[format], coulomb ? 1 : 0, h->gacc_active, fused ? 1 : 0,
+                   p_sr, seed, 0, nullptr};
+    return run_captured(h, key, sweep0, [&]() -> lgf_status {
+        for (int k = 0; k < n; ++k)
+            LGF_TRY(full_sweep(h, format, field, omega, p_sr, seed, sr ? (uint64_t)k : sweep0 + (uint64_t)k,
+                               coulomb, meas_of(k)));
+        return LGF_OK;
+    });
+}
+
+// The autotuners' search over `variants`: each timed once over `trials` full
+// sweeps (stage 1), then the four fastest and the default again over ten times
+// as many sweeps in five interleaved rounds; the smallest median wins, but a
+// variant replaces the default only when at least 1 % faster (single short
+// timings of variants a few per cent apart are within the run-to-run noise,
+// and near-ties within what one GPU's timings drift over a long run).
+// time_variant(tuning, n, &ms) times n full sweeps.  With LGF_AUTOTUNE_LOG
+// set, the stage-2 medians go to stderr.  False when a timing failed.
+template <class TimeFn>
+bool pick_variant(const std::vector<lgf::SweepTuning> &variants, const lgf::SweepTuning &dflt, int trials,
+                  const char *who, int format, TimeFn &&time_variant, lgf::SweepTuning *best)
+{
+    struct Cand {
+        lgf::SweepTuning t;
+        double ms;
+    };
+    std::vector<Cand> cands;
+    for (const auto &t : variants) {
+        Cand c{t, 0.0};
+        if (!time_variant(t, trials, &c.ms)) return false;
+        cands.push_back(c);
+    }
+    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    std::vector<lgf::SweepTuning> finals;
+    for (size_t i = 0; i < cands.size() && finals.size() < 4; ++i) finals.push_back(cands[i].t);
+    bool have_default = false;
+    for (const auto &t : finals) have_default = have_default || t == dflt;
+    if (!have_default) finals.push_back(dflt);
+    std::vector<std::vector<double>> ms(finals.size());
+    const int n2 = std::max(10 * trials, 20);
+    for (int round = 0; round < 5; ++round)
+        for (size_t i = 0; i < finals.size(); ++i) {
+            double m = 0.0;
+            if (!time_variant(finals[i], n2, &m)) return false;
+            ms[i].push_back(m);
+        }
+    double best_ms = 1e300;
+    const bool log = std::getenv("LGF_AUTOTUNE_LOG") != nullptr;
+    for (size_t i = 0; i < finals.size(); ++i) {
+        std::sort(ms[i].begin(), ms[i].end());
+        if (log) {
+            const lgf::SweepTuning &t = finals[i];
+            std::fprintf(stderr, "%s format %d: lanes %d block %d xcd %d nt %d schedule %d spt %d: "
+                         "median %.4f ms per full sweep (min %.4f, max %.4f)\n", who, format, t.lanes_per_site,
+                         t.block, t.xcd_remap, t.nontemporal, t.schedule, t.sites_per_thread, ms[i][2], ms[i][0],
+                         ms[i][4]);
+        }
+        if (ms[i][2] < best_ms) {
+            best_ms = ms[i][2];
+            *best = finals[i];
         }
     }
-    hipGraph_t graph = nullptr;
-    LGF_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    lgf_status st = LGF_OK;
-    h->sweep_base_active = sr ? h->d_sweep_base : nullptr;
-    for (int k = 0; k < n && st == LGF_OK; ++k)
-        st = full_sweep(h, format, field, omega, p_sr, seed, sr ? (uint64_t)k : sweep0 + (uint64_t)k, coulomb,
-                        meas_of(k));
-    h->sweep_base_active = nullptr;
-    hipError_t e = hipStreamEndCapture(h->stream, &graph);
-    if (st != LGF_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
+    for (size_t i = 0; i < finals.size(); ++i)
+        if (finals[i] == dflt && best_ms > 0.99 * ms[i][2]) *best = dflt;
+    return true;
+}
+
+// ----------------------------------------------------------------------------
+// Fixed-link form: the links stay as they are and the sweeps update the gauge
+// transformation g, a site field in the sweep's format.
+// ----------------------------------------------------------------------------
+
+// Starting tuning of the fixed-link sweep: 2 lanes per site (one lane per site
+// does not fit the registers in FP64); FP64 formats in 64-lane workgroups over
+// the blocked tile order, FP32 ones in 256-lane workgroups in lexicographic
+// order (the fastest measured at 64^4).
+lgf::SweepTuning default_fixed_tuning(int format)
+{
+    lgf::SweepTuning t{};
+    t.lanes_per_site = 2;
+    const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12);
+    t.block = fp64 ? 64 : 256;
+    t.xcd_remap = fp64 ? 2 : 0;
+    return t;
+}
+
+lgf_status ensure_gfix(lgf_lattice *h, int format)
+{
+    if (!h->gfix[format]) {
+        const size_t bytes = (size_t)h->V * lgf::link_bytes(format);
+        if (hipMalloc(&h->gfix[format], bytes) != hipSuccess) {
+            h->gfix[format] = nullptr;
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the gauge transformation", bytes);
+        }
     }
-    if (e != hipSuccess) return fail(LGF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(LGF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    if (h->graphs.size() >= 8) {
-        (void)hipGraphExecDestroy(h->graphs.front().exec);
-        h->graphs.erase(h->graphs.begin());
+    return LGF_OK;
+}
+
+// the links of the fixed-link sweeps in `format`: the handle's own field, or
+// a copy of it in the working buffer of that format
+lgf_status links_in_format(lgf_lattice *h, int format, void **links)
+{
+    if (format == h->format) {
+        *links = h->field;
+        return LGF_OK;
     }
-    h->graphs.push_back(
-        GraphEntry{format, field, n, omega, t, coulomb ? 1 : 0, h->gacc_active, fused ? 1 : 0, p_sr, seed, exec});
-    LGF_HIP(hipGraphLaunch(exec, h->stream));
+    LGF_TRY(ensure_work(h, format));
+    LGF_HIP(lgf::launch_convert(h->format, h->field, format, h->work[format], h->geom, false, h->stream));
+    *links = h->work[format];
+    return LGF_OK;
+}
+
+// n full sweeps in the fixed-link form.  The chunk's last sweep stores every g
+// reunitarized (both half-sweeps); with fused, its parity-1 half-sweep also
+// leaves the (F, theta) partial sums of its sites in h->d_fused.
+lgf_status run_chunk_fixed(lgf_lattice *h, int format, const void *links, void *gf, int n, double omega,
+                           double p_sr, uint64_t seed, uint64_t sweep0, bool use_graph, bool fused)
+{
+    const lgf::SweepTuning &t = h->tune_fixed[format];
+    if (fused)
+        LGF_TRY(ensure_fused_cap(h, (size_t)lgf::fixed_sweep_groups(h->geom, t) + (size_t)lgf::measure_blocks(h->geom)));
+    const bool sr = p_sr > 0.0;
+    auto issue = [&](bool captured) -> lgf_status {
+        for (int k = 0; k < n; ++k) {
+            const bool last = (k == n - 1);
+            lgf::SweepArgs a{0, omega, p_sr, seed, (captured && sr) ? (uint64_t)k : sweep0 + (uint64_t)k, 0u};
+            a.sweep_base = h->sweep_base_active;
+            LGF_HIP(lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, last ? 1 : 0, h->stream));
+            a.parity = 1;
+            a.meas = (last && fused) ? h->d_fused : nullptr;
+            LGF_HIP(lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, last ? (fused ? 2 : 1) : 0, h->stream));
+        }
+        return LGF_OK;
+    };
+    if (!use_graph) return issue(false);
+    GraphEntry key{format, const_cast<void *>(links), n, omega, t, 0, gf, fused ? 1 : 0, p_sr, seed, 1, nullptr};
+    return run_captured(h, key, sweep0, [&]() { return issue(true); });
+}
+
+// F and theta of the links g(x) U_mu(x) g(x+mu)^dag: after a fused chunk its
+// partial sums plus a read-only pass over the parity-0 sites, else a pass
+// over each parity
+lgf_status measure_fixed_field(lgf_lattice *h, int format, const void *links, const void *gf, bool fused,
+                               double *F, double *theta)
+{
+    int n0 = 0, n1 = 0;
+    if (fused) {
+        const int ng = (int)lgf::fixed_sweep_groups(h->geom, h->tune_fixed[format]);
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused + 2 * (size_t)ng, &n0, h->stream));
+        LGF_HIP(lgf::launch_finish_measure(h->d_fused, ng + n0, (double)h->V, h->d_out, h->stream));
+    } else {
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_partials, &n0, h->stream));
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 1, h->d_partials + 2 * (size_t)n0, &n1,
+                                          h->stream));
+        LGF_HIP(lgf::launch_finish_measure(h->d_partials, n0 + n1, (double)h->V, h->d_out, h->stream));
+    }
+    LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    if (F) *F = h->h_out[0];
+    if (theta) *theta = h->h_out[1];
+    return LGF_OK;
+}
+
+// lgf_gauge_fix with fixed_links set (the parameters are checked by the
+// caller): the same chunks, measurements and precision switch, on (U, g)
+// instead of on the links; at the end the handle's links become
+// g(x) U_mu(x) g(x+mu)^dag, computed from the untouched input.
+lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, int finish, lgf_fix_result *res,
+                           double *history, int history_cap)
+{
+    const bool mixed = (bulk != finish);
+    const auto t_start = std::chrono::steady_clock::now();
+    int nh = 0;
+    auto record = [&](int64_t sweeps, double F, double th) {
+        if (history && nh < history_cap) {
+            history[3 * nh] = (double)sweeps;
+            history[3 * nh + 1] = F;
+            history[3 * nh + 2] = th;
+            ++nh;
+        }
+    };
+    auto timed = [&](double &acc_ms, auto &&body) -> lgf_status {
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(body());
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        acc_ms += elapsed_ms(h->ev0, h->ev1);
+        return LGF_OK;
+    };
+
+    double F = 0.0, theta = 0.0;
+    LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_field(h, h->format, h->field, false, &F, &theta); }));
+    record(0, F, theta);
+
+    int64_t sweeps = 0, sweeps_bulk = 0;
+    uint64_t ctr = p.sweep_offset;
+    lgf_status status = LGF_ENOTCONV;
+    if (!std::isfinite(F) || !std::isfinite(theta)) status = LGF_ENUMERIC;
+    else if (theta < p.theta_target) status = LGF_OK;
+
+    bool in_bulk = mixed;
+    int cur = in_bulk ? bulk : finish;
+    void *links = nullptr;
+    bool started = false;
+    if (status == LGF_ENOTCONV && p.max_sweeps > 0) {
+        LGF_TRY(ensure_gfix(h, cur));
+        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+            LGF_TRY(links_in_format(h, cur, &links));
+            LGF_HIP(lgf::launch_site_field(cur, h->gfix[cur], h->geom, 0, h->stream));
+            return LGF_OK;
+        }));
+        started = true;
+    }
+    const bool fuse = !p.separate_measure;
+    while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
+            return run_chunk_fixed(h, cur, links, h->gfix[cur], n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0,
+                                   fuse);
+        }));
+        if (in_bulk) sweeps_bulk += n;
+        sweeps += n;
+        ctr += (uint64_t)n;
+        LGF_TRY(timed(res->t_measure_ms,
+                      [&]() { return measure_fixed_field(h, cur, links, h->gfix[cur], fuse, &F, &theta); }));
+        record(sweeps, F, theta);
+        if (!std::isfinite(F) || !std::isfinite(theta)) {
+            status = LGF_ENUMERIC;
+            break;
+        }
+        if (in_bulk && (theta < p.theta_switch || theta < p.theta_target)) {
+            // the finish precision starts from the bulk's g, reunitarized in
+            // FP64, on the links of its own format (the input itself when the
+            // formats agree)
+            LGF_TRY(ensure_gfix(h, finish));
+            LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+                LGF_TRY(links_in_format(h, finish, &links));
+                LGF_HIP(lgf::launch_site_convert(bulk, h->gfix[bulk], finish, h->gfix[finish], h->geom, h->stream));
+                return LGF_OK;
+            }));
+            cur = finish;
+            in_bulk = false;
+            if (theta < p.theta_target) {
+                LGF_TRY(timed(res->t_measure_ms, [&]() {
+                    return measure_fixed_field(h, cur, links, h->gfix[cur], false, &F, &theta);
+                }));
+                record(sweeps, F, theta);
+            } else {
+                continue;
+            }
+        }
+        if (!in_bulk && theta < p.theta_target) status = LGF_OK;
+    }
+    if (started) {
+        // the links in the final gauge, from the untouched input (element-wise
+        // per link, so in place)
+        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, cur, h->gfix[cur], h->format, h->field, h->geom,
+                                                h->stream));
+            return LGF_OK;
+        }));
+    }
+    res->sweeps = sweeps;
+    res->sweeps_bulk = sweeps_bulk;
+    res->theta = theta;
+    res->F = F;
+    res->status = status;
+    res->n_history = nh;
+    res->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (status == LGF_ENOTCONV)
+        return fail(LGF_ENOTCONV, "theta %g after %lld sweeps has not reached %g", theta, (long long)sweeps,
+                    p.theta_target);
+    if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", F, theta);
     return LGF_OK;
 }
 
@@ -553,7 +853,10 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     h->field_bytes = need;
     // defaults: one lane per site, 128-thread workgroups, non-temporal
     // streaming (fastest measured at 64^4 for every format)
-    for (int f = 0; f < 4; ++f) h->tune[f] = default_tuning(f);
+    for (int f = 0; f < 4; ++f) {
+        h->tune[f] = default_tuning(f);
+        h->tune_fixed[f] = default_fixed_tuning(f);
+    }
 
     auto bail = [&](lgf_status st) {
         lgf_destroy(h);
@@ -604,6 +907,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
     for (int f = 0; f < 4; ++f) {
         if (h->work[f]) (void)hipFree(h->work[f]);
         if (h->partner[f]) (void)hipFree(h->partner[f]);
+        if (h->gfix[f]) (void)hipFree(h->gfix[f]);
     }
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_fused) (void)hipFree(h->d_fused);
@@ -797,6 +1101,12 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
         lgf_lattice *h;
         ~AccOff() { h->gacc_active = nullptr; }
     } acc_off{h};
+    if (p.fixed_links) {
+        if (!is64(h->format)) return fail(LGF_EINVAL, "fixed_links needs an FP64 handle");
+        LGF_TRY(use_device(h));
+        std::memset(res, 0, sizeof *res);
+        return gauge_fix_fixed(h, p, bulk, finish, res, history, history_cap);
+    }
     if (acc && !(mixed && !is64(bulk) && is64(finish) && is64(h->format)))
         return fail(LGF_EINVAL, "accumulate_g needs an FP32 bulk, an FP64 finish and an FP64 handle");
     LGF_TRY(use_device(h));
@@ -1199,6 +1509,101 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *t)
     return LGF_OK;
 }
 
+lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *t)
+{
+    if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    const lgf_sweep_tuning u = *t;
+    if (u.lanes_per_site != 2 && u.lanes_per_site != 4)
+        return fail(LGF_EINVAL, "the fixed-link sweep takes lanes_per_site 2 or 4");
+    if (u.block != 64 && u.block != 128 && u.block != 256) return fail(LGF_EINVAL, "block must be 64, 128 or 256");
+    if (u.xcd_remap < 0 || u.xcd_remap > 2) return fail(LGF_EINVAL, "xcd_remap must be 0, 1 or 2");
+    if (u.sites_per_thread != 1 || u.nontemporal != 1 || u.schedule != lgf::kScheduleInPlace)
+        return fail(LGF_EINVAL, "the fixed-link sweep takes sites_per_thread 1, nontemporal 1, schedule 0");
+    lgf::SweepTuning n{};
+    n.lanes_per_site = u.lanes_per_site;
+    n.block = u.block;
+    n.xcd_remap = u.xcd_remap;
+    h->tune_fixed[format] = n;
+    drop_graphs(h);
+    return LGF_OK;
+}
+
+lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *t)
+{
+    if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    const lgf::SweepTuning &u = h->tune_fixed[format];
+    t->lanes_per_site = u.lanes_per_site;
+    t->sites_per_thread = u.sites_per_thread;
+    t->block = u.block;
+    t->xcd_remap = u.xcd_remap;
+    t->nontemporal = u.nontemporal;
+    t->schedule = u.schedule;
+    return LGF_OK;
+}
+
+lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
+    if (h->format != LGF_FP64_18 && h->format != LGF_FP64_12)
+        return fail(LGF_EINVAL, "the fixed-link form needs an FP64 handle");
+    LGF_TRY(use_device(h));
+    // The fixed-link sweeps only read the links (the handle's own, or their
+    // working copy in this format) and write the gauge transformation, which
+    // the gauge fixing resets before use: nothing needs saving.
+    void *links = nullptr;
+    LGF_TRY(ensure_gfix(h, format));
+    LGF_TRY(links_in_format(h, format, &links));
+    void *gf = h->gfix[format];
+    LGF_HIP(lgf::launch_site_field(format, gf, h->geom, 0, h->stream));
+    hipError_t e = hipSuccess;
+    auto sweep = [&](const lgf::SweepTuning &t) {
+        lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};
+        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, 0, h->stream);
+        a.parity = 1;
+        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, 0, h->stream);
+    };
+    auto time_variant = [&](const lgf::SweepTuning &t, int n, double *ms) {
+        sweep(t);
+        if (e == hipSuccess) e = hipEventRecord(h->ev0, h->stream);
+        for (int k = 0; k < n && e == hipSuccess; ++k) sweep(t);
+        if (e == hipSuccess) e = hipEventRecord(h->ev1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+        if (e != hipSuccess) return false;
+        *ms = elapsed_ms(h->ev0, h->ev1) / n;
+        return true;
+    };
+    const lgf::SweepTuning dflt = default_fixed_tuning(format);
+    // warm-up under the same sustained load, as for the link sweeps
+    const auto w0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < 2000 && e == hipSuccess; k += 20) {
+        for (int j = 0; j < 20; ++j) sweep(dflt);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 3.0) break;
+    }
+    std::vector<lgf::SweepTuning> variants;
+    for (int lps : {2, 4})
+        for (int block : {64, 128, 256})
+            for (int order = 0; order < 3; ++order) {
+                lgf::SweepTuning t{};
+                t.lanes_per_site = lps;
+                t.block = block;
+                t.xcd_remap = order;
+                variants.push_back(t);
+            }
+    lgf::SweepTuning best = h->tune_fixed[format];
+    const bool ok = e == hipSuccess &&
+                    pick_variant(variants, dflt, trials, "lgf_autotune_fixed", format, time_variant, &best);
+    (void)hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(LGF_EHIP, "autotune_fixed: %s", hipGetErrorString(e));
+    if (ok) h->tune_fixed[format] = best;
+    drop_graphs(h);
+    return LGF_OK;
+}
+
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
@@ -1264,72 +1669,23 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
         }
     }
     // stage 1: every variant once
-    struct Cand {
-        lgf::SweepTuning t;
-        double ms;
-    };
-    std::vector<Cand> cands;
+    std::vector<lgf::SweepTuning> variants;
     const int lps_list[3] = {1, 2, 4};
     const int block_list[3] = {64, 128, 256};
-    bool ok = (e == hipSuccess && st == LGF_OK);
-    for (int li = 0; li < 3 && ok; ++li)
-        for (int bi = 0; bi < 3 && ok; ++bi)
-            for (int v = 0; v < 48 && ok; ++v) {
+    for (int li = 0; li < 3; ++li)
+        for (int bi = 0; bi < 3; ++bi)
+            for (int v = 0; v < 48; ++v) {
                 const int xcd = v & 1, nt = (v >> 1) & 1, sched = (v >> 2) % 3, spt = 1 << (v / 12);
                 // the t-slice pipeline is measured slower at every size it was
                 // tried on; it stays a manual option (lgf_set_tuning)
                 if (sched == lgf::kSchedulePipeline || spt > 4) continue;
                 if (sched == lgf::kScheduleOutOfPlace && (!nt || !can_oop)) continue;
                 if (spt > 1 && xcd) continue;
-                Cand c{lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched, spt}, 0.0};
-                ok = time_variant(c.t, trials, &c.ms);
-                if (ok) cands.push_back(c);
+                variants.push_back(lgf::SweepTuning{lps_list[li], block_list[bi], xcd, nt, sched, spt});
             }
-    // stage 2: the four fastest and the default, timed again over ten times
-    // as many sweeps in five interleaved rounds; the smallest median wins
-    // (single short timings of variants a few per cent apart are within the
-    // run-to-run noise)
     lgf::SweepTuning best = saved;
-    if (ok) {
-        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
-        std::vector<lgf::SweepTuning> finals;
-        for (size_t i = 0; i < cands.size() && finals.size() < 4; ++i) finals.push_back(cands[i].t);
-        const lgf::SweepTuning dflt = default_tuning(format);
-        bool have_default = false;
-        for (const auto &t : finals)
-            have_default = have_default || t == dflt;
-        if (!have_default) finals.push_back(dflt);
-        std::vector<std::vector<double>> ms(finals.size());
-        const int n2 = std::max(10 * trials, 20);
-        for (int round = 0; round < 5 && ok; ++round)
-            for (size_t i = 0; i < finals.size() && ok; ++i) {
-                double m = 0.0;
-                ok = time_variant(finals[i], n2, &m);
-                ms[i].push_back(m);
-            }
-        if (ok) {
-            double best_ms = 1e300;
-            const bool log = std::getenv("LGF_AUTOTUNE_LOG") != nullptr;
-            for (size_t i = 0; i < finals.size(); ++i) {
-                std::sort(ms[i].begin(), ms[i].end());
-                if (log) {
-                    const lgf::SweepTuning &t = finals[i];
-                    std::fprintf(stderr, "lgf_autotune format %d: lanes %d block %d xcd %d nt %d schedule %d spt %d: "
-                                 "median %.4f ms per full sweep (min %.4f, max %.4f)\n", format, t.lanes_per_site,
-                                 t.block, t.xcd_remap, t.nontemporal, t.schedule, t.sites_per_thread, ms[i][2],
-                                 ms[i][0], ms[i][4]);
-                }
-                if (ms[i][2] < best_ms) {
-                    best_ms = ms[i][2];
-                    best = finals[i];
-                }
-            }
-            // a variant replaces the default only when clearly faster: near-ties
-            // are within what one GPU's timings drift over a long run
-            for (size_t i = 0; i < finals.size(); ++i)
-                if (finals[i] == dflt && best_ms > 0.99 * ms[i][2]) best = dflt;
-        }
-    }
+    if (e == hipSuccess && st == LGF_OK)
+        (void)pick_variant(variants, default_tuning(format), trials, "lgf_autotune", format, time_variant, &best);
     h->tune[format] = saved;
     if (backup) {
         const hipError_t e2 = hipMemcpyAsync(h->field, backup, bytes, hipMemcpyDeviceToDevice, h->stream);

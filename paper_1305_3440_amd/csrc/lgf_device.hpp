@@ -171,7 +171,9 @@ __device__ __forceinline__ typename Fmt<F>::V *block_ptr(void *field, uint32_t V
            (size_t)((parity * 4 + mu) * Fmt<F>::NV) * Vh;
 }
 
-template <int F, bool NT = false>
+// ROW2 = false leaves row 2 of a 12-real link unset (for callers that only
+// read rows 0 and 1)
+template <int F, bool NT = false, bool ROW2 = true>
 __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *blk,
                                           uint32_t Vh, uint32_t h)
 {
@@ -189,7 +191,7 @@ __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typ
             u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v[k].z, v[k].w};
         }
     }
-    if constexpr (S::R == 2) rebuild_row2(u);
+    if constexpr (S::R == 2 && ROW2) rebuild_row2(u);
 }
 
 template <int F, bool NT = false>
@@ -257,6 +259,17 @@ __device__ __forceinline__ uint32_t back_half(const Geom &g, const Site &c, uint
     const uint32_t ext = g.L[mu];
     const uint32_t hs = g.hs[mu];
     return (coord == 0) ? h + (ext - 1) * hs : h - hs;
+}
+
+// half index (in the other parity) of the site x + mu
+__device__ __forceinline__ uint32_t fwd_half(const Geom &g, const Site &c, uint32_t h, int mu)
+{
+    if (mu == 3) {
+        const uint32_t xf = (c.x + 1 == g.L[3]) ? 0 : c.x + 1;
+        return c.row * g.hx + (xf >> 1);
+    }
+    const uint32_t coord = (mu == 0) ? c.t : (mu == 1) ? c.z : c.y;
+    return (coord + 1 == g.L[mu]) ? h - (g.L[mu] - 1) * g.hs[mu] : h + g.hs[mu];
 }
 
 __device__ __forceinline__ uint32_t lex_index(const Geom &g, const Site &c) { return c.row * g.L[3] + c.x; }

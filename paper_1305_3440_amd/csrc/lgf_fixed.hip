@@ -1,0 +1,233 @@
+// lgf_fixed.hip -- kernels of the fixed-link form of the relaxation sweep:
+// the links keep their input values, the sweep updates the gauge
+// transformation g (a site field in the links' format) and forms each link in
+// the current gauge, g(x) U_mu(x) g(x+mu)^dag (Eq. (3)), in registers only.
+//
+// Per site update the stream is 8 links in (read only) plus g(x) in and out,
+// and the 8 neighbouring g of the other parity, each shared by 8 sites of the
+// half-sweep and mostly served by L2 and the last-level cache: 1056 B of
+// unique traffic per site update in FP64-12 against 1536 B for the update that
+// rewrites the links, 528 B against 768 B in FP32-12.  The price is the 8
+// products U g^dag, g U per site, ~1.3k more multiply-adds, still well under
+// the time the bytes take at either precision.
+#include "lgf_device.hpp"
+#include "lgf_internal.hpp"
+#include "lgf_site.hpp"
+
+namespace lgf {
+
+// Order in which the workgroups walk the tiles of a half-sweep (a tile is the
+// block / LPS consecutive sites of one workgroup).  Every g of the other
+// parity is read by the 8 neighbours of its site, so the order decides how
+// often it comes from L2 rather than from HBM: in the lexicographic order the
+// y-neighbour rows lie in the next workgroup, which the round-robin dispatch
+// puts on another XCD, and the t-neighbours a whole t-slice of tiles away.
+//   mode 0: lexicographic;
+//   mode 1: contiguous ranges of tiles per XCD;
+//   mode 2: blocks of Bt t-slices x Bz z-planes (all y and x) per XCD, each
+//           walked with z fastest, then t, then the tiles of a plane, so that
+//           the t-, z- and y-neighbours of a tile are 1, Bz and Bt Bz tiles
+//           earlier or later on the same XCD.  Block k goes to XCD k % 8 (the
+//           dispatch deals workgroup b to XCD b % 8).
+struct TileOrder {
+    uint32_t mode;
+    uint32_t tile;   // sites per tile
+    uint32_t P;      // tiles per (t, z) plane
+    uint32_t plane;  // sites per (t, z) plane, Ly Lx / 2
+    uint32_t Bt, Bz, nzb;  // block extents in t and z; Lz / Bz
+    uint32_t tpb;    // tiles per block, Bt Bz P
+};
+
+// One half-sweep over all Vh sites of a parity, LPS lanes per site; POST as
+// in update_site_fixed, with workgroup b's (F, theta) sums in partials[2b]
+// when POST == 2.
+template <int F, int LPS, bool SR, int POST>
+__global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict__ links, void *__restrict__ gf,
+                                                          Geom g, int parity, RelaxArgs<typename Fmt<F>::T> a,
+                                                          TileOrder o, uint32_t n_groups,
+                                                          double *__restrict__ partials)
+{
+    const uint32_t b = blockIdx.x;
+    uint32_t h0;        // first site of the tile (Vh <= 2^30, LPS <= 4)
+    uint32_t slot = b;  // partial-sum slot of the tile, < n_groups
+    if (o.mode == 2) {
+        const uint32_t s = b >> 3, blk = (s / o.tpb) * 8u + (b & 7u), i = s % o.tpb;
+        const uint32_t r = i % (o.Bt * o.Bz);
+        const uint32_t t = (blk / o.nzb) * o.Bt + r / o.Bz, z = (blk % o.nzb) * o.Bz + r % o.Bz;
+        h0 = (t * g.L[1] + z) * o.plane + (i / (o.Bt * o.Bz)) * o.tile;
+    } else if (o.mode == 1) {
+        const uint32_t per = gridDim.x >> 3, w = (b & 7u) * per + (b >> 3);
+        if (w >= n_groups) return;  // the whole workgroup: no tile
+        h0 = w * o.tile;
+        slot = w;
+    } else {
+        h0 = b * o.tile;
+    }
+    const uint32_t grp = h0 + threadIdx.x / LPS;
+    const bool active = grp < g.Vh;
+    MeasAcc acc;
+    update_site_fixed<F, LPS, SR, POST>(links, gf, g, parity, active ? grp : g.Vh - 1, (int)(threadIdx.x % LPS),
+                                        active, a, &acc);
+    if constexpr (POST == 2) block_sum2_any(acc.f, acc.th, partials + 2 * slot);
+}
+
+uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t)
+{
+    const uint64_t threads = (uint64_t)g.Vh * (uint64_t)t.lanes_per_site;
+    return (uint32_t)((threads + t.block - 1) / t.block);
+}
+
+// The tile order of a tuning on this lattice; mode 2 takes the largest
+// blocks of 8, 4 or 2 t-slices and z-planes that divide the lattice into a
+// multiple of 8 blocks of whole tiles, else it falls back to mode 0.
+static TileOrder tile_order(const Geom &g, const SweepTuning &t)
+{
+    TileOrder o{};
+    o.mode = (uint32_t)t.xcd_remap;
+    o.tile = (uint32_t)(t.block / t.lanes_per_site);
+    o.plane = g.L[2] * g.hx;
+    if (o.mode != 2) return o;
+    o.mode = 0;
+    if (o.plane % o.tile != 0) return o;
+    o.P = o.plane / o.tile;
+    for (uint32_t B = 8; B >= 2; B >>= 1) {
+        if (g.L[0] % B != 0 || g.L[1] % B != 0) continue;
+        const uint32_t nb = (g.L[0] / B) * (g.L[1] / B);
+        if (nb % 8 != 0) continue;
+        o.mode = 2;
+        o.Bt = o.Bz = B;
+        o.nzb = g.L[1] / B;
+        o.tpb = B * B * o.P;
+        break;
+    }
+    return o;
+}
+
+template <int F, int LPS>
+static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
+                                 int post, hipStream_t s)
+{
+    using T = typename Fmt<F>::T;
+    const uint32_t ng = fixed_sweep_groups(g, t);
+    const TileOrder o = tile_order(g, t);
+    const dim3 grid(o.mode == 1 ? ((ng + 7u) / 8u) * 8u : ng), block(t.block);
+    RelaxArgs<T> ra{(T)a.omega, (a.omega != 1.0) ? 1 : 0, 0, (uint32_t)a.seed, (uint32_t)(a.seed >> 32),
+                    (uint32_t)a.sweep_index, a.instance, nullptr, a.sweep_base};
+    const bool sr = a.p_sr > 0.0;
+    if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
+    double *m = a.meas;
+    if (post == 2 && !m) return hipErrorInvalidValue;
+#define LGF_FIX_LAUNCH(SRV, P) \
+    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, m)
+    if (sr) {
+        if (post == 0) LGF_FIX_LAUNCH(true, 0);
+        else if (post == 1) LGF_FIX_LAUNCH(true, 1);
+        else LGF_FIX_LAUNCH(true, 2);
+    } else {
+        if (post == 0) LGF_FIX_LAUNCH(false, 0);
+        else if (post == 1) LGF_FIX_LAUNCH(false, 1);
+        else LGF_FIX_LAUNCH(false, 2);
+    }
+#undef LGF_FIX_LAUNCH
+    return hipGetLastError();
+}
+
+template <int F>
+static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
+                                 int post, hipStream_t s)
+{
+    switch (t.lanes_per_site) {
+    case 2: return launch_fixed_t<F, 2>(links, gf, g, a, t, post, s);
+    case 4: return launch_fixed_t<F, 4>(links, gf, g, a, t, post, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
+                              const SweepTuning &t, int post, hipStream_t s)
+{
+    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0 || post < 0 || post > 2 || a.h_end != 0 || a.out)
+        return hipErrorInvalidValue;
+    switch (format) {
+    case kF64_18: return launch_fixed_f<kF64_18>(links, gf, g, a, t, post, s);
+    case kF32_18: return launch_fixed_f<kF32_18>(links, gf, g, a, t, post, s);
+    case kF32_12: return launch_fixed_f<kF32_12>(links, gf, g, a, t, post, s);
+    case kF64_12: return launch_fixed_f<kF64_12>(links, gf, g, a, t, post, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int F>
+__global__ void __launch_bounds__(kMeasureBlock) measure_fixed_kernel(const void *__restrict__ links,
+                                                                      const void *__restrict__ gf, Geom g,
+                                                                      int parity, double *partials)
+{
+    const uint32_t h0 = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const bool active = h0 < g.Vh;
+    double f, th;
+    measure_site_fixed<F>(links, gf, g, parity, active ? h0 : g.Vh - 1, active, f, th);
+    block_sum2<kMeasureBlock>(f, th, partials + 2 * blockIdx.x);
+}
+
+hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
+                                double *partials, int *n_partials, hipStream_t s)
+{
+    const int nb = measure_blocks(g);
+    *n_partials = nb;
+    const dim3 grid(nb), block(kMeasureBlock);
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((measure_fixed_kernel<kF64_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF32_18: hipLaunchKernelGGL((measure_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF32_12: hipLaunchKernelGGL((measure_fixed_kernel<kF32_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF64_12: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// site field conversion with FP64 reunitarization (the gauge transformation
+// handed from the bulk precision to the finish precision)
+template <int FS, int FD>
+__global__ void __launch_bounds__(256) site_convert_kernel(const void *__restrict__ src, void *__restrict__ dst,
+                                                           uint32_t Vh)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= Vh) return;
+    const int parity = blockIdx.y;
+    mat3<typename Fmt<FS>::T> a;
+    load_link<FS>(a, site_field_ptr<FS>(const_cast<void *>(src), Vh, parity), Vh, h);
+    mat3<double> d;
+    convert(d, a);
+    reunitarize(d);
+    mat3<typename Fmt<FD>::T> o;
+    convert(o, d);
+    store_link<FD>(site_field_ptr<FD>(dst, Vh, parity), Vh, h, o);
+}
+
+template <int FS>
+static hipError_t launch_site_convert_s(const void *src, int fd, void *dst, uint32_t Vh, hipStream_t s)
+{
+    const dim3 grid((Vh + 255) / 256, 2);
+    switch (fd) {
+    case kF64_18: hipLaunchKernelGGL((site_convert_kernel<FS, kF64_18>), grid, dim3(256), 0, s, src, dst, Vh); break;
+    case kF32_18: hipLaunchKernelGGL((site_convert_kernel<FS, kF32_18>), grid, dim3(256), 0, s, src, dst, Vh); break;
+    case kF32_12: hipLaunchKernelGGL((site_convert_kernel<FS, kF32_12>), grid, dim3(256), 0, s, src, dst, Vh); break;
+    case kF64_12: hipLaunchKernelGGL((site_convert_kernel<FS, kF64_12>), grid, dim3(256), 0, s, src, dst, Vh); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const Geom &g, hipStream_t s)
+{
+    if (src == dst) return hipErrorInvalidValue;
+    switch (fs) {
+    case kF64_18: return launch_site_convert_s<kF64_18>(src, fd, dst, g.Vh, s);
+    case kF32_18: return launch_site_convert_s<kF32_18>(src, fd, dst, g.Vh, s);
+    case kF32_12: return launch_site_convert_s<kF32_12>(src, fd, dst, g.Vh, s);
+    case kF64_12: return launch_site_convert_s<kF64_12>(src, fd, dst, g.Vh, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lgf

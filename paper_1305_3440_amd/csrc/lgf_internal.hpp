@@ -100,7 +100,8 @@ hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *
 // site field (2 parities x one SU(3) per site, link-direction layout):
 // mode 0 sets the identity, mode 1 reunitarizes in FP64
 hipError_t launch_site_field(int format, void *gf, const Geom &g, int mode, hipStream_t s);
-// dst (format fd, FP64) <- g(x) src_mu(x) g(x+mu)^dag for src FP64 and g FP32
+// dst (format fd, FP64) <- g(x) src_mu(x) g(x+mu)^dag for src FP64 and g in
+// any format (reunitarized in FP64 as it is read); dst may be src
 hipError_t launch_gauge_transform(int fs, const void *src, int fg, const void *gf, int fd, void *dst,
                                   const Geom &g, hipStream_t s);
 
@@ -108,5 +109,19 @@ hipError_t launch_gauge_transform(int fs, const void *src, int fg, const void *g
 // entry of each pair); finish with launch_finish_measure (out[0] * 12 V / 18 V)
 hipError_t launch_plaquette(int format, void *field, const Geom &g, double *partials, int *n_partials,
                             hipStream_t s);
+
+// Fixed-link form of the sweep (links read only, the site field gf of the
+// gauge transformation updated; both in `format`).  post: 0 plain, 1 the new
+// g reunitarized in FP64 as it is stored, 2 as 1 plus the per-workgroup
+// (F, theta) partial sums of the updated sites in a.meas.  Tuning: lanes per
+// site 1 or 2, block, xcd_remap.
+hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
+                              const SweepTuning &t, int post, hipStream_t s);
+uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
+// per-block (F, theta) partial sums over one parity's sites, fixed-link form
+hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
+                                double *partials, int *n_partials, hipStream_t s);
+// site field dst (format fd) <- src (format fs), reunitarized in FP64
+hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const Geom &g, hipStream_t s);
 
 }  // namespace lgf

@@ -692,17 +692,6 @@ hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *
 
 namespace lgf {
 
-// half index (in the other parity) of the site x + mu
-__device__ __forceinline__ uint32_t fwd_half(const Geom &g, const Site &c, uint32_t h, int mu)
-{
-    if (mu == 3) {
-        const uint32_t xf = (c.x + 1 == g.L[3]) ? 0 : c.x + 1;
-        return c.row * g.hx + (xf >> 1);
-    }
-    const uint32_t coord = (mu == 0) ? c.t : (mu == 1) ? c.z : c.y;
-    return (coord + 1 == g.L[mu]) ? h - (g.L[mu] - 1) * g.hs[mu] : h + g.hs[mu];
-}
-
 template <int F>
 __global__ void __launch_bounds__(kMeasureBlock) plaquette_kernel(void *__restrict__ field, Geom g,
                                                                   double *partials)
@@ -840,10 +829,12 @@ static hipError_t launch_gt_d(int fd, const void *src, const void *gf, void *dst
 hipError_t launch_gauge_transform(int fs, const void *src, int fg, const void *gf, int fd, void *dst, const Geom &g,
                                   hipStream_t s)
 {
-    if (fs == kF64_18 && fg == kF32_12) return launch_gt_d<kF64_18, kF32_12>(fd, src, gf, dst, g, s);
-    if (fs == kF64_18 && fg == kF32_18) return launch_gt_d<kF64_18, kF32_18>(fd, src, gf, dst, g, s);
-    if (fs == kF64_12 && fg == kF32_12) return launch_gt_d<kF64_12, kF32_12>(fd, src, gf, dst, g, s);
-    if (fs == kF64_12 && fg == kF32_18) return launch_gt_d<kF64_12, kF32_18>(fd, src, gf, dst, g, s);
+#define LGF_GT_CASE(FS, FG) \
+    if (fs == FS && fg == FG) return launch_gt_d<FS, FG>(fd, src, gf, dst, g, s);
+    LGF_GT_CASE(kF64_18, kF32_12) LGF_GT_CASE(kF64_18, kF32_18) LGF_GT_CASE(kF64_18, kF64_12)
+    LGF_GT_CASE(kF64_18, kF64_18) LGF_GT_CASE(kF64_12, kF32_12) LGF_GT_CASE(kF64_12, kF32_18)
+    LGF_GT_CASE(kF64_12, kF64_12) LGF_GT_CASE(kF64_12, kF64_18)
+#undef LGF_GT_CASE
     return hipErrorInvalidValue;
 }
 

@@ -239,6 +239,292 @@ __device__ __forceinline__ void update_site(void *__restrict__ field, const Geom
 }
 
 // ----------------------------------------------------------------------------
+// Fixed-link form of the sweep.  The links U keep their input values and the
+// sweep updates the gauge transformation g instead; the link in the current
+// gauge, g(x) U_mu(x) g(x+mu)^dag (Eq. (3)), exists only in registers.  With
+// those links the K(x) of Eq. (8) factorises as
+//   K(x) = g(x) M(x),  M(x) = sum_mu U_mu(x) g(x+mu)^dag + [g(x-mu) U_mu(x-mu)]^dag,
+// so a site update reads its 8 links and the 8 neighbouring g of the other
+// parity, runs the same three SU(2) steps on K starting from G = g(x), and
+// stores only the new g(x).  A half-sweep moves 8 links in and one g in and
+// out per site instead of 8 links in and out; the neighbouring g are shared by
+// 8 sites each and mostly come from the caches.
+// ----------------------------------------------------------------------------
+
+// acc += p (all 9 entries)
+template <typename T> __device__ __forceinline__ void add_to(mat3<T> &acc, const mat3<T> &p)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc.e[i][j] = acc.e[i][j] + p.e[i][j];
+}
+
+// acc += p^dag
+template <typename T> __device__ __forceinline__ void add_dag_to(mat3<T> &acc, const mat3<T> &p)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc.e[i][j] = acc.e[i][j] + conj(p.e[j][i]);
+}
+
+// Re tr[a b]
+__device__ __forceinline__ double re_tr_mul(const mat3<double> &a, const mat3<double> &b)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += a.e[i][k].re * b.e[k][i].re - a.e[i][k].im * b.e[k][i].im;
+    return s;
+}
+
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The products of the fixed-link update as explicit multiply-add chains (the
+// complex operators round every product and sum separately): rows [0, R) of
+// r = u y^dag ...
+template <int R, typename T>
+__device__ __forceinline__ void mul_dag_fma(mat3<T> &r, const mat3<T> &u, const mat3<T> &y)
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T re = u.e[i][0].re * y.e[j][0].re, im = u.e[i][0].im * y.e[j][0].re;
+            re = fmadd(u.e[i][0].im, y.e[j][0].im, re);
+            im = fmadd(-u.e[i][0].re, y.e[j][0].im, im);
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                re = fmadd(u.e[i][k].re, y.e[j][k].re, re);
+                re = fmadd(u.e[i][k].im, y.e[j][k].im, re);
+                im = fmadd(u.e[i][k].im, y.e[j][k].re, im);
+                im = fmadd(-u.e[i][k].re, y.e[j][k].im, im);
+            }
+            r.e[i][j] = {re, im};
+        }
+}
+
+// ... rows [0, R) of r = y u ...
+template <int R, typename T>
+__device__ __forceinline__ void mul_fma(mat3<T> &r, const mat3<T> &y, const mat3<T> &u)
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T re = y.e[i][0].re * u.e[0][j].re, im = y.e[i][0].re * u.e[0][j].im;
+            re = fmadd(-y.e[i][0].im, u.e[0][j].im, re);
+            im = fmadd(y.e[i][0].im, u.e[0][j].re, im);
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                re = fmadd(y.e[i][k].re, u.e[k][j].re, re);
+                re = fmadd(-y.e[i][k].im, u.e[k][j].im, re);
+                im = fmadd(y.e[i][k].re, u.e[k][j].im, im);
+                im = fmadd(y.e[i][k].im, u.e[k][j].re, im);
+            }
+            r.e[i][j] = {re, im};
+        }
+}
+
+// ... and row 2 = conj(row0 x row1), the last row of an SU(3) matrix
+template <typename T> __device__ __forceinline__ void row2_fma(mat3<T> &m)
+{
+    auto cross = [&](int a, int b, int c, int d) {  // conj(m0a m1b - m0c m1d)
+        const cpx<T> A = m.e[0][a], B = m.e[1][b], C = m.e[0][c], D = m.e[1][d];
+        T re = C.im * D.im;
+        re = fmadd(-C.re, D.re, re);
+        re = fmadd(-A.im, B.im, re);
+        re = fmadd(A.re, B.re, re);
+        T s = C.re * D.im;
+        s = fmadd(C.im, D.re, s);
+        T im = fmadd(A.re, B.im, -s);
+        im = fmadd(A.im, B.re, im);
+        return cpx<T>{re, -im};
+    };
+    m.e[2][0] = cross(1, 2, 2, 1);
+    m.e[2][1] = cross(2, 0, 0, 2);
+    m.e[2][2] = cross(0, 1, 1, 0);
+}
+
+// The fused measurement's FP64 copy of one term of M (POST == 2), computed as
+// the read-only measurement computes it: the operands with row 2 rebuilt as
+// a load rebuilds it, whole products in FP64.  BWD: the term is (a b)^dag
+// (a = g(x-mu), b = U_mu(x-mu)); else a b^dag (a = U_mu(x), b = g(x+mu)).
+template <int R, bool BWD, typename T>
+__device__ __forceinline__ void fixed_meas_term(mat3<double> &acc, const mat3<T> &a, const mat3<T> &b)
+{
+    mat3<T> a2 = a, b2 = b;
+    if constexpr (R == 2) {
+        rebuild_row2(a2);
+        rebuild_row2(b2);
+    }
+    mat3<double> ad, bd, pd;
+    convert(ad, a2);
+    convert(bd, b2);
+    if constexpr (BWD) {
+        left_mul<3>(pd, ad, bd);
+        add_dag_to(acc, pd);
+    } else {
+        right_mul_dag<3>(pd, ad, bd);
+        add_to(acc, pd);
+    }
+}
+
+template <int LPS, typename T> __device__ __forceinline__ void lane_sum(mat3<T> &m)
+{
+#pragma unroll
+    for (int s = 1; s < LPS; s <<= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                m.e[i][j].re += shfl_xor_t(m.e[i][j].re, s);
+                m.e[i][j].im += shfl_xor_t(m.e[i][j].im, s);
+            }
+}
+
+// The update of site h of the given parity in the fixed-link form, LPS lanes
+// per site (each gathers the terms of 4 / LPS directions; M is summed over the
+// lanes, every lane then runs the SU(2) steps and lane 0 stores).  links and
+// the site field gf are in format F.
+// POST = 1: the new g(x) is reunitarized in FP64 and rounded to the format
+// before it is stored.  POST = 2: as 1, and the site's contributions to F and
+// theta, from the links formed with the stored g(x) and the stored
+// neighbours, go to acc (Re tr of its 4 forward links, tr[Delta Delta^dag]).
+template <int F, int LPS, bool SR, int POST>
+__device__ __forceinline__ void update_site_fixed(const void *__restrict__ links, void *__restrict__ gf,
+                                                  const Geom &g, int parity, uint32_t h, int lane, bool active,
+                                                  const RelaxArgs<typename Fmt<F>::T> &a, MeasAcc *acc)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    constexpr int NL = 4 / LPS;
+    void *U = const_cast<void *>(links);
+    const typename S::V *gn = site_field_ptr<F>(gf, g.Vh, parity ^ 1);
+    const Site c = decode(g, parity, h);
+
+    mat3<T> M;
+    set_zero(M);
+    mat3<double> Mf, Mb;  // POST == 2: forward and backward terms in FP64
+    if constexpr (POST == 2) {
+        set_zero(Mf);
+        set_zero(Mb);
+    }
+    // In the 12-real formats only rows 0 and 1 of each product are multiplied
+    // out; row 2 of a product of two SU(3) matrices is conj(row0 x row1).
+    constexpr int R = S::R;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int mu = lane + k * LPS;
+        mat3<T> u, y, p;
+        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
+        load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
+        if constexpr (R == 2) row2_fma(y);
+        mul_dag_fma<R>(p, u, y);  // U_mu(x) g(x+mu)^dag
+        if constexpr (R == 2) row2_fma(p);
+        add_to(M, p);
+        if constexpr (POST == 2) fixed_meas_term<R, false>(Mf, u, y);
+        const uint32_t hb = back_half(g, c, h, mu);
+        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
+        load_link<F, false, false>(y, gn, g.Vh, hb);
+        if constexpr (R == 2) row2_fma(u);
+        mul_fma<R>(p, y, u);  // g(x-mu) U_mu(x-mu)
+        if constexpr (R == 2) row2_fma(p);
+        add_dag_to(M, p);
+        if constexpr (POST == 2) fixed_meas_term<R, true>(Mb, y, u);
+    }
+    lane_sum<LPS>(M);
+    if constexpr (POST == 2) {
+        lane_sum<LPS>(Mf);
+        lane_sum<LPS>(Mb);
+    }
+
+    bool sq0 = false, sq1 = false, sq2 = false;
+    if constexpr (SR) {
+        const uint32_t sweep = a.sweep_base ? (uint32_t)(*a.sweep_base + a.sweep) : a.sweep;
+        const uint4 w = philox4x32_10(make_uint4(lex_index(g, c), sweep, a.instance, 3u), a.key0, a.key1);
+        sq0 = (uint64_t)w.x < a.sr_threshold;
+        sq1 = (uint64_t)w.y < a.sr_threshold;
+        sq2 = (uint64_t)w.z < a.sr_threshold;
+    }
+
+    typename S::V *gx = site_field_ptr<F>(gf, g.Vh, parity);
+    mat3<T> G, K;
+    load_link<F, true, false>(G, gx, g.Vh, h);
+    if constexpr (R == 2) row2_fma(G);
+    mul_fma<3>(K, G, M);
+    const bool orl = a.overrelax != 0;
+    su2_step<0, 1, true>(K, G, a.omega, orl, sq0);
+    su2_step<0, 2, true>(K, G, a.omega, orl, sq1);
+    su2_step<1, 2, false>(K, G, a.omega, orl, sq2);
+
+    if constexpr (POST >= 1) {
+        mat3<double> Gd;
+        convert(Gd, G);
+        reunitarize(Gd);
+        round_to_format<F>(Gd, G);
+        if constexpr (POST == 2) {
+            mat3<double> Md = Mf, Kn;
+            add_to(Md, Mb);
+            left_mul<3>(Kn, Gd, Md);
+            if (active && lane == 0) {
+                acc->f += re_tr_mul(Gd, Mf);
+                acc->th += theta_of_K(Kn);
+            }
+        }
+    }
+    if (active && lane == 0) store_link<F, true>(gx, g.Vh, h, G);
+}
+
+// Site h's F and theta contributions in the fixed-link form (read only, FP64):
+// f = sum_mu Re tr[g(x) U_mu(x) g(x+mu)^dag], th = tr[Delta Delta^dag] of
+// K(x) = g(x) M(x).  Inactive lanes return zeros.
+template <int F>
+__device__ __forceinline__ void measure_site_fixed(const void *__restrict__ links, const void *__restrict__ gf,
+                                                   const Geom &g, int parity, uint32_t h, bool active, double &f,
+                                                   double &th)
+{
+    using S = Fmt<F>;
+    using T = typename S::T;
+    void *U = const_cast<void *>(links);
+    void *G = const_cast<void *>(gf);
+    const typename S::V *gn = site_field_ptr<F>(G, g.Vh, parity ^ 1);
+    const Site c = decode(g, parity, h);
+    mat3<double> Mf, Mb;
+    set_zero(Mf);
+    set_zero(Mb);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3<T> ut, yt;
+        mat3<double> u, y, p;
+        load_link<F>(ut, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
+        load_link<F>(yt, gn, g.Vh, fwd_half(g, c, h, mu));
+        convert(u, ut);
+        convert(y, yt);
+        right_mul_dag<3>(p, u, y);
+        add_to(Mf, p);
+        const uint32_t hb = back_half(g, c, h, mu);
+        load_link<F>(ut, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
+        load_link<F>(yt, gn, g.Vh, hb);
+        convert(u, ut);
+        convert(y, yt);
+        left_mul<3>(p, y, u);
+        add_dag_to(Mb, p);
+    }
+    mat3<T> xt;
+    mat3<double> x, Md = Mf, K;
+    load_link<F>(xt, site_field_ptr<F>(G, g.Vh, parity), g.Vh, h);
+    convert(x, xt);
+    add_to(Md, Mb);
+    left_mul<3>(K, x, Md);
+    f = active ? re_tr_mul(x, Mf) : 0.0;
+    th = active ? theta_of_K(K) : 0.0;
+}
+
+// ----------------------------------------------------------------------------
 // F and theta (Eqs. (2), (4), (5)), optionally fused with reunitarization.
 // Delta(x) = [(K - K^dag)/(2i)]_traceless, which equals sum_mu A_mu(x) -
 // A_mu(x - mu) for A_mu = [(U - U^dag)/(2i)]_traceless.  All in FP64.

@@ -29,7 +29,7 @@ class lgf_fix_params(ctypes.Structure):
                 ("bulk_format", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("finish_format", ctypes.c_int),
                 ("accumulate_g", ctypes.c_int), ("separate_measure", ctypes.c_int),
-                ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("fixed_links", ctypes.c_int), ("max_sweeps", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("sweep_offset", ctypes.c_uint64)]
 
 
@@ -55,7 +55,8 @@ EXPORTS = [
     "lgf_destroy", "lgf_get_info", "lgf_load_links", "lgf_store_links", "lgf_peek_links",
     "lgf_generate_links", "lgf_convert", "lgf_sweep", "lgf_reunitarize", "lgf_measure",
     "lgf_gauge_fix", "lgf_synchronize", "lgf_set_tuning", "lgf_get_tuning", "lgf_autotune",
-    "lgf_time_sweeps", "lgf_copy_bandwidth",
+    "lgf_time_sweeps", "lgf_copy_bandwidth", "lgf_set_fixed_tuning", "lgf_get_fixed_tuning",
+    "lgf_autotune_fixed",
 ]
 
 _lib = None
@@ -91,6 +92,9 @@ def load_library(path: str = LIB_PATH):
         "lgf_synchronize": (I, [P]),
         "lgf_set_tuning": (I, [P, I, P]),
         "lgf_get_tuning": (I, [P, I, P]),
+        "lgf_set_fixed_tuning": (I, [P, I, P]),
+        "lgf_get_fixed_tuning": (I, [P, I, P]),
+        "lgf_autotune_fixed": (I, [P, I, I]),
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
         "lgf_copy_bandwidth": (I, [SZ, I, P, P]),
@@ -252,6 +256,23 @@ def lgf_get_tuning(h, fmt: int):
     t = lgf_sweep_tuning()
     _check(load_library().lgf_get_tuning(h, fmt, ctypes.byref(t)))
     return tuple(getattr(t, k) for k in TUNING_FIELDS)
+
+
+def lgf_set_fixed_tuning(h, fmt: int, lanes_per_site: int = 2, block: int = 128, xcd_remap: int = 0) -> None:
+    t = lgf_sweep_tuning(lanes_per_site=lanes_per_site, sites_per_thread=1, block=block, xcd_remap=xcd_remap,
+                         nontemporal=1, schedule=0)
+    _check(load_library().lgf_set_fixed_tuning(h, fmt, ctypes.byref(t)))
+
+
+def lgf_get_fixed_tuning(h, fmt: int):
+    """(lanes_per_site, block, xcd_remap) of the fixed-link sweep"""
+    t = lgf_sweep_tuning()
+    _check(load_library().lgf_get_fixed_tuning(h, fmt, ctypes.byref(t)))
+    return (t.lanes_per_site, t.block, t.xcd_remap)
+
+
+def lgf_autotune_fixed(h, fmt: int, trials: int = 4) -> None:
+    _check(load_library().lgf_autotune_fixed(h, fmt, trials))
 
 
 def lgf_autotune(h, fmt: int, trials: int = 4) -> None:
