@@ -637,7 +637,8 @@ lgf_status run_chunk_fixed(lgf_lattice *h, int format, const void *links, void *
 {
     const lgf::SweepTuning &t = h->tune_fixed[format];
     if (fused)
-        LGF_TRY(ensure_fused_cap(h, (size_t)lgf::fixed_sweep_groups(h->geom, t) + (size_t)lgf::measure_blocks(h->geom)));
+        LGF_TRY(ensure_fused_cap(h, (size_t)lgf::fixed_sweep_groups(h->geom, t) +
+                                        (size_t)lgf::fixed_measure_blocks(h->geom)));
     const bool sr = p_sr > 0.0;
     auto issue = [&](bool captured) -> lgf_status {
         for (int k = 0; k < n; ++k) {
@@ -668,10 +669,12 @@ lgf_status measure_fixed_field(lgf_lattice *h, int format, const void *links, co
         LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused + 2 * (size_t)ng, &n0, h->stream));
         LGF_HIP(lgf::launch_finish_measure(h->d_fused, ng + n0, (double)h->V, h->d_out, h->stream));
     } else {
-        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_partials, &n0, h->stream));
-        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 1, h->d_partials + 2 * (size_t)n0, &n1,
+        // the two passes' partial sums in the fused-measurement buffer
+        LGF_TRY(ensure_fused_cap(h, 2 * (size_t)lgf::fixed_measure_blocks(h->geom)));
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused, &n0, h->stream));
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 1, h->d_fused + 2 * (size_t)n0, &n1,
                                           h->stream));
-        LGF_HIP(lgf::launch_finish_measure(h->d_partials, n0 + n1, (double)h->V, h->d_out, h->stream));
+        LGF_HIP(lgf::launch_finish_measure(h->d_fused, n0 + n1, (double)h->V, h->d_out, h->stream));
     }
     LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     LGF_HIP(hipStreamSynchronize(h->stream));

@@ -157,22 +157,33 @@ hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geo
     }
 }
 
+// Read-only F / theta pass of the fixed-link form: 2 lanes per site,
+// kMeasureBlock lanes per workgroup, one (F, theta) partial pair per workgroup.
+constexpr int kMeasureFixedLanes = 2;
+
+int fixed_measure_blocks(const Geom &g)
+{
+    return (int)(((uint64_t)g.Vh * kMeasureFixedLanes + kMeasureBlock - 1) / kMeasureBlock);
+}
+
 template <int F>
 __global__ void __launch_bounds__(kMeasureBlock) measure_fixed_kernel(const void *__restrict__ links,
                                                                       const void *__restrict__ gf, Geom g,
                                                                       int parity, double *partials)
 {
-    const uint32_t h0 = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const uint32_t tid = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const uint32_t h0 = tid / kMeasureFixedLanes;
     const bool active = h0 < g.Vh;
     double f, th;
-    measure_site_fixed<F>(links, gf, g, parity, active ? h0 : g.Vh - 1, active, f, th);
+    measure_site_fixed<F, kMeasureFixedLanes>(links, gf, g, parity, active ? h0 : g.Vh - 1,
+                                              (int)(tid % kMeasureFixedLanes), active, f, th);
     block_sum2<kMeasureBlock>(f, th, partials + 2 * blockIdx.x);
 }
 
 hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
                                 double *partials, int *n_partials, hipStream_t s)
 {
-    const int nb = measure_blocks(g);
+    const int nb = fixed_measure_blocks(g);
     *n_partials = nb;
     const dim3 grid(nb), block(kMeasureBlock);
     switch (format) {

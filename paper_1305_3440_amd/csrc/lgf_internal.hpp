@@ -118,7 +118,9 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
-// per-block (F, theta) partial sums over one parity's sites, fixed-link form
+// per-block (F, theta) partial sums over one parity's sites, fixed-link form;
+// *n_partials = fixed_measure_blocks(g) pairs
+int fixed_measure_blocks(const Geom &g);
 hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
                                 double *partials, int *n_partials, hipStream_t s);
 // site field dst (format fd) <- src (format fs), reunitarized in FP64

@@ -349,28 +349,40 @@ template <typename T> __device__ __forceinline__ void row2_fma(mat3<T> &m)
     m.e[2][2] = cross(0, 1, 1, 0);
 }
 
-// The fused measurement's FP64 copy of one term of M (POST == 2), computed as
-// the read-only measurement computes it: the operands with row 2 rebuilt as
-// a load rebuilds it, whole products in FP64.  BWD: the term is (a b)^dag
-// (a = g(x-mu), b = U_mu(x-mu)); else a b^dag (a = U_mu(x), b = g(x+mu)).
-template <int R, bool BWD, typename T>
-__device__ __forceinline__ void fixed_meas_term(mat3<double> &acc, const mat3<T> &a, const mat3<T> &b)
+// dst <- src on rows [0, R)
+template <int R, typename A, typename B>
+__device__ __forceinline__ void convert_rows(mat3<B> &dst, const mat3<A> &src)
 {
-    mat3<T> a2 = a, b2 = b;
-    if constexpr (R == 2) {
-        rebuild_row2(a2);
-        rebuild_row2(b2);
-    }
-    mat3<double> ad, bd, pd;
-    convert(ad, a2);
-    convert(bd, b2);
-    if constexpr (BWD) {
-        left_mul<3>(pd, ad, bd);
-        add_dag_to(acc, pd);
-    } else {
-        right_mul_dag<3>(pd, ad, bd);
-        add_to(acc, pd);
-    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dst.e[i][j] = {B(src.e[i][j].re), B(src.e[i][j].im)};
+}
+
+// The measurement's FP64 terms of M, from the operands exactly as the update
+// holds them (u: rows [0, R); y: all rows): acc += u y^dag (forward) and
+// acc += (y u)^dag (backward, y: rows [0, R); u: all rows).  In the FP64
+// formats they are the update's own products bit for bit.
+template <int R, typename T>
+__device__ __forceinline__ void meas_term_fwd(mat3<double> &acc, const mat3<T> &u, const mat3<T> &y)
+{
+    mat3<double> ud, yd, pd;
+    convert_rows<R>(ud, u);
+    convert(yd, y);
+    mul_dag_fma<R>(pd, ud, yd);
+    if constexpr (R == 2) row2_fma(pd);
+    add_to(acc, pd);
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void meas_term_bwd(mat3<double> &acc, const mat3<T> &y, const mat3<T> &u)
+{
+    mat3<double> yd, ud, pd;
+    convert_rows<R>(yd, y);
+    convert(ud, u);
+    mul_fma<R>(pd, yd, ud);
+    if constexpr (R == 2) row2_fma(pd);
+    add_dag_to(acc, pd);
 }
 
 template <int LPS, typename T> __device__ __forceinline__ void lane_sum(mat3<T> &m)
@@ -408,7 +420,7 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
 
     mat3<T> M;
     set_zero(M);
-    mat3<double> Mf, Mb;  // POST == 2: forward and backward terms in FP64
+    mat3<double> Mf, Mb;  // POST == 2: forward (and in FP32 formats backward) terms in FP64
     if constexpr (POST == 2) {
         set_zero(Mf);
         set_zero(Mb);
@@ -426,7 +438,10 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
         mul_dag_fma<R>(p, u, y);  // U_mu(x) g(x+mu)^dag
         if constexpr (R == 2) row2_fma(p);
         add_to(M, p);
-        if constexpr (POST == 2) fixed_meas_term<R, false>(Mf, u, y);
+        if constexpr (POST == 2) {
+            if constexpr (sizeof(T) == sizeof(double)) add_to(Mf, p);
+            else meas_term_fwd<R>(Mf, u, y);
+        }
         const uint32_t hb = back_half(g, c, h, mu);
         load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
         load_link<F, false, false>(y, gn, g.Vh, hb);
@@ -434,12 +449,13 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
         mul_fma<R>(p, y, u);  // g(x-mu) U_mu(x-mu)
         if constexpr (R == 2) row2_fma(p);
         add_dag_to(M, p);
-        if constexpr (POST == 2) fixed_meas_term<R, true>(Mb, y, u);
+        // (FP64 formats: the backward terms are in M already; see below)
+        if constexpr (POST == 2 && sizeof(T) != sizeof(double)) meas_term_bwd<R>(Mb, y, u);
     }
     lane_sum<LPS>(M);
     if constexpr (POST == 2) {
         lane_sum<LPS>(Mf);
-        lane_sum<LPS>(Mb);
+        if constexpr (sizeof(T) != sizeof(double)) lane_sum<LPS>(Mb);
     }
 
     bool sq0 = false, sq1 = false, sq2 = false;
@@ -467,9 +483,17 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
         reunitarize(Gd);
         round_to_format<F>(Gd, G);
         if constexpr (POST == 2) {
-            mat3<double> Md = Mf, Kn;
-            add_to(Md, Mb);
-            left_mul<3>(Kn, Gd, Md);
+            // K of the stored g(x): in the FP64 formats from the update's own M
+            // (its terms are the measurement's, summed in the update's order),
+            // in the FP32 formats from the FP64 terms
+            mat3<double> Md, Kn;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                convert(Md, M);
+            } else {
+                Md = Mf;
+                add_to(Md, Mb);
+            }
+            mul_fma<3>(Kn, Gd, Md);
             if (active && lane == 0) {
                 acc->f += re_tr_mul(Gd, Mf);
                 acc->th += theta_of_K(Kn);
@@ -479,16 +503,20 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
     if (active && lane == 0) store_link<F, true>(gx, g.Vh, h, G);
 }
 
-// Site h's F and theta contributions in the fixed-link form (read only, FP64):
-// f = sum_mu Re tr[g(x) U_mu(x) g(x+mu)^dag], th = tr[Delta Delta^dag] of
-// K(x) = g(x) M(x).  Inactive lanes return zeros.
-template <int F>
+// Site h's F and theta contributions in the fixed-link form (read only, FP64),
+// LPS lanes per site: f = sum_mu Re tr[g(x) U_mu(x) g(x+mu)^dag] and th =
+// tr[Delta Delta^dag] of K(x) = g(x) M(x), every term of M formed as the
+// update forms it (meas_term_fwd / _bwd) and g(x) with row 2 rebuilt as a
+// store-and-load rebuilds it, so that the fused measurement of a sweep gets
+// the same terms.  Only lane 0 of an active site returns non-zero sums.
+template <int F, int LPS>
 __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ links, const void *__restrict__ gf,
-                                                   const Geom &g, int parity, uint32_t h, bool active, double &f,
-                                                   double &th)
+                                                   const Geom &g, int parity, uint32_t h, int lane, bool active,
+                                                   double &f, double &th)
 {
     using S = Fmt<F>;
     using T = typename S::T;
+    constexpr int R = S::R;
     void *U = const_cast<void *>(links);
     void *G = const_cast<void *>(gf);
     const typename S::V *gn = site_field_ptr<F>(G, g.Vh, parity ^ 1);
@@ -497,31 +525,30 @@ __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ link
     set_zero(Mf);
     set_zero(Mb);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        mat3<T> ut, yt;
-        mat3<double> u, y, p;
-        load_link<F>(ut, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
-        load_link<F>(yt, gn, g.Vh, fwd_half(g, c, h, mu));
-        convert(u, ut);
-        convert(y, yt);
-        right_mul_dag<3>(p, u, y);
-        add_to(Mf, p);
+    for (int k = 0; k < 4 / LPS; ++k) {
+        const int mu = lane + k * LPS;
+        mat3<T> u, y;
+        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
+        load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
+        if constexpr (R == 2) row2_fma(y);
+        meas_term_fwd<R>(Mf, u, y);
         const uint32_t hb = back_half(g, c, h, mu);
-        load_link<F>(ut, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
-        load_link<F>(yt, gn, g.Vh, hb);
-        convert(u, ut);
-        convert(y, yt);
-        left_mul<3>(p, y, u);
-        add_dag_to(Mb, p);
+        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
+        load_link<F, false, false>(y, gn, g.Vh, hb);
+        if constexpr (R == 2) row2_fma(u);
+        meas_term_bwd<R>(Mb, y, u);
     }
+    lane_sum<LPS>(Mf);
+    lane_sum<LPS>(Mb);
     mat3<T> xt;
-    mat3<double> x, Md = Mf, K;
     load_link<F>(xt, site_field_ptr<F>(G, g.Vh, parity), g.Vh, h);
+    mat3<double> x, Md = Mf, K;
     convert(x, xt);
     add_to(Md, Mb);
-    left_mul<3>(K, x, Md);
-    f = active ? re_tr_mul(x, Mf) : 0.0;
-    th = active ? theta_of_K(K) : 0.0;
+    mul_fma<3>(K, x, Md);
+    const bool own = active && lane == 0;
+    f = own ? re_tr_mul(x, Mf) : 0.0;
+    th = own ? theta_of_K(K) : 0.0;
 }
 
 // ----------------------------------------------------------------------------
