@@ -327,8 +327,11 @@ lgf_status lgf_measure_coulomb(lgf_lattice *h, double *F_t, double *theta_t);
  * theta_target; the mixed-precision switch happens once every live timeslice
  * is below theta_switch.  result: sweeps (total), theta = largest theta_C(t),
  * F = mean F_C(t); sweeps_t, F_t, theta_t (host arrays of Lt doubles, may be
- * NULL) receive per-timeslice sweeps, F_C and theta_C.  accumulate_g works as
- * in lgf_gauge_fix; separate_measure is ignored (two measurement passes). */
+ * NULL) receive per-timeslice sweeps, F_C and theta_C.  accumulate_g and
+ * fixed_links work as in lgf_gauge_fix (in the fixed-link form a site update
+ * reads only its 6 spatial links; the temporal links enter only the final
+ * g(x) U_mu(x) g(x+mu)^dag); separate_measure is ignored (two measurement
+ * passes). */
 lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
                                  double *sweeps_t, double *F_t, double *theta_t);
 

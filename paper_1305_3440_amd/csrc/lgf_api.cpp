@@ -368,7 +368,9 @@ lgf_status ensure_coulomb(lgf_lattice *h)
 {
     if (h->d_mask) return LGF_OK;
     const int Lt = h->dims[0];
-    const size_t parts = (size_t)4 * Lt * lgf::coulomb_blocks_per_slice(h->geom);
+    // room for the link form's and the fixed-link form's partial sums
+    const size_t bps = (size_t)std::max(lgf::coulomb_blocks_per_slice(h->geom), lgf::coulomb_fixed_blocks(h->geom));
+    const size_t parts = (size_t)4 * Lt * bps;
     hipError_t e;
     if ((e = hipMalloc(&h->d_mask, Lt)) != hipSuccess ||
         (e = hipHostMalloc((void **)&h->h_mask, Lt, hipHostMallocDefault)) != hipSuccess ||
@@ -397,7 +399,8 @@ lgf_status measure_coulomb_field(lgf_lattice *h, int format, void *field, bool r
     const size_t half = (size_t)2 * h->dims[0] * lgf::coulomb_blocks_per_slice(h->geom);
     LGF_HIP(lgf::launch_measure_coulomb(format, field, h->geom, 0, reunit, reunit, h->d_cpart, h->stream));
     LGF_HIP(lgf::launch_measure_coulomb(format, field, h->geom, 1, reunit, false, h->d_cpart + half, h->stream));
-    LGF_HIP(lgf::launch_finish_coulomb(h->d_cpart, h->geom, h->d_cout, h->stream));
+    LGF_HIP(lgf::launch_finish_coulomb(h->d_cpart, h->geom, lgf::coulomb_blocks_per_slice(h->geom), h->d_cout,
+                                       h->stream));
     LGF_HIP(hipMemcpyAsync(h->h_cout, h->d_cout, 2 * h->dims[0] * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));
     LGF_HIP(hipStreamSynchronize(h->stream));
@@ -633,7 +636,8 @@ lgf_status links_in_format(lgf_lattice *h, int format, void **links)
 // reunitarized (both half-sweeps); with fused, its parity-1 half-sweep also
 // leaves the (F, theta) partial sums of its sites in h->d_fused.
 lgf_status run_chunk_fixed(lgf_lattice *h, int format, const void *links, void *gf, int n, double omega,
-                           double p_sr, uint64_t seed, uint64_t sweep0, bool use_graph, bool fused)
+                           double p_sr, uint64_t seed, uint64_t sweep0, bool use_graph, bool fused,
+                           bool coulomb = false)
 {
     const lgf::SweepTuning &t = h->tune_fixed[format];
     if (fused)
@@ -645,6 +649,15 @@ lgf_status run_chunk_fixed(lgf_lattice *h, int format, const void *links, void *
             const bool last = (k == n - 1);
             lgf::SweepArgs a{0, omega, p_sr, seed, (captured && sr) ? (uint64_t)k : sweep0 + (uint64_t)k, 0u};
             a.sweep_base = h->sweep_base_active;
+            if (coulomb) {
+                // timeslice flags read from the device at run time (set before the chunk)
+                LGF_HIP(lgf::launch_fixed_sweep_coulomb(format, links, gf, h->geom, a, t, last ? 1 : 0, h->d_mask,
+                                                        h->stream));
+                a.parity = 1;
+                LGF_HIP(lgf::launch_fixed_sweep_coulomb(format, links, gf, h->geom, a, t, last ? 1 : 0, h->d_mask,
+                                                        h->stream));
+                continue;
+            }
             LGF_HIP(lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, last ? 1 : 0, h->stream));
             a.parity = 1;
             a.meas = (last && fused) ? h->d_fused : nullptr;
@@ -653,7 +666,8 @@ lgf_status run_chunk_fixed(lgf_lattice *h, int format, const void *links, void *
         return LGF_OK;
     };
     if (!use_graph) return issue(false);
-    GraphEntry key{format, const_cast<void *>(links), n, omega, t, 0, gf, fused ? 1 : 0, p_sr, seed, 1, nullptr};
+    GraphEntry key{format, const_cast<void *>(links), n, omega, t, coulomb ? 1 : 0, gf, fused ? 1 : 0, p_sr, seed,
+                   1, nullptr};
     return run_captured(h, key, sweep0, [&]() { return issue(true); });
 }
 
@@ -680,6 +694,20 @@ lgf_status measure_fixed_field(lgf_lattice *h, int format, const void *links, co
     LGF_HIP(hipStreamSynchronize(h->stream));
     if (F) *F = h->h_out[0];
     if (theta) *theta = h->h_out[1];
+    return LGF_OK;
+}
+
+// per-timeslice F_C(t), theta_C(t) of the links g U g^dag into h->h_cout
+lgf_status measure_coulomb_fixed_field(lgf_lattice *h, int format, const void *links, const void *gf)
+{
+    const int bps = lgf::coulomb_fixed_blocks(h->geom);
+    const size_t half = (size_t)2 * h->dims[0] * bps;
+    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 0, h->d_cpart, h->stream));
+    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 1, h->d_cpart + half, h->stream));
+    LGF_HIP(lgf::launch_finish_coulomb(h->d_cpart, h->geom, bps, h->d_cout, h->stream));
+    LGF_HIP(hipMemcpyAsync(h->h_cout, h->d_cout, 2 * h->dims[0] * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
     return LGF_OK;
 }
 
@@ -795,6 +823,137 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
         return fail(LGF_ENOTCONV, "theta %g after %lld sweeps has not reached %g", theta, (long long)sweeps,
                     p.theta_target);
     if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", F, theta);
+    return LGF_OK;
+}
+
+// lgf_coulomb_gauge_fix with fixed_links set (parameters checked by the
+// caller): the per-timeslice stopping and the precision switch of the link
+// form, on (U, g); the temporal links are read only by the final
+// transformation, which rebuilds all links from the untouched input.
+lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, int finish, lgf_fix_result *res,
+                             double *sweeps_t, double *F_t, double *theta_t)
+{
+    LGF_TRY(ensure_coulomb(h));
+    const int Lt = h->dims[0];
+    const bool mixed = (bulk != finish);
+    const auto t_start = std::chrono::steady_clock::now();
+    std::vector<double> sw(Lt, 0.0), F(Lt), th(Lt);
+    std::vector<unsigned char> act(Lt, 1);
+    auto timed = [&](double &acc_ms, auto &&body) -> lgf_status {
+        LGF_HIP(hipEventRecord(h->ev0, h->stream));
+        LGF_TRY(body());
+        LGF_HIP(hipEventRecord(h->ev1, h->stream));
+        LGF_HIP(hipEventSynchronize(h->ev1));
+        acc_ms += elapsed_ms(h->ev0, h->ev1);
+        return LGF_OK;
+    };
+    auto read_out = [&](bool only_active) {
+        for (int t = 0; t < Lt; ++t)
+            if (!only_active || act[t]) {
+                F[t] = h->h_cout[2 * t];
+                th[t] = h->h_cout[2 * t + 1];
+            }
+    };
+    auto n_live = [&] {
+        int n = 0;
+        for (int t = 0; t < Lt; ++t) n += act[t];
+        return n;
+    };
+    auto worst = [&] {
+        double m = 0.0;
+        for (int t = 0; t < Lt; ++t)
+            if (act[t] && th[t] > m) m = th[t];
+        return m;
+    };
+    // the input itself (g = 1)
+    LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_coulomb_field(h, h->format, h->field, false); }));
+    read_out(false);
+    lgf_status status = LGF_ENOTCONV;
+    for (int t = 0; t < Lt; ++t) {
+        if (!std::isfinite(F[t]) || !std::isfinite(th[t])) status = LGF_ENUMERIC;
+        if (th[t] < p.theta_target) act[t] = 0;
+    }
+    int nh = 1;
+    bool in_bulk = mixed, started = false;
+    int cur = in_bulk ? bulk : finish;
+    void *links = nullptr;
+    int64_t sweeps = 0, sweeps_bulk = 0;
+    uint64_t ctr = p.sweep_offset;
+    if (status != LGF_ENUMERIC && n_live() > 0 && p.max_sweeps > 0) {
+        LGF_TRY(ensure_gfix(h, cur));
+        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+            LGF_TRY(links_in_format(h, cur, &links));
+            LGF_HIP(lgf::launch_site_field(cur, h->gfix[cur], h->geom, 0, h->stream));
+            return LGF_OK;
+        }));
+        started = true;
+    }
+    while (status != LGF_ENUMERIC && n_live() > 0 && sweeps < p.max_sweeps) {
+        LGF_TRY(upload_mask(h, act.data()));
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
+            return run_chunk_fixed(h, cur, links, h->gfix[cur], n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0,
+                                   false, true);
+        }));
+        if (in_bulk) sweeps_bulk += n;
+        sweeps += n;
+        ctr += (uint64_t)n;
+        LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_coulomb_fixed_field(h, cur, links, h->gfix[cur]); }));
+        read_out(true);
+        ++nh;
+        for (int t = 0; t < Lt; ++t) {
+            if (!act[t]) continue;
+            sw[t] = (double)sweeps;
+            if (!std::isfinite(F[t]) || !std::isfinite(th[t])) status = LGF_ENUMERIC;
+        }
+        if (status == LGF_ENUMERIC) break;
+        if (in_bulk) {
+            // leave the bulk precision once every live timeslice is below the switch
+            if (worst() < p.theta_switch) {
+                LGF_TRY(ensure_gfix(h, finish));
+                LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+                    LGF_TRY(links_in_format(h, finish, &links));
+                    LGF_HIP(lgf::launch_site_convert(bulk, h->gfix[bulk], finish, h->gfix[finish], h->geom,
+                                                     h->stream));
+                    return LGF_OK;
+                }));
+                cur = finish;
+                in_bulk = false;
+            }
+            continue;
+        }
+        for (int t = 0; t < Lt; ++t)
+            if (act[t] && th[t] < p.theta_target) act[t] = 0;
+    }
+    if (status != LGF_ENUMERIC) status = n_live() == 0 ? LGF_OK : LGF_ENOTCONV;
+    if (started) {
+        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, cur, h->gfix[cur], h->format, h->field, h->geom,
+                                                h->stream));
+            return LGF_OK;
+        }));
+    }
+    double tmax = 0.0, fsum = 0.0;
+    for (int t = 0; t < Lt; ++t) {
+        tmax = th[t] > tmax ? th[t] : tmax;
+        fsum += F[t];
+        if (sweeps_t) sweeps_t[t] = sw[t];
+        if (F_t) F_t[t] = F[t];
+        if (theta_t) theta_t[t] = th[t];
+    }
+    res->sweeps = sweeps;
+    res->sweeps_bulk = sweeps_bulk;
+    res->theta = tmax;
+    res->F = fsum / Lt;
+    res->status = status;
+    res->n_history = nh;
+    res->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (status == LGF_ENOTCONV)
+        return fail(LGF_ENOTCONV, "not every timeslice reached theta_C < %g in %lld sweeps", p.theta_target,
+                    (long long)sweeps);
+    if (status == LGF_ENUMERIC) return fail(LGF_ENUMERIC, "F_C or theta_C is not finite");
     return LGF_OK;
 }
 
@@ -1317,6 +1476,12 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
     auto is64 = [](int f) { return f == LGF_FP64_18 || f == LGF_FP64_12; };
+    if (p.fixed_links) {
+        if (!is64(h->format)) return fail(LGF_EINVAL, "fixed_links needs an FP64 handle");
+        LGF_TRY(use_device(h));
+        std::memset(res, 0, sizeof *res);
+        return coulomb_fix_fixed(h, p, bulk, finish, res, sweeps_t, F_t, theta_t);
+    }
     const bool acc = p.accumulate_g != 0;
     if (acc && !(mixed && !is64(bulk) && is64(finish) && is64(h->format)))
         return fail(LGF_EINVAL, "accumulate_g needs an FP32 bulk, an FP64 finish and an FP64 handle");

@@ -40,12 +40,14 @@ struct TileOrder {
 
 // One half-sweep over all Vh sites of a parity, LPS lanes per site; POST as
 // in update_site_fixed, with workgroup b's (F, theta) sums in partials[2b]
-// when POST == 2.
-template <int F, int LPS, bool SR, int POST>
+// when POST == 2.  MU0 = 1: Coulomb gauge, with the timeslice flags
+// slice_active.
+template <int F, int LPS, bool SR, int POST, int MU0 = 0>
 __global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict__ links, void *__restrict__ gf,
                                                           Geom g, int parity, RelaxArgs<typename Fmt<F>::T> a,
                                                           TileOrder o, uint32_t n_groups,
-                                                          double *__restrict__ partials)
+                                                          double *__restrict__ partials,
+                                                          const uint8_t *__restrict__ slice_active)
 {
     const uint32_t b = blockIdx.x;
     uint32_t h0;        // first site of the tile (Vh <= 2^30, LPS <= 4)
@@ -66,8 +68,8 @@ __global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict
     const uint32_t grp = h0 + threadIdx.x / LPS;
     const bool active = grp < g.Vh;
     MeasAcc acc;
-    update_site_fixed<F, LPS, SR, POST>(links, gf, g, parity, active ? grp : g.Vh - 1, (int)(threadIdx.x % LPS),
-                                        active, a, &acc);
+    update_site_fixed<F, LPS, SR, POST, MU0>(links, gf, g, parity, active ? grp : g.Vh - 1,
+                                             (int)(threadIdx.x % LPS), active, a, &acc, slice_active);
     if constexpr (POST == 2) block_sum2_any(acc.f, acc.th, partials + 2 * slot);
 }
 
@@ -105,7 +107,7 @@ static TileOrder tile_order(const Geom &g, const SweepTuning &t)
 
 template <int F, int LPS>
 static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
-                                 int post, hipStream_t s)
+                                 int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
     using T = typename Fmt<F>::T;
     const uint32_t ng = fixed_sweep_groups(g, t);
@@ -116,10 +118,22 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     const bool sr = a.p_sr > 0.0;
     if (sr) ra.sr_threshold = (uint64_t)floor(a.p_sr * 4294967296.0);
     double *m = a.meas;
-    if (post == 2 && !m) return hipErrorInvalidValue;
+    if (post == 2 && (!m || coulomb)) return hipErrorInvalidValue;
 #define LGF_FIX_LAUNCH(SRV, P) \
-    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, m)
-    if (sr) {
+    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, m, \
+                       nullptr)
+#define LGF_FIX_LAUNCH_C(SRV, P) \
+    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 1>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, \
+                       nullptr, slices)
+    if (coulomb) {
+        if (sr) {
+            if (post == 0) LGF_FIX_LAUNCH_C(true, 0);
+            else LGF_FIX_LAUNCH_C(true, 1);
+        } else {
+            if (post == 0) LGF_FIX_LAUNCH_C(false, 0);
+            else LGF_FIX_LAUNCH_C(false, 1);
+        }
+    } else if (sr) {
         if (post == 0) LGF_FIX_LAUNCH(true, 0);
         else if (post == 1) LGF_FIX_LAUNCH(true, 1);
         else LGF_FIX_LAUNCH(true, 2);
@@ -129,16 +143,31 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
         else LGF_FIX_LAUNCH(false, 2);
     }
 #undef LGF_FIX_LAUNCH
+#undef LGF_FIX_LAUNCH_C
     return hipGetLastError();
 }
 
 template <int F>
 static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
-                                 int post, hipStream_t s)
+                                 int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
     switch (t.lanes_per_site) {
-    case 2: return launch_fixed_t<F, 2>(links, gf, g, a, t, post, s);
-    case 4: return launch_fixed_t<F, 4>(links, gf, g, a, t, post, s);
+    case 2: return launch_fixed_t<F, 2>(links, gf, g, a, t, post, slices, coulomb, s);
+    case 4: return launch_fixed_t<F, 4>(links, gf, g, a, t, post, slices, coulomb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_fixed_any(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
+                                   const SweepTuning &t, int post, const uint8_t *slices, bool coulomb, hipStream_t s)
+{
+    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0 || post < 0 || post > 2 || a.h_end != 0 || a.out)
+        return hipErrorInvalidValue;
+    switch (format) {
+    case kF64_18: return launch_fixed_f<kF64_18>(links, gf, g, a, t, post, slices, coulomb, s);
+    case kF32_18: return launch_fixed_f<kF32_18>(links, gf, g, a, t, post, slices, coulomb, s);
+    case kF32_12: return launch_fixed_f<kF32_12>(links, gf, g, a, t, post, slices, coulomb, s);
+    case kF64_12: return launch_fixed_f<kF64_12>(links, gf, g, a, t, post, slices, coulomb, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -146,15 +175,13 @@ static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, con
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s)
 {
-    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0 || post < 0 || post > 2 || a.h_end != 0 || a.out)
-        return hipErrorInvalidValue;
-    switch (format) {
-    case kF64_18: return launch_fixed_f<kF64_18>(links, gf, g, a, t, post, s);
-    case kF32_18: return launch_fixed_f<kF32_18>(links, gf, g, a, t, post, s);
-    case kF32_12: return launch_fixed_f<kF32_12>(links, gf, g, a, t, post, s);
-    case kF64_12: return launch_fixed_f<kF64_12>(links, gf, g, a, t, post, s);
-    default: return hipErrorInvalidValue;
-    }
+    return launch_fixed_any(format, links, gf, g, a, t, post, nullptr, false, s);
+}
+
+hipError_t launch_fixed_sweep_coulomb(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
+                                      const SweepTuning &t, int post, const uint8_t *slice_active, hipStream_t s)
+{
+    return launch_fixed_any(format, links, gf, g, a, t, post, slice_active, true, s);
 }
 
 // Read-only F / theta pass of the fixed-link form: 2 lanes per site,
@@ -191,6 +218,44 @@ hipError_t launch_measure_fixed(int format, const void *links, const void *gf, c
     case kF32_18: hipLaunchKernelGGL((measure_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF32_12: hipLaunchKernelGGL((measure_fixed_kernel<kF32_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF64_12: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Coulomb gauge, read only: per timeslice t and parity pass, partial (F_C,
+// theta_C) pairs at partials[2 (t bps + b)] for the bps = coulomb_fixed_blocks
+// workgroups of a slice (the layout finish_coulomb_kernel sums).
+int coulomb_fixed_blocks(const Geom &g)
+{
+    return (int)(((uint64_t)g.hs[0] * kMeasureFixedLanes + kMeasureBlock - 1) / kMeasureBlock);
+}
+
+template <int F>
+__global__ void __launch_bounds__(kMeasureBlock) measure_coulomb_fixed_kernel(const void *__restrict__ links,
+                                                                              const void *__restrict__ gf, Geom g,
+                                                                              int parity, double *partials)
+{
+    const uint32_t t = blockIdx.y;
+    const uint32_t tid = blockIdx.x * kMeasureBlock + threadIdx.x;
+    const uint32_t i = tid / kMeasureFixedLanes;
+    const bool active = i < g.hs[0];
+    const uint32_t h = t * g.hs[0] + (active ? i : g.hs[0] - 1);
+    double f, th;
+    measure_site_fixed<F, kMeasureFixedLanes, 1>(links, gf, g, parity, h, (int)(tid % kMeasureFixedLanes), active,
+                                                 f, th);
+    block_sum2<kMeasureBlock>(f, th, partials + 2 * ((size_t)t * gridDim.x + blockIdx.x));
+}
+
+hipError_t launch_measure_coulomb_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
+                                        double *partials, hipStream_t s)
+{
+    const dim3 grid(coulomb_fixed_blocks(g), g.L[0]), block(kMeasureBlock);
+    switch (format) {
+    case kF64_18: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF32_18: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF32_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF64_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -95,7 +95,9 @@ hipError_t launch_sweep_coulomb(int format, void *field, const Geom &g, const Sw
 int coulomb_blocks_per_slice(const Geom &g);
 hipError_t launch_measure_coulomb(int format, void *field, const Geom &g, int parity, bool reunit_fwd,
                                   bool reunit_bwd, double *partials, hipStream_t s);
-hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *out, hipStream_t s);
+// bps: partial pairs per timeslice and pass (coulomb_blocks_per_slice or
+// coulomb_fixed_blocks)
+hipError_t launch_finish_coulomb(const double *partials, const Geom &g, int bps, double *out, hipStream_t s);
 
 // site field (2 parities x one SU(3) per site, link-direction layout):
 // mode 0 sets the identity, mode 1 reunitarizes in FP64
@@ -118,6 +120,15 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
+// Coulomb gauge in the fixed-link form (post 0 or 1; slice_active: device
+// array of Lt flags)
+hipError_t launch_fixed_sweep_coulomb(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
+                                      const SweepTuning &t, int post, const uint8_t *slice_active, hipStream_t s);
+// per-timeslice partial (F_C, theta_C) pairs of one parity pass, fixed-link
+// form: Lt x coulomb_fixed_blocks(g) pairs, summed by launch_finish_coulomb
+int coulomb_fixed_blocks(const Geom &g);
+hipError_t launch_measure_coulomb_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
+                                        double *partials, hipStream_t s);
 // per-block (F, theta) partial sums over one parity's sites, fixed-link form;
 // *n_partials = fixed_measure_blocks(g) pairs
 int fixed_measure_blocks(const Geom &g);

@@ -675,11 +675,11 @@ __global__ void __launch_bounds__(256) finish_coulomb_kernel(const double *__res
     }
 }
 
-hipError_t launch_finish_coulomb(const double *partials, const Geom &g, double *out, hipStream_t s)
+hipError_t launch_finish_coulomb(const double *partials, const Geom &g, int bps, double *out, hipStream_t s)
 {
     const double V3 = 2.0 * (double)g.hs[0];
     hipLaunchKernelGGL(finish_coulomb_kernel, dim3(g.L[0]), dim3(256), 0, s, partials,
-                       coulomb_blocks_per_slice(g), V3, out);
+                       bps, V3, out);
     return hipGetLastError();
 }
 

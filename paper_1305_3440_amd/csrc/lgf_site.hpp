@@ -406,17 +406,24 @@ template <int LPS, typename T> __device__ __forceinline__ void lane_sum(mat3<T> 
 // before it is stored.  POST = 2: as 1, and the site's contributions to F and
 // theta, from the links formed with the stored g(x) and the stored
 // neighbours, go to acc (Re tr of its 4 forward links, tr[Delta Delta^dag]).
-template <int F, int LPS, bool SR, int POST>
+// MU0 = 1: the Coulomb-gauge update, M from the spatial directions only (the
+// temporal links are not read at all); slice_active (optional, one flag per
+// timeslice) leaves the sites of frozen timeslices alone -- the LPS lanes of
+// a site share its timeslice, so they leave together.
+template <int F, int LPS, bool SR, int POST, int MU0 = 0>
 __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links, void *__restrict__ gf,
                                                   const Geom &g, int parity, uint32_t h, int lane, bool active,
-                                                  const RelaxArgs<typename Fmt<F>::T> &a, MeasAcc *acc)
+                                                  const RelaxArgs<typename Fmt<F>::T> &a, MeasAcc *acc,
+                                                  const uint8_t *__restrict__ slice_active = nullptr)
 {
+    static_assert(!(POST == 2 && MU0 != 0), "the fused measurement is the Landau one");
     using S = Fmt<F>;
     using T = typename S::T;
     constexpr int NL = 4 / LPS;
     void *U = const_cast<void *>(links);
     const typename S::V *gn = site_field_ptr<F>(gf, g.Vh, parity ^ 1);
     const Site c = decode(g, parity, h);
+    if (slice_active && !slice_active[c.t]) return;
 
     mat3<T> M;
     set_zero(M);
@@ -431,6 +438,7 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int mu = lane + k * LPS;
+        if (mu < MU0) continue;
         mat3<T> u, y, p;
         load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
@@ -509,7 +517,8 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
 // update forms it (meas_term_fwd / _bwd) and g(x) with row 2 rebuilt as a
 // store-and-load rebuilds it, so that the fused measurement of a sweep gets
 // the same terms.  Only lane 0 of an active site returns non-zero sums.
-template <int F, int LPS>
+// MU0 = 1: the Coulomb-gauge F_C and theta_C contributions (spatial links).
+template <int F, int LPS, int MU0 = 0>
 __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ links, const void *__restrict__ gf,
                                                    const Geom &g, int parity, uint32_t h, int lane, bool active,
                                                    double &f, double &th)
@@ -527,6 +536,7 @@ __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ link
 #pragma unroll
     for (int k = 0; k < 4 / LPS; ++k) {
         const int mu = lane + k * LPS;
+        if (mu < MU0) continue;
         mat3<T> u, y;
         load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));

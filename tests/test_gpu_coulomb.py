@@ -186,3 +186,111 @@ def test_coulomb_48x3x96_sampled(lgf, orc, fmt):
     act = np.array(mask, dtype=bool)
     assert np.all(np.isfinite(F)) and np.all(np.abs(F) < 1) and np.all(th > 0)
     assert F[act].min() > 100 * np.abs(F[~act]).max()
+
+
+# ------------------------------------------------------------ fixed-link form
+
+@pytest.mark.parametrize("dims", DIMS + [(8, 8, 8, 16)])
+@pytest.mark.parametrize("handle_fmt,sweep_fmt", [(0, 0), (0, 3), (0, 2)])
+@pytest.mark.parametrize("omega,p_sr", [(1.7, 0.0), (1.0, 0.5)])
+def test_coulomb_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fmt, omega, p_sr):
+    """One Coulomb sweep of every timeslice with the links fixed (a gauge
+    fixing stopped after one sweep hands back g U g^dag, g reunitarized): the
+    oracle's Coulomb sweep of the links, then reunitarized; the blocked tile
+    order is taken on (8, 8, 8, 16)."""
+    announce("coulomb fixed sweep", dims, handle_fmt, sweep_fmt, omega, p_sr)
+    U = orc.generate_links(dims, 31, 0.35)
+    ref = U.copy()
+    orc.sweep_coulomb(dims, ref, omega, p_sr, seed=4, sweep_index=2)
+    orc.reunitarize(ref)
+    Fr, thr = orc.measure_coulomb(dims, ref)
+    for tune in [(2, 128, 0), (4, 64, 2), (2, 64, 2)]:
+        with lgf.Lattice(dims, handle_fmt) as lat:
+            lgf.lgf_set_fixed_tuning(lat.h, sweep_fmt, *tune)
+            lat.load(U)
+            kw = dict(omega=omega, p_sr=p_sr, seed=4, sweep_offset=2, theta_target=1e-300, check_every=1,
+                      max_sweeps=1, fixed_links=1)
+            if sweep_fmt != handle_fmt:
+                kw.update(bulk_format=sweep_fmt, finish_format=handle_fmt, theta_switch=1e-300)
+            st, res, sw, F, th = lat.coulomb_gauge_fix(**kw)
+            got = lat.store()
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+        assert unitarity_error(got) < 1e-12
+        if sweep_fmt == 2:
+            e = np.linalg.norm((got - ref).reshape(-1, 9), axis=1) / np.linalg.norm(ref.reshape(-1, 9), axis=1)
+            assert float(np.quantile(e, 0.99)) <= 2e-6 and float(e.max()) <= 2e-5, tune
+        else:
+            assert maxabs(got, ref) < 1e-12, (tune, maxabs(got, ref))
+            assert np.abs(F - Fr).max() < 1e-13 and np.all(np.abs(th - thr) <= 1e-12 * thr + 1e-15), tune
+
+
+def test_coulomb_fixed_gauge_fix_matches_link_form(lgf, orc):
+    """FP64 Coulomb gauge fixing with per-timeslice stopping, links fixed:
+    the oracle's per-timeslice sweep counts, theta_C(t) below target, its F_C(t)
+    and links; the Wilson loops of the input kept to 1e-12."""
+    dims = (6, 6, 6, 6)
+    announce("coulomb fixed fix")
+    U = orc.generate_links(dims, 33, 0.25)
+    ref = U.copy()
+    r = orc.coulomb_gauge_fix(dims, ref, 1.7, 1e-12)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-12, fixed_links=1)
+        got = lat.store()
+    assert st == lgf.LGF_OK and r["status"] == 0
+    assert np.array_equal(sw, r["sweeps_t"])
+    assert np.all(th < 1e-12)
+    assert maxabs(got, ref) < 1e-9
+    assert np.abs(F - r["F_t"]).max() < 1e-12
+    for nu in (1, 2, 3):
+        assert abs(orc.wilson_loop(dims, got, 0, nu, 1, 2) - orc.wilson_loop(dims, U, 0, nu, 1, 2)) < 1e-12
+
+
+@pytest.mark.parametrize("finish", [0, 3])
+def test_coulomb_fixed_mixed_keeps_the_orbit(lgf, orc, finish):
+    """Mixed Coulomb gauge fixing (FP32-12 bulk, switch at 1e-8) with the links
+    fixed: every timeslice below theta_C < 1e-14 on the links handed back, an
+    FP64 gauge transformation of the input (temporal and spatial Wilson loops
+    to 1e-12), also when stopped inside the bulk."""
+    dims = (8, 6, 6, 6)
+    announce("coulomb fixed mixed", finish)
+    U = orc.generate_links(dims, 34, 0.3)
+    loops = lambda V: np.array([orc.wilson_loop(dims, V, mu, nu, R, T) for mu in range(4)
+                                for nu in range(mu + 1, 4) for (R, T) in [(1, 1), (1, 2)]])
+    L0 = loops(U)
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                                   bulk_format=lgf.LGF_FP32_12, finish_format=finish,
+                                                   fixed_links=1)
+        got = lat.store()
+    assert st == lgf.LGF_OK and 0 < res["sweeps_bulk"] < res["sweeps"]
+    Fo, tho = orc.measure_coulomb(dims, got)
+    assert np.all(tho < 1e-14) and np.abs(Fo - F).max() < 1e-13 and unitarity_error(got) < 1e-12
+    assert float(np.abs(loops(got) - L0).max()) < 1e-12
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.load(U)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-30,
+                                                   max_sweeps=30, bulk_format=lgf.LGF_FP32_12,
+                                                   finish_format=finish, fixed_links=1)
+        got = lat.store()
+        assert st == lgf.LGF_ENOTCONV and res["sweeps_bulk"] == 30
+        assert float(np.abs(loops(got) - L0).max()) < 1e-12
+
+
+def test_coulomb_fixed_graph_equals_direct(lgf, orc):
+    """Captured chunks of the fixed-link Coulomb sweeps (timeslice flags read
+    from the device) give the direct launches' links bit for bit, OR and SR."""
+    dims = (6, 4, 4, 8)
+    announce("coulomb fixed graph")
+    U = orc.generate_links(dims, 35, 0.3)
+    for kw in (dict(omega=1.7, theta_target=1e-13), dict(omega=1.0, p_sr=0.5, seed=3, theta_target=1e-30,
+                                                         check_every=4, max_sweeps=12)):
+        out = []
+        for g in (0, 1):
+            with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+                lat.load(U)
+                st, res, sw, F, th = lat.coulomb_gauge_fix(use_graph=g, fixed_links=1, **kw)
+                out.append((st, sw, F, th, lat.store()))
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), kw
