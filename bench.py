@@ -272,6 +272,14 @@ def ensemble_bench(lgf, stream):
     t0 = time.perf_counter()
     st, res = lgf.lgf_ensemble_gauge_fix(e, p, len(dims))
     wall = time.perf_counter() - t0
+    # the same mixed gauge fixing with fixed-link sweeps (2 lanes per site)
+    for c in man:
+        lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
+    pf = lgf.fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                        finish_format=lgf.LGF_FP64_12, fixed_links=1)
+    t0 = time.perf_counter()
+    stf, resf = lgf.lgf_ensemble_gauge_fix(e, pf, len(dims))
+    wallf = time.perf_counter() - t0
     # the same 48 fields fixed in plain FP64 (18-real) for the per-configuration F difference
     for c in man:
         lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
@@ -284,6 +292,12 @@ def ensemble_bench(lgf, stream):
     out["gauge_fix_fp64"] = {"status": int(st64), "wall_s": wall64,
                              "all_below_1e-14": all(r["theta"] < 1e-14 for r in res64)}
     out["max_abs_dF_mixed_vs_fp64"] = max(abs(r["F"] - q["F"]) for r, q in zip(res, res64))
+    swf = [r["sweeps"] for r in resf]
+    out["gauge_fix_mixed_fixed_links"] = {
+        "status": int(stf), "wall_s": wallf, "all_below_1e-14": all(r["theta"] < 1e-14 for r in resf),
+        "sweeps_min": min(swf), "sweeps_max": max(swf),
+        "max_abs_dF_vs_fp64": max(abs(r["F"] - q["F"]) for r, q in zip(resf, res64)),
+        "speedup_vs_link_sweeps": wall / wallf}
     sw = [r["sweeps"] for r in res]
     out["gauge_fix_mixed"] = {"status": int(st), "wall_s": wall, "all_below_1e-14": all(
         r["theta"] < 1e-14 for r in res), "sweeps_min": min(sw), "sweeps_max": max(sw),

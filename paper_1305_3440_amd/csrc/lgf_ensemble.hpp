@@ -16,9 +16,14 @@ constexpr int kEnsMaxTile = 256;  // largest tile width (the kernels' launch bou
 struct EnsCfg {         // one configuration as the kernels see it
     Geom g;
     void *field;        // links in the current storage format
+    void *gf;           // fixed-link form: the gauge transformation (site field, same format), else NULL
     int fmt;            // current storage format
     uint32_t instance;  // the configuration's index: third word of the SR counter
 };
+
+// lanes per site of the fixed-link ensemble kernels: a tile of `tile` lanes
+// covers tile / kEnsFixedLanes sites
+constexpr int kEnsFixedLanes = 2;
 
 struct EnsTile {        // `tile` consecutive half indices of one configuration
     uint32_t cfg;
@@ -59,6 +64,18 @@ hipError_t launch_ensemble_finish(const double *partials, uint32_t n_tiles, cons
 // workgroups of `tile` lanes that fill every CU for the sweep kernel of a
 // format pair, times grid_mult
 int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt, int tile, int grid_mult);
+
+// The fixed-link form of the persistent sweep (links read only, cfgs[].gf
+// updated; post as launch_fixed_sweep: 0 plain, 1 g reunitarized as stored,
+// 2 also the per-tile (F, theta) sums in the second-pass slots of meas) and
+// its read-only measurement pass (one workgroup per listed tile).  Format
+// pairs: ensemble_fixed_pair.
+bool ensemble_fixed_pair(int fa, int fb);
+hipError_t launch_ensemble_fixed_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
+                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s);
+hipError_t launch_ensemble_fixed_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
+                                         double *partials, hipStream_t s);
+int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult);
 // *p = v, as a one-lane kernel on the stream (safe inside a captured graph)
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 

@@ -31,6 +31,7 @@ struct EnsGraph {
     bool nt;
     int tile, grid_mult;
     bool fused;
+    bool fixed;  // fixed-link form
     hipGraphExec_t exec;
 };
 
@@ -52,6 +53,9 @@ struct lgf_ensemble {
     std::vector<size_t> home_off;
     void *work[4] = {nullptr, nullptr, nullptr, nullptr};  // per-format copies, same offsets scheme
     std::vector<size_t> work_off[4];
+    // fixed-link form: per-format gauge transformations (site fields) of every configuration
+    void *gfix[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<size_t> gfix_off[4];
     // work list (device) and its pinned host mirrors
     lgf::EnsCfg *d_cfgs = nullptr;
     lgf::EnsTile *d_tiles = nullptr;
@@ -96,6 +100,26 @@ void *field_of(lgf_ensemble *e, int fmt, int i)
     return (char *)e->work[fmt] + e->work_off[fmt][i];
 }
 
+void *gf_of(lgf_ensemble *e, int fmt, int i) { return (char *)e->gfix[fmt] + e->gfix_off[fmt][i]; }
+
+lgf_status ensure_gfix(lgf_ensemble *e, int fmt)
+{
+    if (e->gfix[fmt]) return LGF_OK;
+    std::vector<size_t> off(e->n);
+    size_t total = 0;
+    for (int i = 0; i < e->n; ++i) {
+        off[i] = total;
+        total += align_up((size_t)e->V[i] * lgf::link_bytes(fmt));
+    }
+    if (hipMalloc(&e->gfix[fmt], total) != hipSuccess) {
+        e->gfix[fmt] = nullptr;
+        (void)hipGetLastError();
+        return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the ensemble's gauge transformations", total);
+    }
+    e->gfix_off[fmt] = off;
+    return LGF_OK;
+}
+
 lgf_status ensure_work(lgf_ensemble *e, int fmt)
 {
     if (fmt == e->format || e->work[fmt]) return LGF_OK;
@@ -120,10 +144,12 @@ void drop_graphs(lgf_ensemble *e)
     e->graphs.clear();
 }
 
-// Work list of the configurations whose phase is in `want`, each in format
-// fmt_of[i]; uploads descriptors, tiles and their count.  Returns the tiles.
+// Work list of the configurations not done (all with include_done), each in
+// format fmt_of[i], in tiles of `sites` sites (0: e->tile, one lane per site);
+// fixed: the descriptors also carry the gauge transformation of that format.
+// Fills the host mirrors and returns the tiles (upload_work sends them).
 uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::vector<int> &fmt_of,
-                    bool include_done, std::vector<int> &listed)
+                    bool include_done, std::vector<int> &listed, int sites = 0, bool fixed = false)
 {
     uint32_t nt = 0;
     listed.clear();
@@ -131,9 +157,10 @@ uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::v
         e->h_cfgs[i].g = e->geom[i];
         e->h_cfgs[i].fmt = fmt_of[i];
         e->h_cfgs[i].field = field_of(e, fmt_of[i], i);
+        e->h_cfgs[i].gf = (fixed && e->gfix[fmt_of[i]]) ? gf_of(e, fmt_of[i], i) : nullptr;
         e->h_cfgs[i].instance = (uint32_t)i;
         if (!include_done && phase[i] == kDone) continue;
-        const uint32_t w = (uint32_t)e->tile;
+        const uint32_t w = (uint32_t)(sites > 0 ? sites : e->tile);
         const uint32_t tiles = (e->geom[i].Vh + w - 1) / w;
         e->h_spans[listed.size()] = lgf::EnsSpan{(uint32_t)i, nt, tiles, (double)e->V[i]};
         for (uint32_t t = 0; t < tiles; ++t) e->h_tiles[nt + t] = lgf::EnsTile{(uint32_t)i, t * w};
@@ -199,7 +226,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
     for (auto &g : e->graphs)
         if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.p_sr == p_sr &&
             (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult &&
-            g.fused == fused) {
+            g.fused == fused && !g.fixed) {
             LGF_HIP(hipGraphLaunch(g.exec, e->stream));
             return LGF_OK;
         }
@@ -222,7 +249,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, false, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }
@@ -249,6 +276,78 @@ lgf_status measure_listed_fused(lgf_ensemble *e, int fa, int fb, uint32_t nt, co
     if (nt == 0) return LGF_OK;
     const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
     LGF_HIP(lgf::launch_ensemble_measure(fa, fb, L, nt, 0, false, false, e->d_partials, e->stream));
+    LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
+    LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    return LGF_OK;
+}
+
+// n full sweeps of every listed configuration in the fixed-link form; the
+// chunk's last sweep stores every g reunitarized, and with fused its parity-1
+// launch leaves the per-tile (F, theta) sums in the second-pass slots of
+// d_partials (see measure_listed_fixed).  Graphs as in run_chunk.
+lgf_status run_chunk_fixed(lgf_ensemble *e, int fa, int fb, int n, double omega, double p_sr, uint64_t seed,
+                           uint64_t sweep0, bool use_graph, bool fused)
+{
+    LGF_HIP(lgf::launch_set_u64(e->d_sweep_base, sweep0, e->stream));
+    const bool sr = p_sr > 0.0;
+    const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
+    lgf::EnsLaunch L = launch_desc(e, fa, fb, sr);
+    L.grid = (uint32_t)lgf::ensemble_fixed_grid(fa, fb, sr, e->tile, e->grid_mult);
+    auto issue = [&]() -> hipError_t {
+        hipError_t err = hipSuccess;
+        for (int k = 0; k < n && err == hipSuccess; ++k)
+            for (int parity = 0; parity < 2 && err == hipSuccess; ++parity) {
+                const bool last = (k == n - 1);
+                const int post = last ? ((parity == 1 && fused) ? 2 : 1) : 0;
+                err = lgf::launch_ensemble_fixed_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, post,
+                                                       post == 2 ? e->d_partials : nullptr, e->stream);
+            }
+        return err;
+    };
+    if (!use_graph) {
+        LGF_HIP(issue());
+        return LGF_OK;
+    }
+    const bool nt = e->nontemporal != 0;
+    for (auto &g : e->graphs)
+        if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.p_sr == p_sr &&
+            (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult &&
+            g.fused == fused && g.fixed) {
+            LGF_HIP(hipGraphLaunch(g.exec, e->stream));
+            return LGF_OK;
+        }
+    hipGraph_t graph = nullptr;
+    LGF_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = issue();
+    hipError_t e2 = hipStreamEndCapture(e->stream, &graph);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(LGF_EHIP, "ensemble graph capture: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err != hipSuccess) return fail(LGF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(err));
+    if (e->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(e->graphs.front().exec);
+        e->graphs.erase(e->graphs.begin());
+    }
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, true, exec});
+    LGF_HIP(hipGraphLaunch(exec, e->stream));
+    return LGF_OK;
+}
+
+// F, theta of the listed configurations in the fixed-link form: after a fused
+// chunk a read-only parity-0 pass (first-pass slots) joins the chunk's sums,
+// else both parities are measured read-only; then the per-configuration finish
+lgf_status measure_listed_fixed(lgf_ensemble *e, int fa, int fb, uint32_t nt, const std::vector<int> &listed,
+                                bool fused)
+{
+    if (nt == 0) return LGF_OK;
+    const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
+    LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 0, e->d_partials, e->stream));
+    if (!fused) LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 1, e->d_partials + 2 * (size_t)nt, e->stream));
     LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
     LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
     LGF_HIP(hipStreamSynchronize(e->stream));
@@ -306,6 +405,154 @@ void drop_scratch(lgf_ensemble *e)
     e->scratch_off.clear();
 }
 
+// lgf_ensemble_gauge_fix with fixed_links set (parameters checked by the
+// caller): per-configuration phases and stopping as in the link form, on
+// (U, g); at the end every configuration that was swept gets
+// g(x) U_mu(x) g(x+mu)^dag from its untouched home links.
+lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk, int finish,
+                              lgf_fix_result *results)
+{
+    const bool mixed = bulk != finish;
+    const auto t_start = std::chrono::steady_clock::now();
+    auto now_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    std::memset(results, 0, sizeof(lgf_fix_result) * e->n);
+    double t_bulk = 0.0, t_finish = 0.0, t_meas = 0.0, t_conv = 0.0;
+    auto timed = [&](double &acc_ms, auto &&body) -> lgf_status {
+        LGF_HIP(hipEventRecord(e->ev0, e->stream));
+        LGF_TRY(body());
+        LGF_HIP(hipEventRecord(e->ev1, e->stream));
+        LGF_HIP(hipEventSynchronize(e->ev1));
+        acc_ms += lgf::elapsed_ms(e->ev0, e->ev1);
+        return LGF_OK;
+    };
+    // configuration i's links in format f: its home field, or a copy of it
+    auto links_to = [&](int i, int f) -> lgf_status {
+        if (f == e->format) return LGF_OK;
+        LGF_TRY(ensure_work(e, f));
+        LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i], false,
+                                    e->stream));
+        return LGF_OK;
+    };
+    std::vector<int> phase(e->n, mixed ? kBulk : kFinish), fmt(e->n, e->format), listed;
+    std::vector<char> started(e->n, 0);
+    // measurement 0 on the home links (g = 1)
+    uint32_t nt = build_work(e, phase, fmt, true, listed);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_TRY(timed(t_meas, [&]() { return measure_listed(e, e->format, e->format, nt, listed, false); }));
+    for (int i = 0; i < e->n; ++i) {
+        lgf_fix_result &r = results[i];
+        r.F = e->h_out[2 * i];
+        r.theta = e->h_out[2 * i + 1];
+        r.n_history = 1;
+        r.status = LGF_ENOTCONV;
+        if (!std::isfinite(r.F) || !std::isfinite(r.theta)) {
+            r.status = LGF_ENUMERIC;
+            phase[i] = kDone;
+        } else if (r.theta < p.theta_target || p.max_sweeps == 0) {
+            r.status = r.theta < p.theta_target ? LGF_OK : LGF_ENOTCONV;
+            phase[i] = kDone;
+        }
+    }
+    // every live configuration: links in its first sweep format, g = 1
+    LGF_TRY(timed(t_conv, [&]() -> lgf_status {
+        for (int i = 0; i < e->n; ++i) {
+            if (phase[i] == kDone) continue;
+            const int f = (phase[i] == kBulk) ? bulk : finish;
+            LGF_TRY(links_to(i, f));
+            LGF_TRY(ensure_gfix(e, f));
+            LGF_HIP(lgf::launch_site_field(f, gf_of(e, f, i), e->geom[i], 0, e->stream));
+            fmt[i] = f;
+            started[i] = 1;
+        }
+        return LGF_OK;
+    }));
+    int64_t sweeps = 0;
+    uint64_t ctr = p.sweep_offset;
+    auto live = [&] {
+        for (int i = 0; i < e->n; ++i)
+            if (phase[i] != kDone) return true;
+        return false;
+    };
+    const bool fuse = !p.separate_measure;
+    const int sites = e->tile / lgf::kEnsFixedLanes;
+    while (live() && sweeps < p.max_sweeps) {
+        nt = build_work(e, phase, fmt, false, listed, sites, true);
+        LGF_TRY(upload_work(e, nt, listed.size()));
+        bool any_bulk = false, any_finish = false;
+        for (int i : listed) (phase[i] == kBulk ? any_bulk : any_finish) = true;
+        const int fa = any_bulk ? bulk : finish, fb = any_finish ? finish : bulk;
+        const int64_t left = p.max_sweeps - sweeps;
+        const int n = (int)(left < p.check_every ? left : p.check_every);
+        LGF_TRY(timed(any_bulk ? t_bulk : t_finish, [&]() {
+            return run_chunk_fixed(e, fa, fb, n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0, fuse);
+        }));
+        sweeps += n;
+        ctr += (uint64_t)n;
+        LGF_TRY(timed(t_meas, [&]() { return measure_listed_fixed(e, fa, fb, nt, listed, fuse); }));
+        LGF_TRY(timed(t_conv, [&]() -> lgf_status {
+            for (int i : listed) {
+                lgf_fix_result &r = results[i];
+                r.F = e->h_out[2 * i];
+                r.theta = e->h_out[2 * i + 1];
+                r.sweeps = sweeps;
+                if (phase[i] == kBulk) r.sweeps_bulk += n;
+                r.n_history += 1;
+                if (!std::isfinite(r.F) || !std::isfinite(r.theta)) {
+                    r.status = LGF_ENUMERIC;
+                    phase[i] = kDone;
+                    continue;
+                }
+                if (phase[i] == kBulk && (r.theta < p.theta_switch || r.theta < p.theta_target)) {
+                    // the finish starts from the bulk's g, reunitarized in FP64
+                    LGF_TRY(links_to(i, finish));
+                    LGF_TRY(ensure_gfix(e, finish));
+                    LGF_HIP(lgf::launch_site_convert(bulk, gf_of(e, bulk, i), finish, gf_of(e, finish, i),
+                                                     e->geom[i], e->stream));
+                    fmt[i] = finish;
+                    phase[i] = kFinish;
+                    continue;  // the next measurement is taken in the finish format
+                }
+                if (phase[i] == kFinish && r.theta < p.theta_target) {
+                    r.status = LGF_OK;
+                    r.t_total_ms = now_ms();
+                    phase[i] = kDone;
+                }
+            }
+            return LGF_OK;
+        }));
+    }
+    // the links in the final gauge, from the untouched home links (in place)
+    LGF_TRY(timed(t_conv, [&]() -> lgf_status {
+        for (int i = 0; i < e->n; ++i)
+            if (started[i])
+                LGF_HIP(lgf::launch_gauge_transform(e->format, field_of(e, e->format, i), fmt[i],
+                                                    gf_of(e, fmt[i], i), e->format, field_of(e, e->format, i),
+                                                    e->geom[i], e->stream));
+        return LGF_OK;
+    }));
+    bool any_bad = false;
+    for (int i = 0; i < e->n; ++i) {
+        lgf_fix_result &r = results[i];
+        if (r.t_total_ms == 0.0) r.t_total_ms = now_ms();
+        r.t_sweep_bulk_ms = t_bulk;
+        r.t_sweep_finish_ms = t_finish;
+        r.t_measure_ms = t_meas;
+        r.t_convert_ms = t_conv;
+        if (r.status != LGF_OK) any_bad = true;
+    }
+    LGF_HIP(hipStreamSynchronize(e->stream));
+    if (any_bad) {
+        for (int i = 0; i < e->n; ++i)
+            if (results[i].status == LGF_ENUMERIC)
+                return fail(LGF_ENUMERIC, "configuration %d: F or theta is not finite", i);
+        return fail(LGF_ENOTCONV, "not every configuration reached theta < %g in %lld sweeps", p.theta_target,
+                    (long long)sweeps);
+    }
+    return LGF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,7 +577,9 @@ lgf_status lgf_ensemble_create(int n, const int *dims, int format, void *stream,
         e->V.push_back((int64_t)dims[4 * i] * dims[4 * i + 1] * dims[4 * i + 2] * dims[4 * i + 3]);
         e->home_off.push_back(total);
         total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(format));
-        tiles += (e->geom[i].Vh + lgf::kEnsMinTile - 1) / lgf::kEnsMinTile;
+        // the smallest tiles: kEnsMinTile lanes, kEnsFixedLanes per site in the fixed-link form
+        const uint32_t min_sites = lgf::kEnsMinTile / lgf::kEnsFixedLanes;
+        tiles += (e->geom[i].Vh + min_sites - 1) / min_sites;
     }
     e->max_tiles = (uint32_t)tiles;
     auto bail = [&](lgf_status st) {
@@ -379,8 +628,10 @@ lgf_status lgf_ensemble_destroy(lgf_ensemble *e)
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     drop_graphs(e);
     if (e->home) (void)hipFree(e->home);
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 4; ++f) {
         if (e->work[f]) (void)hipFree(e->work[f]);
+        if (e->gfix[f]) (void)hipFree(e->gfix[f]);
+    }
     if (e->scratch) (void)hipFree(e->scratch);
     void *dev[] = {e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base, e->d_spans, e->d_partials, e->d_out};
     for (void *p : dev)
@@ -504,6 +755,14 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
+    if (p.fixed_links) {
+        if (!is_fp64(e->format)) return fail(LGF_EINVAL, "fixed_links needs an FP64 ensemble");
+        if (!lgf::ensemble_fixed_pair(bulk, finish))
+            return fail(LGF_EINVAL, "fixed_links on an ensemble takes the formats FP32-12 / FP64-12 (bulk / finish, "
+                                    "or either alone) or FP64-18 alone");
+        LGF_TRY(ens_use_device(e));
+        return ensemble_fix_fixed(e, p, bulk, finish, results);
+    }
     if (p.accumulate_g)
         return fail(LGF_EINVAL, "accumulate_g is supported by lgf_gauge_fix and lgf_coulomb_gauge_fix only");
     LGF_TRY(ens_use_device(e));

@@ -98,6 +98,65 @@ __global__ void __launch_bounds__(256) ensemble_finish_kernel(const double *__re
 }
 
 // ----------------------------------------------------------------------------
+// Fixed-link form: the links stay as stored, each configuration's gauge
+// transformation cfgs[].gf is updated (update_site_fixed, 2 lanes per site).
+// ----------------------------------------------------------------------------
+
+template <int F, bool SR, int POST>
+__device__ __forceinline__ void ensemble_site_fixed(const EnsCfg &c, int parity, uint32_t h, int lane, bool active,
+                                                    const EnsRelax &r, uint32_t sweep, MeasAcc *acc)
+{
+    using T = typename Fmt<F>::T;
+    const RelaxArgs<T> a{(T)r.omega, r.overrelax, r.sr_threshold, r.key0, r.key1, sweep, c.instance};
+    update_site_fixed<F, kEnsFixedLanes, SR, POST>(c.field, c.gf, c.g, parity, h, lane, active, a, acc);
+}
+
+template <int FA, int FB, bool SR, int POST>
+__global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_kernel(const EnsCfg *__restrict__ cfgs,
+                                                                   const EnsTile *__restrict__ tiles,
+                                                                   const uint32_t *__restrict__ n_tiles,
+                                                                   const uint64_t *__restrict__ sweep_base,
+                                                                   int parity, EnsRelax r, uint32_t sweep_offset,
+                                                                   double *__restrict__ partials)
+{
+    const uint32_t n = *n_tiles;
+    const uint32_t sweep = (uint32_t)(*sweep_base + sweep_offset);
+    const int lane = (int)(threadIdx.x % kEnsFixedLanes);
+    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const EnsTile w = tiles[t];
+        const EnsCfg c = cfgs[w.cfg];
+        const uint32_t h0 = w.h0 + threadIdx.x / kEnsFixedLanes;
+        const bool active = h0 < c.g.Vh;
+        const uint32_t h = active ? h0 : c.g.Vh - 1;
+        MeasAcc acc;
+        if (c.fmt == FA) ensemble_site_fixed<FA, SR, POST>(c, parity, h, lane, active, r, sweep, &acc);
+        else if (FB != FA && c.fmt == FB) ensemble_site_fixed<FB, SR, POST>(c, parity, h, lane, active, r, sweep, &acc);
+        if constexpr (POST == 2) {
+            block_sum2_any(acc.f, acc.th, partials + 2 * ((size_t)n + t));
+            __syncthreads();  // the block sum's shared slots are reused by the next tile
+        }
+    }
+}
+
+template <int FA, int FB>
+__global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_measure_kernel(const EnsCfg *__restrict__ cfgs,
+                                                                           const EnsTile *__restrict__ tiles,
+                                                                           int parity, double *partials)
+{
+    const EnsTile w = tiles[blockIdx.x];
+    const EnsCfg c = cfgs[w.cfg];
+    const uint32_t h0 = w.h0 + threadIdx.x / kEnsFixedLanes;
+    const int lane = (int)(threadIdx.x % kEnsFixedLanes);
+    const bool active = h0 < c.g.Vh;
+    const uint32_t h = active ? h0 : c.g.Vh - 1;
+    double f = 0.0, th = 0.0;
+    if (c.fmt == FA) measure_site_fixed<FA, kEnsFixedLanes>(c.field, c.gf, c.g, parity, h, lane, active, f, th);
+    else if (FB != FA && c.fmt == FB)
+        measure_site_fixed<FB, kEnsFixedLanes>(c.field, c.gf, c.g, parity, h, lane, active, f, th);
+    block_sum2_any(f, th, partials + 2 * blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
 
@@ -173,6 +232,84 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s)
 {
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
+}
+
+// format pairs of the fixed-link kernels: (a, b) with a <= b
+#define LGF_ENS_FIXED_PAIRS(X) X(0, 0) X(2, 2) X(2, 3) X(3, 3)
+
+bool ensemble_fixed_pair(int fa, int fb)
+{
+    if (fa > fb) { const int t = fa; fa = fb; fb = t; }
+#define LGF_CASE(A, B) if (fa == A && fb == B) return true;
+    LGF_ENS_FIXED_PAIRS(LGF_CASE)
+#undef LGF_CASE
+    return false;
+}
+
+template <int FA, int FB>
+static hipError_t launch_ens_fixed_t(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
+                                     bool sr, int post, double *meas, hipStream_t s)
+{
+    const dim3 grid(L.grid), block(L.tile);
+#define LGF_EF(SRV, P)                                                                                      \
+    hipLaunchKernelGGL((ensemble_fixed_kernel<FA, FB, SRV, P>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, \
+                       L.sweep_base, parity, r, sweep_offset, meas)
+    if (post == 2 && !meas) return hipErrorInvalidValue;
+    if (sr) {
+        if (post == 0) LGF_EF(true, 0);
+        else if (post == 1) LGF_EF(true, 1);
+        else LGF_EF(true, 2);
+    } else {
+        if (post == 0) LGF_EF(false, 0);
+        else if (post == 1) LGF_EF(false, 1);
+        else LGF_EF(false, 2);
+    }
+#undef LGF_EF
+    return hipGetLastError();
+}
+
+hipError_t launch_ensemble_fixed_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
+                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s)
+{
+    if (post < 0 || post > 2 || L.tile % 64 != 0) return hipErrorInvalidValue;
+    if (fa > fb) { const int t = fa; fa = fb; fb = t; }
+#define LGF_CASE(A, B) if (fa == A && fb == B) return launch_ens_fixed_t<A, B>(L, parity, r, sweep_offset, sr, post, meas, s);
+    LGF_ENS_FIXED_PAIRS(LGF_CASE)
+#undef LGF_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ensemble_fixed_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
+                                         double *partials, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    if (fa > fb) { const int t = fa; fa = fb; fb = t; }
+#define LGF_CASE(A, B)                                                                                        \
+    if (fa == A && fb == B) {                                                                                 \
+        hipLaunchKernelGGL((ensemble_fixed_measure_kernel<A, B>), dim3(n_tiles), dim3(L.tile), 0, s, L.cfgs,   \
+                           L.tiles, parity, partials);                                                       \
+        return hipGetLastError();                                                                             \
+    }
+    LGF_ENS_FIXED_PAIRS(LGF_CASE)
+#undef LGF_CASE
+    return hipErrorInvalidValue;
+}
+
+int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult)
+{
+    if (fa > fb) { const int t = fa; fa = fb; fb = t; }
+    const void *fn = nullptr;
+#define LGF_CASE(A, B)                                                                                      \
+    if (fa == A && fb == B)                                                                                 \
+        fn = sr ? reinterpret_cast<const void *>(&ensemble_fixed_kernel<A, B, true, 0>)                      \
+                : reinterpret_cast<const void *>(&ensemble_fixed_kernel<A, B, false, 0>);
+    LGF_ENS_FIXED_PAIRS(LGF_CASE)
+#undef LGF_CASE
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tile, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu * (grid_mult > 1 ? grid_mult : 1);
 }
 
 int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt, int tile, int grid_mult)

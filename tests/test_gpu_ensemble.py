@@ -264,3 +264,87 @@ def test_manifest_ensemble_sr_sampled(lgf, orc):
                 orc.sweep(d, ref, 1.0, 0.5, seed=5, sweep_index=0, instance=i)
                 e = np.linalg.norm((got - ref).reshape(-1, 9), axis=1) / np.sqrt(3)
                 assert np.quantile(e, 0.99) <= 2e-6 and e.max() <= 2e-5, (i, e.max())
+
+
+# ------------------------------------------------------------ fixed-link form
+
+@pytest.mark.parametrize("tile", [64, 256])
+def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
+    """The ensemble in the fixed-link form (2 lanes per site, tiles of tile/2
+    sites), mixed FP32-12 / FP64-12 and plain FP64-18: every configuration
+    with the sweeps and the links, bit for bit, of the single-lattice
+    fixed-link driver, theta < 1e-12 on the links handed back (the oracle
+    measures them), and the input's Wilson loops kept to 1e-12."""
+    announce("ensemble fixed fix", tile)
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8), (8, 6, 4, 12), (2, 2, 2, 2)]
+    Us = [orc.generate_links(d, 120 + i, 0.3) for i, d in enumerate(dims)]
+    for kw in (dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                    finish_format=lgf.LGF_FP64_12, fixed_links=1),
+               dict(omega=1.7, theta_target=1e-12, fixed_links=1)):
+        with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+            lgf.lgf_ensemble_set_tuning(ens.e, tile, 1, 1)
+            for i, U in enumerate(Us):
+                ens.load(i, U)
+            st, res = ens.gauge_fix(**kw)
+            got = [ens.store(i) for i in range(len(dims))]
+        assert st == lgf.LGF_OK, kw
+        for i, d in enumerate(dims):
+            assert res[i]["status"] == 0 and res[i]["theta"] < 1e-12
+            assert orc.measure(d, got[i])[1] < 1e-12
+            assert unitarity_error(got[i]) < 1e-12
+            for mu, nu in ((0, 1), (2, 3)):
+                assert abs(orc.wilson_loop(d, got[i], mu, nu, 1, 2) - orc.wilson_loop(d, Us[i], mu, nu, 1, 2)) < 1e-12
+            with lgf.Lattice(d, lgf.LGF_FP64_18) as lat:
+                lat.load(Us[i])
+                st1, r1, _ = lat.gauge_fix(**kw)
+                ref = lat.store()
+            assert r1["sweeps"] == res[i]["sweeps"] and r1["sweeps_bulk"] == res[i]["sweeps_bulk"], (kw, i)
+            assert np.array_equal(ref, got[i]), (kw, i, maxabs(ref, got[i]))
+
+
+def test_ensemble_fixed_fused_and_graph(lgf, orc):
+    """Fixed-link ensemble: the fused measurement against two read-only passes,
+    and graph replays against direct launches (stochastic relaxation, whose
+    counter the graph reads from device memory): the same sweeps and links."""
+    announce("ensemble fixed fused/graph")
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8)]
+    Us = [orc.generate_links(d, 130 + i, 0.3) for i, d in enumerate(dims)]
+    runs = {"fused": [dict(separate_measure=1), dict(separate_measure=0)],
+            "graph": [dict(use_graph=0, p_sr=0.5, seed=7, omega=1.0), dict(use_graph=1, p_sr=0.5, seed=7, omega=1.0)]}
+    for name, pair in runs.items():
+        outs = []
+        for extra in pair:
+            kw = dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                      finish_format=lgf.LGF_FP64_12, fixed_links=1)
+            kw.update(extra)
+            if "p_sr" in extra:
+                kw.update(theta_target=1e-10, bulk_format=-1, finish_format=-1, theta_switch=0.0)
+            with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+                for i, U in enumerate(Us):
+                    ens.load(i, U)
+                st, res = ens.gauge_fix(**kw)
+                assert st == lgf.LGF_OK, (name, extra)
+                outs.append(([r["sweeps"] for r in res], [r["F"] for r in res],
+                             [ens.store(i) for i in range(len(dims))]))
+        assert outs[0][0] == outs[1][0], name
+        for a, b in zip(outs[0][2], outs[1][2]):
+            assert np.array_equal(a, b), name
+        assert np.allclose(outs[0][1], outs[1][1], rtol=1e-13, atol=0), name
+
+
+def test_ensemble_fixed_args(lgf, orc):
+    announce("ensemble fixed args")
+    dims = [(4, 4, 4, 4), (4, 4, 4, 6)]
+    with lgf.Ensemble(dims, lgf.LGF_FP32_12) as ens:
+        for i in range(2):
+            ens.generate(i, i, 0.3)
+        with pytest.raises(lgf.LgfError):
+            ens.gauge_fix(omega=1.7, fixed_links=1)   # FP32 home format
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i in range(2):
+            ens.generate(i, i, 0.3)
+        with pytest.raises(lgf.LgfError):   # FP32-12 bulk with an FP64-18 finish: no kernel for the pair
+            ens.gauge_fix(omega=1.7, fixed_links=1, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                          finish_format=lgf.LGF_FP64_18)
+        st, res = ens.gauge_fix(omega=1.7, theta_target=1e-30, max_sweeps=20, fixed_links=1)
+        assert st == lgf.LGF_ENOTCONV and all(r["sweeps"] == 20 for r in res)
