@@ -374,7 +374,11 @@ lgf_status lgf_ensemble_measure(lgf_ensemble *e, double *F, double *theta);
  * persistent launch, whatever their phase.  results[i] (n entries) gets each
  * configuration's sweeps, theta, F and status; its time fields hold the
  * ensemble totals (chunks holding any bulk configuration count as bulk time),
- * except t_total_ms, the time at which that configuration finished. */
+ * except t_total_ms, the time at which that configuration finished.
+ * fixed_links works as in lgf_gauge_fix (2 lanes per site, so a tile of
+ * `tile` lanes covers tile/2 sites; FP64 home format; bulk/finish FP32-12 /
+ * FP64-12, or one of them, or FP64-18 alone: LGF_EINVAL otherwise);
+ * accumulate_g is rejected. */
 lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
                                   lgf_fix_result *results);
 
