@@ -170,7 +170,8 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     import csv
     per = {}
     fixed_seq = {}  # (counter, format, lanes) -> plain fixed-sweep readings in dispatch order
-    fixed_pat = re.compile(r"fixed_sweep_kernel<(\d+),\s*(\d+),\s*false,\s*0>")
+    # fixed_sweep_kernel<format, lanes, SR, post, mu0>: the plain Landau instances
+    fixed_pat = re.compile(r"fixed_sweep_kernel<(\d+),\s*(\d+),\s*false,\s*0,\s*0>")
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         with open(_find(d, "counter_collection.csv")) as f:
             rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
@@ -214,7 +215,7 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
             if len(chunk) != per_variant:
                 continue
             key = fixed_traffic_key(fmt, v[0], v[1], v[2], dims)
-            e = out["kernels"].setdefault(key, {"kernel": f"fixed_sweep_kernel<{fmt}, {lanes}, false, 0>",
+            e = out["kernels"].setdefault(key, {"kernel": f"fixed_sweep_kernel<{fmt}, {lanes}, false, 0, 0>",
                                                 "format": fmt, "fixed": True, "block": v[1], "order": v[2]})
             e[counter.lower() + "_bytes_per_launch"] = sum(chunk) / len(chunk) * scale[counter]
             e[counter.lower() + "_dispatches"] = len(chunk)
