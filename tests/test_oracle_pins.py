@@ -292,6 +292,43 @@ def test_gauge_invariance(orc):
     assert np.abs(_loops(orc, dims, U) - L0).max() < 1e-12
 
 
+def test_fixed_link_identity(orc):
+    """The identity behind the fixed-link form of the sweep: for links
+    transformed by g (the oracle's Eq. (3)), K(x) of the transformed links
+    (Eq. (8), written out in numpy) equals g(x) M(x) with M(x) = sum_mu
+    U_mu(x) g(x+mu)^dag + [g(x-mu) U_mu(x-mu)]^dag of the untransformed U,
+    and the oracle's local update of the transformed links equals the update
+    computed from g(x) M(x) alone."""
+    dims = (4, 4, 6, 8)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(26)
+    U = orc.generate_links(dims, 8, 0.3)
+    g = random_su3(rng, V)
+    Ug = U.copy()
+    orc.gauge_transform(dims, Ug, g)
+    K = K_field(dims, Ug)
+    G = g.reshape(*dims, 3, 3)
+    Ugrid = as_grid(dims, U)
+    M = np.zeros(tuple(dims) + (3, 3), dtype=np.complex128)
+    for mu in range(4):
+        g_fwd = np.roll(G, -1, axis=mu)
+        g_bwd = np.roll(G, 1, axis=mu)
+        M += Ugrid[..., mu, :, :] @ dag(g_fwd) + dag(g_bwd @ backward(dims, U, mu))
+    assert np.abs(K - G @ M).max() < 1e-13
+    # the update of a site depends on its links only through K: the oracle's
+    # update of the transformed links and of links whose K is g M agree
+    s = 37
+    t, z, y, x = np.unravel_index(s, dims)
+    fw = [Ug.reshape(V, 4, 3, 3)[s, mu] for mu in range(4)]
+    bw = [Ug.reshape(V, 4, 3, 3)[orc.neighbor(dims, s, mu, -1), mu] for mu in range(4)]
+    new, Gs = orc.local_update(np.array(fw + bw), 1.7, [0, 0, 0])
+    # a link set with the same K: the forward links carry g M, the rest cancel
+    alt = np.zeros((8, 3, 3), dtype=np.complex128)
+    alt[0] = G[t, z, y, x] @ M[t, z, y, x]
+    new2, Gs2 = orc.local_update(alt, 1.7, [0, 0, 0])
+    assert np.abs(Gs - Gs2).max() < 1e-12
+
+
 def test_wilson_loops_of_abelian_field(orc):
     """For links diag(e^{i a}, e^{i b}, e^{-i(a+b)}) the path product of a loop
     is diagonal with the phases summed around the rectangle, so (1/3) Re tr of
