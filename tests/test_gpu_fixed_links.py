@@ -305,3 +305,32 @@ def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
         if errs:
             assert float(max(errs)) <= 2e-5 and float(np.quantile(errs, 0.99)) <= 2e-6
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+
+
+def test_fixed_large_lattice_beyond_32bit_vector_indices(lgf, orc):
+    """64 x 128^3 (134M sites) with FP64-18 links and g: 4.8e9 16-byte link
+    vectors, so addresses pass 2^32 vectors.  One fixed-link sweep (fused
+    measurement included), checked on sampled parity-1 sites, the last planes
+    among them, against the oracle's updates of the neighbourhood."""
+    dims = (64, 128, 128, 128)
+    seed, eps, omega = 4, 0.3, 1.8
+    announce("fixed 64x128^3")
+    from test_gpu_parity import gpu_links8, oracle_links8, sample_sites
+    rng = np.random.default_rng(5)
+
+    def upd(s):
+        out, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), omega, [0, 0, 0])
+        return out
+
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.generate(seed, eps, True)
+        st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1)
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+        for y in sample_sites(orc, dims, 1, 6, rng):
+            links = np.zeros((8, 3, 3), dtype=np.complex128)
+            for mu in range(4):
+                links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]
+                links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]
+            ref, _ = orc.local_update(links, omega, [0, 0, 0])
+            assert maxabs(gpu_links8(lat, orc, dims, y), ref) < 1e-12, y
+        assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
