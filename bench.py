@@ -524,6 +524,10 @@ def main():
                 "avg_launch_ms": round(dk["avg_launch_ms"], 4),
                 "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
 
+    if traffic:
+        # the HBM bytes the counters saw per launch, at the launch time measured here
+        roofline["traffic_GBs"] = round(traffic / (dk["avg_launch_ms"] * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_GBs"] / HBM_PEAK_GBS, 4)
     # the streaming ceiling on this GPU: a plain one-pass device copy of 4 GiB
     copy_gbs = lgf.lgf_copy_bandwidth(4 << 30, 10, stream)
     roofline["copy_ceiling_GBs"] = round(copy_gbs, 1)
