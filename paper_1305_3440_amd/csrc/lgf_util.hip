@@ -1,5 +1,5 @@
 // lgf_util.hip -- measurement utility: the bandwidth of a plain device copy,
-// the practical ceiling against which the streaming sweep kernels are judged
+// the practical ceiling against which the streaming sweep kernels are measured
 // (one 16-byte vector per lane, non-temporal loads and stores, one pass).
 #include <hip/hip_runtime.h>
 
