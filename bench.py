@@ -410,6 +410,8 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
     ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
+    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32"),
+                    help="run only this extra workload and print its JSON (for profiling it alone)")
     args = ap.parse_args()
     if args.summarize_traffic:
         dims = tuple(int(x) for x in args.dims.split(","))
@@ -440,6 +442,11 @@ def main():
     stream = torch.cuda.current_stream()
     if args.traffic_run:
         traffic_run(lgf, torch, dims, seed, eps, omega)
+        return
+    if args.leg:
+        legs = {"coulomb": lambda: coulomb_bench(lgf, stream), "ensemble": lambda: ensemble_bench(lgf, stream),
+                "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream)}
+        print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
 
     nbytes = lgf.lgf_required_bytes(dims, home)
