@@ -334,3 +334,36 @@ def test_fixed_large_lattice_beyond_32bit_vector_indices(lgf, orc):
             ref, _ = orc.local_update(links, omega, [0, 0, 0])
             assert maxabs(gpu_links8(lat, orc, dims, y), ref) < 1e-12, y
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+
+
+def _random_cases():
+    """Seeded lattice shapes (even extents 2..12), formats and tunings, plus
+    shapes on which the blocked tile order is taken (with 2 and 4 t-z blocks)."""
+    rng = np.random.default_rng(2026)
+    cases = []
+    for k in range(12):
+        dims = tuple(int(2 * rng.integers(1, 7)) for _ in range(4))
+        tune = (int(rng.choice([2, 4])), int(rng.choice([64, 128, 256])), int(rng.integers(0, 3)))
+        fmt = int(rng.choice([0, 3, 2, 1]))
+        cases.append((dims, tune, fmt) + [(1.7, 0.0), (1.0, 0.5), (1.9, 0.2)][k % 3])
+    cases += [((8, 8, 16, 8), (2, 64, 2), 3, 1.7, 0.0), ((16, 8, 4, 16), (4, 128, 2), 0, 1.0, 0.5),
+              ((16, 16, 8, 16), (2, 128, 2), 2, 1.8, 0.0), ((8, 8, 8, 16), (4, 256, 2), 3, 1.9, 0.2)]
+    return cases
+
+
+@pytest.mark.parametrize("dims,tune,fmt,omega,p_sr", _random_cases())
+def test_fixed_sweep_random_shapes(lgf, orc, dims, tune, fmt, omega, p_sr):
+    """One fixed-link sweep on seeded random lattice shapes, formats and
+    tunings (tile orders included) against the oracle's sweep of the links."""
+    announce("fixed random", dims, tune, fmt, omega, p_sr)
+    U = orc.generate_links(dims, 61, 0.35)
+    ref = U.copy()
+    orc.sweep(dims, ref, omega, p_sr, seed=12, sweep_index=7)
+    orc.reunitarize(ref)
+    handle = 0 if fmt in (1, 2) else fmt
+    got, res, _ = one_fixed_sweep(lgf, dims, U, handle, fmt, tune, omega, p_sr, 12, 7)
+    if fmt in (0, 3):
+        assert maxabs(got, ref) <= 1e-12, maxabs(got, ref)
+    else:
+        assert fp32_ok(got, ref), float(link_errs(got, ref).max())
+    assert unitarity_error(got) < 1e-12
