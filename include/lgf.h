@@ -55,7 +55,17 @@ typedef enum {
     LGF_FP64_18 = 0,
     LGF_FP32_18 = 1,
     LGF_FP32_12 = 2,
-    LGF_FP64_12 = 3
+    LGF_FP64_12 = 3,
+    /* Sweep format of the fixed-link form only (bulk_format / finish_format
+     * with fixed_links set, and the fixed-link tuning calls), never a storage
+     * format of a handle: FP64 arithmetic with g in FP64-12, the read-only
+     * links in a split copy -- every real entry x of rows 0 and 1 as hi =
+     * fl32(x) plus a 16-bit integer q = round((x - hi) 2^40), read back as
+     * hi + q 2^-40, within 2^-40 of x for |x| <= 1 (every SU(3) entry): 72 B
+     * per link against 96 B in FP64-12.  Links are re-split from the
+     * handle's FP64 field at the start of each gauge fixing, at the precision
+     * switch when the finish uses this format. */
+    LGF_FP64_12S = 4
 } lgf_format;
 
 typedef struct lgf_lattice lgf_lattice;   /* opaque handle: one lattice on one GPU */
@@ -90,8 +100,10 @@ typedef struct {
                               g is handed over (reunitarized in FP64) and the finish runs on the
                               FP64 links; at the end the handle's links become g U g^dag from the
                               untouched input, an exact gauge transformation of it.  Needs an FP64
-                              handle; accumulate_g is implied.  0 (default): the sweeps rewrite
-                              the links. */
+                              handle; accumulate_g is implied.  The sweep formats may include
+                              LGF_FP64_12S; when the last sweeps ran in it, the result's F and theta
+                              (and the stopping test) come from one more measurement on the
+                              transformed FP64 links.  0 (default): the sweeps rewrite the links. */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
@@ -263,7 +275,8 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tu
  * the first round (>= 1); the fastest few are re-timed over longer runs. */
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
 
-/* Tuning of the fixed-link sweep (lgf_fix_params.fixed_links) per format:
+/* Tuning of the fixed-link sweep (lgf_fix_params.fixed_links) per sweep
+ * format (LGF_FP64_12S included, the default that of the FP64 formats):
  * lanes_per_site 2 or 4 (one lane per site does not fit the registers),
  * block 64, 128 or 256, xcd_remap 0 (lexicographic tiles), 1 (contiguous
  * ranges per XCD) or 2 (each XCD takes blocks of 8, 4 or 2 t-slices x z-planes,

@@ -149,7 +149,8 @@ struct lgf_lattice {
     // fixed-link form: the gauge transformation per sweep format (owned site
     // fields) and the tuning of its sweep
     void *gfix[4];
-    lgf::SweepTuning tune_fixed[4];
+    lgf::SweepTuning tune_fixed[5];  // per sweep format, LGF_FP64_12S included
+    void *split;       // the links in the split storage of LGF_FP64_12S (owned)
 };
 
 namespace {
@@ -599,18 +600,26 @@ lgf::SweepTuning default_fixed_tuning(int format)
 {
     lgf::SweepTuning t{};
     t.lanes_per_site = 2;
-    const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12);
+    const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12 || format == LGF_FP64_12S);
     t.block = fp64 ? 64 : 256;
     t.xcd_remap = fp64 ? 2 : 0;
     return t;
 }
 
+// format of the gauge transformation of a fixed-link sweep format (FP64-12
+// for the split links) and its site field
+int gf_format(int format) { return format == LGF_FP64_12S ? LGF_FP64_12 : format; }
+void *gfix_of(lgf_lattice *h, int format) { return h->gfix[gf_format(format)]; }
+
+bool valid_fixed_format(int f) { return valid_format(f) || f == LGF_FP64_12S; }
+
 lgf_status ensure_gfix(lgf_lattice *h, int format)
 {
-    if (!h->gfix[format]) {
-        const size_t bytes = (size_t)h->V * lgf::link_bytes(format);
-        if (hipMalloc(&h->gfix[format], bytes) != hipSuccess) {
-            h->gfix[format] = nullptr;
+    const int f = gf_format(format);
+    if (!h->gfix[f]) {
+        const size_t bytes = (size_t)h->V * lgf::link_bytes(f);
+        if (hipMalloc(&h->gfix[f], bytes) != hipSuccess) {
+            h->gfix[f] = nullptr;
             (void)hipGetLastError();
             return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the gauge transformation", bytes);
         }
@@ -619,9 +628,23 @@ lgf_status ensure_gfix(lgf_lattice *h, int format)
 }
 
 // the links of the fixed-link sweeps in `format`: the handle's own field, or
-// a copy of it in the working buffer of that format
+// a copy of it in the working buffer of that format (LGF_FP64_12S: in the
+// split storage)
 lgf_status links_in_format(lgf_lattice *h, int format, void **links)
 {
+    if (format == LGF_FP64_12S) {
+        if (!h->split) {
+            const size_t bytes = lgf::split_links_bytes(h->geom);
+            if (hipMalloc(&h->split, bytes) != hipSuccess) {
+                h->split = nullptr;
+                (void)hipGetLastError();
+                return fail(LGF_ENOMEM, "cannot allocate %zu bytes for the split links", bytes);
+            }
+        }
+        LGF_HIP(lgf::launch_split_links(h->format, h->field, h->split, h->geom, h->stream));
+        *links = h->split;
+        return LGF_OK;
+    }
     if (format == h->format) {
         *links = h->field;
         return LGF_OK;
@@ -756,7 +779,7 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
         LGF_TRY(ensure_gfix(h, cur));
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
             LGF_TRY(links_in_format(h, cur, &links));
-            LGF_HIP(lgf::launch_site_field(cur, h->gfix[cur], h->geom, 0, h->stream));
+            LGF_HIP(lgf::launch_site_field(gf_format(cur), gfix_of(h, cur), h->geom, 0, h->stream));
             return LGF_OK;
         }));
         started = true;
@@ -766,14 +789,14 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
         const int64_t left = p.max_sweeps - sweeps;
         const int n = (int)(left < p.check_every ? left : p.check_every);
         LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
-            return run_chunk_fixed(h, cur, links, h->gfix[cur], n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0,
-                                   fuse);
+            return run_chunk_fixed(h, cur, links, gfix_of(h, cur), n, p.omega, p.p_sr, p.seed, ctr,
+                                   p.use_graph != 0, fuse);
         }));
         if (in_bulk) sweeps_bulk += n;
         sweeps += n;
         ctr += (uint64_t)n;
         LGF_TRY(timed(res->t_measure_ms,
-                      [&]() { return measure_fixed_field(h, cur, links, h->gfix[cur], fuse, &F, &theta); }));
+                      [&]() { return measure_fixed_field(h, cur, links, gfix_of(h, cur), fuse, &F, &theta); }));
         record(sweeps, F, theta);
         if (!std::isfinite(F) || !std::isfinite(theta)) {
             status = LGF_ENUMERIC;
@@ -786,14 +809,15 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
             LGF_TRY(ensure_gfix(h, finish));
             LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
                 LGF_TRY(links_in_format(h, finish, &links));
-                LGF_HIP(lgf::launch_site_convert(bulk, h->gfix[bulk], finish, h->gfix[finish], h->geom, h->stream));
+                LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gfix_of(h, bulk), gf_format(finish),
+                                                 gfix_of(h, finish), h->geom, h->stream));
                 return LGF_OK;
             }));
             cur = finish;
             in_bulk = false;
             if (theta < p.theta_target) {
                 LGF_TRY(timed(res->t_measure_ms, [&]() {
-                    return measure_fixed_field(h, cur, links, h->gfix[cur], false, &F, &theta);
+                    return measure_fixed_field(h, cur, links, gfix_of(h, cur), false, &F, &theta);
                 }));
                 record(sweeps, F, theta);
             } else {
@@ -806,10 +830,17 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
         // the links in the final gauge, from the untouched input (element-wise
         // per link, so in place)
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, cur, h->gfix[cur], h->format, h->field, h->geom,
-                                                h->stream));
+            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, gf_format(cur), gfix_of(h, cur), h->format,
+                                                h->field, h->geom, h->stream));
             return LGF_OK;
         }));
+        if (cur == LGF_FP64_12S) {
+            // the sweeps measured on the split links (within 2^-40 of the
+            // input's): F and theta of the result from the FP64 links themselves
+            LGF_TRY(timed(res->t_measure_ms,
+                          [&]() { return measure_field(h, h->format, h->field, false, &F, &theta); }));
+            if (status == LGF_OK && !(theta < p.theta_target)) status = LGF_ENOTCONV;
+        }
     }
     res->sweeps = sweeps;
     res->sweeps_bulk = sweeps_bulk;
@@ -1015,10 +1046,8 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     h->field_bytes = need;
     // defaults: one lane per site, 128-thread workgroups, non-temporal
     // streaming (fastest measured at 64^4 for every format)
-    for (int f = 0; f < 4; ++f) {
-        h->tune[f] = default_tuning(f);
-        h->tune_fixed[f] = default_fixed_tuning(f);
-    }
+    for (int f = 0; f < 4; ++f) h->tune[f] = default_tuning(f);
+    for (int f = 0; f <= LGF_FP64_12S; ++f) h->tune_fixed[f] = default_fixed_tuning(f);
 
     auto bail = [&](lgf_status st) {
         lgf_destroy(h);
@@ -1071,6 +1100,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
         if (h->partner[f]) (void)hipFree(h->partner[f]);
         if (h->gfix[f]) (void)hipFree(h->gfix[f]);
     }
+    if (h->split) (void)hipFree(h->split);
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_fused) (void)hipFree(h->d_fused);
     if (h->d_sweep_base) (void)hipFree(h->d_sweep_base);
@@ -1251,8 +1281,10 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     if (history_cap < 0 || (history_cap > 0 && !history)) return fail(LGF_EINVAL, "bad history buffer");
     const int bulk = (p.bulk_format < 0) ? h->format : p.bulk_format;
     const int finish = (p.finish_format < 0) ? h->format : p.finish_format;
-    if (!valid_format(bulk)) return fail(LGF_EINVAL, "unknown bulk format %d", bulk);
-    if (!valid_format(finish)) return fail(LGF_EINVAL, "unknown finish format %d", finish);
+    // LGF_FP64_12S: the fixed-link form's sweeps only
+    auto valid = [&](int f) { return p.fixed_links ? valid_fixed_format(f) : valid_format(f); };
+    if (!valid(bulk)) return fail(LGF_EINVAL, "unknown bulk format %d", bulk);
+    if (!valid(finish)) return fail(LGF_EINVAL, "unknown finish format %d", finish);
     const bool mixed = (bulk != finish);
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
@@ -1680,7 +1712,7 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *t)
 lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *t)
 {
     if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
-    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     const lgf_sweep_tuning u = *t;
     if (u.lanes_per_site != 2 && u.lanes_per_site != 4)
         return fail(LGF_EINVAL, "the fixed-link sweep takes lanes_per_site 2 or 4");
@@ -1700,7 +1732,7 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
 lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *t)
 {
     if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
-    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     const lgf::SweepTuning &u = h->tune_fixed[format];
     t->lanes_per_site = u.lanes_per_site;
     t->sites_per_thread = u.sites_per_thread;
@@ -1714,7 +1746,7 @@ lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuni
 lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
-    if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
     if (h->format != LGF_FP64_18 && h->format != LGF_FP64_12)
         return fail(LGF_EINVAL, "the fixed-link form needs an FP64 handle");
@@ -1725,8 +1757,8 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
     void *links = nullptr;
     LGF_TRY(ensure_gfix(h, format));
     LGF_TRY(links_in_format(h, format, &links));
-    void *gf = h->gfix[format];
-    LGF_HIP(lgf::launch_site_field(format, gf, h->geom, 0, h->stream));
+    void *gf = gfix_of(h, format);
+    LGF_HIP(lgf::launch_site_field(gf_format(format), gf, h->geom, 0, h->stream));
     hipError_t e = hipSuccess;
     auto sweep = [&](const lgf::SweepTuning &t) {
         lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};

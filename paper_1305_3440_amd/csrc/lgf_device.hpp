@@ -138,7 +138,9 @@ __device__ __forceinline__ void convert(mat3<B> &dst, const mat3<A> &src)
 // A link is stored row-major, (row, column, re/im), rows 0..R-1.
 // ----------------------------------------------------------------------------
 
-enum : int { kF64_18 = 0, kF32_18 = 1, kF32_12 = 2, kF64_12 = 3 };
+// kF64_12S: the fixed-link sweep in FP64 with g stored as FP64-12 and the
+// read-only links in the split storage below (never a link field's format).
+enum : int { kF64_18 = 0, kF32_18 = 1, kF32_12 = 2, kF64_12 = 3, kF64_12S = 4 };
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v2f __attribute__((ext_vector_type(2)));
@@ -149,6 +151,7 @@ template <> struct Fmt<kF64_18> { using T = double; using V = v2d; static conste
 template <> struct Fmt<kF64_12> { using T = double; using V = v2d; static constexpr int R = 2, NV = 6, CPV = 1; };
 template <> struct Fmt<kF32_18> { using T = float;  using V = v2f; static constexpr int R = 3, NV = 9, CPV = 1; };
 template <> struct Fmt<kF32_12> { using T = float;  using V = v4f; static constexpr int R = 2, NV = 3, CPV = 2; };
+template <> struct Fmt<kF64_12S> : Fmt<kF64_12> {};  // the site field g
 
 // vector load / store, optionally marked non-temporal (streamed past the
 // caches: every link is read and written once per half-sweep)
@@ -212,6 +215,45 @@ __device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh,
             v.w = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].im;
         }
         vstore<NT>(blk + (size_t)k * Vh + h, v);
+    }
+}
+
+// Split FP64 storage of read-only links: rows 0 and 1 of each link rounded
+// to FP32, laid out as the FP32-12 field, followed by a second field of the
+// same shape holding each element's remainder x - hi as a 16-bit integer q in
+// units of 2^-40 (three 4 x int16 vectors per link).  The element read back,
+// hi + q 2^-40, is exact in FP64 and within 2^-40 of x for |x| <= 1 (every
+// entry of an SU(3) matrix): 72 B per link instead of 96 B in FP64-12.
+typedef short v4s __attribute__((ext_vector_type(4)));
+constexpr double kSplitUnit = 0x1p-40;
+
+__device__ __forceinline__ v4s *split_res_ptr(void *field, uint32_t Vh, int parity, int mu)
+{
+    return reinterpret_cast<v4s *>(reinterpret_cast<v4f *>(field) + (size_t)24 * Vh) +
+           (size_t)((parity * 4 + mu) * 3) * Vh;
+}
+
+__device__ __forceinline__ void split_encode(double x, float &hi, short &q)
+{
+    hi = (float)x;  // round to nearest, ties to even
+    const double r = rint((x - (double)hi) * 0x1p40);  // x - hi is exact
+    q = (short)fmin(fmax(r, -32767.0), 32767.0);
+}
+
+template <bool NT>
+__device__ __forceinline__ void load_link_split(mat3<double> &u, void *field, uint32_t Vh, int parity, int mu,
+                                                uint32_t h)
+{
+    const v4f *hb = block_ptr<kF32_12>(field, Vh, parity, mu);
+    const v4s *qb = split_res_ptr(field, Vh, parity, mu);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const v4f a = vload<NT>(hb + (size_t)k * Vh + h);
+        const v4s q = vload<NT>(qb + (size_t)k * Vh + h);
+        u.e[(2 * k) / 3][(2 * k) % 3] = {(double)a.x + (double)q.x * kSplitUnit,
+                                         (double)a.y + (double)q.y * kSplitUnit};
+        u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(double)a.z + (double)q.z * kSplitUnit,
+                                                 (double)a.w + (double)q.w * kSplitUnit};
     }
 }
 

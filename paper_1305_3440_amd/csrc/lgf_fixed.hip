@@ -168,6 +168,9 @@ static hipError_t launch_fixed_any(int format, const void *links, void *gf, cons
     case kF32_18: return launch_fixed_f<kF32_18>(links, gf, g, a, t, post, slices, coulomb, s);
     case kF32_12: return launch_fixed_f<kF32_12>(links, gf, g, a, t, post, slices, coulomb, s);
     case kF64_12: return launch_fixed_f<kF64_12>(links, gf, g, a, t, post, slices, coulomb, s);
+    case kF64_12S:
+        if (coulomb) return hipErrorInvalidValue;
+        return launch_fixed_f<kF64_12S>(links, gf, g, a, t, post, slices, coulomb, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -218,6 +221,7 @@ hipError_t launch_measure_fixed(int format, const void *links, const void *gf, c
     case kF32_18: hipLaunchKernelGGL((measure_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF32_12: hipLaunchKernelGGL((measure_fixed_kernel<kF32_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF64_12: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF64_12S: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12S>), grid, block, 0, s, links, gf, g, parity, partials); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -304,6 +308,48 @@ hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const
     case kF64_12: return launch_site_convert_s<kF64_12>(src, fd, dst, g.Vh, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// FP64 links (format fs, a link field) into the split storage of kF64_12S:
+// one lane per link of block (parity, mu) = blockIdx.y
+template <int FS>
+__global__ void __launch_bounds__(256) split_links_kernel(const void *__restrict__ src, void *__restrict__ dst,
+                                                          uint32_t Vh)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= Vh) return;
+    const int parity = (int)(blockIdx.y >> 2), mu = (int)(blockIdx.y & 3);
+    mat3<double> u;
+    load_link<FS, true, false>(u, block_ptr<FS>(const_cast<void *>(src), Vh, parity, mu), Vh, h);
+    v4f *hb = block_ptr<kF32_12>(dst, Vh, parity, mu);
+    v4s *qb = split_res_ptr(dst, Vh, parity, mu);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const cpx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+        v4f hi;
+        v4s q;
+        float f;
+        short r;
+        split_encode(a.re, f, r); hi.x = f; q.x = r;
+        split_encode(a.im, f, r); hi.y = f; q.y = r;
+        split_encode(b.re, f, r); hi.z = f; q.z = r;
+        split_encode(b.im, f, r); hi.w = f; q.w = r;
+        vstore<true>(hb + (size_t)k * Vh + h, hi);
+        vstore<true>(qb + (size_t)k * Vh + h, q);
+    }
+}
+
+size_t split_links_bytes(const Geom &g) { return (size_t)g.Vh * 24 * (16 + 8); }
+
+hipError_t launch_split_links(int fs, const void *src, void *dst, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((g.Vh + 255) / 256, 8);
+    switch (fs) {
+    case kF64_18: hipLaunchKernelGGL((split_links_kernel<kF64_18>), grid, dim3(256), 0, s, src, dst, g.Vh); break;
+    case kF64_12: hipLaunchKernelGGL((split_links_kernel<kF64_12>), grid, dim3(256), 0, s, src, dst, g.Vh); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace lgf

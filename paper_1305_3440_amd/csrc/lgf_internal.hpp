@@ -113,10 +113,11 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
                             hipStream_t s);
 
 // Fixed-link form of the sweep (links read only, the site field gf of the
-// gauge transformation updated; both in `format`).  post: 0 plain, 1 the new
-// g reunitarized in FP64 as it is stored, 2 as 1 plus the per-workgroup
-// (F, theta) partial sums of the updated sites in a.meas.  Tuning: lanes per
-// site 1 or 2, block, xcd_remap.
+// gauge transformation updated; both in `format`, or for kF64_12S gf in
+// FP64-12 and the links in the split storage of launch_split_links).  post: 0
+// plain, 1 the new g reunitarized in FP64 as it is stored, 2 as 1 plus the
+// per-workgroup (F, theta) partial sums of the updated sites in a.meas.
+// Tuning: lanes per site 2 or 4, block, xcd_remap.  (Coulomb: not kF64_12S.)
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
@@ -136,5 +137,9 @@ hipError_t launch_measure_fixed(int format, const void *links, const void *gf, c
                                 double *partials, int *n_partials, hipStream_t s);
 // site field dst (format fd) <- src (format fs), reunitarized in FP64
 hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const Geom &g, hipStream_t s);
+// FP64 link field src (format fs, kF64_18 or kF64_12) into the split storage
+// dst of kF64_12S, split_links_bytes(g) bytes
+size_t split_links_bytes(const Geom &g);
+hipError_t launch_split_links(int fs, const void *src, void *dst, const Geom &g, hipStream_t s);
 
 }  // namespace lgf

@@ -398,10 +398,21 @@ template <int LPS, typename T> __device__ __forceinline__ void lane_sum(mat3<T> 
             }
 }
 
+// link mu of parity-`parity` site h for the fixed-link sweep in format F
+// (kF64_12S: from the split storage; row 2 left unset)
+template <int F>
+__device__ __forceinline__ void load_fixed_link(mat3<typename Fmt<F>::T> &u, void *links, uint32_t Vh, int parity,
+                                                int mu, uint32_t h)
+{
+    if constexpr (F == kF64_12S) load_link_split<true>(u, links, Vh, parity, mu, h);
+    else load_link<F, true, false>(u, block_ptr<F>(links, Vh, parity, mu), Vh, h);
+}
+
 // The update of site h of the given parity in the fixed-link form, LPS lanes
 // per site (each gathers the terms of 4 / LPS directions; M is summed over the
 // lanes, every lane then runs the SU(2) steps and lane 0 stores).  links and
-// the site field gf are in format F.
+// the site field gf are in format F (kF64_12S: gf in FP64-12, the links in
+// the split storage).
 // POST = 1: the new g(x) is reunitarized in FP64 and rounded to the format
 // before it is stored.  POST = 2: as 1, and the site's contributions to F and
 // theta, from the links formed with the stored g(x) and the stored
@@ -440,7 +451,7 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
         const int mu = lane + k * LPS;
         if (mu < MU0) continue;
         mat3<T> u, y, p;
-        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
+        load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
         if constexpr (R == 2) row2_fma(y);
         mul_dag_fma<R>(p, u, y);  // U_mu(x) g(x+mu)^dag
@@ -451,7 +462,7 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
             else meas_term_fwd<R>(Mf, u, y);
         }
         const uint32_t hb = back_half(g, c, h, mu);
-        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
+        load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
         load_link<F, false, false>(y, gn, g.Vh, hb);
         if constexpr (R == 2) row2_fma(u);
         mul_fma<R>(p, y, u);  // g(x-mu) U_mu(x-mu)
@@ -538,12 +549,12 @@ __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ link
         const int mu = lane + k * LPS;
         if (mu < MU0) continue;
         mat3<T> u, y;
-        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity, mu), g.Vh, h);
+        load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
         if constexpr (R == 2) row2_fma(y);
         meas_term_fwd<R>(Mf, u, y);
         const uint32_t hb = back_half(g, c, h, mu);
-        load_link<F, true, false>(u, block_ptr<F>(U, g.Vh, parity ^ 1, mu), g.Vh, hb);
+        load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
         load_link<F, false, false>(y, gn, g.Vh, hb);
         if constexpr (R == 2) row2_fma(u);
         meas_term_bwd<R>(Mb, y, u);

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_PKG, "liblgf.so")
 LGF_OK, LGF_EINVAL, LGF_ENOMEM, LGF_EHIP, LGF_ENOTCONV, LGF_ENUMERIC, LGF_ESTATE = range(7)
 STATUS_NAMES = {0: "LGF_OK", 1: "LGF_EINVAL", 2: "LGF_ENOMEM", 3: "LGF_EHIP", 4: "LGF_ENOTCONV",
                 5: "LGF_ENUMERIC", 6: "LGF_ESTATE"}
-LGF_FP64_18, LGF_FP32_18, LGF_FP32_12, LGF_FP64_12 = range(4)
-FORMAT_NAMES = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12"}
+LGF_FP64_18, LGF_FP32_18, LGF_FP32_12, LGF_FP64_12, LGF_FP64_12S = range(5)
+FORMAT_NAMES = {0: "fp64-18", 1: "fp32-18", 2: "fp32-12", 3: "fp64-12", 4: "fp64-12s"}
 LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
 
 

@@ -102,3 +102,32 @@ def stored_as(U, fmt):
     if fmt in (2, 3):
         W[..., 2, :] = np.conj(np.cross(W[..., 0, :], W[..., 1, :]))
     return W.astype(np.complex128)
+
+
+SPLIT_UNIT = 2.0 ** -40
+
+
+def split_entry(x):
+    """The split FP64 storage of one real array: hi = fl32(x) (nearest, ties
+    to even) and q = round((x - hi) / 2^-40) clipped to +-32767; returns (hi
+    as float32, q as int16)."""
+    x = np.asarray(x, dtype=np.float64)
+    hi = x.astype(np.float32)
+    q = np.clip(np.rint((x - hi.astype(np.float64)) / SPLIT_UNIT), -32767, 32767).astype(np.int16)
+    return hi, q
+
+
+def split_stored(U):
+    """Links as the split storage reads them back: every real entry of rows
+    0 and 1 as hi + q 2^-40, row 2 rebuilt as conj(row0 x row1)."""
+    U = np.asarray(U, dtype=np.complex128)
+    out = U.copy()
+
+    def back(x):
+        hi, q = split_entry(x)
+        return hi.astype(np.float64) + q.astype(np.float64) * SPLIT_UNIT
+
+    r01 = U[..., :2, :]
+    out[..., :2, :] = back(r01.real) + 1j * back(r01.imag)
+    out[..., 2, :] = np.conj(np.cross(out[..., 0, :], out[..., 1, :]))
+    return out
