@@ -30,7 +30,18 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96}
+# bytes per link as the sweeps read it (4: the split FP64 copy of the
+# fixed-link form, FP32 rows plus 16-bit remainders) and per g(x) of the
+# fixed-link form (4: FP64-12)
+LINK_BYTES = {0: 144, 1: 72, 2: 48, 3: 96, 4: 72}
+G_BYTES = {0: 144, 1: 72, 2: 48, 3: 96, 4: 96}
+
+
+def fixed_site_bytes(fmt: int) -> int:
+    """Algorithmic bytes per site update of the fixed-link sweep: 8 links in,
+    g(x) in and out, and the neighbouring g of the other parity (each shared
+    by the 8 sites around it) in once."""
+    return 8 * LINK_BYTES[fmt] + 3 * G_BYTES[fmt]
 # the sources that define the sweep kernels and their launch shape (the host
 # driver only picks among them)
 KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_amd/csrc/lgf_fixed.hip",
@@ -140,7 +151,7 @@ def traffic_run(lgf, torch, dims, seed, eps, omega):
     # the order of TRAFFIC_FIXED_VARIANTS (the summary groups the dispatches by it)
     h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
     lgf.lgf_generate_links(h, seed, eps, True)
-    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_12S):
         for v in TRAFFIC_FIXED_VARIANTS:
             lgf.lgf_set_fixed_tuning(h, fmt, *v)
             p = lgf.fix_params(omega=omega, theta_target=1e-300, check_every=TRAFFIC_FIXED_SWEEPS,
@@ -222,7 +233,7 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     for key, e in out["kernels"].items():
         # link sweep: 8 links in and out per site; fixed-link sweep: 8 links in,
         # g(x) in and out, the neighbouring g of the other parity in once
-        alg = Vh * (11 if e.get("fixed") else 16) * LINK_BYTES[e["format"]]
+        alg = Vh * (fixed_site_bytes(e["format"]) if e.get("fixed") else 16 * LINK_BYTES[e["format"]])
         e["algorithmic_bytes_per_launch"] = alg
         e["hbm_bytes_per_launch"] = e.get("fetch_size_bytes_per_launch", 0) + e.get(
             "write_size_bytes_per_launch", 0)
@@ -438,7 +449,10 @@ def main():
     V = dims[0] * dims[1] * dims[2] * dims[3]
     seed, eps, omega = 3, 0.3, 1.8
     theta_target, theta_switch = 1e-14, 1e-8
-    bulk, finish, home = lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_18
+    # the finish reads the links from their split FP64 copy (FP64 arithmetic);
+    # the link-rewriting comparison runs finish in FP64-12
+    bulk, finish, home = lgf.LGF_FP32_12, lgf.LGF_FP64_12S, lgf.LGF_FP64_18
+    finish12 = lgf.LGF_FP64_12
     stream = torch.cuda.current_stream()
     if args.traffic_run:
         traffic_run(lgf, torch, dims, seed, eps, omega)
@@ -460,13 +474,13 @@ def main():
     lgf.lgf_autotune_fixed(hw, bulk, 4)
     lgf.lgf_autotune_fixed(hw, finish, 4)
     lgf.lgf_autotune(hw, bulk, 4)
-    lgf.lgf_autotune(hw, finish, 4)
+    lgf.lgf_autotune(hw, finish12, 4)
     torch.cuda.synchronize()
     fixed_tuning = {f: lgf.lgf_get_fixed_tuning(hw, f) for f in (bulk, finish)}
-    tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish, home)}
+    tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish12, home)}
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, "
-        f"order) fp32-12 {fixed_tuning[bulk]} fp64-12 {fixed_tuning[finish]}; link-sweep tuning fp32-12 "
-        f"{tuning[bulk]} fp64-12 {tuning[finish]}")
+        f"order) fp32-12 {fixed_tuning[bulk]} fp64-12s {fixed_tuning[finish]}; link-sweep tuning fp32-12 "
+        f"{tuning[bulk]} fp64-12 {tuning[finish12]}")
 
     params = lgf.lgf_fix_params_default()
     params.omega = omega
@@ -507,12 +521,10 @@ def main():
     tb = sum(r["t_sweep_bulk_ms"] for r in results)
     tf = sum(r["t_sweep_finish_ms"] for r in results)
     kernels = {}
-    for name, fmt, nsw, tms in (("fixed_sweep_fp32_12", bulk, sb, tb), ("fixed_sweep_fp64_12", finish, sf, tf)):
+    for name, fmt, nsw, tms in (("fixed_sweep_fp32_12", bulk, sb, tb), ("fixed_sweep_fp64_12s", finish, sf, tf)):
         if nsw > 0:
             launch_ms = tms / (2 * nsw)
-            # 8 links in, g(x) in and out, the 8 neighbouring g (each shared by
-            # 8 sites of the half-sweep) in once: 11 matrices per site
-            by = Vh * 11 * LINK_BYTES[fmt]
+            by = Vh * fixed_site_bytes(fmt)
             kernels[name] = {"launches": 2 * nsw, "avg_launch_ms": launch_ms,
                              "algorithmic_bytes_per_launch": by,
                              "achieved_GBs": by / (launch_ms * 1e-3) / 1e9,
@@ -545,7 +557,7 @@ def main():
     if not args.no_extras:
         # the same mixed gauge fixing with sweeps that rewrite the links
         plink = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch,
-                               bulk_format=bulk, finish_format=finish, check_every=20, use_graph=1)
+                               bulk_format=bulk, finish_format=finish12, check_every=20, use_graph=1)
         rl = step(plink)
         extras["link_sweeps_mixed"] = {
             "time_to_theta_s": rl["t_total_ms"] / 1e3, "sweeps": rl["sweeps"], "sweeps_bulk": rl["sweeps_bulk"],
@@ -553,8 +565,21 @@ def main():
             "site_updates_per_s": V * rl["sweeps"] / (rl["t_total_ms"] / 1e3),
             "sweep_ms_per_launch": {"fp32-12": rl["t_sweep_bulk_ms"] / (2 * rl["sweeps_bulk"]),
                                     "fp64-12": rl["t_sweep_finish_ms"] / (2 * (rl["sweeps"] - rl["sweeps_bulk"]))},
-            "tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, tuning[f])) for f in (bulk, finish)}}
+            "tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, tuning[f])) for f in (bulk, finish12)}}
         log(f"[bench] link sweeps, mixed: {rl['sweeps']} sweeps, {rl['t_total_ms']:.0f} ms, F {rl['F']:.12f}")
+        # the same fixed-link gauge fixing with the finish on FP64-12 links
+        lgf.lgf_autotune_fixed(hw, finish12, 4)
+        p12 = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch,
+                             bulk_format=bulk, finish_format=finish12, check_every=20, use_graph=1, fixed_links=1)
+        r12 = step(p12)
+        extras["fixed_links_fp64_12_finish"] = {
+            "time_to_theta_s": r12["t_total_ms"] / 1e3, "sweeps": r12["sweeps"], "sweeps_bulk": r12["sweeps_bulk"],
+            "theta": r12["theta"], "F": r12["F"],
+            "site_updates_per_s": V * r12["sweeps"] / (r12["t_total_ms"] / 1e3),
+            "fp64_12_ms_per_launch": r12["t_sweep_finish_ms"] / (2 * (r12["sweeps"] - r12["sweeps_bulk"])),
+            "tuning": dict(zip(("lanes_per_site", "block", "order"), lgf.lgf_get_fixed_tuning(hw, finish12)))}
+        log(f"[bench] fixed links, FP64-12 finish: {r12['sweeps']} sweeps, {r12['t_total_ms']:.0f} ms, "
+            f"F {r12['F']:.15f}")
         # plain FP64 on the same input, its sweep variant autotuned the same way
         lgf.lgf_autotune(hw, home, 4)
         extras["fp64_plain_tuning"] = dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home)))
@@ -589,6 +614,8 @@ def main():
         extras["dF_mixed_vs_fp64"] = results[-1]["F"] - r64["F"]
         extras["dF_link_sweeps_mixed_vs_fp64"] = rl["F"] - r64["F"]
         extras["fixed_speedup_vs_link_sweeps"] = extras["link_sweeps_mixed"]["time_to_theta_s"] / mixed_s
+        extras["split_speedup_vs_fp64_12_finish"] = extras["fixed_links_fp64_12_finish"]["time_to_theta_s"] / mixed_s
+        extras["dF_split_vs_fp64_12_finish"] = results[-1]["F"] - r12["F"]
         log(f"[bench] fp64 plain: {r64['sweeps']} sweeps, {r64['t_total_ms']:.0f} ms; "
             f"SR fp64 {ms_sr64:.3f} ms/launch, SR fp32-12 {ms_sr32:.3f}, OR fp32-12 {ms_or32:.3f}")
     lgf.lgf_destroy(hw)
@@ -635,7 +662,9 @@ def main():
         "dtype": "fp32+fp64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau OR gauge fixing, mixed "
-                               f"FP32-12 bulk / FP64-12 finish, theta<1e-14, fixed-link sweeps",
+                               f"FP32-12 bulk / FP64 finish (FP64 arithmetic and g; links read from a split "
+                               f"copy, fl32 + 16-bit remainder, within 2^-40), theta<1e-14 measured on the "
+                               f"FP64 result, fixed-link sweeps",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
                    "sweeps_per_step": [r["sweeps"] for r in results],
