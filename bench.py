@@ -364,19 +364,20 @@ def gauge_32x4_bench(lgf, torch, stream):
 
 def coulomb_bench(lgf, stream):
     """Coulomb gauge on 48^3 x 96 (seed 5, eps 0.3, Haar): the 96 timeslices
-    relaxed together by one launch per parity, mixed FP32-12 bulk / FP64-12
-    finish, omega 1.7, each timeslice stopping at its own theta_C < 1e-14; with
-    the fixed-link sweeps (reported first) and with the link-rewriting ones."""
+    relaxed together by one launch per parity, mixed FP32-12 bulk / FP64
+    finish, omega 1.7, each timeslice stopping at its own theta_C < 1e-14: the
+    fixed-link sweeps with the finish on the split links (reported first), on
+    FP64-12 links, and the link-rewriting sweeps (FP64-12 finish)."""
     dims = (96, 48, 48, 48)
     V3 = dims[1] * dims[2] * dims[3]
     V = V3 * dims[0]
     h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
 
-    def run(fixed):
-        # the same start for both runs: the seeded generator, run again
+    def run(fixed, finish):
+        # the same start for every run: the seeded generator, run again
         lgf.lgf_generate_links(h, 5, 0.3, True)
         p = lgf.fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
-                           finish_format=lgf.LGF_FP64_12, fixed_links=fixed)
+                           finish_format=finish, fixed_links=fixed)
         lgf.lgf_synchronize(h)
         t0 = time.perf_counter()
         st, res, sw, F, th = lgf.lgf_coulomb_gauge_fix(h, p, dims[0])
@@ -384,12 +385,12 @@ def coulomb_bench(lgf, stream):
         su = float(sw.sum()) * V3
         # algorithmic bytes per site update: link sweeps move 8 links in and
         # out; fixed-link sweeps read the 6 spatial links, g(x) in and out and
-        # the neighbouring g once (9 matrices); FP32-12 bulk (every timeslice
-        # live), FP64-12 finish (live timeslices only)
-        per = 9 if fixed else 16
+        # the neighbouring g once; FP32-12 bulk (every timeslice live), FP64
+        # finish (live timeslices only)
+        def per(fmt):
+            return 6 * LINK_BYTES[fmt] + 3 * G_BYTES[fmt] if fixed else 16 * LINK_BYTES[fmt]
         su_bulk = float(res["sweeps_bulk"]) * V
-        alg_bytes = (su_bulk * per * LINK_BYTES[lgf.LGF_FP32_12] +
-                     (su - su_bulk) * per * LINK_BYTES[lgf.LGF_FP64_12])
+        alg_bytes = su_bulk * per(lgf.LGF_FP32_12) + (su - su_bulk) * per(finish)
         t_sweep_s = (res["t_sweep_bulk_ms"] + res["t_sweep_finish_ms"]) / 1e3
         return {"status": int(st), "wall_s": wall, "sweeps_total": res["sweeps"],
                 "sweep_algorithmic_GBs": alg_bytes / t_sweep_s / 1e9,
@@ -399,11 +400,15 @@ def coulomb_bench(lgf, stream):
                 "t_sweep_ms": res["t_sweep_bulk_ms"] + res["t_sweep_finish_ms"],
                 "t_measure_ms": res["t_measure_ms"]}
 
-    fixed = run(1)
-    link = run(0)
+    fixed = run(1, lgf.LGF_FP64_12S)
+    fixed12 = run(1, lgf.LGF_FP64_12)
+    link = run(0, lgf.LGF_FP64_12)
     lgf.lgf_destroy(h)
-    out = {"dims": list(dims), "sweeps": "fixed-link", **fixed, "link_sweeps": link,
-           "fixed_speedup_vs_link_sweeps": link["wall_s"] / fixed["wall_s"]}
+    out = {"dims": list(dims), "sweeps": "fixed-link, FP64 finish on split links", **fixed,
+           "fixed_links_fp64_12_finish": fixed12, "link_sweeps": link,
+           "fixed_speedup_vs_link_sweeps": link["wall_s"] / fixed["wall_s"],
+           "split_speedup_vs_fp64_12_finish": fixed12["wall_s"] / fixed["wall_s"],
+           "dF_mean_split_vs_fp64_12_finish": fixed["F_mean"] - fixed12["F_mean"]}
     return out
 
 

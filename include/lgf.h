@@ -57,7 +57,8 @@ typedef enum {
     LGF_FP32_12 = 2,
     LGF_FP64_12 = 3,
     /* Sweep format of the fixed-link form only (bulk_format / finish_format
-     * with fixed_links set, and the fixed-link tuning calls), never a storage
+     * of lgf_gauge_fix and lgf_coulomb_gauge_fix with fixed_links set, and the
+     * fixed-link tuning calls; not the ensembles), never a storage
      * format of a handle: FP64 arithmetic with g in FP64-12, the read-only
      * links in a split copy -- every real entry x of rows 0 and 1 as hi =
      * fl32(x) plus a 16-bit integer q = round((x - hi) 2^40), read back as
@@ -343,8 +344,10 @@ lgf_status lgf_measure_coulomb(lgf_lattice *h, double *F_t, double *theta_t);
  * NULL) receive per-timeslice sweeps, F_C and theta_C.  accumulate_g and
  * fixed_links work as in lgf_gauge_fix (in the fixed-link form a site update
  * reads only its 6 spatial links; the temporal links enter only the final
- * g(x) U_mu(x) g(x+mu)^dag); separate_measure is ignored (two measurement
- * passes). */
+ * g(x) U_mu(x) g(x+mu)^dag; with LGF_FP64_12S last, every timeslice's F_C
+ * and theta_C of the result, and the stopping test, come from one more
+ * measurement of the transformed FP64 links); separate_measure is ignored
+ * (two measurement passes). */
 lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
                                  double *sweeps_t, double *F_t, double *theta_t);
 

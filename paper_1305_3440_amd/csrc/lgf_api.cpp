@@ -914,7 +914,7 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
         LGF_TRY(ensure_gfix(h, cur));
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
             LGF_TRY(links_in_format(h, cur, &links));
-            LGF_HIP(lgf::launch_site_field(cur, h->gfix[cur], h->geom, 0, h->stream));
+            LGF_HIP(lgf::launch_site_field(gf_format(cur), gfix_of(h, cur), h->geom, 0, h->stream));
             return LGF_OK;
         }));
         started = true;
@@ -924,13 +924,13 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
         const int64_t left = p.max_sweeps - sweeps;
         const int n = (int)(left < p.check_every ? left : p.check_every);
         LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
-            return run_chunk_fixed(h, cur, links, h->gfix[cur], n, p.omega, p.p_sr, p.seed, ctr, p.use_graph != 0,
-                                   false, true);
+            return run_chunk_fixed(h, cur, links, gfix_of(h, cur), n, p.omega, p.p_sr, p.seed, ctr,
+                                   p.use_graph != 0, false, true);
         }));
         if (in_bulk) sweeps_bulk += n;
         sweeps += n;
         ctr += (uint64_t)n;
-        LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_coulomb_fixed_field(h, cur, links, h->gfix[cur]); }));
+        LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_coulomb_fixed_field(h, cur, links, gfix_of(h, cur)); }));
         read_out(true);
         ++nh;
         for (int t = 0; t < Lt; ++t) {
@@ -945,8 +945,8 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
                 LGF_TRY(ensure_gfix(h, finish));
                 LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
                     LGF_TRY(links_in_format(h, finish, &links));
-                    LGF_HIP(lgf::launch_site_convert(bulk, h->gfix[bulk], finish, h->gfix[finish], h->geom,
-                                                     h->stream));
+                    LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gfix_of(h, bulk), gf_format(finish),
+                                                     gfix_of(h, finish), h->geom, h->stream));
                     return LGF_OK;
                 }));
                 cur = finish;
@@ -960,10 +960,19 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
     if (status != LGF_ENUMERIC) status = n_live() == 0 ? LGF_OK : LGF_ENOTCONV;
     if (started) {
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, cur, h->gfix[cur], h->format, h->field, h->geom,
-                                                h->stream));
+            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, gf_format(cur), gfix_of(h, cur), h->format,
+                                                h->field, h->geom, h->stream));
             return LGF_OK;
         }));
+        if (cur == LGF_FP64_12S) {
+            // the sweeps measured on the split links: every timeslice's F_C and
+            // theta_C of the result from the FP64 links themselves
+            LGF_TRY(timed(res->t_measure_ms, [&]() { return measure_coulomb_field(h, h->format, h->field, false); }));
+            read_out(false);
+            if (status == LGF_OK)
+                for (int t = 0; t < Lt; ++t)
+                    if (!(th[t] < p.theta_target)) status = LGF_ENOTCONV;
+        }
     }
     double tmax = 0.0, fsum = 0.0;
     for (int t = 0; t < Lt; ++t) {
@@ -1503,7 +1512,9 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
     if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
     const int bulk = (p.bulk_format < 0) ? h->format : p.bulk_format;
     const int finish = (p.finish_format < 0) ? h->format : p.finish_format;
-    if (!valid_format(bulk) || !valid_format(finish)) return fail(LGF_EINVAL, "unknown format");
+    // LGF_FP64_12S: the fixed-link form's sweeps only
+    auto valid = [&](int f) { return p.fixed_links ? valid_fixed_format(f) : valid_format(f); };
+    if (!valid(bulk) || !valid(finish)) return fail(LGF_EINVAL, "unknown format");
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");

@@ -168,9 +168,7 @@ static hipError_t launch_fixed_any(int format, const void *links, void *gf, cons
     case kF32_18: return launch_fixed_f<kF32_18>(links, gf, g, a, t, post, slices, coulomb, s);
     case kF32_12: return launch_fixed_f<kF32_12>(links, gf, g, a, t, post, slices, coulomb, s);
     case kF64_12: return launch_fixed_f<kF64_12>(links, gf, g, a, t, post, slices, coulomb, s);
-    case kF64_12S:
-        if (coulomb) return hipErrorInvalidValue;
-        return launch_fixed_f<kF64_12S>(links, gf, g, a, t, post, slices, coulomb, s);
+    case kF64_12S: return launch_fixed_f<kF64_12S>(links, gf, g, a, t, post, slices, coulomb, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -260,6 +258,7 @@ hipError_t launch_measure_coulomb_fixed(int format, const void *links, const voi
     case kF32_18: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF32_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF64_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12>), grid, block, 0, s, links, gf, g, parity, partials); break;
+    case kF64_12S: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12S>), grid, block, 0, s, links, gf, g, parity, partials); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

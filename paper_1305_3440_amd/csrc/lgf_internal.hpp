@@ -117,7 +117,7 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 // FP64-12 and the links in the split storage of launch_split_links).  post: 0
 // plain, 1 the new g reunitarized in FP64 as it is stored, 2 as 1 plus the
 // per-workgroup (F, theta) partial sums of the updated sites in a.meas.
-// Tuning: lanes per site 2 or 4, block, xcd_remap.  (Coulomb: not kF64_12S.)
+// Tuning: lanes per site 2 or 4, block, xcd_remap.
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);

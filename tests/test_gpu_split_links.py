@@ -215,9 +215,9 @@ def test_split_64x4_sampled(lgf, orc):
 
 
 def test_split_argument_checks(lgf, orc):
-    """LGF_FP64_12S is a sweep format of the fixed-link form of
-    lgf_gauge_fix only: not a handle's format, not for the link-rewriting
-    sweeps, the Coulomb gauge or the link-sweep tuning."""
+    """LGF_FP64_12S is a sweep format of the fixed-link form only: not a
+    handle's format, not for the link-rewriting sweeps (Landau or Coulomb),
+    the link-sweep tuning or the ensembles."""
     dims = (4, 4, 4, 4)
     announce("split checks")
     with pytest.raises(lgf.LgfError):
@@ -227,7 +227,7 @@ def test_split_argument_checks(lgf, orc):
         with pytest.raises(lgf.LgfError):
             lat.gauge_fix(omega=1.7, finish_format=lgf.LGF_FP64_12S)
         with pytest.raises(lgf.LgfError):
-            lat.coulomb_gauge_fix(omega=1.7, fixed_links=1, finish_format=lgf.LGF_FP64_12S)
+            lat.coulomb_gauge_fix(omega=1.7, finish_format=lgf.LGF_FP64_12S)   # link-rewriting form
         with pytest.raises(lgf.LgfError):
             lgf.lgf_set_tuning(lat.h, lgf.LGF_FP64_12S, 1, 128)
         assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 64, 2)
@@ -237,3 +237,68 @@ def test_split_argument_checks(lgf, orc):
         st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-13, fixed_links=1,
                                    bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
         assert st == 0 and res["theta"] < 1e-13
+    with lgf.Ensemble([dims, dims], lgf.LGF_FP64_18) as ens:
+        with pytest.raises(lgf.LgfError):
+            ens.gauge_fix(omega=1.7, fixed_links=1, bulk_format=lgf.LGF_FP64_12S,
+                          finish_format=lgf.LGF_FP64_12S)
+
+
+# ------------------------------------------------------------ Coulomb gauge
+
+@pytest.mark.parametrize("dims", DIMS + [(8, 8, 8, 16)])
+@pytest.mark.parametrize("omega,p_sr", [(1.7, 0.0), (1.0, 0.5)])
+def test_split_coulomb_sweep_matches_fp64_12_and_oracle(lgf, orc, dims, omega, p_sr):
+    """One Coulomb sweep of every timeslice on grid links with the split
+    finish: the FP64-12 fixed-link Coulomb sweep of the same links to 1e-15,
+    the oracle's Coulomb sweep within 1e-12 + 2 delta (as for the Landau
+    sweep), and per-timeslice F_C, theta_C of the links handed back."""
+    announce("split coulomb sweep", dims, omega, p_sr)
+    U = split_stored(orc.generate_links(dims, 31, 0.35))
+    bar = 1e-12 + 2 * unitarity_error(U)
+    ref = U.copy()
+    orc.sweep_coulomb(dims, ref, omega, p_sr, seed=4, sweep_index=2)
+    for tune in [(2, 128, 0), (4, 64, 2), (2, 64, 2)]:
+        out = {}
+        for fmt in (lgf.LGF_FP64_12S, lgf.LGF_FP64_12):
+            with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+                lgf.lgf_set_fixed_tuning(lat.h, fmt, *tune)
+                lat.load(U)
+                st, res, sw, F, th = lat.coulomb_gauge_fix(omega=omega, p_sr=p_sr, seed=4, sweep_offset=2,
+                                                           theta_target=1e-300, check_every=1, max_sweeps=1,
+                                                           fixed_links=1, bulk_format=fmt, finish_format=fmt)
+                assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+                out[fmt] = (lat.store(), F, th)
+        got, F, th = out[lgf.LGF_FP64_12S]
+        assert maxabs(got, out[lgf.LGF_FP64_12][0]) <= 1e-15, tune
+        assert maxabs(got, ref) <= bar, (tune, maxabs(got, ref), bar)
+        Fo, tho = orc.measure_coulomb(dims, got)
+        assert np.abs(F - Fo).max() < 1e-13 and np.all(np.abs(th - tho) <= 1e-12 * tho + 1e-15), tune
+
+
+def test_split_coulomb_mixed_keeps_the_orbit(lgf, orc):
+    """Mixed Coulomb gauge fixing (FP32-12 bulk, switch at 1e-8, split
+    finish) on ordinary links: every timeslice below theta_C < 1e-14 by the
+    oracle on the links handed back, equal to the reported F_C, theta_C; the
+    input's Wilson loops to 1e-12; the per-timeslice sweeps of the FP64-12
+    finish and F_C within 1e-12 of it."""
+    dims = (8, 6, 6, 6)
+    announce("split coulomb mixed")
+    U = orc.generate_links(dims, 34, 0.3)
+    L0 = loops(orc, dims, U)
+    out = {}
+    for finish in (lgf.LGF_FP64_12, lgf.LGF_FP64_12S):
+        with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+            lat.load(U)
+            out[finish] = lat.coulomb_gauge_fix(omega=1.7, theta_target=1e-14, theta_switch=1e-8,
+                                                bulk_format=lgf.LGF_FP32_12, finish_format=finish,
+                                                fixed_links=1) + (lat.store(),)
+    st, res, sw, F, th, got = out[lgf.LGF_FP64_12S]
+    assert st == lgf.LGF_OK and 0 < res["sweeps_bulk"] < res["sweeps"]
+    Fo, tho = orc.measure_coulomb(dims, got)
+    assert np.all(tho < 1e-14) and np.abs(Fo - F).max() < 1e-13
+    assert np.all(np.abs(tho - th) <= 1e-8 * tho + 1e-20)
+    assert float(np.abs(loops(orc, dims, got) - L0).max()) < 1e-12 and unitarity_error(got) < 1e-12
+    st4, res4, sw4, F4, th4, _ = out[lgf.LGF_FP64_12]
+    assert st4 == lgf.LGF_OK and res4["sweeps_bulk"] == res["sweeps_bulk"]
+    assert np.abs(sw4 - sw).max() <= 20
+    assert np.abs(F4 - F).max() < 1e-12
