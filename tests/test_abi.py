@@ -81,6 +81,20 @@ def test_create_rejects_bad_dims_without_gpu(lgf, dims):
     assert "even" in lgf.lgf_last_error()
 
 
+def test_format_codes_match_header(lgf):
+    """The binding's format constants are the header's enum values; the split
+    FP64 sweep format of the fixed-link form is no storage format."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef enum \{([^}]*)\} lgf_format;", text).group(1)
+    enum = {k: int(v) for k, v in re.findall(r"(LGF_FP\w+)\s*=\s*(\d+)", body)}
+    assert enum == {k: getattr(lgf, k) for k in enum}
+    assert set(enum) == {"LGF_FP64_18", "LGF_FP32_18", "LGF_FP32_12", "LGF_FP64_12", "LGF_FP64_12S"}
+    assert lgf.lgf_required_bytes((8, 8, 8, 8), lgf.LGF_FP64_12S) == 0
+    with pytest.raises(lgf.LgfError) as e:
+        lgf.lgf_create((4, 4, 4, 4), lgf.LGF_FP64_12S)
+    assert e.value.status == lgf.LGF_EINVAL
+
+
 def test_create_rejects_bad_format_and_small_buffer(lgf):
     with pytest.raises(lgf.LgfError) as e:
         lgf.lgf_create((4, 4, 4, 4), 7)
