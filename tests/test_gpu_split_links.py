@@ -214,6 +214,37 @@ def test_split_64x4_sampled(lgf, orc):
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
 
 
+def test_split_large_lattice_beyond_32bit_vector_indices(lgf, orc):
+    """64 x 128^3 (134M sites): the split copy's residual planes start 24 Vh
+    16-byte vectors into it (3.2e9), so its addresses pass 2^32 vectors.  One
+    split sweep checked on sampled parity-1 sites, the last planes among
+    them, with the bar of the 64^4 sampled test."""
+    dims = (64, 128, 128, 128)
+    seed, eps, omega = 4, 0.3, 1.8
+    announce("split 64x128^3")
+    from test_gpu_parity import gpu_links8, oracle_links8, sample_sites
+    rng = np.random.default_rng(5)
+    bar = 36 * SPLIT_UNIT + 1e-12
+
+    def upd(s):
+        out, _ = orc.local_update(split_stored(oracle_links8(orc, dims, seed, eps, s)), omega, [0, 0, 0])
+        return out
+
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        lat.generate(seed, eps, True)
+        st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1,
+                                   bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+        for y in sample_sites(orc, dims, 1, 6, rng):
+            links = np.zeros((8, 3, 3), dtype=np.complex128)
+            for mu in range(4):
+                links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]
+                links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]
+            ref, _ = orc.local_update(split_stored(links), omega, [0, 0, 0])
+            assert maxabs(gpu_links8(lat, orc, dims, y), ref) < bar, y
+        assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+
+
 def test_split_argument_checks(lgf, orc):
     """LGF_FP64_12S is a sweep format of the fixed-link form only: not a
     handle's format, not for the link-rewriting sweeps (Landau or Coulomb),
