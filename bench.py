@@ -292,6 +292,14 @@ def ensemble_bench(lgf, stream):
     t0 = time.perf_counter()
     stf, resf = lgf.lgf_ensemble_gauge_fix(e, pf, len(dims))
     wallf = time.perf_counter() - t0
+    # and with the FP64 finish on the split links
+    for c in man:
+        lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
+    ps = lgf.fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                        finish_format=lgf.LGF_FP64_12S, fixed_links=1)
+    t0 = time.perf_counter()
+    sts, ress = lgf.lgf_ensemble_gauge_fix(e, ps, len(dims))
+    walls = time.perf_counter() - t0
     # the same 48 fields fixed in plain FP64 (18-real) for the per-configuration F difference
     for c in man:
         lgf.lgf_ensemble_generate(e, c["index"], c["seed"], c["eps"], True)
@@ -310,6 +318,13 @@ def ensemble_bench(lgf, stream):
         "sweeps_min": min(swf), "sweeps_max": max(swf),
         "max_abs_dF_vs_fp64": max(abs(r["F"] - q["F"]) for r, q in zip(resf, res64)),
         "speedup_vs_link_sweeps": wall / wallf}
+    sws = [r["sweeps"] for r in ress]
+    out["gauge_fix_mixed_fixed_links_split_finish"] = {
+        "status": int(sts), "wall_s": walls, "all_below_1e-14": all(r["theta"] < 1e-14 for r in ress),
+        "sweeps_min": min(sws), "sweeps_max": max(sws),
+        "max_abs_dF_vs_fp64": max(abs(r["F"] - q["F"]) for r, q in zip(ress, res64)),
+        "max_abs_dF_vs_fp64_12_finish": max(abs(r["F"] - q["F"]) for r, q in zip(ress, resf)),
+        "speedup_vs_fp64_12_finish": wallf / walls, "speedup_vs_link_sweeps": wall / walls}
     sw = [r["sweeps"] for r in res]
     out["gauge_fix_mixed"] = {"status": int(st), "wall_s": wall, "all_below_1e-14": all(
         r["theta"] < 1e-14 for r in res), "sweeps_min": min(sw), "sweeps_max": max(sw),

@@ -57,8 +57,8 @@ typedef enum {
     LGF_FP32_12 = 2,
     LGF_FP64_12 = 3,
     /* Sweep format of the fixed-link form only (bulk_format / finish_format
-     * of lgf_gauge_fix and lgf_coulomb_gauge_fix with fixed_links set, and the
-     * fixed-link tuning calls; not the ensembles), never a storage
+     * of lgf_gauge_fix, lgf_coulomb_gauge_fix and lgf_ensemble_gauge_fix with
+     * fixed_links set, and the fixed-link tuning calls), never a storage
      * format of a handle: FP64 arithmetic with g in FP64-12, the read-only
      * links in a split copy -- every real entry x of rows 0 and 1 as hi =
      * fl32(x) plus a 16-bit integer q = round((x - hi) 2^40), read back as
@@ -393,7 +393,9 @@ lgf_status lgf_ensemble_measure(lgf_ensemble *e, double *F, double *theta);
  * except t_total_ms, the time at which that configuration finished.
  * fixed_links works as in lgf_gauge_fix (2 lanes per site, so a tile of
  * `tile` lanes covers tile/2 sites; FP64 home format; bulk/finish FP32-12 /
- * FP64-12, or one of them, or FP64-18 alone: LGF_EINVAL otherwise);
+ * FP64-12 or FP64-12S, or one of them, or FP64-18 alone: LGF_EINVAL
+ * otherwise; a configuration whose last sweeps ran in FP64-12S gets its F,
+ * theta and status from one more measurement of its FP64 home links);
  * accumulate_g is rejected. */
 lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
                                   lgf_fix_result *results);

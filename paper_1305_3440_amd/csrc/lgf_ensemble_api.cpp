@@ -51,8 +51,9 @@ struct lgf_ensemble {
     int device = 0;
     void *home = nullptr;                 // one allocation, configurations at offsets
     std::vector<size_t> home_off;
-    void *work[4] = {nullptr, nullptr, nullptr, nullptr};  // per-format copies, same offsets scheme
-    std::vector<size_t> work_off[4];
+    // per-format copies, same offsets scheme (slot 4: the split links of FP64-12S)
+    void *work[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::vector<size_t> work_off[5];
     // fixed-link form: per-format gauge transformations (site fields) of every configuration
     void *gfix[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<size_t> gfix_off[4];
@@ -100,10 +101,19 @@ void *field_of(lgf_ensemble *e, int fmt, int i)
     return (char *)e->work[fmt] + e->work_off[fmt][i];
 }
 
-void *gf_of(lgf_ensemble *e, int fmt, int i) { return (char *)e->gfix[fmt] + e->gfix_off[fmt][i]; }
+// format of the gauge transformation of a fixed-link sweep format (FP64-12
+// for the split links)
+int gf_format(int fmt) { return fmt == LGF_FP64_12S ? LGF_FP64_12 : fmt; }
+
+void *gf_of(lgf_ensemble *e, int fmt, int i)
+{
+    fmt = gf_format(fmt);
+    return (char *)e->gfix[fmt] + e->gfix_off[fmt][i];
+}
 
 lgf_status ensure_gfix(lgf_ensemble *e, int fmt)
 {
+    fmt = gf_format(fmt);
     if (e->gfix[fmt]) return LGF_OK;
     std::vector<size_t> off(e->n);
     size_t total = 0;
@@ -127,7 +137,8 @@ lgf_status ensure_work(lgf_ensemble *e, int fmt)
     size_t total = 0;
     for (int i = 0; i < e->n; ++i) {
         off[i] = total;
-        total += align_up((size_t)e->V[i] * 4 * lgf::link_bytes(fmt));
+        total += align_up(fmt == LGF_FP64_12S ? lgf::split_links_bytes(e->geom[i])
+                                              : (size_t)e->V[i] * 4 * lgf::link_bytes(fmt));
     }
     if (hipMalloc(&e->work[fmt], total) != hipSuccess) {
         e->work[fmt] = nullptr;
@@ -157,7 +168,7 @@ uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::v
         e->h_cfgs[i].g = e->geom[i];
         e->h_cfgs[i].fmt = fmt_of[i];
         e->h_cfgs[i].field = field_of(e, fmt_of[i], i);
-        e->h_cfgs[i].gf = (fixed && e->gfix[fmt_of[i]]) ? gf_of(e, fmt_of[i], i) : nullptr;
+        e->h_cfgs[i].gf = (fixed && e->gfix[gf_format(fmt_of[i])]) ? gf_of(e, fmt_of[i], i) : nullptr;
         e->h_cfgs[i].instance = (uint32_t)i;
         if (!include_done && phase[i] == kDone) continue;
         const uint32_t w = (uint32_t)(sites > 0 ? sites : e->tile);
@@ -431,8 +442,12 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
     auto links_to = [&](int i, int f) -> lgf_status {
         if (f == e->format) return LGF_OK;
         LGF_TRY(ensure_work(e, f));
-        LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i], false,
-                                    e->stream));
+        if (f == LGF_FP64_12S)
+            LGF_HIP(lgf::launch_split_links(e->format, field_of(e, e->format, i), field_of(e, f, i), e->geom[i],
+                                            e->stream));
+        else
+            LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i],
+                                        false, e->stream));
         return LGF_OK;
     };
     std::vector<int> phase(e->n, mixed ? kBulk : kFinish), fmt(e->n, e->format), listed;
@@ -462,7 +477,7 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
             const int f = (phase[i] == kBulk) ? bulk : finish;
             LGF_TRY(links_to(i, f));
             LGF_TRY(ensure_gfix(e, f));
-            LGF_HIP(lgf::launch_site_field(f, gf_of(e, f, i), e->geom[i], 0, e->stream));
+            LGF_HIP(lgf::launch_site_field(gf_format(f), gf_of(e, f, i), e->geom[i], 0, e->stream));
             fmt[i] = f;
             started[i] = 1;
         }
@@ -508,8 +523,8 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
                     // the finish starts from the bulk's g, reunitarized in FP64
                     LGF_TRY(links_to(i, finish));
                     LGF_TRY(ensure_gfix(e, finish));
-                    LGF_HIP(lgf::launch_site_convert(bulk, gf_of(e, bulk, i), finish, gf_of(e, finish, i),
-                                                     e->geom[i], e->stream));
+                    LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gf_of(e, bulk, i), gf_format(finish),
+                                                     gf_of(e, finish, i), e->geom[i], e->stream));
                     fmt[i] = finish;
                     phase[i] = kFinish;
                     continue;  // the next measurement is taken in the finish format
@@ -527,11 +542,34 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
     LGF_TRY(timed(t_conv, [&]() -> lgf_status {
         for (int i = 0; i < e->n; ++i)
             if (started[i])
-                LGF_HIP(lgf::launch_gauge_transform(e->format, field_of(e, e->format, i), fmt[i],
+                LGF_HIP(lgf::launch_gauge_transform(e->format, field_of(e, e->format, i), gf_format(fmt[i]),
                                                     gf_of(e, fmt[i], i), e->format, field_of(e, e->format, i),
                                                     e->geom[i], e->stream));
         return LGF_OK;
     }));
+    // configurations whose last sweeps read the split links: F and theta of
+    // the result from their FP64 home links (and the stopping test with them)
+    {
+        std::vector<int> ph(e->n, kDone), fh(e->n, e->format);
+        bool any = false;
+        for (int i = 0; i < e->n; ++i)
+            if (started[i] && fmt[i] == LGF_FP64_12S) {
+                ph[i] = kFinish;
+                any = true;
+            }
+        if (any) {
+            nt = build_work(e, ph, fh, false, listed);
+            LGF_TRY(upload_work(e, nt, listed.size()));
+            LGF_TRY(timed(t_meas, [&]() { return measure_listed(e, e->format, e->format, nt, listed, false); }));
+            for (int i : listed) {
+                lgf_fix_result &r = results[i];
+                r.F = e->h_out[2 * i];
+                r.theta = e->h_out[2 * i + 1];
+                if (!std::isfinite(r.F) || !std::isfinite(r.theta)) r.status = LGF_ENUMERIC;
+                else if (r.status == LGF_OK && !(r.theta < p.theta_target)) r.status = LGF_ENOTCONV;
+            }
+        }
+    }
     bool any_bad = false;
     for (int i = 0; i < e->n; ++i) {
         lgf_fix_result &r = results[i];
@@ -628,6 +666,7 @@ lgf_status lgf_ensemble_destroy(lgf_ensemble *e)
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     drop_graphs(e);
     if (e->home) (void)hipFree(e->home);
+    if (e->work[LGF_FP64_12S]) (void)hipFree(e->work[LGF_FP64_12S]);
     for (int f = 0; f < 4; ++f) {
         if (e->work[f]) (void)hipFree(e->work[f]);
         if (e->gfix[f]) (void)hipFree(e->gfix[f]);
@@ -751,15 +790,17 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *pp, lgf
     if (p.max_sweeps < 0) return fail(LGF_EINVAL, "max_sweeps must be >= 0");
     const int bulk = (p.bulk_format < 0) ? e->format : p.bulk_format;
     const int finish = (p.finish_format < 0) ? e->format : p.finish_format;
-    if (!lgf::valid_format(bulk) || !lgf::valid_format(finish)) return fail(LGF_EINVAL, "unknown format");
+    // LGF_FP64_12S: the fixed-link form's sweeps only
+    auto valid = [&](int f) { return lgf::valid_format(f) || (p.fixed_links && f == LGF_FP64_12S); };
+    if (!valid(bulk) || !valid(finish)) return fail(LGF_EINVAL, "unknown format");
     const bool mixed = bulk != finish;
     if (mixed && !(p.theta_switch > 0.0))
         return fail(LGF_EINVAL, "a bulk format other than the finish format needs theta_switch > 0");
     if (p.fixed_links) {
         if (!is_fp64(e->format)) return fail(LGF_EINVAL, "fixed_links needs an FP64 ensemble");
-        if (!lgf::ensemble_fixed_pair(bulk, finish))
-            return fail(LGF_EINVAL, "fixed_links on an ensemble takes the formats FP32-12 / FP64-12 (bulk / finish, "
-                                    "or either alone) or FP64-18 alone");
+        if (!lgf::ensemble_fixed_pair(bulk, finish) || (bulk == LGF_FP64_12S && finish != LGF_FP64_12S))
+            return fail(LGF_EINVAL, "fixed_links on an ensemble takes the formats FP32-12 / FP64-12 or FP64-12S "
+                                    "(bulk / finish, or either alone) or FP64-18 alone");
         LGF_TRY(ens_use_device(e));
         return ensemble_fix_fixed(e, p, bulk, finish, results);
     }

@@ -234,8 +234,9 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-// format pairs of the fixed-link kernels: (a, b) with a <= b
-#define LGF_ENS_FIXED_PAIRS(X) X(0, 0) X(2, 2) X(2, 3) X(3, 3)
+// format pairs of the fixed-link kernels: (a, b) with a <= b (4: FP64 on
+// the split links, g in FP64-12)
+#define LGF_ENS_FIXED_PAIRS(X) X(0, 0) X(2, 2) X(2, 3) X(3, 3) X(2, 4) X(4, 4)
 
 bool ensemble_fixed_pair(int fa, int fb)
 {

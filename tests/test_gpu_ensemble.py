@@ -271,15 +271,18 @@ def test_manifest_ensemble_sr_sampled(lgf, orc):
 @pytest.mark.parametrize("tile", [64, 256])
 def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
     """The ensemble in the fixed-link form (2 lanes per site, tiles of tile/2
-    sites), mixed FP32-12 / FP64-12 and plain FP64-18: every configuration
-    with the sweeps and the links, bit for bit, of the single-lattice
-    fixed-link driver, theta < 1e-12 on the links handed back (the oracle
-    measures them), and the input's Wilson loops kept to 1e-12."""
+    sites), mixed FP32-12 / FP64-12, mixed FP32-12 / FP64-12S (the finish on
+    the split links) and plain FP64-18: every configuration with the sweeps,
+    the links and (split finish) the final F and theta, bit for bit, of the
+    single-lattice fixed-link driver, theta < 1e-12 on the links handed back
+    (the oracle measures them), and the input's Wilson loops kept to 1e-12."""
     announce("ensemble fixed fix", tile)
     dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8), (8, 6, 4, 12), (2, 2, 2, 2)]
     Us = [orc.generate_links(d, 120 + i, 0.3) for i, d in enumerate(dims)]
     for kw in (dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
                     finish_format=lgf.LGF_FP64_12, fixed_links=1),
+               dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                    finish_format=lgf.LGF_FP64_12S, fixed_links=1),
                dict(omega=1.7, theta_target=1e-12, fixed_links=1)):
         with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
             lgf.lgf_ensemble_set_tuning(ens.e, tile, 1, 1)
@@ -300,6 +303,12 @@ def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
                 ref = lat.store()
             assert r1["sweeps"] == res[i]["sweeps"] and r1["sweeps_bulk"] == res[i]["sweeps_bulk"], (kw, i)
             assert np.array_equal(ref, got[i]), (kw, i, maxabs(ref, got[i]))
+            if kw.get("finish_format") == lgf.LGF_FP64_12S:
+                # both from one FP64 measurement of the same links (summation
+                # orders of the two drivers' reductions differ)
+                F, th = orc.measure(d, got[i])
+                assert abs(res[i]["F"] - F) <= 1e-13 and abs(res[i]["theta"] - th) <= 1e-8 * th + 1e-20
+                assert abs(r1["F"] - res[i]["F"]) <= 1e-13
 
 
 def test_ensemble_fixed_fused_and_graph(lgf, orc):

@@ -247,8 +247,9 @@ def test_split_large_lattice_beyond_32bit_vector_indices(lgf, orc):
 
 def test_split_argument_checks(lgf, orc):
     """LGF_FP64_12S is a sweep format of the fixed-link form only: not a
-    handle's format, not for the link-rewriting sweeps (Landau or Coulomb),
-    the link-sweep tuning or the ensembles."""
+    handle's format, not for the link-rewriting sweeps (Landau, Coulomb,
+    ensembles) or the link-sweep tuning; an ensemble takes it as the finish
+    after an FP32-12 bulk or alone."""
     dims = (4, 4, 4, 4)
     announce("split checks")
     with pytest.raises(lgf.LgfError):
@@ -269,9 +270,11 @@ def test_split_argument_checks(lgf, orc):
                                    bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
         assert st == 0 and res["theta"] < 1e-13
     with lgf.Ensemble([dims, dims], lgf.LGF_FP64_18) as ens:
-        with pytest.raises(lgf.LgfError):
-            ens.gauge_fix(omega=1.7, fixed_links=1, bulk_format=lgf.LGF_FP64_12S,
-                          finish_format=lgf.LGF_FP64_12S)
+        with pytest.raises(lgf.LgfError):   # link-rewriting form
+            ens.gauge_fix(omega=1.7, bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
+        with pytest.raises(lgf.LgfError):   # split bulk before an FP32 finish: no such pair
+            ens.gauge_fix(omega=1.7, fixed_links=1, theta_switch=1e-8, bulk_format=lgf.LGF_FP64_12S,
+                          finish_format=lgf.LGF_FP32_12)
 
 
 # ------------------------------------------------------------ Coulomb gauge
