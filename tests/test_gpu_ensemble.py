@@ -311,11 +311,15 @@ def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
                 assert abs(r1["F"] - res[i]["F"]) <= 1e-13
 
 
-def test_ensemble_fixed_fused_and_graph(lgf, orc):
+@pytest.mark.parametrize("split", [False, True])
+def test_ensemble_fixed_fused_and_graph(lgf, orc, split):
     """Fixed-link ensemble: the fused measurement against two read-only passes,
     and graph replays against direct launches (stochastic relaxation, whose
-    counter the graph reads from device memory): the same sweeps and links."""
-    announce("ensemble fixed fused/graph")
+    counter the graph reads from device memory): the same sweeps and links.
+    With `split` the finish reads the split links (FP64-12S), and the graph
+    pair runs the mixed FP32-12 / FP64-12S fixing too."""
+    announce("ensemble fixed fused/graph", split)
+    finish = lgf.LGF_FP64_12S if split else lgf.LGF_FP64_12
     dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8)]
     Us = [orc.generate_links(d, 130 + i, 0.3) for i, d in enumerate(dims)]
     runs = {"fused": [dict(separate_measure=1), dict(separate_measure=0)],
@@ -324,10 +328,12 @@ def test_ensemble_fixed_fused_and_graph(lgf, orc):
         outs = []
         for extra in pair:
             kw = dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
-                      finish_format=lgf.LGF_FP64_12, fixed_links=1)
+                      finish_format=finish, fixed_links=1)
             kw.update(extra)
             if "p_sr" in extra:
-                kw.update(theta_target=1e-10, bulk_format=-1, finish_format=-1, theta_switch=0.0)
+                kw.update(theta_target=1e-10)
+                if not split:
+                    kw.update(bulk_format=-1, finish_format=-1, theta_switch=0.0)
             with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
                 for i, U in enumerate(Us):
                     ens.load(i, U)
