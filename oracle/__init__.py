@@ -80,6 +80,10 @@ def _load():
         "orc_half_sweep_coulomb": (None, [P, P, I, D, D, U64, U64, U32, P]),
         "orc_measure_coulomb": (None, [P, P, P, P]),
         "orc_coulomb_gauge_fix": (I, [P, P, D, D, D, I, I, I64, U64, U32, P, P, P, P]),
+        "orc_su2_heatbath": (I, [P, D, U64, I64, U64, U32, I, P]),
+        "orc_half_sweep_sa": (I64, [P, P, I, D, U64, U64, U32]),
+        "orc_anneal_temperature": (D, [I64, I64, D, D]),
+        "orc_anneal": (I64, [P, P, I64, D, D, U64, U64, U32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -320,6 +324,40 @@ def coulomb_gauge_fix(dims, U: np.ndarray, omega: float, theta_target: float, p:
                                        _ptr(sw), _ptr(F), _ptr(th), _ptr(tot))
     return {"status": int(st), "sweeps": int(tot[0]), "sweeps_t": sw.astype(np.int64), "F_t": F,
             "theta_t": th}
+
+
+# ---------------------------------------------------------------- simulated annealing
+
+def su2_heatbath(w: np.ndarray, T: float, seed: int, s: int, sweep: int, instance: int = 0, k: int = 0):
+    """Heat-bath draw for one subgroup block w (2x2 complex) at temperature T,
+    from Philox counter (s, sweep, instance, tag of subgroup k).  Returns
+    (quaternion r, accept-reject trials used)."""
+    w = np.asarray(w, dtype=np.complex128).reshape(2, 2)
+    wv = np.ascontiguousarray(np.array([w[0, 0].real, w[0, 0].imag, w[0, 1].real, w[0, 1].imag,
+                                        w[1, 0].real, w[1, 0].imag, w[1, 1].real, w[1, 1].imag]))
+    out = np.zeros(4, dtype=np.float64)
+    n = _load().orc_su2_heatbath(_ptr(wv), T, seed, s, sweep, instance, k, _ptr(out))
+    return out, int(n)
+
+
+def half_sweep_sa(dims, U: np.ndarray, parity: int, T: float, seed: int = 0, sweep: int = 0,
+                  instance: int = 0) -> int:
+    """One annealing half-sweep at temperature T; returns the accept-reject trials."""
+    _links_arg(U)
+    return int(_load().orc_half_sweep_sa(_ptr(_dims(dims)), _ptr(U), parity, T, seed, sweep, instance))
+
+
+def anneal_temperature(n: int, n_sweeps: int, T_start: float, T_end: float) -> float:
+    return float(_load().orc_anneal_temperature(n, n_sweeps, T_start, T_end))
+
+
+def anneal(dims, U: np.ndarray, n_sweeps: int, T_start: float, T_end: float, seed: int = 0,
+           sweep0: int = 0, instance: int = 0) -> int:
+    """n_sweeps annealing sweeps with the linear schedule (reunitarized every 20
+    sweeps and at the end); returns the accept-reject trials."""
+    _links_arg(U)
+    return int(_load().orc_anneal(_ptr(_dims(dims)), _ptr(U), n_sweeps, T_start, T_end, seed, sweep0,
+                                  instance))
 
 
 def num_threads() -> int:

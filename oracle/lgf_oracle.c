@@ -782,6 +782,196 @@ double orc_plaquette(const int dims[4], const double *U)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Simulated annealing.  The paper lists it among the supported methods        */
+/* (Sec. 1) without its details, which it leaves to a reference not included. */
+/* Reading used here: the SU(2) step of each Cabibbo-Marinari subgroup draws   */
+/* r from the Boltzmann weight exp(Re tr[s(r) w] / T) on SU(2) (a heat bath at */
+/* temperature T for the local functional of Eq. (7)); T falls linearly over   */
+/* the annealing sweeps, and overrelaxation then takes the result to the gauge */
+/* precision (Sec. 4).                                                         */
+/* ------------------------------------------------------------------------ */
+
+#define SA_TRIALS 64      /* accept-reject attempts per subgroup step */
+#define SA_SWITCH 0.7     /* alpha below which the uniform proposal is used */
+
+/* A uniform variate in (0,1) from one Philox word: (w + 1/2) 2^-32. */
+static double unit_uniform(uint32_t w) { return ((double)w + 0.5) / 4294967296.0; }
+
+/* Philox tag (fourth counter word) of trial t of subgroup k, and of the
+ * subgroup's direction draw (t = 0xFFFF). */
+static uint32_t sa_tag(int k, uint32_t t) { return ((uint32_t)(k + 1) << 16) | t; }
+
+/* x0 in [-1, 1] with density proportional to sqrt(1 - x0^2) exp(alpha x0):
+ * the component along the maximum of an SU(2) element drawn from
+ * exp(alpha <x, 1>) times the Haar measure (the Haar measure of SU(2) = S^3
+ * gives x0 the density sqrt(1 - x0^2)).  Each trial uses the words of one
+ * Philox call keyed by the seed with counter (site, sweep, instance,
+ * sa_tag(k, trial)).
+ *  - alpha >= SA_SWITCH, Kennedy-Pendleton (Phys. Lett. B 156 (1985) 393):
+ *    x0 = 1 - 2 l with l = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha), a
+ *    Gamma(3/2) variate of rate 2 alpha, accepted when u4^2 <= 1 - l.
+ *  - alpha < SA_SWITCH: x0 = 2 u1 - 1 accepted when
+ *    u2^2 <= (1 - x0^2) exp(2 alpha (x0 - 1)).
+ * Both accept at least 40 % of trials for every alpha.  Returns the trials
+ * used; when all SA_TRIALS fail (probability below 1e-14) x0 = 1 and the
+ * count is SA_TRIALS + 1. */
+static int heatbath_x0(double alpha, uint64_t seed, uint32_t s, uint32_t sweep, uint32_t instance, int k,
+                       double *x0)
+{
+    for (uint32_t t = 0; t < SA_TRIALS; ++t) {
+        uint32_t w[4];
+        philox_seeded(seed, s, sweep, instance, sa_tag(k, t), w);
+        const double u1 = unit_uniform(w[0]), u2 = unit_uniform(w[1]);
+        const double u3 = unit_uniform(w[2]), u4 = unit_uniform(w[3]);
+        if (alpha >= SA_SWITCH) {
+            const double c = cos(2.0 * M_PI * u2);
+            const double l = -(log(u1) + c * c * log(u3)) / (2.0 * alpha);
+            if (u4 * u4 <= 1.0 - l) {
+                *x0 = 1.0 - 2.0 * l;
+                return (int)t + 1;
+            }
+        } else {
+            const double x = 2.0 * u1 - 1.0;
+            if (u2 * u2 <= (1.0 - x * x) * exp(2.0 * alpha * (x - 1.0))) {
+                *x0 = x;
+                return (int)t + 1;
+            }
+        }
+    }
+    *x0 = 1.0;
+    return SA_TRIALS + 1;
+}
+
+/* The heat-bath step of one subgroup.  w as in orc_su2_step; with a its
+ * quaternion projection, Re tr[s(r) w] = 2 |a| <r, b>, b = (a0, -a)/|a| the
+ * maximum of Eq. (9) (b = 1 when a = 0).  Writing r = x b (quaternion
+ * product, s(r) = s(x) s(b)), <r, b> = x0 and the Haar measure is unchanged,
+ * so x is drawn from exp(alpha x0) dHaar(x) with alpha = 2 |a| / T: x0 by
+ * heatbath_x0, the direction of (x1, x2, x3) uniform on the sphere of radius
+ * sqrt(1 - x0^2) (cos theta = 2 v1 - 1, phi = 2 pi v2 from the words of the
+ * call with tag sa_tag(k, 0xFFFF)).  Returns the accept-reject trials used;
+ * r = (r0, r1, r2, r3). */
+int orc_su2_heatbath(const double w[8], double T, uint64_t seed, int64_t s, uint64_t sweep,
+                     uint32_t instance, int k, double r[4])
+{
+    double a0 = 0.5 * (w[0] + w[6]);
+    double a3 = 0.5 * (w[1] - w[7]);
+    double a1 = 0.5 * (w[3] + w[5]);
+    double a2 = 0.5 * (w[2] - w[4]);
+    double na = sqrt(a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3);
+    double b0 = 1.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    if (na > 0.0) { b0 = a0 / na; b1 = -a1 / na; b2 = -a2 / na; b3 = -a3 / na; }
+    const double alpha = 2.0 * na / T;
+    double x0;
+    const int trials = heatbath_x0(alpha, seed, (uint32_t)s, (uint32_t)sweep, instance, k, &x0);
+    uint32_t v[4];
+    philox_seeded(seed, (uint32_t)s, (uint32_t)sweep, instance, sa_tag(k, 0xFFFFu), v);
+    const double ct = 2.0 * unit_uniform(v[0]) - 1.0;
+    const double phi = 2.0 * M_PI * unit_uniform(v[1]);
+    const double st = sqrt(1.0 - ct * ct);
+    const double rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
+    const double x1 = rad * st * cos(phi), x2 = rad * st * sin(phi), x3 = rad * ct;
+    /* s(x) s(b) = (x0 b0 - x.b) + i (x0 b + b0 x - x cross b).sigma */
+    r[0] = x0 * b0 - (x1 * b1 + x2 * b2 + x3 * b3);
+    r[1] = x0 * b1 + b0 * x1 - (x2 * b3 - x3 * b2);
+    r[2] = x0 * b2 + b0 * x2 - (x3 * b1 - x1 * b3);
+    r[3] = x0 * b3 + b0 * x3 - (x1 * b2 - x2 * b1);
+    return trials;
+}
+
+/* The annealing update of one site: K(x) as in the local update (Eq. (8)),
+ * the three subgroups in order with the heat-bath step, G applied to the 8
+ * links.  Returns the accept-reject trials of the three steps. */
+static int64_t local_update_sa(double *links, double T, uint64_t seed, int64_t s, uint64_t sweep,
+                               uint32_t instance)
+{
+    static const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    mat3 K = mat_zero();
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3 uf = mat_load(links + 18 * mu);
+        mat3 ub = mat_load(links + 18 * (4 + mu));
+        mat3 ubd = mat_dag(&ub);
+        K = mat_add(&K, &uf);
+        K = mat_add(&K, &ubd);
+    }
+    mat3 W = K, G = mat_identity();
+    int64_t trials = 0;
+    for (int k = 0; k < 3; ++k) {
+        int i = sub[k][0], j = sub[k][1];
+        double w[8] = {creal(W.m[i][i]), cimag(W.m[i][i]), creal(W.m[i][j]), cimag(W.m[i][j]),
+                       creal(W.m[j][i]), cimag(W.m[j][i]), creal(W.m[j][j]), cimag(W.m[j][j])};
+        double r[4];
+        trials += orc_su2_heatbath(w, T, seed, s, sweep, instance, k, r);
+        mat3 R = su2_embed(r, i, j);
+        W = mat_mul(&R, &W);
+        G = mat_mul(&R, &G);
+    }
+    mat3 Gd = mat_dag(&G);
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3 uf = mat_load(links + 18 * mu);
+        mat3 ub = mat_load(links + 18 * (4 + mu));
+        mat3 nf = mat_mul(&G, &uf);
+        mat3 nb = mat_mul(&ub, &Gd);
+        mat_store(&nf, links + 18 * mu);
+        mat_store(&nb, links + 18 * (4 + mu));
+    }
+    return trials;
+}
+
+/* One annealing half-sweep at temperature T: every site of the parity gets
+ * its heat-bath update (same-parity sites share no link, Sec. 3).  Returns the
+ * total accept-reject trials. */
+int64_t orc_half_sweep_sa(const int dims[4], double *U, int parity, double T, uint64_t seed,
+                          uint64_t sweep, uint32_t instance)
+{
+    lattice lat = make_lattice(dims);
+    int64_t trials = 0;
+    #pragma omp parallel for schedule(static) reduction(+:trials)
+    for (int64_t s = 0; s < lat.V; ++s) {
+        if (site_parity(&lat, s) != parity) continue;
+        double links[8 * 18];
+        int64_t back[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            back[mu] = site_neighbor(&lat, s, mu, -1);
+            memcpy(links + 18 * mu, link_cptr(U, s, mu), 18 * sizeof(double));
+            memcpy(links + 18 * (4 + mu), link_cptr(U, back[mu], mu), 18 * sizeof(double));
+        }
+        trials += local_update_sa(links, T, seed, s, sweep, instance);
+        for (int mu = 0; mu < 4; ++mu) {
+            memcpy(link_ptr(U, s, mu), links + 18 * mu, 18 * sizeof(double));
+            memcpy(link_ptr(U, back[mu], mu), links + 18 * (4 + mu), 18 * sizeof(double));
+        }
+    }
+    return trials;
+}
+
+/* Temperature of annealing sweep n of n_sweeps: linear from T_start (n = 0)
+ * to T_end (n = n_sweeps - 1). */
+double orc_anneal_temperature(int64_t n, int64_t n_sweeps, double T_start, double T_end)
+{
+    if (n_sweeps <= 1) return T_start;
+    const double f = (double)n / (double)(n_sweeps - 1);
+    return T_start * (1.0 - f) + T_end * f;
+}
+
+/* n_sweeps annealing sweeps (parity 0, then 1) with the linear schedule; sweep
+ * n uses Philox counter sweep0 + n; the links are reunitarized after every
+ * 20 sweeps and at the end.  Returns the total accept-reject trials. */
+int64_t orc_anneal(const int dims[4], double *U, int64_t n_sweeps, double T_start, double T_end,
+                   uint64_t seed, uint64_t sweep0, uint32_t instance)
+{
+    lattice lat = make_lattice(dims);
+    int64_t trials = 0;
+    for (int64_t n = 0; n < n_sweeps; ++n) {
+        const double T = orc_anneal_temperature(n, n_sweeps, T_start, T_end);
+        trials += orc_half_sweep_sa(dims, U, 0, T, seed, sweep0 + (uint64_t)n, instance);
+        trials += orc_half_sweep_sa(dims, U, 1, T, seed, sweep0 + (uint64_t)n, instance);
+        if ((n + 1) % 20 == 0 || n + 1 == n_sweeps) orc_reunitarize(lat.V * 4, U);
+    }
+    return trials;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Iterate until the requested precision (Sec. 4)                             */
 /* ------------------------------------------------------------------------ */
 
