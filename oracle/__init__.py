@@ -82,6 +82,7 @@ def _load():
         "orc_coulomb_gauge_fix": (I, [P, P, D, D, D, I, I, I64, U64, U32, P, P, P, P]),
         "orc_su2_heatbath": (I, [P, D, U64, I64, U64, U32, I, P]),
         "orc_half_sweep_sa": (I64, [P, P, I, D, U64, U64, U32]),
+        "orc_local_update_sa": (I64, [P, D, U64, I64, U64, U32]),
         "orc_anneal_temperature": (D, [I64, I64, D, D]),
         "orc_anneal": (I64, [P, P, I64, D, D, U64, U64, U32]),
     }
@@ -338,6 +339,14 @@ def su2_heatbath(w: np.ndarray, T: float, seed: int, s: int, sweep: int, instanc
     out = np.zeros(4, dtype=np.float64)
     n = _load().orc_su2_heatbath(_ptr(wv), T, seed, s, sweep, instance, k, _ptr(out))
     return out, int(n)
+
+
+def local_update_sa(links8: np.ndarray, T: float, seed: int, s: int, sweep: int, instance: int = 0):
+    """Annealing update of the 8 links of site s (forward then backward);
+    returns (updated links8, trials)."""
+    L = np.ascontiguousarray(np.array(links8, dtype=np.complex128).reshape(8, 3, 3))
+    n = _load().orc_local_update_sa(_ptr(L), T, seed, s, sweep, instance)
+    return L, int(n)
 
 
 def half_sweep_sa(dims, U: np.ndarray, parity: int, T: float, seed: int = 0, sweep: int = 0,

@@ -918,6 +918,15 @@ static int64_t local_update_sa(double *links, double T, uint64_t seed, int64_t s
     return trials;
 }
 
+/* The annealing update of the 8 links of site s (forward, then backward, as
+ * in orc_local_update) with the Philox counters of site s; returns the
+ * trials. */
+int64_t orc_local_update_sa(double *links, double T, uint64_t seed, int64_t s, uint64_t sweep,
+                            uint32_t instance)
+{
+    return local_update_sa(links, T, seed, s, sweep, instance);
+}
+
 /* One annealing half-sweep at temperature T: every site of the parity gets
  * its heat-bath update (same-parity sites share no link, Sec. 3).  Returns the
  * total accept-reject trials. */
