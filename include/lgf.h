@@ -104,7 +104,11 @@ typedef struct {
                               handle; accumulate_g is implied.  The sweep formats may include
                               LGF_FP64_12S; when the last sweeps ran in it, the result's F and theta
                               (and the stopping test) come from one more measurement on the
-                              transformed FP64 links.  0 (default): the sweeps rewrite the links. */
+                              transformed FP64 links (one more history entry); if that one is not
+                              below theta_target, the sweeps go on in FP64-12 from the transformed
+                              links (g restarting at 1) while max_sweeps allows.  FP64-12 and
+                              LGF_FP64_12S may be paired as bulk and finish in either order.
+                              0 (default): the sweeps rewrite the links. */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
     uint64_t sweep_offset; /* counter value of the first sweep (for resumed runs) */
@@ -231,6 +235,62 @@ lgf_status lgf_plaquette(lgf_lattice *h, double *P);
  * every case. */
 lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_result *result,
                          double *history, int history_cap);
+
+/* Stepwise gauge fixing in the fixed-link form, for callers that drive the
+ * iteration of Sec. 4 themselves (sweep the two parities in turn, check theta
+ * of Eq. (5) every few sweeps, stop at a precision of their choosing).
+ * lgf_fix_begin opens a session on an FP64 handle: the gauge transformation
+ * g (a site field owned by the handle, in the sweep format's precision;
+ * FP64-12 for LGF_FP64_12S) is set to 1 and the read-only links are prepared
+ * in `format` (any format of lgf_fix_params.fixed_links, LGF_FP64_12S
+ * included); it allocates what the session needs on the first call
+ * (LGF_ENOMEM).  lgf_fix_chunk runs n full sweeps (parity 0, then 1) with
+ * overrelaxation omega in [1, 2] or stochastic relaxation p_sr in [0, 1]
+ * (Philox key `seed`, counters sweep0 .. sweep0+n-1), captured in a hipGraph
+ * when use_graph is set; its last sweep stores every g reunitarized, and F
+ * (Eq. (2)) and theta (Eq. (5)) of the links g(x) U(x) g(x+mu)^dag are
+ * measured in FP64 (for LGF_FP64_12S on the split links, within 2^-40 of the
+ * FP64 ones) and returned; *sweep_ms (may be NULL) gets the time of the n
+ * sweeps from HIP events on the handle's stream.  Synchronises.  LGF_ENUMERIC
+ * when F or theta is not finite.  lgf_fix_end writes g U g^dag (from the
+ * untouched input) into the handle's field and closes the session.  Any call
+ * that loads, generates, converts, sweeps, tunes or gauge-fixes the handle
+ * closes the session without applying g; lgf_fix_chunk and lgf_fix_end then
+ * return LGF_ESTATE. */
+lgf_status lgf_fix_begin(lgf_lattice *h, int format);
+lgf_status lgf_fix_chunk(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed, uint64_t sweep0,
+                         int use_graph, double *F, double *theta, double *sweep_ms);
+lgf_status lgf_fix_end(lgf_lattice *h);
+
+/* Simulated annealing.  The paper names it among the supported methods
+ * (Sec. 1) and leaves its heat bath and schedule to a reference; the reading
+ * implemented here: the site update of Sec. 3 (K(x) of Eq. (8), the three
+ * Cabibbo-Marinari subgroups in order, G applied to the 8 links) with the
+ * SU(2) step of each subgroup drawn from the Boltzmann weight
+ * exp(Re tr[s(r) w] / T) against the SU(2) Haar measure, a heat bath for the
+ * local functional of Eq. (7) at temperature T.  As T -> 0 the draw becomes
+ * the maximum of Eq. (9).  The draw writes r = x b with b that maximum,
+ * x0 = <r, b> of density sqrt(1 - x0^2) exp(alpha x0), alpha = 2|a|/T (a the
+ * quaternion projection of the block): Kennedy-Pendleton above alpha = 0.7, a
+ * uniform proposal below, at most 64 trials (then x = 1); (x1, x2, x3)
+ * uniform on the sphere.  Random words: Philox4x32-10 keyed by `seed`, counter
+ * (site index, sweep, 0, ((k + 1) << 16) | trial) for subgroup k, trial 0xFFFF
+ * for the direction.  FP64 arithmetic; FP64 handles only (LGF_EINVAL
+ * otherwise).
+ * lgf_anneal_sweep: one heat-bath half-sweep (parity 0 or 1) or full sweep
+ * (2: parity 0, then 1) at temperature T > 0 with counter sweep_index;
+ * *trials (may be NULL; then the call does not synchronise) receives the
+ * accept-reject trials of the call.
+ * lgf_anneal: n_sweeps >= 1 full sweeps with T falling linearly from T_start
+ * (first sweep) to T_end (last), sweep n taking counter sweep0 + n; the links
+ * are reunitarized after every 20 sweeps and after the last one.  *trials and
+ * *ms (each may be NULL) receive the trials and the time of the sweeps (HIP
+ * events on the handle's stream).  Synchronises.  Anneal first, then fix the
+ * gauge with lgf_gauge_fix (overrelaxation to the target precision). */
+lgf_status lgf_anneal_sweep(lgf_lattice *h, int parity, double T, uint64_t seed, uint64_t sweep_index,
+                            uint64_t *trials);
+lgf_status lgf_anneal(lgf_lattice *h, int64_t n_sweeps, double T_start, double T_end, uint64_t seed,
+                      uint64_t sweep0, uint64_t *trials, double *ms);
 
 /* Block until all work queued on the handle's stream has finished. */
 lgf_status lgf_synchronize(lgf_lattice *h);

@@ -8,6 +8,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -16,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblgf.so")
 
-SOURCES = ["lgf_kernels.hip", "lgf_fixed.hip", "lgf_ensemble_kernels.hip", "lgf_util.hip", "lgf_api.cpp", "lgf_ensemble_api.cpp"]
+SOURCES = ["lgf_kernels.hip", "lgf_fixed.hip", "lgf_ensemble_kernels.hip", "lgf_util.hip", "lgf_anneal.hip",
+           "lgf_api.cpp", "lgf_ensemble_api.cpp"]
 
 ARCH = "gfx950"
 
@@ -44,15 +46,22 @@ def _hipcc() -> str:
 def build(verbose: bool = False, extra_flags=()) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, "-x", "hip", *HIP_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc, "-x", "hip", *HIP_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+        for f in [pool.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB_PATH + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -151,6 +151,12 @@ struct lgf_lattice {
     void *gfix[4];
     lgf::SweepTuning tune_fixed[5];  // per sweep format, LGF_FP64_12S included
     void *split;       // the links in the split storage of LGF_FP64_12S (owned)
+    // stepwise fixed-link gauge fixing (lgf_fix_begin .. lgf_fix_end)
+    bool fix_on;
+    int fix_format;
+    const void *fix_links;
+    // accept-reject trial counter of the annealing sweeps (lazily)
+    unsigned long long *d_trials;
 };
 
 namespace {
@@ -785,62 +791,87 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
         started = true;
     }
     const bool fuse = !p.separate_measure;
-    while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
-        const int64_t left = p.max_sweeps - sweeps;
-        const int n = (int)(left < p.check_every ? left : p.check_every);
-        LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
-            return run_chunk_fixed(h, cur, links, gfix_of(h, cur), n, p.omega, p.p_sr, p.seed, ctr,
-                                   p.use_graph != 0, fuse);
-        }));
-        if (in_bulk) sweeps_bulk += n;
-        sweeps += n;
-        ctr += (uint64_t)n;
-        LGF_TRY(timed(res->t_measure_ms,
-                      [&]() { return measure_fixed_field(h, cur, links, gfix_of(h, cur), fuse, &F, &theta); }));
-        record(sweeps, F, theta);
-        if (!std::isfinite(F) || !std::isfinite(theta)) {
-            status = LGF_ENUMERIC;
-            break;
+    for (;;) {
+        while (status == LGF_ENOTCONV && sweeps < p.max_sweeps) {
+            const int64_t left = p.max_sweeps - sweeps;
+            const int n = (int)(left < p.check_every ? left : p.check_every);
+            LGF_TRY(timed(in_bulk ? res->t_sweep_bulk_ms : res->t_sweep_finish_ms, [&]() {
+                return run_chunk_fixed(h, cur, links, gfix_of(h, cur), n, p.omega, p.p_sr, p.seed, ctr,
+                                       p.use_graph != 0, fuse);
+            }));
+            if (in_bulk) sweeps_bulk += n;
+            sweeps += n;
+            ctr += (uint64_t)n;
+            LGF_TRY(timed(res->t_measure_ms,
+                          [&]() { return measure_fixed_field(h, cur, links, gfix_of(h, cur), fuse, &F, &theta); }));
+            record(sweeps, F, theta);
+            if (!std::isfinite(F) || !std::isfinite(theta)) {
+                status = LGF_ENUMERIC;
+                break;
+            }
+            if (in_bulk && (theta < p.theta_switch || theta < p.theta_target)) {
+                // the finish precision starts from the bulk's g, reunitarized in
+                // FP64, on the links of its own format (the input itself when the
+                // formats agree)
+                LGF_TRY(ensure_gfix(h, finish));
+                LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+                    LGF_TRY(links_in_format(h, finish, &links));
+                    // FP64-12 and the split format share one g field (stored
+                    // reunitarized by the chunk's last sweep): nothing to hand over
+                    if (gf_format(bulk) != gf_format(finish))
+                        LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gfix_of(h, bulk), gf_format(finish),
+                                                         gfix_of(h, finish), h->geom, h->stream));
+                    return LGF_OK;
+                }));
+                cur = finish;
+                in_bulk = false;
+                if (theta < p.theta_target) {
+                    LGF_TRY(timed(res->t_measure_ms, [&]() {
+                        return measure_fixed_field(h, cur, links, gfix_of(h, cur), false, &F, &theta);
+                    }));
+                    record(sweeps, F, theta);
+                } else {
+                    continue;
+                }
+            }
+            if (!in_bulk && theta < p.theta_target) status = LGF_OK;
         }
-        if (in_bulk && (theta < p.theta_switch || theta < p.theta_target)) {
-            // the finish precision starts from the bulk's g, reunitarized in
-            // FP64, on the links of its own format (the input itself when the
-            // formats agree)
-            LGF_TRY(ensure_gfix(h, finish));
+        if (started) {
+            // the links in the final gauge, from the untouched input (element-wise
+            // per link, so in place)
             LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-                LGF_TRY(links_in_format(h, finish, &links));
-                LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gfix_of(h, bulk), gf_format(finish),
-                                                 gfix_of(h, finish), h->geom, h->stream));
+                LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, gf_format(cur), gfix_of(h, cur), h->format,
+                                                    h->field, h->geom, h->stream));
                 return LGF_OK;
             }));
-            cur = finish;
-            in_bulk = false;
-            if (theta < p.theta_target) {
-                LGF_TRY(timed(res->t_measure_ms, [&]() {
-                    return measure_fixed_field(h, cur, links, gfix_of(h, cur), false, &F, &theta);
-                }));
+            if (cur == LGF_FP64_12S) {
+                // the sweeps measured on the split links (within 2^-40 of the
+                // input's): F and theta of the result from the FP64 links themselves
+                LGF_TRY(timed(res->t_measure_ms,
+                              [&]() { return measure_field(h, h->format, h->field, false, &F, &theta); }));
                 record(sweeps, F, theta);
-            } else {
-                continue;
+                if (!std::isfinite(F) || !std::isfinite(theta)) {
+                    status = LGF_ENUMERIC;
+                } else if (status == LGF_OK && !(theta < p.theta_target)) {
+                    // the split links' fixed point is not yet below the target on
+                    // the FP64 links: go on in FP64-12 from the transformed links,
+                    // g starting again at 1, while max_sweeps allows
+                    status = LGF_ENOTCONV;
+                    if (sweeps < p.max_sweeps) {
+                        LGF_TRY(ensure_gfix(h, LGF_FP64_12));
+                        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
+                            LGF_TRY(links_in_format(h, LGF_FP64_12, &links));
+                            LGF_HIP(lgf::launch_site_field(LGF_FP64_12, gfix_of(h, LGF_FP64_12), h->geom, 0,
+                                                           h->stream));
+                            return LGF_OK;
+                        }));
+                        cur = LGF_FP64_12;
+                        continue;
+                    }
+                }
             }
         }
-        if (!in_bulk && theta < p.theta_target) status = LGF_OK;
-    }
-    if (started) {
-        // the links in the final gauge, from the untouched input (element-wise
-        // per link, so in place)
-        LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-            LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, gf_format(cur), gfix_of(h, cur), h->format,
-                                                h->field, h->geom, h->stream));
-            return LGF_OK;
-        }));
-        if (cur == LGF_FP64_12S) {
-            // the sweeps measured on the split links (within 2^-40 of the
-            // input's): F and theta of the result from the FP64 links themselves
-            LGF_TRY(timed(res->t_measure_ms,
-                          [&]() { return measure_field(h, h->format, h->field, false, &F, &theta); }));
-            if (status == LGF_OK && !(theta < p.theta_target)) status = LGF_ENOTCONV;
-        }
+        break;
     }
     res->sweeps = sweeps;
     res->sweeps_bulk = sweeps_bulk;
@@ -1113,6 +1144,7 @@ lgf_status lgf_destroy(lgf_lattice *h)
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_fused) (void)hipFree(h->d_fused);
     if (h->d_sweep_base) (void)hipFree(h->d_sweep_base);
+    if (h->d_trials) (void)hipFree(h->d_trials);
     if (h->d_out) (void)hipFree(h->d_out);
     if (h->h_out) (void)hipHostFree(h->h_out);
     if (h->d_stage) (void)hipFree(h->d_stage);
@@ -1142,6 +1174,7 @@ lgf_status lgf_get_info(const lgf_lattice *h, int dims[4], int *format)
 lgf_status lgf_load_links(lgf_lattice *h, const double *host_canon, size_t n_doubles)
 {
     if (!h || !host_canon) return fail(LGF_EINVAL, "NULL handle or host array");
+    h->fix_on = false;
     if (n_doubles != (size_t)h->V * 72)
         return fail(LGF_EINVAL, "host array has %zu doubles, the lattice needs %lld", n_doubles,
                     (long long)h->V * 72);
@@ -1203,6 +1236,7 @@ lgf_status lgf_peek_links(lgf_lattice *h, const int64_t *sites, int64_t n_sites,
 lgf_status lgf_generate_links(lgf_lattice *h, uint64_t seed, double eps, int haar)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(LGF_EINVAL, "eps must be finite and >= 0");
     LGF_TRY(use_device(h));
     LGF_HIP(lgf::launch_generate(h->format, h->field, h->geom, seed, eps, haar != 0, h->stream));
@@ -1212,6 +1246,7 @@ lgf_status lgf_generate_links(lgf_lattice *h, uint64_t seed, double eps, int haa
 lgf_status lgf_convert(lgf_lattice *h, int format)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (format == h->format) return LGF_OK;
     if (!h->owned) return fail(LGF_ESTATE, "cannot change the format of a borrowed buffer");
@@ -1241,6 +1276,7 @@ lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint
                      uint64_t sweep_index)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
     if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
@@ -1257,6 +1293,7 @@ lgf_status lgf_sweep(lgf_lattice *h, int parity, double omega, double p_sr, uint
 lgf_status lgf_reunitarize(lgf_lattice *h)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     LGF_TRY(use_device(h));
     LGF_HIP(lgf::launch_convert(h->format, h->field, h->format, h->field, h->geom, true, h->stream));
     return LGF_OK;
@@ -1281,6 +1318,7 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
                          int history_cap)
 {
     if (!h || !pp || !res) return fail(LGF_EINVAL, "NULL handle, params or result");
+    h->fix_on = false;
     const lgf_fix_params p = *pp;
     if (!(p.omega >= 1.0 && p.omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", p.omega);
     if (!(p.p_sr >= 0.0 && p.p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p.p_sr);
@@ -1459,6 +1497,146 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_fix_resul
     return LGF_OK;
 }
 
+lgf_status lgf_fix_begin(lgf_lattice *h, int format)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
+    if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
+    if (h->format != LGF_FP64_18 && h->format != LGF_FP64_12)
+        return fail(LGF_EINVAL, "the fixed-link form needs an FP64 handle");
+    LGF_TRY(use_device(h));
+    void *links = nullptr;
+    LGF_TRY(ensure_gfix(h, format));
+    LGF_TRY(links_in_format(h, format, &links));
+    LGF_HIP(lgf::launch_site_field(gf_format(format), gfix_of(h, format), h->geom, 0, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    h->fix_format = format;
+    h->fix_links = links;
+    h->fix_on = true;
+    return LGF_OK;
+}
+
+lgf_status lgf_fix_chunk(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed, uint64_t sweep0,
+                         int use_graph, double *F, double *theta, double *sweep_ms)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!h->fix_on) return fail(LGF_ESTATE, "no stepwise gauge fixing open (lgf_fix_begin)");
+    if (n < 1) return fail(LGF_EINVAL, "n must be >= 1");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(use_device(h));
+    const int fmt = h->fix_format;
+    void *gf = gfix_of(h, fmt);
+    LGF_HIP(hipEventRecord(h->ev0, h->stream));
+    LGF_TRY(run_chunk_fixed(h, fmt, h->fix_links, gf, n, omega, p_sr, seed, sweep0, use_graph != 0, true));
+    LGF_HIP(hipEventRecord(h->ev1, h->stream));
+    double f = 0.0, th = 0.0;
+    LGF_TRY(measure_fixed_field(h, fmt, h->fix_links, gf, true, &f, &th));
+    if (sweep_ms) *sweep_ms = elapsed_ms(h->ev0, h->ev1);
+    if (F) *F = f;
+    if (theta) *theta = th;
+    if (!std::isfinite(f) || !std::isfinite(th))
+        return fail(LGF_ENUMERIC, "F or theta is not finite (F=%g theta=%g)", f, th);
+    return LGF_OK;
+}
+
+lgf_status lgf_fix_end(lgf_lattice *h)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    if (!h->fix_on) return fail(LGF_ESTATE, "no stepwise gauge fixing open (lgf_fix_begin)");
+    h->fix_on = false;
+    LGF_TRY(use_device(h));
+    LGF_HIP(lgf::launch_gauge_transform(h->format, h->field, gf_format(h->fix_format), gfix_of(h, h->fix_format),
+                                        h->format, h->field, h->geom, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    return LGF_OK;
+}
+
+namespace {
+
+// checks shared by the annealing entry points; allocates the trial counter
+lgf_status anneal_ready(lgf_lattice *h)
+{
+    if (h->format != LGF_FP64_18 && h->format != LGF_FP64_12)
+        return fail(LGF_EINVAL, "simulated annealing needs an FP64 handle");
+    LGF_TRY(use_device(h));
+    if (!h->d_trials) {
+        if (hipMalloc(&h->d_trials, sizeof(unsigned long long)) != hipSuccess) {
+            h->d_trials = nullptr;
+            (void)hipGetLastError();
+            return fail(LGF_ENOMEM, "cannot allocate the trial counter");
+        }
+    }
+    return LGF_OK;
+}
+
+// the trial counter, read back (synchronises the stream)
+lgf_status read_trials(lgf_lattice *h, uint64_t *trials)
+{
+    LGF_HIP(hipMemcpyAsync(h->h_out, h->d_trials, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+    LGF_HIP(hipStreamSynchronize(h->stream));
+    unsigned long long v;
+    std::memcpy(&v, h->h_out, sizeof v);
+    *trials = (uint64_t)v;
+    return LGF_OK;
+}
+
+// temperature of annealing sweep n of n_sweeps, linear from T_start to T_end
+// (both ends exact)
+double anneal_temperature(int64_t n, int64_t n_sweeps, double T_start, double T_end)
+{
+#pragma clang fp contract(off)
+    if (n_sweeps <= 1) return T_start;
+    const double f = (double)n / (double)(n_sweeps - 1);
+    return T_start * (1.0 - f) + T_end * f;
+}
+
+}  // namespace
+
+lgf_status lgf_anneal_sweep(lgf_lattice *h, int parity, double T, uint64_t seed, uint64_t sweep_index,
+                            uint64_t *trials)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
+    if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(LGF_EINVAL, "temperature %g must be finite and > 0", T);
+    LGF_TRY(anneal_ready(h));
+    unsigned long long *ctr = trials ? h->d_trials : nullptr;
+    if (ctr) LGF_HIP(lgf::launch_set_u64(reinterpret_cast<uint64_t *>(ctr), 0, h->stream));
+    for (int p = 0; p < 2; ++p)
+        if (parity == 2 || parity == p)
+            LGF_HIP(lgf::launch_anneal(h->format, h->field, h->geom, p, T, seed, sweep_index, 0u, ctr, h->stream));
+    if (trials) LGF_TRY(read_trials(h, trials));
+    return LGF_OK;
+}
+
+lgf_status lgf_anneal(lgf_lattice *h, int64_t n_sweeps, double T_start, double T_end, uint64_t seed,
+                      uint64_t sweep0, uint64_t *trials, double *ms)
+{
+    if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
+    if (n_sweeps < 1) return fail(LGF_EINVAL, "n_sweeps must be >= 1");
+    if (!(T_start > 0.0) || !std::isfinite(T_start) || !(T_end > 0.0) || !std::isfinite(T_end))
+        return fail(LGF_EINVAL, "temperatures must be finite and > 0 (%g, %g)", T_start, T_end);
+    LGF_TRY(anneal_ready(h));
+    LGF_HIP(lgf::launch_set_u64(reinterpret_cast<uint64_t *>(h->d_trials), 0, h->stream));
+    LGF_HIP(hipEventRecord(h->ev0, h->stream));
+    for (int64_t n = 0; n < n_sweeps; ++n) {
+        const double T = anneal_temperature(n, n_sweeps, T_start, T_end);
+        for (int p = 0; p < 2; ++p)
+            LGF_HIP(lgf::launch_anneal(h->format, h->field, h->geom, p, T, seed, sweep0 + (uint64_t)n, 0u,
+                                       h->d_trials, h->stream));
+        if ((n + 1) % 20 == 0 || n + 1 == n_sweeps)
+            LGF_HIP(lgf::launch_convert(h->format, h->field, h->format, h->field, h->geom, true, h->stream));
+    }
+    LGF_HIP(hipEventRecord(h->ev1, h->stream));
+    uint64_t t = 0;
+    LGF_TRY(read_trials(h, &t));
+    if (trials) *trials = t;
+    if (ms) *ms = elapsed_ms(h->ev0, h->ev1);
+    return LGF_OK;
+}
+
 lgf_status lgf_plaquette(lgf_lattice *h, double *P)
 {
     if (!h || !P) return fail(LGF_EINVAL, "NULL handle or output");
@@ -1476,6 +1654,7 @@ lgf_status lgf_sweep_coulomb(lgf_lattice *h, int parity, double omega, double p_
                              uint64_t sweep_index, const unsigned char *slice_active)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (parity < 0 || parity > 2) return fail(LGF_EINVAL, "parity must be 0, 1 or 2 (both)");
     if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
@@ -1504,6 +1683,7 @@ lgf_status lgf_coulomb_gauge_fix(lgf_lattice *h, const lgf_fix_params *pp, lgf_f
                                  double *F_t, double *theta_t)
 {
     if (!h || !pp || !res) return fail(LGF_EINVAL, "NULL handle, params or result");
+    h->fix_on = false;
     const lgf_fix_params p = *pp;
     if (!(p.omega >= 1.0 && p.omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", p.omega);
     if (!(p.p_sr >= 0.0 && p.p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p.p_sr);
@@ -1757,6 +1937,7 @@ lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuni
 lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
     if (h->format != LGF_FP64_18 && h->format != LGF_FP64_12)
@@ -1818,6 +1999,7 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials)
 {
     if (!h) return fail(LGF_EINVAL, "handle is NULL");
+    h->fix_on = false;
     if (!valid_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     if (trials < 1) return fail(LGF_EINVAL, "trials must be >= 1");
     LGF_TRY(use_device(h));
@@ -1919,6 +2101,7 @@ lgf_status lgf_time_sweeps(lgf_lattice *h, int n, double omega, double p_sr, uin
                            uint64_t sweep_index, double *ms_per_launch)
 {
     if (!h || !ms_per_launch) return fail(LGF_EINVAL, "NULL handle or output");
+    h->fix_on = false;
     if (n < 1) return fail(LGF_EINVAL, "n must be >= 1");
     if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
     if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);

@@ -142,4 +142,10 @@ hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const
 size_t split_links_bytes(const Geom &g);
 hipError_t launch_split_links(int fs, const void *src, void *dst, const Geom &g, hipStream_t s);
 
+// Simulated annealing: one heat-bath half-sweep of the link-rewriting form at
+// temperature temp > 0 (FP64 formats only).  trials (device counter, may be
+// NULL) accumulates the accept-reject trials of the launch.
+hipError_t launch_anneal(int format, void *field, const Geom &g, int parity, double temp, uint64_t seed,
+                         uint64_t sweep, uint32_t instance, unsigned long long *trials, hipStream_t s);
+
 }  // namespace lgf

@@ -56,7 +56,7 @@ EXPORTS = [
     "lgf_generate_links", "lgf_convert", "lgf_sweep", "lgf_reunitarize", "lgf_measure",
     "lgf_gauge_fix", "lgf_synchronize", "lgf_set_tuning", "lgf_get_tuning", "lgf_autotune",
     "lgf_time_sweeps", "lgf_copy_bandwidth", "lgf_set_fixed_tuning", "lgf_get_fixed_tuning",
-    "lgf_autotune_fixed",
+    "lgf_autotune_fixed", "lgf_fix_begin", "lgf_fix_chunk", "lgf_fix_end", "lgf_anneal_sweep", "lgf_anneal",
 ]
 
 _lib = None
@@ -69,6 +69,15 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1305_3440_amd.build`")
+    # PyTorch brings its own HIP runtime and puts it in the global symbol
+    # scope.  liblgf.so must bind every HIP call to that same runtime, or the
+    # torch streams and device buffers handed across the boundary belong to
+    # another runtime than the library's kernels: import torch before the
+    # library is loaded (its HIP symbols then all resolve to torch's runtime).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I, I64, U64, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
                              ctypes.c_double, ctypes.c_size_t)
@@ -98,6 +107,11 @@ def load_library(path: str = LIB_PATH):
         "lgf_autotune": (I, [P, I, I]),
         "lgf_time_sweeps": (I, [P, I, D, D, U64, U64, P]),
         "lgf_copy_bandwidth": (I, [SZ, I, P, P]),
+        "lgf_fix_begin": (I, [P, I]),
+        "lgf_fix_chunk": (I, [P, I, D, D, U64, U64, I, P, P, P]),
+        "lgf_fix_end": (I, [P]),
+        "lgf_anneal_sweep": (I, [P, I, D, U64, U64, P]),
+        "lgf_anneal": (I, [P, I64, D, D, U64, U64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -286,6 +300,37 @@ def lgf_time_sweeps(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0,
     return ms.value
 
 
+def lgf_fix_begin(h, fmt: int) -> None:
+    _check(load_library().lgf_fix_begin(h, fmt))
+
+
+def lgf_fix_chunk(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0, sweep0: int = 0,
+                  use_graph: int = 1):
+    """Returns (F, theta, sweep_ms) after n sweeps of the open session."""
+    F, th, ms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().lgf_fix_chunk(h, n, omega, p_sr, seed, sweep0, use_graph, ctypes.byref(F),
+                                        ctypes.byref(th), ctypes.byref(ms)))
+    return F.value, th.value, ms.value
+
+
+def lgf_fix_end(h) -> None:
+    _check(load_library().lgf_fix_end(h))
+
+
+def lgf_anneal_sweep(h, parity: int, T: float, seed: int = 0, sweep_index: int = 0, count: bool = True):
+    """Returns the accept-reject trials (None when count is False)."""
+    n = ctypes.c_uint64()
+    _check(load_library().lgf_anneal_sweep(h, parity, T, seed, sweep_index, ctypes.byref(n) if count else None))
+    return n.value if count else None
+
+
+def lgf_anneal(h, n_sweeps: int, T_start: float, T_end: float, seed: int = 0, sweep0: int = 0):
+    """Returns (accept-reject trials, ms of the sweeps)."""
+    n, ms = ctypes.c_uint64(), ctypes.c_double()
+    _check(load_library().lgf_anneal(h, n_sweeps, T_start, T_end, seed, sweep0, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
 def fix_params(**kw) -> "lgf_fix_params":
     """lgf_fix_params_default() with the named fields replaced (unknown names raise)."""
     p = lgf_fix_params_default()
@@ -363,6 +408,21 @@ class Lattice:
 
     def plaquette(self):
         return lgf_plaquette(self.h)
+
+    def fix_begin(self, fmt):
+        lgf_fix_begin(self.h, fmt)
+
+    def fix_chunk(self, n, omega, p_sr=0.0, seed=0, sweep0=0, use_graph=1):
+        return lgf_fix_chunk(self.h, n, omega, p_sr, seed, sweep0, use_graph)
+
+    def fix_end(self):
+        lgf_fix_end(self.h)
+
+    def anneal_sweep(self, parity, T, seed=0, sweep_index=0, count=True):
+        return lgf_anneal_sweep(self.h, parity, T, seed, sweep_index, count)
+
+    def anneal(self, n_sweeps, T_start, T_end, seed=0, sweep0=0):
+        return lgf_anneal(self.h, n_sweeps, T_start, T_end, seed, sweep0)
 
     def sweep_coulomb(self, parity, omega, p_sr=0.0, seed=0, sweep_index=0, slice_active=None):
         lgf_sweep_coulomb(self.h, parity, omega, p_sr, seed, sweep_index, slice_active)

@@ -152,3 +152,45 @@ def test_fix_params_rejects_unknown_fields(lgf):
     assert p.omega == 1.5 and p.separate_measure == 1 and p.check_every == 20
     with pytest.raises(TypeError):
         lgf.fix_params(omgea=1.5)
+
+
+def _abi_client():
+    exe = os.path.join(ROOT, "tests", "abi_client")
+    if not os.path.exists(exe):
+        import __graft_entry__
+        __graft_entry__.build_abi_client()
+    return exe
+
+
+def test_c_program_links_through_the_header(lgf):
+    """A C program built against include/lgf.h alone links liblgf.so and gets
+    the documented status codes for bad arguments (no GPU needed)."""
+    out = subprocess.run([_abi_client(), "check"], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "check ok"
+    libs = subprocess.run(["ldd", _abi_client()], capture_output=True, text=True, check=True).stdout
+    assert "liblgf.so" in libs
+
+
+@pytest.mark.gpu
+def test_c_program_sweep_matches_oracle(lgf, orc, tmp_path):
+    """create / load / sweep / measure / store / destroy from C: the links
+    after one full sweep and their F, theta match the oracle (1e-12)."""
+    from conftest import gpu_available
+    if not gpu_available():
+        pytest.skip("no GPU visible")
+    dims = (4, 4, 6, 8)
+    U = orc.generate_links(dims, 21, 0.3, True)
+    fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
+    U.tofile(fin)
+    print("[gpu-case] abi_client run", dims, flush=True)
+    out = subprocess.run([_abi_client(), "run", *map(str, dims), "1.7", str(fin), str(fout)],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    F, theta = (float(x) for x in out.stdout.split())
+    got = np.fromfile(fout, dtype=np.complex128).reshape(U.shape)
+    ref = U.copy()
+    orc.sweep(dims, ref, 1.7)
+    F_ref, th_ref = orc.measure(dims, ref)
+    assert float(np.abs(got - ref).max()) <= 1e-12
+    assert abs(F - F_ref) <= 1e-13 and abs(theta - th_ref) <= 1e-12 * th_ref

@@ -91,6 +91,40 @@ def test_split_sweep_matches_fp64_12_and_oracle(lgf, orc, dims, handle_fmt, omeg
         assert unitarity_error(got) < 1e-11   # that of the grid input
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 6, 10), (8, 6, 4, 12), (4, 8, 8, 8)])
+@pytest.mark.parametrize("omega,p_sr", [(1.7, 0.0), (1.8, 0.3)])
+def test_split_sweep_on_ordinary_links(lgf, orc, dims, omega, p_sr):
+    """One split sweep of ordinary FP64 links (not on the split grid) against
+    the oracle's sweep of those very links.  The library decides g from its
+    split copy U' = split_stored(U) and applies it to U itself, so per entry
+    |g U g^dag - ref| <= |g U' g^dag - ref'| + |g (U - U') g^dag| + |ref' - ref|,
+    with ref and ref' the oracle's sweeps of U and U':
+      * the first term is the parity of the grid test, 1e-12 + 2 delta;
+      * the second is at most 3 max|U - U'| (Frobenius norm of the difference,
+        kept by the unitary g);
+      * the third is the update's own sensitivity to the 2^-41 perturbation
+        (large where the SU(2) subproblem is ill conditioned), computed by the
+        oracle.
+    The bar is their sum; the worst |g U g^dag - ref| is printed next to the
+    FP64 bar of 1e-12, which this format does not promise on every link."""
+    announce("split sweep, ordinary links", dims, omega, p_sr)
+    U = orc.generate_links(dims, 7, 0.35)
+    Us = split_stored(U)
+    ref = U.copy()
+    orc.sweep(dims, ref, omega, p_sr, seed=9, sweep_index=3)
+    ref_s = Us.copy()
+    orc.sweep(dims, ref_s, omega, p_sr, seed=9, sweep_index=3)
+    sens, din = maxabs(ref_s, ref), maxabs(Us, U)
+    bar = 1e-12 + 2 * unitarity_error(Us) + 3 * din + sens
+    got, res = fixed_sweep(lgf, dims, U, 0, lgf.LGF_FP64_12S, TUNINGS[0], omega, p_sr)
+    err = maxabs(got, ref)
+    announce(f"split ordinary {dims} omega {omega} p {p_sr}: |gpu - oracle| {err:.3e} (FP64 bar 1e-12), "
+             f"sensitivity {sens:.3e}, input rounding {din:.3e}, bar {bar:.3e}")
+    # the storage's definition: rows 0 and 1 within 2^-40 (row 2 is rebuilt)
+    assert maxabs(Us[..., :2, :], U[..., :2, :]) <= SPLIT_UNIT
+    assert err <= bar, (err, bar)
+
+
 def test_split_history_matches_oracle(lgf, orc):
     """8^4 FP64 gauge fixing to theta < 1e-12 on grid links: the measured
     theta history (1e-8 relative while theta > 1e-10) and F follow the
@@ -191,26 +225,38 @@ def test_split_64x4_sampled(lgf, orc):
     rng = np.random.default_rng(2)
     bar = 36 * SPLIT_UNIT + 1e-12
 
-    def upd(s):
-        out, _ = orc.local_update(split_stored(oracle_links8(orc, dims, seed, eps, s)), omega, [0, 0, 0])
+    def upd(s, split=True):
+        links = oracle_links8(orc, dims, seed, eps, s)
+        out, _ = orc.local_update(split_stored(links) if split else links, omega, [0, 0, 0])
         return out
+
+    def around(y, split):
+        links = np.zeros((8, 3, 3), dtype=np.complex128)
+        for mu in range(4):
+            links[mu] = upd(orc.neighbor(dims, y, mu, +1), split)[4 + mu]
+            links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1), split)[mu]
+        ref, _ = orc.local_update(split_stored(links) if split else links, omega, [0, 0, 0])
+        return ref
 
     with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
         lat.generate(seed, eps, True)
         st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1,
                                    bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
         assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
-        worst = 0.0
+        worst = worst_plain = 0.0
         for y in sample_sites(orc, dims, 1, 8, rng):
-            links = np.zeros((8, 3, 3), dtype=np.complex128)
-            for mu in range(4):
-                links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]
-                links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]
-            ref, _ = orc.local_update(split_stored(links), omega, [0, 0, 0])
-            e = maxabs(gpu_links8(lat, orc, dims, y), ref)
+            got = gpu_links8(lat, orc, dims, y)
+            ref = around(y, True)
+            e = maxabs(got, ref)
             worst = max(worst, e)
             assert e < bar, (y, e)
-        announce("split 64^4 worst", worst)
+            # against the oracle's updates of the unsplit links: the bar plus
+            # the updates' own sensitivity to the split copy's rounding
+            ref_plain = around(y, False)
+            e_plain = maxabs(got, ref_plain)
+            worst_plain = max(worst_plain, e_plain)
+            assert e_plain < bar + maxabs(ref, ref_plain), (y, e_plain)
+        announce("split 64^4 worst", worst, "against the unsplit links", worst_plain)
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
 
 
