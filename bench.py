@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the SU(3) Landau gauge-fixing hot path on one MI355X.
 
-One step = one complete gauge fixing of the 64^4 workload (seeded synthetic
-links: seed 3, eps 0.3, Haar-random gauge) from its stored start to
-theta < 1e-14 with overrelaxation omega = 1.8, in the mixed form: FP32 12-real
-bulk sweeps, FP64 reunitarization + F/theta every 20 sweeps, switch to FP64
-(12-real storage) below theta = 1e-8, result handed back as FP64 18-real.  The
-sweeps run in the fixed-link form (the links stay as stored, the sweeps update
-the gauge transformation g and form g U g^dag in registers; the result is
-g U g^dag from the input).  The start configuration stays resident in HBM (a
-device-to-device copy opens each step).  value = site updates per second over
-the whole step (V x sweeps / step time).
+Workload: the 64^4 lattice of seeded synthetic links (seed 3, eps 0.3, then a
+Haar-random gauge transformation), overrelaxation omega = 1.8.
 
-Also reported: the same gauge fixing with sweeps that rewrite the links, the
-plain-FP64 time-to-theta on the same input, stochastic relaxation (p = 0.5)
-sweep throughput, per-kernel roofline figures from HIP events, and the FP64 CPU
-oracle timed on a bounded sample of the workload.
+One step = one check interval of the FP64 gauge fixing on that lattice: 20
+full sweeps (parity 0, then parity 1) of the fixed-link form replayed from a
+hipGraph, the gauge transformation reunitarized in FP64 as the last sweep
+stores it, and F, theta measured in FP64 (Sec. 4: sweep the parities in turn,
+check theta).  The sweeps compute in FP64 and read the links from their split
+FP64 copy (fl32 + 16-bit remainder, within 2^-40).  The field and the gauge
+transformation stay resident in HBM between steps; a step is the unit the
+gauge fixing repeats until theta < 1e-14.  value = site updates per second
+(V x 20 x steps / timed wall time).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+Reported beside it, each run once: time to theta < 1e-14 of the mixed form
+(FP32 12-real bulk, FP64 finish below theta = 1e-8) and of the plain FP64 form
+on the same input, the roofline of the dominant kernel from HIP events, and
+the FP64 CPU oracle timed on 10 sweeps of the same 64^4 field.  Optional
+items are skipped (and say so) past a wall-clock budget.  Other workloads run
+alone through --leg.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--budget 420]
 """
 from __future__ import annotations
 
@@ -97,33 +101,35 @@ def measured_traffic(key: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(dims, seed, eps, omega, seconds):
-    """The FP64 oracle on a 64^3 x 4 slab of the workload's shape (same
-    generator and parameters), full OR sweeps for about `seconds`."""
+def cpu_baseline(dims, seed, eps, omega, sweeps, max_seconds):
+    """The FP64 oracle on the host cores: full OR sweeps of the benchmark's own
+    field (the same generator and parameters, generated on the host, not
+    timed), `sweeps` of them or as many as fit in `max_seconds`; and the 8^4
+    workload (seed 0, eps 0.25, Haar, omega 1.7) to theta < 1e-12."""
     import oracle
-    Lt = 4
-    sdims = (Lt,) + tuple(dims[1:])
-    U = oracle.generate_links(sdims, seed, eps, True)
+    t_gen = time.perf_counter()
+    U = oracle.generate_links(dims, seed, eps, True)
+    t_gen = time.perf_counter() - t_gen
     n = 0
     t0 = time.perf_counter()
-    while True:
-        oracle.sweep(sdims, U, omega, 0.0, 0, n)
+    while n < sweeps:
+        oracle.sweep(dims, U, omega, 0.0, 0, n)
         n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or n >= 1000:
+        if time.perf_counter() - t0 >= max_seconds:
             break
-    Vs = Lt * dims[1] * dims[2] * dims[3]
-    # and the small 8^4 workload (seed 0, eps 0.25, Haar, omega 1.7) to theta < 1e-12
+    el = time.perf_counter() - t0
+    del U
+    V = dims[0] * dims[1] * dims[2] * dims[3]
     d8 = (8, 8, 8, 8)
     U8 = oracle.generate_links(d8, 0, 0.25, True)
     t8 = time.perf_counter()
     r8 = oracle.gauge_fix(d8, U8, 1.7, 1e-12)
     t8 = time.perf_counter() - t8
-    return {"value": Vs * n / el, "unit": "site-updates/s", "cores": oracle.num_threads(),
+    return {"value": V * n / el, "unit": "site-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} full OR sweeps (omega {omega}) of a {'x'.join(map(str, sdims))} slab "
-                      f"({Vs} sites) with the 64^4 workload's generator (seed {seed}, eps {eps}, "
-                      f"Haar), FP64, {el:.1f} s",
+            "sample": f"{n} full OR sweeps (omega {omega}) of the {'x'.join(map(str, dims))} workload's field "
+                      f"(seed {seed}, eps {eps}, Haar; generated on the host in {t_gen:.1f} s, not timed), "
+                      f"FP64, {el:.1f} s",
             "time_to_theta_8x4_s": t8, "sweeps_8x4": r8["sweeps"]}
 
 
@@ -427,22 +433,86 @@ def coulomb_bench(lgf, stream):
     return out
 
 
+def link64_bench(lgf, torch, stream, dims, seed, eps, omega):
+    """The 64^4 workload's other forms, each timed once: the mixed gauge fixing
+    with sweeps that rewrite the links (autotuned variants), the fixed-link
+    one with its finish on FP64-12 links instead of the split copy, and the
+    sweep rates of stochastic relaxation (p = 0.5, Philox keyed by site and
+    sweep) and of overrelaxation in FP32-12 and FP64-18."""
+    dev = torch.device("cuda:0")
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    Vh = V // 2
+    bulk, home, finish12 = lgf.LGF_FP32_12, lgf.LGF_FP64_18, lgf.LGF_FP64_12
+    nbytes = lgf.lgf_required_bytes(dims, home)
+    pristine = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    work = torch.empty_like(pristine)
+    hp = lgf.lgf_create(dims, home, stream, pristine)
+    lgf.lgf_generate_links(hp, seed, eps, True)
+    hw = lgf.lgf_create(dims, home, stream, work)
+    out = {"dims": list(dims)}
+    lgf.lgf_autotune(hw, bulk, 4)
+    lgf.lgf_autotune(hw, finish12, 4)
+    plink = lgf.fix_params(omega=omega, theta_target=1e-14, theta_switch=1e-8, bulk_format=bulk,
+                           finish_format=finish12)
+    work.copy_(pristine)
+    st, rl, _ = lgf.lgf_gauge_fix(hw, plink)
+    out["link_sweeps_mixed"] = {
+        "status": int(st), "time_to_theta_s": rl["t_total_ms"] / 1e3, "sweeps": rl["sweeps"],
+        "sweeps_bulk": rl["sweeps_bulk"], "theta": rl["theta"], "F": rl["F"],
+        "sweep_ms_per_launch": {"fp32-12": rl["t_sweep_bulk_ms"] / (2 * max(rl["sweeps_bulk"], 1)),
+                                "fp64-12": rl["t_sweep_finish_ms"] / (2 * max(rl["sweeps"] - rl["sweeps_bulk"], 1))},
+        "tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, f)))
+                   for f in (bulk, finish12)}}
+    log(f"[link64] link sweeps, mixed: {json.dumps(out['link_sweeps_mixed'])}")
+    p12 = lgf.fix_params(omega=omega, theta_target=1e-14, theta_switch=1e-8, bulk_format=bulk,
+                         finish_format=finish12, fixed_links=1)
+    work.copy_(pristine)
+    st, r12, _ = lgf.lgf_gauge_fix(hw, p12)
+    out["fixed_links_fp64_12_finish"] = {
+        "status": int(st), "time_to_theta_s": r12["t_total_ms"] / 1e3, "sweeps": r12["sweeps"],
+        "sweeps_bulk": r12["sweeps_bulk"], "theta": r12["theta"], "F": r12["F"],
+        "fp64_12_ms_per_launch": r12["t_sweep_finish_ms"] / (2 * max(r12["sweeps"] - r12["sweeps_bulk"], 1))}
+    log(f"[link64] fixed links, FP64-12 finish: {json.dumps(out['fixed_links_fp64_12_finish'])}")
+    work.copy_(pristine)
+    ms_sr64 = lgf.lgf_time_sweeps(hw, 10, 1.0, 0.5, 17, 0)
+    ms_or64 = lgf.lgf_time_sweeps(hw, 10, omega, 0.0, 0, 0)
+    hsr = lgf.lgf_create(dims, bulk, stream)
+    lgf.lgf_generate_links(hsr, seed, eps, True)
+    ms_sr32 = lgf.lgf_time_sweeps(hsr, 10, 1.0, 0.5, 17, 0)
+    ms_or32 = lgf.lgf_time_sweeps(hsr, 10, omega, 0.0, 0, 0)
+    lgf.lgf_destroy(hsr)
+    for name, ms, by in (("sr_p0.5_fp64_18", ms_sr64, 2304), ("or_fp64_18", ms_or64, 2304),
+                         ("sr_p0.5_fp32_12", ms_sr32, 768), ("or_fp32_12", ms_or32, 768)):
+        out[name] = {"ms_per_launch": ms, "site_updates_per_s": Vh / (ms * 1e-3),
+                     "GBs": Vh * by / (ms * 1e-3) / 1e9}
+    lgf.lgf_destroy(hw)
+    lgf.lgf_destroy(hp)
+    del work, pristine
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
+    t_begin = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dims", default="64,64,64,64")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="wall-clock seconds after which optional items are skipped")
+    ap.add_argument("--cpu-sweeps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and SR reference runs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps and the roofline (no time-to-theta runs)")
     ap.add_argument("--traffic-run", action="store_true",
                     help="only the short workload of the rocprofv3 counter passes")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
     ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
-    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32"),
-                    help="run only this extra workload and print its JSON (for profiling it alone)")
+    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64"),
+                    help="run only this extra workload and print its JSON")
     args = ap.parse_args()
     if args.summarize_traffic:
         dims = tuple(int(x) for x in args.dims.split(","))
@@ -454,6 +524,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE {world}); the multi-GPU split is a design, not an implementation.",
               file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -467,21 +540,36 @@ def main():
 
     dims = tuple(int(x) for x in args.dims.split(","))
     V = dims[0] * dims[1] * dims[2] * dims[3]
+    Vh = V // 2
     seed, eps, omega = 3, 0.3, 1.8
     theta_target, theta_switch = 1e-14, 1e-8
-    # the finish reads the links from their split FP64 copy (FP64 arithmetic);
-    # the link-rewriting comparison runs finish in FP64-12
-    bulk, finish, home = lgf.LGF_FP32_12, lgf.LGF_FP64_12S, lgf.LGF_FP64_18
-    finish12 = lgf.LGF_FP64_12
+    chunk = 20
+    # the step's sweeps: FP64 arithmetic on the split copy of the links; the
+    # mixed form's bulk in FP32-12; the handle's links in FP64-18
+    finish, bulk, home = lgf.LGF_FP64_12S, lgf.LGF_FP32_12, lgf.LGF_FP64_18
     stream = torch.cuda.current_stream()
     if args.traffic_run:
         traffic_run(lgf, torch, dims, seed, eps, omega)
         return
     if args.leg:
         legs = {"coulomb": lambda: coulomb_bench(lgf, stream), "ensemble": lambda: ensemble_bench(lgf, stream),
-                "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream)}
+                "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream),
+                "link64": lambda: link64_bench(lgf, torch, stream, dims, seed, eps, omega)}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
+
+    def elapsed():
+        return time.perf_counter() - t_begin
+
+    skipped = []
+
+    def fits(name, seconds):
+        """Whether an optional item of about `seconds` still fits the budget."""
+        if elapsed() + seconds <= args.budget:
+            return True
+        skipped.append(f"{name} (needs ~{seconds:.0f} s, {elapsed():.0f} s of {args.budget:.0f} s used)")
+        log(f"[bench] skipped {skipped[-1]}")
+        return False
 
     nbytes = lgf.lgf_required_bytes(dims, home)
     pristine = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -489,155 +577,100 @@ def main():
     hp = lgf.lgf_create(dims, home, stream, pristine)
     lgf.lgf_generate_links(hp, seed, eps, True)
     hw = lgf.lgf_create(dims, home, stream, work)
-    # sweep variants picked by the autotuners on this lattice: the fixed-link
-    # sweeps of the step, and the link-rewriting sweeps of the comparison run
-    lgf.lgf_autotune_fixed(hw, bulk, 4)
+    work.copy_(pristine)
+    # the fixed-link sweep variants picked on this lattice and GPU
     lgf.lgf_autotune_fixed(hw, finish, 4)
-    lgf.lgf_autotune(hw, bulk, 4)
-    lgf.lgf_autotune(hw, finish12, 4)
+    lgf.lgf_autotune_fixed(hw, bulk, 4)
     torch.cuda.synchronize()
     fixed_tuning = {f: lgf.lgf_get_fixed_tuning(hw, f) for f in (bulk, finish)}
-    tuning = {f: lgf.lgf_get_tuning(hw, f) for f in (bulk, finish12, home)}
-    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, "
-        f"order) fp32-12 {fixed_tuning[bulk]} fp64-12s {fixed_tuning[finish]}; link-sweep tuning fp32-12 "
-        f"{tuning[bulk]} fp64-12 {tuning[finish12]}")
+    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, order) "
+        f"fp64-12s {fixed_tuning[finish]} fp32-12 {fixed_tuning[bulk]}; {elapsed():.1f} s")
 
-    params = lgf.lgf_fix_params_default()
-    params.omega = omega
-    params.theta_target = theta_target
-    params.theta_switch = theta_switch
-    params.bulk_format = bulk
-    params.finish_format = finish
-    params.check_every = 20
-    params.use_graph = 1
-    params.fixed_links = 1
-
-    def step(p=params):
-        work.copy_(pristine)
-        st, res, hist = lgf.lgf_gauge_fix(hw, p)
-        if st != lgf.LGF_OK:
-            raise RuntimeError(f"gauge fix did not converge: {res}")
-        return res
-
+    # ---- the timed steps: check intervals of the FP64 gauge fixing
+    lgf.lgf_fix_begin(hw, finish)
+    sweep0 = 0
     for w in range(args.warmup):
-        r = step()
-        log(f"[bench] warmup {w}: {r['sweeps']} sweeps ({r['sweeps_bulk']} fp32-12), "
-            f"theta {r['theta']:.3e}, {r['t_total_ms']:.0f} ms")
+        F, th, ms = lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, sweep0)
+        sweep0 += chunk
+        log(f"[bench] warmup {w}: F {F:.12f} theta {th:.3e}, sweeps {ms:.1f} ms")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
+    steps = []
+    for _ in range(args.steps):
+        steps.append(lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, sweep0))
+        sweep0 += chunk
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    elapsed = t1 - t0
-    total_sweeps = sum(r["sweeps"] for r in results)
-    for i, r in enumerate(results):
-        log(f"[bench] step {i}: {r['sweeps']} sweeps ({r['sweeps_bulk']} fp32-12), theta "
-            f"{r['theta']:.3e}, F {r['F']:.12f}, {r['t_total_ms']:.0f} ms")
+    lgf.lgf_fix_end(hw)
+    step_s = t1 - t0
+    sweep_ms = sum(r[2] for r in steps)
+    launch_ms = sweep_ms / (2 * chunk * args.steps)
+    log(f"[bench] {args.steps} steps in {step_s * 1e3:.1f} ms ({step_s / args.steps * 1e3:.2f} ms per step); "
+        f"sweep kernels {launch_ms:.4f} ms per launch; theta {steps[-1][1]:.3e}")
 
-    # per-kernel figures from the driver's HIP events on the launch stream
-    Vh = V // 2
-    sb = sum(r["sweeps_bulk"] for r in results)
-    sf = total_sweeps - sb
-    tb = sum(r["t_sweep_bulk_ms"] for r in results)
-    tf = sum(r["t_sweep_finish_ms"] for r in results)
-    kernels = {}
-    for name, fmt, nsw, tms in (("fixed_sweep_fp32_12", bulk, sb, tb), ("fixed_sweep_fp64_12s", finish, sf, tf)):
-        if nsw > 0:
-            launch_ms = tms / (2 * nsw)
-            by = Vh * fixed_site_bytes(fmt)
-            kernels[name] = {"launches": 2 * nsw, "avg_launch_ms": launch_ms,
-                             "algorithmic_bytes_per_launch": by,
-                             "achieved_GBs": by / (launch_ms * 1e-3) / 1e9,
-                             "site_updates_per_s": Vh / (launch_ms * 1e-3), "total_ms": tms}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    dk = kernels[dom]
-    dfmt = bulk if dom == "fixed_sweep_fp32_12" else finish
-    fmt_name = lgf.FORMAT_NAMES[dfmt]
-    lanes, block, order = fixed_tuning[dfmt]
-    traffic = measured_traffic(fixed_traffic_key(dfmt, lanes, block, order, dims))
-    roofline = {"bound": "hbm", "achieved": round(dk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dk["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
-                "kernel": f"fixed_sweep_kernel<{fmt_name}, lanes/site {lanes}> block {block}, tile order "
+    # roofline of the dominant kernel (the step's sweep), from the HIP events
+    # the library records around each chunk's sweeps on the launch stream
+    lanes, block, order = fixed_tuning[finish]
+    by = Vh * fixed_site_bytes(finish)
+    achieved = by / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(fixed_traffic_key(finish, lanes, block, order, dims))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"fixed_sweep_kernel<fp64-12s, lanes/site {lanes}> block {block}, tile order "
                           f"{['lexicographic', 'XCD ranges', 't-z blocks per XCD'][order]}",
-                "avg_launch_ms": round(dk["avg_launch_ms"], 4),
-                "bytes_per_launch": dk["algorithmic_bytes_per_launch"]}
-
+                "avg_launch_ms": round(launch_ms, 4), "launches": 2 * chunk * args.steps,
+                "bytes_per_launch": by,
+                "basis": f"{Vh} site updates per launch x {fixed_site_bytes(finish)} B: the fixed-link form "
+                         f"reads the 8 links of a site (72 B each in the split FP64 copy), reads and writes "
+                         f"g(x) and reads the neighbouring g of the other parity once (96 B each, FP64-12); "
+                         f"the link-rewriting sweep moves 2304 B per update in FP64-18"}
     if traffic:
-        # the HBM bytes the counters saw per launch, at the launch time measured here
-        roofline["traffic_GBs"] = round(traffic / (dk["avg_launch_ms"] * 1e-3) / 1e9, 1)
+        roofline["traffic_GBs"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(roofline["traffic_GBs"] / HBM_PEAK_GBS, 4)
-    # the streaming ceiling on this GPU: a plain one-pass device copy of 4 GiB
+        roofline["traffic_over_algorithmic"] = round(traffic / by, 4)
     copy_gbs = lgf.lgf_copy_bandwidth(4 << 30, 10, stream)
     roofline["copy_ceiling_GBs"] = round(copy_gbs, 1)
-    roofline["frac_of_copy_ceiling"] = round(dk["achieved_GBs"] / copy_gbs, 4)
-    log(f"[bench] copy ceiling {copy_gbs:.1f} GB/s; dominant kernel at {dk['achieved_GBs']:.1f} GB/s")
+    roofline["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
+    log(f"[bench] copy ceiling {copy_gbs:.1f} GB/s; step sweep kernel at {achieved:.1f} GB/s; {elapsed():.1f} s")
 
+    # ---- time to theta < 1e-14, each form once on the same input
     extras = {}
+
+    def fix_once(name, params, tuned=None):
+        work.copy_(pristine)
+        st, r, _ = lgf.lgf_gauge_fix(hw, params)
+        e = {"status": lgf.STATUS_NAMES.get(int(st), int(st)), "time_to_theta_s": r["t_total_ms"] / 1e3,
+             "sweeps": r["sweeps"], "sweeps_bulk": r["sweeps_bulk"], "theta": r["theta"], "F": r["F"],
+             "site_updates_per_s": V * r["sweeps"] / (r["t_total_ms"] / 1e3),
+             "t_sweep_bulk_s": r["t_sweep_bulk_ms"] / 1e3, "t_sweep_finish_s": r["t_sweep_finish_ms"] / 1e3,
+             "t_measure_s": r["t_measure_ms"] / 1e3, "t_convert_s": r["t_convert_ms"] / 1e3}
+        if tuned:
+            e["tuning"] = tuned
+        extras[name] = e
+        log(f"[bench] {name}: {json.dumps(e)}; {elapsed():.1f} s")
+        return e
+
+    time_to_theta = {}
     if not args.no_extras:
-        # the same mixed gauge fixing with sweeps that rewrite the links
-        plink = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch,
-                               bulk_format=bulk, finish_format=finish12, check_every=20, use_graph=1)
-        rl = step(plink)
-        extras["link_sweeps_mixed"] = {
-            "time_to_theta_s": rl["t_total_ms"] / 1e3, "sweeps": rl["sweeps"], "sweeps_bulk": rl["sweeps_bulk"],
-            "theta": rl["theta"], "F": rl["F"],
-            "site_updates_per_s": V * rl["sweeps"] / (rl["t_total_ms"] / 1e3),
-            "sweep_ms_per_launch": {"fp32-12": rl["t_sweep_bulk_ms"] / (2 * rl["sweeps_bulk"]),
-                                    "fp64-12": rl["t_sweep_finish_ms"] / (2 * (rl["sweeps"] - rl["sweeps_bulk"]))},
-            "tuning": {lgf.FORMAT_NAMES[f]: dict(zip(lgf.TUNING_FIELDS, tuning[f])) for f in (bulk, finish12)}}
-        log(f"[bench] link sweeps, mixed: {rl['sweeps']} sweeps, {rl['t_total_ms']:.0f} ms, F {rl['F']:.12f}")
-        # the same fixed-link gauge fixing with the finish on FP64-12 links
-        lgf.lgf_autotune_fixed(hw, finish12, 4)
-        p12 = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch,
-                             bulk_format=bulk, finish_format=finish12, check_every=20, use_graph=1, fixed_links=1)
-        r12 = step(p12)
-        extras["fixed_links_fp64_12_finish"] = {
-            "time_to_theta_s": r12["t_total_ms"] / 1e3, "sweeps": r12["sweeps"], "sweeps_bulk": r12["sweeps_bulk"],
-            "theta": r12["theta"], "F": r12["F"],
-            "site_updates_per_s": V * r12["sweeps"] / (r12["t_total_ms"] / 1e3),
-            "fp64_12_ms_per_launch": r12["t_sweep_finish_ms"] / (2 * (r12["sweeps"] - r12["sweeps_bulk"])),
-            "tuning": dict(zip(("lanes_per_site", "block", "order"), lgf.lgf_get_fixed_tuning(hw, finish12)))}
-        log(f"[bench] fixed links, FP64-12 finish: {r12['sweeps']} sweeps, {r12['t_total_ms']:.0f} ms, "
-            f"F {r12['F']:.15f}")
-        # plain FP64 on the same input, its sweep variant autotuned the same way
-        lgf.lgf_autotune(hw, home, 4)
-        extras["fp64_plain_tuning"] = dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home)))
-        p64 = lgf.lgf_fix_params_default()
-        p64.omega = omega
-        p64.theta_target = theta_target
-        work.copy_(pristine)
-        st, r64, _ = lgf.lgf_gauge_fix(hw, p64)
-        extras["time_to_theta_fp64_s"] = r64["t_total_ms"] / 1e3
-        extras["sweeps_fp64"] = r64["sweeps"]
-        extras["F_fp64"] = r64["F"]
-        extras["theta_fp64"] = r64["theta"]
-        launch64 = r64["t_sweep_finish_ms"] / (2 * r64["sweeps"])
-        extras["fp64_plain_sweep_GBs"] = Vh * 2304 / (launch64 * 1e-3) / 1e9
-        # stochastic relaxation p = 0.5 (omega 1), Philox keyed by (site, sweep)
-        work.copy_(pristine)
-        ms_sr64 = lgf.lgf_time_sweeps(hw, 10, 1.0, 0.5, 17, 0)
-        hsr = lgf.lgf_create(dims, bulk, stream)
-        lgf.lgf_generate_links(hsr, seed, eps, True)
-        ms_sr32 = lgf.lgf_time_sweeps(hsr, 10, 1.0, 0.5, 17, 0)
-        ms_or32 = lgf.lgf_time_sweeps(hsr, 10, omega, 0.0, 0, 0)
-        lgf.lgf_destroy(hsr)
-        extras["sr_p0.5_fp64_18"] = {"site_updates_per_s": Vh / (ms_sr64 * 1e-3),
-                                     "GBs": Vh * 2304 / (ms_sr64 * 1e-3) / 1e9}
-        extras["sr_p0.5_fp32_12"] = {"site_updates_per_s": Vh / (ms_sr32 * 1e-3),
-                                     "GBs": Vh * 768 / (ms_sr32 * 1e-3) / 1e9}
-        extras["or_fp32_12_isolated"] = {"site_updates_per_s": Vh / (ms_or32 * 1e-3),
-                                         "GBs": Vh * 768 / (ms_or32 * 1e-3) / 1e9}
-        mixed_s = sum(r["t_total_ms"] for r in results) / len(results) / 1e3
-        extras["time_to_theta_mixed_s"] = mixed_s
-        extras["mixed_speedup_vs_fp64"] = extras["time_to_theta_fp64_s"] / mixed_s
-        extras["dF_mixed_vs_fp64"] = results[-1]["F"] - r64["F"]
-        extras["dF_link_sweeps_mixed_vs_fp64"] = rl["F"] - r64["F"]
-        extras["fixed_speedup_vs_link_sweeps"] = extras["link_sweeps_mixed"]["time_to_theta_s"] / mixed_s
-        extras["split_speedup_vs_fp64_12_finish"] = extras["fixed_links_fp64_12_finish"]["time_to_theta_s"] / mixed_s
-        extras["dF_split_vs_fp64_12_finish"] = results[-1]["F"] - r12["F"]
-        log(f"[bench] fp64 plain: {r64['sweeps']} sweeps, {r64['t_total_ms']:.0f} ms; "
-            f"SR fp64 {ms_sr64:.3f} ms/launch, SR fp32-12 {ms_sr32:.3f}, OR fp32-12 {ms_or32:.3f}")
+        pm = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch, bulk_format=bulk,
+                            finish_format=finish, fixed_links=1)
+        mixed = fix_once("mixed_fp32-12_bulk_fp64-12s_finish", pm)
+        time_to_theta["mixed_s"] = mixed["time_to_theta_s"]
+        est = 1.3 * mixed["t_sweep_finish_s"] * mixed["sweeps"] / max(mixed["sweeps"] - mixed["sweeps_bulk"], 1)
+        if fits("plain FP64 time-to-theta", est):
+            p64 = lgf.fix_params(omega=omega, theta_target=theta_target, bulk_format=finish, finish_format=finish,
+                                 fixed_links=1)
+            plain = fix_once("fp64_fp64-12s", p64)
+            time_to_theta["fp64_s"] = plain["time_to_theta_s"]
+            time_to_theta["mixed_speedup_vs_fp64"] = plain["time_to_theta_s"] / mixed["time_to_theta_s"]
+            time_to_theta["dF_mixed_vs_fp64"] = mixed["F"] - plain["F"]
+        # the paper's form: FP64 18-real links rewritten by every update
+        if fits("plain FP64-18 link-rewriting time-to-theta", 150.0 + (40.0 if not args.no_cpu_baseline else 0.0)):
+            p18 = lgf.fix_params(omega=omega, theta_target=theta_target)
+            r18 = fix_once("fp64_18_link_sweeps", p18,
+                           tuned=dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home))))
+            time_to_theta["fp64_18_link_sweeps_s"] = r18["time_to_theta_s"]
+            time_to_theta["mixed_speedup_vs_fp64_18_link_sweeps"] = r18["time_to_theta_s"] / mixed["time_to_theta_s"]
     lgf.lgf_destroy(hw)
     lgf.lgf_destroy(hp)
     del work, pristine
@@ -646,57 +679,47 @@ def main():
         # the small 8^4 workload to theta < 1e-12, plain FP64-18 (its oracle time is in cpu_baseline)
         h8 = lgf.lgf_create((8, 8, 8, 8), home, stream)
         lgf.lgf_generate_links(h8, 0, 0.25, True)
-        p8 = lgf.lgf_fix_params_default()
-        p8.omega, p8.theta_target = 1.7, 1e-12
+        p8 = lgf.fix_params(omega=1.7, theta_target=1e-12)
         lgf.lgf_synchronize(h8)
         st8, r8, _ = lgf.lgf_gauge_fix(h8, p8)
         lgf.lgf_destroy(h8)
         extras["gauge_8x4"] = {"status": int(st8), "sweeps": r8["sweeps"],
                                "time_to_theta_s": r8["t_total_ms"] / 1e3, "theta": r8["theta"]}
-        log("[bench] 32^4 plain vs mixed, plaquette drift")
-        extras["gauge_32x4"] = gauge_32x4_bench(lgf, torch, stream)
-        log(f"[bench] 32^4: {json.dumps(extras['gauge_32x4'])}")
-        log("[bench] 48-configuration ensemble")
-        extras["ensemble48"] = ensemble_bench(lgf, stream)
-        log(f"[bench] ensemble: {json.dumps(extras['ensemble48'])}")
-        log("[bench] Coulomb gauge 48^3 x 96")
-        extras["coulomb_48x3x96"] = coulomb_bench(lgf, stream)
-        log(f"[bench] coulomb: {json.dumps(extras['coulomb_48x3x96'])}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 25.0):
         log("[bench] timing the FP64 oracle on the host")
-        cpu = cpu_baseline(dims, seed, eps, omega, args.cpu_seconds)
+        cpu = cpu_baseline(dims, seed, eps, omega, args.cpu_sweeps, args.cpu_seconds)
+        log(f"[bench] cpu_baseline: {json.dumps(cpu)}; {elapsed():.1f} s")
 
     out = {
-        "metric": "OR site-updates/s (64^4 Landau gauge fixing to theta<1e-14, mixed FP32-12/FP64)",
-        "value": V * total_sweeps / elapsed,
+        "metric": "OR site-updates/s at 64^4 (FP64 check intervals of the Landau gauge fixing); "
+                  "time-to-theta<1e-14 mixed vs FP64",
+        "value": V * chunk * args.steps / step_s,
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": step_s / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32+fp64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau OR gauge fixing, mixed "
-                               f"FP32-12 bulk / FP64 finish (FP64 arithmetic and g; links read from a split "
-                               f"copy, fl32 + 16-bit remainder, within 2^-40), theta<1e-14 measured on the "
-                               f"FP64 result, fixed-link sweeps",
+        "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau overrelaxation (omega {omega}): one step = "
+                               f"{chunk} full sweeps of the fixed-link form (FP64 arithmetic and g; links read "
+                               f"from their split FP64 copy, fl32 + 16-bit remainder, within 2^-40) from a "
+                               f"hipGraph + FP64 reunitarization of g + FP64 F/theta measurement",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
-                   "theta_target": theta_target, "theta_switch": theta_switch, "check_every": 20,
-                   "sweeps_per_step": [r["sweeps"] for r in results],
+                   "sweeps_per_step": chunk, "theta_after_steps": steps[-1][1],
                    "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(("lanes_per_site", "block", "order"), t))
                                           for f, t in fixed_tuning.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": kernels,
-        "step_breakdown_ms": {k: sum(r[k] for r in results) / len(results)
-                              for k in ("t_sweep_bulk_ms", "t_sweep_finish_ms", "t_measure_ms", "t_convert_ms",
-                                        "t_total_ms")},
+        "time_to_theta": time_to_theta,
         "extras": extras,
+        "skipped": skipped,
+        "wall_s": round(elapsed(), 1),
     }
     print(json.dumps(out), flush=True)
 
