@@ -292,6 +292,20 @@ lgf_status lgf_anneal_sweep(lgf_lattice *h, int parity, double T, uint64_t seed,
 lgf_status lgf_anneal(lgf_lattice *h, int64_t n_sweeps, double T_start, double T_end, uint64_t seed,
                       uint64_t sweep0, uint64_t *trials, double *ms);
 
+/* F and theta of the handle's links, as lgf_measure computes them (the same
+ * kernels and summation order, so the same bits), written to d_out[0] = F,
+ * d_out[1] = theta in device memory on the handle's device; enqueued on the
+ * handle's stream and not synchronised.  For callers that cannot allocate
+ * device memory -- code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc: this call allocates nothing.  Its
+ * per-workgroup partial sums go to a 4 MiB device array of the library (one
+ * per GPU, held until the process ends), so it serves lattices of at most
+ * 2^26 sites (LGF_EINVAL beyond).  Calls that overlap on one GPU (several
+ * streams or threads) share that array and race; the caller orders them.
+ * Every call writes all the partial sums it reads, so nothing carries over
+ * from one call to the next. */
+lgf_status lgf_measure_noalloc(lgf_lattice *h, double *d_out);
+
 /* Block until all work queued on the handle's stream has finished. */
 lgf_status lgf_synchronize(lgf_lattice *h);
 

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1634,6 +1635,59 @@ lgf_status lgf_anneal(lgf_lattice *h, int64_t n_sweeps, double T_start, double T
     LGF_TRY(read_trials(h, &t));
     if (trials) *trials = t;
     if (ms) *ms = elapsed_ms(h->ev0, h->ev1);
+    return LGF_OK;
+}
+
+// ----------------------------------------------------------------------------
+// The allocation-free measurement.  Its per-workgroup partial sums live in a
+// file-scope device array instead of handle memory; each GPU holds its own
+// copy of the array, whose address the runtime gives per device.
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(4) << 20;  // 4 MiB: (F, theta) partials of up to 2^26 sites
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxScratchDevices];  // device address of `scratch` on each device (set on first use)
+
+// the address of `scratch` on device dev, which must be current
+lgf_status scratch_on(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(LGF_EINVAL, "device %d: the scratch table holds devices 0..%d", dev, kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LGF_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return LGF_OK;
+}
+
+}  // namespace
+
+lgf_status lgf_measure_noalloc(lgf_lattice *h, double *d_out)
+{
+    if (!h || !d_out) return fail(LGF_EINVAL, "NULL handle or output");
+    const size_t need = (size_t)4 * (size_t)lgf::measure_blocks(h->geom) * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(LGF_EINVAL,
+                    "a lattice of %lld sites needs %zu bytes of partial sums, more than the %zu bytes of the "
+                    "allocation-free measurement (at most 2^26 sites); use lgf_measure",
+                    (long long)h->V, need, kScratchBytes);
+    LGF_TRY(use_device(h));
+    void *scr = nullptr;
+    LGF_TRY(scratch_on(h->device, &scr));
+    double *part = static_cast<double *>(scr);
+    int n0 = 0, n1 = 0;
+    LGF_HIP(lgf::launch_measure(h->format, h->field, h->geom, 0, false, false, part, &n0, h->stream));
+    LGF_HIP(lgf::launch_measure(h->format, h->field, h->geom, 1, false, false, part + 2 * n0, &n1, h->stream));
+    LGF_HIP(lgf::launch_finish_measure(part, n0 + n1, (double)h->V, d_out, h->stream));
     return LGF_OK;
 }
 

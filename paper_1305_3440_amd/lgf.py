@@ -57,6 +57,7 @@ EXPORTS = [
     "lgf_gauge_fix", "lgf_synchronize", "lgf_set_tuning", "lgf_get_tuning", "lgf_autotune",
     "lgf_time_sweeps", "lgf_copy_bandwidth", "lgf_set_fixed_tuning", "lgf_get_fixed_tuning",
     "lgf_autotune_fixed", "lgf_fix_begin", "lgf_fix_chunk", "lgf_fix_end", "lgf_anneal_sweep", "lgf_anneal",
+    "lgf_measure_noalloc",
 ]
 
 _lib = None
@@ -112,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "lgf_fix_end": (I, [P]),
         "lgf_anneal_sweep": (I, [P, I, D, U64, U64, P]),
         "lgf_anneal": (I, [P, I64, D, D, U64, U64, P, P]),
+        "lgf_measure_noalloc": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -298,6 +300,11 @@ def lgf_time_sweeps(h, n: int, omega: float, p_sr: float = 0.0, seed: int = 0,
     ms = ctypes.c_double()
     _check(load_library().lgf_time_sweeps(h, n, omega, p_sr, seed, sweep_index, ctypes.byref(ms)))
     return ms.value
+
+
+def lgf_measure_noalloc(h, d_out) -> None:
+    """d_out: device buffer (e.g. a torch tensor) of 2 doubles; not synchronised."""
+    _check(load_library().lgf_measure_noalloc(h, _ptr_of(d_out)))
 
 
 def lgf_fix_begin(h, fmt: int) -> None:
