@@ -13,6 +13,7 @@ import sys
 import numpy as np
 import pytest
 
+import fp32_model as fm
 from conftest import gpu_available
 from lattice_np import unitarity_error
 
@@ -49,9 +50,10 @@ def link_errs(A, B):
     return d / n
 
 
-def fp32_ok(got, ref):
-    e = link_errs(got, ref)
-    return float(np.quantile(e, 0.99)) <= 2e-6 and float(e.max()) <= 2e-5
+def fp32_ok(got, ref, env):
+    """2e-6 relative on 99 % of the links, and on every link twice its
+    randomised-rounding envelope (fp32_model) plus u"""
+    return fm.fp32_bar_ok(got, ref, env)[0]
 
 
 def loops(orc, dims, U):
@@ -87,6 +89,9 @@ def test_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fmt, omega
     orc.sweep(dims, ref, omega, p_sr, seed=9, sweep_index=3)
     orc.reunitarize(ref)
     F_ref, th_ref = orc.measure(dims, ref)
+    env = None
+    if sweep_fmt not in (0, 3):
+        env = fm.fixed_sweep_envelope(orc, dims, U, sweep_fmt, ref, omega, p_sr, 9, 3)
     for tune in FIXED_TUNINGS:
         got, res, hist = one_fixed_sweep(lgf, dims, U, handle_fmt, sweep_fmt, tune, omega, p_sr, 9, 3)
         if sweep_fmt in (0, 3):
@@ -94,7 +99,7 @@ def test_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fmt, omega
             assert abs(res["F"] - F_ref) <= 1e-13 and abs(res["theta"] - th_ref) <= 1e-12 * th_ref + 1e-15, (
                 tune, res["F"] - F_ref, res["theta"] / th_ref - 1)
         else:
-            assert fp32_ok(got, ref), (tune, float(link_errs(got, ref).max()))
+            assert fp32_ok(got, ref, env), (tune, fm.fp32_bar_ok(got, ref, env)[1])
         assert unitarity_error(got) < 1e-12
 
 
@@ -265,6 +270,37 @@ def test_fixed_links_argument_checks(lgf, orc):
         assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (2, 256, 0)
 
 
+def fixed_links8_model(R, orc, dims, seed, eps, omega, ys, fmt):
+    """The randomised-rounding model of one fixed-link FP32 sweep around
+    parity-1 sites ys: the parity-0 neighbours' g from their own links (g = 1
+    around them), then g(y) from those, and the 8 links of y as the library
+    hands them back, g U g^dag in FP64 (forward links then backward)."""
+    from test_gpu_parity import oracle_links8
+    n = len(ys)
+    eye = np.broadcast_to(np.eye(3, dtype=np.complex128), (1, 4, 3, 3))
+
+    def g_new(L8):
+        m = L8.shape[0]
+        L = fm.stored(R, L8, fmt)
+        one = np.broadcast_to(eye, (m, 4, 3, 3))
+        return fm.fixed_update(R, L[:, :4], one, L[:, 4:], one, one[:, 0], omega, np.zeros((m, 3), bool), fmt)
+
+    nbf = [orc.neighbor(dims, y, mu, +1) for y in ys for mu in range(4)]
+    nbb = [orc.neighbor(dims, y, mu, -1) for y in ys for mu in range(4)]
+    gf = g_new(np.array([oracle_links8(orc, dims, seed, eps, s) for s in nbf])).reshape(n, 4, 3, 3)
+    gb = g_new(np.array([oracle_links8(orc, dims, seed, eps, s) for s in nbb])).reshape(n, 4, 3, 3)
+    Ly = np.array([oracle_links8(orc, dims, seed, eps, y) for y in ys])
+    Ls = fm.stored(R, Ly, fmt)
+    one = np.broadcast_to(np.eye(3, dtype=np.complex128), (n, 3, 3))
+    gy = fm.fixed_update(R, Ls[:, :4], gf, Ls[:, 4:], gb, one, omega, np.zeros((n, 3), bool), fmt)
+    gy, gf, gb = fm.reunitarize(gy), fm.reunitarize(gf), fm.reunitarize(gb)
+    out = np.empty_like(Ly)
+    for mu in range(4):
+        out[:, mu] = gy @ Ly[:, mu] @ fm.dag(gf[:, mu])
+        out[:, 4 + mu] = gb[:, mu] @ Ly[:, 4 + mu] @ fm.dag(gy)
+    return out
+
+
 @pytest.mark.parametrize("handle_fmt,sweep_fmt", [(0, 3), (0, 2)])
 def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
     """The 64^4 workload (seed 3, eps 0.3, Haar gauge) at omega 1.8: one full
@@ -290,7 +326,7 @@ def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
             kw.update(bulk_format=sweep_fmt, finish_format=sweep_fmt)
         st, res, _ = lat.gauge_fix(**kw)
         assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
-        errs = []
+        ys, gots, refs = [], [], []
         for y in sample_sites(orc, dims, 1, 8, rng):
             links = np.zeros((8, 3, 3), dtype=np.complex128)
             for mu in range(4):
@@ -300,10 +336,14 @@ def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
             got = gpu_links8(lat, orc, dims, y)
             if sweep_fmt in (0, 3):
                 assert maxabs(got, ref) < 1e-12, y
-            else:
-                errs.extend(link_errs(got, ref))
-        if errs:
-            assert float(max(errs)) <= 2e-5 and float(np.quantile(errs, 0.99)) <= 2e-6
+            ys.append(y)
+            gots.append(got)
+            refs.append(ref)
+        if sweep_fmt not in (0, 3):
+            env = fm.envelope(lambda R: fixed_links8_model(R, orc, dims, seed, eps, omega, ys, sweep_fmt),
+                              np.array(refs))
+            ok, info = fm.fp32_bar_ok(np.array(gots), np.array(refs), env)
+            assert ok, info
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
 
 
@@ -365,5 +405,6 @@ def test_fixed_sweep_random_shapes(lgf, orc, dims, tune, fmt, omega, p_sr):
     if fmt in (0, 3):
         assert maxabs(got, ref) <= 1e-12, maxabs(got, ref)
     else:
-        assert fp32_ok(got, ref), float(link_errs(got, ref).max())
+        env = fm.fixed_sweep_envelope(orc, dims, U, fmt, ref, omega, p_sr, 12, 7)
+        assert fp32_ok(got, ref, env), fm.fp32_bar_ok(got, ref, env)[1]
     assert unitarity_error(got) < 1e-12
