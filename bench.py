@@ -8,18 +8,19 @@ One step = one check interval of the FP64 gauge fixing on that lattice: 20
 full sweeps (parity 0, then parity 1) of the fixed-link form replayed from a
 hipGraph, the gauge transformation reunitarized in FP64 as the last sweep
 stores it, and F, theta measured in FP64 (Sec. 4: sweep the parities in turn,
-check theta).  The sweeps compute in FP64 and read the links from their split
-FP64 copy (fl32 + 16-bit remainder, within 2^-40).  The field and the gauge
-transformation stay resident in HBM between steps; a step is the unit the
-gauge fixing repeats until theta < 1e-14.  value = site updates per second
-(V x 20 x steps / timed wall time).
+check theta).  The sweeps compute in FP64 on links and gauge transformation
+stored in FP64 12-real form (rows 0 and 1; row 2 rebuilt).  The field and the
+gauge transformation stay resident in HBM between steps; a step is the unit
+the gauge fixing repeats until theta < 1e-14.  value = site updates per
+second (V x 20 x steps / timed wall time).
 
 Reported beside it, each run once: time to theta < 1e-14 of the mixed form
 (FP32 12-real bulk, FP64 finish below theta = 1e-8) and of the plain FP64 form
-on the same input, the roofline of the dominant kernel from HIP events, and
-the FP64 CPU oracle timed on 10 sweeps of the same 64^4 field.  Optional
-items are skipped (and say so) past a wall-clock budget.  Other workloads run
-alone through --leg.
+on the same input, the same with the finish reading the links from a split
+copy (fl32 + 16-bit remainder), the paper's link-rewriting FP64 form, the
+roofline of the dominant kernel from HIP events, and the FP64 CPU oracle
+timed on 10 sweeps of the same 64^4 field.  Optional items are skipped (and
+say so) past a wall-clock budget.  Other workloads run alone through --leg.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--budget 420]
 """
@@ -544,9 +545,10 @@ def main():
     seed, eps, omega = 3, 0.3, 1.8
     theta_target, theta_switch = 1e-14, 1e-8
     chunk = 20
-    # the step's sweeps: FP64 arithmetic on the split copy of the links; the
-    # mixed form's bulk in FP32-12; the handle's links in FP64-18
-    finish, bulk, home = lgf.LGF_FP64_12S, lgf.LGF_FP32_12, lgf.LGF_FP64_18
+    # the step's sweeps: FP64 arithmetic on FP64-12 links and g; the mixed
+    # form's bulk in FP32-12; the handle's links in FP64-18; the split copy of
+    # the links (FP64 arithmetic, links within 2^-40) as an extra finish
+    finish, bulk, home, split = lgf.LGF_FP64_12, lgf.LGF_FP32_12, lgf.LGF_FP64_18, lgf.LGF_FP64_12S
     stream = torch.cuda.current_stream()
     if args.traffic_run:
         traffic_run(lgf, torch, dims, seed, eps, omega)
@@ -584,7 +586,7 @@ def main():
     torch.cuda.synchronize()
     fixed_tuning = {f: lgf.lgf_get_fixed_tuning(hw, f) for f in (bulk, finish)}
     log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, order) "
-        f"fp64-12s {fixed_tuning[finish]} fp32-12 {fixed_tuning[bulk]}; {elapsed():.1f} s")
+        f"fp64-12 {fixed_tuning[finish]} fp32-12 {fixed_tuning[bulk]}; {elapsed():.1f} s")
 
     # ---- the timed steps: check intervals of the FP64 gauge fixing
     lgf.lgf_fix_begin(hw, finish)
@@ -616,14 +618,14 @@ def main():
     traffic = measured_traffic(fixed_traffic_key(finish, lanes, block, order, dims))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"fixed_sweep_kernel<fp64-12s, lanes/site {lanes}> block {block}, tile order "
+                "kernel": f"fixed_sweep_kernel<fp64-12, lanes/site {lanes}> block {block}, tile order "
                           f"{['lexicographic', 'XCD ranges', 't-z blocks per XCD'][order]}",
                 "avg_launch_ms": round(launch_ms, 4), "launches": 2 * chunk * args.steps,
                 "bytes_per_launch": by,
                 "basis": f"{Vh} site updates per launch x {fixed_site_bytes(finish)} B: the fixed-link form "
-                         f"reads the 8 links of a site (72 B each in the split FP64 copy), reads and writes "
-                         f"g(x) and reads the neighbouring g of the other parity once (96 B each, FP64-12); "
-                         f"the link-rewriting sweep moves 2304 B per update in FP64-18"}
+                         f"reads the 8 links of a site, reads and writes g(x) and reads the neighbouring g of "
+                         f"the other parity once (96 B each, FP64-12); the link-rewriting sweep moves 2304 B "
+                         f"per update in FP64-18, 1536 B in FP64-12"}
     if traffic:
         roofline["traffic_GBs"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(roofline["traffic_GBs"] / HBM_PEAK_GBS, 4)
@@ -651,21 +653,37 @@ def main():
         return e
 
     time_to_theta = {}
+    cpu = None
     if not args.no_extras:
         pm = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch, bulk_format=bulk,
                             finish_format=finish, fixed_links=1)
-        mixed = fix_once("mixed_fp32-12_bulk_fp64-12s_finish", pm)
+        mixed = fix_once("mixed_fp32-12_bulk_fp64-12_finish", pm)
         time_to_theta["mixed_s"] = mixed["time_to_theta_s"]
         est = 1.3 * mixed["t_sweep_finish_s"] * mixed["sweeps"] / max(mixed["sweeps"] - mixed["sweeps_bulk"], 1)
-        if fits("plain FP64 time-to-theta", est):
+        if fits("plain FP64 time-to-theta", est + args.cpu_seconds + 25.0):
             p64 = lgf.fix_params(omega=omega, theta_target=theta_target, bulk_format=finish, finish_format=finish,
                                  fixed_links=1)
-            plain = fix_once("fp64_fp64-12s", p64)
+            plain = fix_once("fp64_fp64-12", p64)
             time_to_theta["fp64_s"] = plain["time_to_theta_s"]
             time_to_theta["mixed_speedup_vs_fp64"] = plain["time_to_theta_s"] / mixed["time_to_theta_s"]
             time_to_theta["dF_mixed_vs_fp64"] = mixed["F"] - plain["F"]
+    # the CPU baseline before the optional runs (the line needs it)
+    if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 25.0):
+        log("[bench] timing the FP64 oracle on the host")
+        cpu = cpu_baseline(dims, seed, eps, omega, args.cpu_sweeps, args.cpu_seconds)
+        log(f"[bench] cpu_baseline: {json.dumps(cpu)}; {elapsed():.1f} s")
+    if not args.no_extras and "mixed_s" in time_to_theta:
+        # the finish on the split copy of the links (FP64 arithmetic; links
+        # within 2^-40, so a sweep is within ~1e-11 of the FP64 one, not 1e-12)
+        if fits("mixed time-to-theta with the split finish", 1.1 * time_to_theta["mixed_s"]):
+            lgf.lgf_autotune_fixed(hw, split, 4)
+            ps = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=theta_switch, bulk_format=bulk,
+                                finish_format=split, fixed_links=1)
+            rs = fix_once("mixed_fp32-12_bulk_fp64-12s_finish", ps)
+            time_to_theta["mixed_split_finish_s"] = rs["time_to_theta_s"]
+            time_to_theta["dF_mixed_split_vs_mixed"] = rs["F"] - mixed["F"]
         # the paper's form: FP64 18-real links rewritten by every update
-        if fits("plain FP64-18 link-rewriting time-to-theta", 150.0 + (40.0 if not args.no_cpu_baseline else 0.0)):
+        if fits("plain FP64-18 link-rewriting time-to-theta", 150.0):
             p18 = lgf.fix_params(omega=omega, theta_target=theta_target)
             r18 = fix_once("fp64_18_link_sweeps", p18,
                            tuned=dict(zip(lgf.TUNING_FIELDS, lgf.lgf_get_tuning(hw, home))))
@@ -686,12 +704,6 @@ def main():
         extras["gauge_8x4"] = {"status": int(st8), "sweeps": r8["sweeps"],
                                "time_to_theta_s": r8["t_total_ms"] / 1e3, "theta": r8["theta"]}
 
-    cpu = None
-    if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 25.0):
-        log("[bench] timing the FP64 oracle on the host")
-        cpu = cpu_baseline(dims, seed, eps, omega, args.cpu_sweeps, args.cpu_seconds)
-        log(f"[bench] cpu_baseline: {json.dumps(cpu)}; {elapsed():.1f} s")
-
     out = {
         "metric": "OR site-updates/s at 64^4 (FP64 check intervals of the Landau gauge fixing); "
                   "time-to-theta<1e-14 mixed vs FP64",
@@ -707,9 +719,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau overrelaxation (omega {omega}): one step = "
-                               f"{chunk} full sweeps of the fixed-link form (FP64 arithmetic and g; links read "
-                               f"from their split FP64 copy, fl32 + 16-bit remainder, within 2^-40) from a "
-                               f"hipGraph + FP64 reunitarization of g + FP64 F/theta measurement",
+                               f"{chunk} full sweeps of the fixed-link form (FP64 arithmetic, links and g in "
+                               f"FP64 12-real storage) from a hipGraph + FP64 reunitarization of g + FP64 "
+                               f"F/theta measurement",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "sweeps_per_step": chunk, "theta_after_steps": steps[-1][1],
                    "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(("lanes_per_site", "block", "order"), t))

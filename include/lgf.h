@@ -366,7 +366,8 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
 lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
 
 /* Pick the fastest fixed-link sweep variant for `format` on this lattice
- * (lanes 2/4 x block 64/128/256 x tile order 0/1/2): each timed over `trials`
+ * (lanes 2/4 x block 64/128/256 x tile order 0/1/2; the FP64 formats keep
+ * tile order 2 wherever the lattice admits it): each timed over `trials`
  * full sweeps, the fastest again over ten times as many in five interleaved
  * rounds; the default stays unless another is 1 % faster.  The sweeps read the
  * handle's links (or their copy in `format`) and write only the gauge

@@ -2030,16 +2030,24 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 3.0) break;
     }
+    // FP64 sweep formats keep the blocked tile order wherever the lattice
+    // admits it: it reads each neighbouring g about once (counted HBM traffic
+    // 1.05-1.07x the algorithmic bytes at 64^4, against 1.2-1.4x for the
+    // other orders, which win only within the timing noise)
+    const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12 || format == LGF_FP64_12S);
     std::vector<lgf::SweepTuning> variants;
     for (int lps : {2, 4})
-        for (int block : {64, 128, 256})
+        for (int block : {64, 128, 256}) {
+            lgf::SweepTuning t{};
+            t.lanes_per_site = lps;
+            t.block = block;
+            const bool blocked = fp64 && lgf::fixed_blocked_order(h->geom, t);
             for (int order = 0; order < 3; ++order) {
-                lgf::SweepTuning t{};
-                t.lanes_per_site = lps;
-                t.block = block;
+                if (blocked && order != 2) continue;
                 t.xcd_remap = order;
                 variants.push_back(t);
             }
+        }
     lgf::SweepTuning best = h->tune_fixed[format];
     const bool ok = e == hipSuccess &&
                     pick_variant(variants, dflt, trials, "lgf_autotune_fixed", format, time_variant, &best);

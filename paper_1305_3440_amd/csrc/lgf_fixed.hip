@@ -105,6 +105,13 @@ static TileOrder tile_order(const Geom &g, const SweepTuning &t)
     return o;
 }
 
+bool fixed_blocked_order(const Geom &g, const SweepTuning &t)
+{
+    SweepTuning b = t;
+    b.xcd_remap = 2;
+    return tile_order(g, b).mode == 2;
+}
+
 template <int F, int LPS>
 static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  int post, const uint8_t *slices, bool coulomb, hipStream_t s)

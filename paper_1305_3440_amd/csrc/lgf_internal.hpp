@@ -121,6 +121,9 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
+// whether tile order 2 (blocks of t-slices x z-planes per XCD) applies to
+// this lattice with the tuning's tile size (else it falls back to order 0)
+bool fixed_blocked_order(const Geom &g, const SweepTuning &t);
 // Coulomb gauge in the fixed-link form (post 0 or 1; slice_active: device
 // array of Lt flags)
 hipError_t launch_fixed_sweep_coulomb(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
