@@ -20,7 +20,8 @@ on the same input, the same with the finish reading the links from a split
 copy (fl32 + 16-bit remainder), the paper's link-rewriting FP64 form, the
 roofline of the dominant kernel from HIP events, and the FP64 CPU oracle
 timed on 10 sweeps of the same 64^4 field.  Optional items are skipped (and
-say so) past a wall-clock budget.  Other workloads run alone through --leg.
+say so) past a wall-clock budget.  Other workloads run alone through --leg (link64, gauge32, ensemble, coulomb,
+anneal).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--budget 420]
 """
@@ -493,6 +494,49 @@ def link64_bench(lgf, torch, stream, dims, seed, eps, omega):
     return out
 
 
+def anneal_bench(lgf, torch, stream, dims, seed, eps, omega):
+    """Simulated annealing on the 64^4 workload (FP64-12 handle, link-
+    rewriting heat-bath sweeps): the sweep rate of a 100-sweep schedule
+    (T 1.0 -> 0.05) with its algorithmic bytes (8 links read and written per
+    site update), then overrelaxation (fixed-link mixed form) to theta < 1e-14,
+    against the same overrelaxation without annealing: time, sweeps and the
+    F reached (annealing is meant to reach a higher maximum)."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    fmt = lgf.LGF_FP64_12
+    h = lgf.lgf_create(dims, fmt, stream)
+    out = {"dims": list(dims), "format": lgf.FORMAT_NAMES[fmt], "schedule": {"sweeps": 100, "T_start": 1.0,
+                                                                             "T_end": 0.05}}
+
+    def fix():
+        p = lgf.fix_params(omega=omega, theta_target=1e-14, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+                           finish_format=lgf.LGF_FP64_12, fixed_links=1)
+        st, r, _ = lgf.lgf_gauge_fix(h, p)
+        return {"status": lgf.STATUS_NAMES.get(int(st), int(st)), "time_s": r["t_total_ms"] / 1e3,
+                "sweeps": r["sweeps"], "F": r["F"], "theta": r["theta"]}
+
+    lgf.lgf_generate_links(h, seed, eps, True)
+    out["overrelaxation_only"] = fix()
+    log(f"[anneal] overrelaxation only: {json.dumps(out['overrelaxation_only'])}")
+    lgf.lgf_generate_links(h, seed, eps, True)
+    lgf.lgf_anneal(h, 4, 1.0, 1.0, 99, 1000)  # warm-up of the kernel
+    lgf.lgf_generate_links(h, seed, eps, True)
+    lgf.lgf_synchronize(h)
+    trials, ms = lgf.lgf_anneal(h, 100, 1.0, 0.05, 7, 0)
+    # 100 sweeps moving 8 links in and out per site update (FP64-12: 1536 B),
+    # 5 reunitarizations reading and writing every link (768 B per site)
+    by = 100 * V * 1536 + 5 * V * 768
+    out["anneal"] = {"ms": ms, "trials_per_subgroup_step": trials / (3 * V * 100),
+                     "site_updates_per_s": V * 100 / (ms * 1e-3), "algorithmic_GBs": by / (ms * 1e-3) / 1e9,
+                     "frac_of_8TBs": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    F0, th0 = lgf.lgf_measure(h)
+    out["anneal"]["F_after"], out["anneal"]["theta_after"] = F0, th0
+    log(f"[anneal] schedule: {json.dumps(out['anneal'])}")
+    out["anneal_then_overrelaxation"] = fix()
+    out["dF_anneal_vs_overrelaxation_only"] = out["anneal_then_overrelaxation"]["F"] - out["overrelaxation_only"]["F"]
+    lgf.lgf_destroy(h)
+    return out
+
+
 def main():
     t_begin = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -512,7 +556,7 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
     ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
-    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64"),
+    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64", "anneal"),
                     help="run only this extra workload and print its JSON")
     args = ap.parse_args()
     if args.summarize_traffic:
@@ -556,7 +600,8 @@ def main():
     if args.leg:
         legs = {"coulomb": lambda: coulomb_bench(lgf, stream), "ensemble": lambda: ensemble_bench(lgf, stream),
                 "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream),
-                "link64": lambda: link64_bench(lgf, torch, stream, dims, seed, eps, omega)}
+                "link64": lambda: link64_bench(lgf, torch, stream, dims, seed, eps, omega),
+                "anneal": lambda: anneal_bench(lgf, torch, stream, dims, seed, eps, omega)}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
 
