@@ -225,16 +225,45 @@ hipError_t launch_measure(int format, void *field, const Geom &g, int parity, bo
 
 // Deterministic final sum: thread t adds partials t, t+256, ... in order,
 // then a fixed tree over the block.
-__global__ void __launch_bounds__(256) finish_measure_kernel(const double *partials, int n, double V,
-                                                             double *out)
+// One workgroup reads every pair, so the sum is limited by the loads one CU
+// keeps in flight: 1024 lanes with 8 independent 16-byte loads each.  Lane t
+// adds pairs t + 1024 (8 j + k) into accumulator k, j = 0, 1, ...; the 8
+// accumulators are then added in order k = 0..7 and the lanes in the fixed
+// tree of block_sum2 -- a fixed order for a given n.
+constexpr int kFinishBlock = 1024, kFinishAcc = 8;
+
+__global__ void __launch_bounds__(kFinishBlock) finish_measure_kernel(const double *partials, int n, double V,
+                                                                      double *out)
 {
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        a += partials[2 * i];
-        b += partials[2 * i + 1];
+    const double2 *p = reinterpret_cast<const double2 *>(partials);
+    double a[kFinishAcc], b[kFinishAcc];
+#pragma unroll
+    for (int k = 0; k < kFinishAcc; ++k) a[k] = b[k] = 0.0;
+    const int step = kFinishBlock * kFinishAcc;
+    int i = threadIdx.x;
+    for (; i + (kFinishAcc - 1) * kFinishBlock < n; i += step) {
+        double2 v[kFinishAcc];
+#pragma unroll
+        for (int k = 0; k < kFinishAcc; ++k) v[k] = p[i + k * kFinishBlock];
+#pragma unroll
+        for (int k = 0; k < kFinishAcc; ++k) {
+            a[k] += v[k].x;
+            b[k] += v[k].y;
+        }
+    }
+    for (int k = 0; k < kFinishAcc && i + k * kFinishBlock < n; ++k) {
+        const double2 v = p[i + k * kFinishBlock];
+        a[k] += v.x;
+        b[k] += v.y;
+    }
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int k = 0; k < kFinishAcc; ++k) {
+        ta += a[k];
+        tb += b[k];
     }
     __shared__ double r[2];
-    block_sum2<256>(a, b, r);
+    block_sum2<kFinishBlock>(ta, tb, r);
     if (threadIdx.x == 0) {
         out[0] = r[0] / (12.0 * V);
         out[1] = r[1] / (3.0 * V);
@@ -243,7 +272,7 @@ __global__ void __launch_bounds__(256) finish_measure_kernel(const double *parti
 
 hipError_t launch_finish_measure(const double *partials, int n, double V, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(finish_measure_kernel, dim3(1), dim3(256), 0, s, partials, n, V, out);
+    hipLaunchKernelGGL(finish_measure_kernel, dim3(1), dim3(kFinishBlock), 0, s, partials, n, V, out);
     return hipGetLastError();
 }
 

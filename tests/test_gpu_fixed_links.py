@@ -301,17 +301,19 @@ def fixed_links8_model(R, orc, dims, seed, eps, omega, ys, fmt):
     return out
 
 
-@pytest.mark.parametrize("handle_fmt,sweep_fmt", [(0, 3), (0, 2)])
-def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
+@pytest.mark.parametrize("handle_fmt,sweep_fmt,driver", [(0, 3, "gauge_fix"), (0, 2, "gauge_fix"), (0, 3, "session")])
+def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt, driver):
     """The 64^4 workload (seed 3, eps 0.3, Haar gauge) at omega 1.8: one full
-    sweep with the links fixed, in the formats of the benchmark's finish and
-    bulk, checked on sampled parity-1 sites (edges and wrap-arounds included):
-    the oracle rebuilds the input links from its own generator, redoes the
-    parity-0 updates at the other ends of the site's links, then the site's
-    own update."""
+    sweep with the links fixed, in the formats of the benchmark's step (FP64-12)
+    and bulk, checked on sampled parity-1 sites (edges and wrap-arounds
+    included): the oracle rebuilds the input links from its own generator,
+    redoes the parity-0 updates at the other ends of the site's links, then the
+    site's own update.  driver "session": the sweep as the benchmark's step
+    runs it, one chunk of a stepwise session (captured in a hipGraph, the
+    autotuner's variant)."""
     dims = (64, 64, 64, 64)
     seed, eps, omega = 3, 0.3, 1.8
-    announce("fixed 64^4 sampled", handle_fmt, sweep_fmt)
+    announce("fixed 64^4 sampled", handle_fmt, sweep_fmt, driver)
     from test_gpu_parity import gpu_links8, oracle_links8, sample_sites
     rng = np.random.default_rng(2)
 
@@ -321,11 +323,18 @@ def test_fixed_64x4_sampled(lgf, orc, handle_fmt, sweep_fmt):
 
     with lgf.Lattice(dims, handle_fmt) as lat:
         lat.generate(seed, eps, True)
-        kw = dict(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1)
-        if sweep_fmt != handle_fmt:
-            kw.update(bulk_format=sweep_fmt, finish_format=sweep_fmt)
-        st, res, _ = lat.gauge_fix(**kw)
-        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+        if driver == "session":
+            lgf.lgf_autotune_fixed(lat.h, sweep_fmt, 2)
+            lat.fix_begin(sweep_fmt)
+            F, th, _ = lat.fix_chunk(1, omega)
+            lat.fix_end()
+            res = {"F": F, "theta": th}
+        else:
+            kw = dict(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1)
+            if sweep_fmt != handle_fmt:
+                kw.update(bulk_format=sweep_fmt, finish_format=sweep_fmt)
+            st, res, _ = lat.gauge_fix(**kw)
+            assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
         ys, gots, refs = [], [], []
         for y in sample_sites(orc, dims, 1, 8, rng):
             links = np.zeros((8, 3, 3), dtype=np.complex128)
