@@ -566,7 +566,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+        print(f"bench.py: this implementation runs on one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE {world}); the multi-GPU split is a design, not an implementation.",
               file=sys.stderr)
         sys.exit(2)

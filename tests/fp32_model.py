@@ -11,7 +11,7 @@ than a random one; how far a link can move under them is set by the link's
 conditioning (an SU(2) subproblem with |a| small against |W| amplifies the
 rounding of W by |W|/|a|).  The envelope of a link is the largest error of
 N independent runs; the bar on a link is twice that, plus one unit u, and
-the benchmark spec's 2e-6 still holds for 99 % of the links.  The CPU tests check
+the stated 2e-6 still holds for 99 % of the links.  The CPU tests check
 that exact IEEE FP32 evaluations of the same steps in two different operation
 orders stay within the bar on every link.
 
