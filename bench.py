@@ -494,6 +494,42 @@ def link64_bench(lgf, torch, stream, dims, seed, eps, omega):
     return out
 
 
+def or_kernels_32x4(lgf, stream, omega):
+    """The paper's single-GPU measurement (Sec. 4, Fig. 1: the overrelaxation
+    kernel on a 32^4 lattice in single, mixed and double precision), per
+    storage format: site updates per second of one launch (a half-sweep) of
+    the link-rewriting sweep (autotuned) and of the fixed-link sweep
+    (its autotuned variant, inside a stepwise session), with the launch's
+    algorithmic bytes.  The 32^4 field (seed 1, eps 0.25, Haar gauge) is
+    generated on the device."""
+    dims = (32, 32, 32, 32)
+    Vh = 32 ** 4 // 2
+    out = {"dims": list(dims)}
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP32_18, lgf.LGF_FP64_12, lgf.LGF_FP64_18):
+        h = lgf.lgf_create(dims, fmt, stream)
+        lgf.lgf_generate_links(h, 1, 0.25, True)
+        lgf.lgf_autotune(h, fmt, 4)
+        lgf.lgf_time_sweeps(h, 20, omega)
+        ms = lgf.lgf_time_sweeps(h, 100, omega)
+        lgf.lgf_destroy(h)
+        out[f"link_sweep_{lgf.FORMAT_NAMES[fmt]}"] = {
+            "ms_per_launch": ms, "site_updates_per_s": Vh / (ms * 1e-3),
+            "GBs": Vh * 16 * LINK_BYTES[fmt] / (ms * 1e-3) / 1e9}
+    h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
+    lgf.lgf_generate_links(h, 1, 0.25, True)
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+        lgf.lgf_autotune_fixed(h, fmt, 4)
+        lgf.lgf_fix_begin(h, fmt)
+        lgf.lgf_fix_chunk(h, 20, omega)
+        ms = sum(lgf.lgf_fix_chunk(h, 20, omega, 0.0, 0, 20 * (k + 1))[2] for k in range(5)) / (5 * 40)
+        lgf.lgf_fix_end(h)
+        out[f"fixed_sweep_{lgf.FORMAT_NAMES[fmt]}"] = {
+            "ms_per_launch": ms, "site_updates_per_s": Vh / (ms * 1e-3),
+            "GBs": Vh * fixed_site_bytes(fmt) / (ms * 1e-3) / 1e9}
+    lgf.lgf_destroy(h)
+    return out
+
+
 def anneal_bench(lgf, torch, stream, dims, seed, eps, omega):
     """Simulated annealing on the 64^4 workload (FP64-12 handle, link-
     rewriting heat-bath sweeps): the sweep rate of a 100-sweep schedule
@@ -556,7 +592,7 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
     ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
-    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64", "anneal"),
+    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64", "anneal", "or32"),
                     help="run only this extra workload and print its JSON")
     args = ap.parse_args()
     if args.summarize_traffic:
@@ -601,7 +637,8 @@ def main():
         legs = {"coulomb": lambda: coulomb_bench(lgf, stream), "ensemble": lambda: ensemble_bench(lgf, stream),
                 "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream),
                 "link64": lambda: link64_bench(lgf, torch, stream, dims, seed, eps, omega),
-                "anneal": lambda: anneal_bench(lgf, torch, stream, dims, seed, eps, omega)}
+                "anneal": lambda: anneal_bench(lgf, torch, stream, dims, seed, eps, omega),
+                "or32": lambda: or_kernels_32x4(lgf, stream, 1.7)}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
 
@@ -738,6 +775,9 @@ def main():
     lgf.lgf_destroy(hp)
     del work, pristine
     torch.cuda.empty_cache()
+    if not args.no_extras and fits("overrelaxation kernels at 32^4", 30.0):
+        extras["or_kernel_32x4"] = or_kernels_32x4(lgf, stream, 1.7)
+        log(f"[bench] 32^4 overrelaxation kernels: {json.dumps(extras['or_kernel_32x4'])}; {elapsed():.1f} s")
     if not args.no_extras:
         # the small 8^4 workload to theta < 1e-12, plain FP64-18 (its oracle time is in cpu_baseline)
         h8 = lgf.lgf_create((8, 8, 8, 8), home, stream)
