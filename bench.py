@@ -18,10 +18,12 @@ Reported beside it, each run once: time to theta < 1e-14 of the mixed form
 (FP32 12-real bulk, FP64 finish below theta = 1e-8) and of the plain FP64 form
 on the same input, the same with the finish reading the links from a split
 copy (fl32 + 16-bit remainder), the paper's link-rewriting FP64 form, the
-roofline of the dominant kernel from HIP events, and the FP64 CPU oracle
-timed on 10 sweeps of the same 64^4 field.  Optional items are skipped (and
-say so) past a wall-clock budget.  Other workloads run alone through --leg (link64, gauge32, ensemble, coulomb,
-anneal).
+roofline of the dominant kernel from HIP events, the FP64 CPU oracle timed
+on 10 sweeps of the same 64^4 field on all host cores and on one more sweep
+on one core, and the overrelaxation kernels at 32^4 per storage format.
+Optional items are skipped (and say so) past a wall-clock budget.  Other
+workloads run alone through --leg (link64, gauge32, ensemble, coulomb, anneal,
+or32).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--budget 420]
 """
@@ -120,6 +122,13 @@ def cpu_baseline(dims, seed, eps, omega, sweeps, max_seconds):
         if time.perf_counter() - t0 >= max_seconds:
             break
     el = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    # the same oracle on one core: one more full sweep of the same field
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.sweep(dims, U, omega, 0.0, 0, n)
+    el1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
     del U
     V = dims[0] * dims[1] * dims[2] * dims[3]
     d8 = (8, 8, 8, 8)
@@ -127,8 +136,10 @@ def cpu_baseline(dims, seed, eps, omega, sweeps, max_seconds):
     t8 = time.perf_counter()
     r8 = oracle.gauge_fix(d8, U8, 1.7, 1e-12)
     t8 = time.perf_counter() - t8
-    return {"value": V * n / el, "unit": "site-updates/s", "cores": oracle.num_threads(),
+    return {"value": V * n / el, "unit": "site-updates/s", "cores": cores,
             "kind": "oracle",
+            "single_thread": {"value": V / el1, "unit": "site-updates/s", "cores": 1,
+                              "sample": f"1 full OR sweep of the same field, {el1:.1f} s"},
             "sample": f"{n} full OR sweeps (omega {omega}) of the {'x'.join(map(str, dims))} workload's field "
                       f"(seed {seed}, eps {eps}, Haar; generated on the host in {t_gen:.1f} s, not timed), "
                       f"FP64, {el:.1f} s",
@@ -742,7 +753,7 @@ def main():
         mixed = fix_once("mixed_fp32-12_bulk_fp64-12_finish", pm)
         time_to_theta["mixed_s"] = mixed["time_to_theta_s"]
         est = 1.3 * mixed["t_sweep_finish_s"] * mixed["sweeps"] / max(mixed["sweeps"] - mixed["sweeps_bulk"], 1)
-        if fits("plain FP64 time-to-theta", est + args.cpu_seconds + 25.0):
+        if fits("plain FP64 time-to-theta", est + args.cpu_seconds + 40.0):
             p64 = lgf.fix_params(omega=omega, theta_target=theta_target, bulk_format=finish, finish_format=finish,
                                  fixed_links=1)
             plain = fix_once("fp64_fp64-12", p64)
@@ -750,7 +761,7 @@ def main():
             time_to_theta["mixed_speedup_vs_fp64"] = plain["time_to_theta_s"] / mixed["time_to_theta_s"]
             time_to_theta["dF_mixed_vs_fp64"] = mixed["F"] - plain["F"]
     # the CPU baseline before the optional runs (the line needs it)
-    if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 25.0):
+    if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 40.0):
         log("[bench] timing the FP64 oracle on the host")
         cpu = cpu_baseline(dims, seed, eps, omega, args.cpu_sweeps, args.cpu_seconds)
         log(f"[bench] cpu_baseline: {json.dumps(cpu)}; {elapsed():.1f} s")

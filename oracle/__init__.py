@@ -76,6 +76,7 @@ def _load():
         "orc_plaquette": (D, [P, P]),
         "orc_gauge_fix": (I, [P, P, D, D, D, I, I, I64, U64, U32, P, P, P, P, I64, P]),
         "orc_num_threads": (I, []),
+        "orc_set_num_threads": (None, [I]),
         "orc_local_update_coulomb": (None, [P, D, P, P]),
         "orc_half_sweep_coulomb": (None, [P, P, I, D, D, U64, U64, U32, P]),
         "orc_measure_coulomb": (None, [P, P, P, P]),
@@ -371,3 +372,7 @@ def anneal(dims, U: np.ndarray, n_sweeps: int, T_start: float, T_end: float, see
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))

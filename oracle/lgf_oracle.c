@@ -1073,6 +1073,17 @@ int orc_coulomb_gauge_fix(const int dims[4], double *U, double omega, double p, 
     return n_active > 0 ? 1 : 0;
 }
 
+/* Threads for the oracle's later parallel regions (n >= 1; a no-op without
+   OpenMP).  Used only to time the oracle on one core beside all of them. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region of the oracle uses. */
 int orc_num_threads(void)
 {
