@@ -19,8 +19,13 @@
 // storage formats only: its accept-reject decisions must be the ones an FP64
 // computation takes.  Like the relaxation sweep the update reads and writes
 // the 8 links of a site once (HBM bound for the links; the transcendental
-// functions of 1-2 trials per subgroup add ~20 % arithmetic); two lanes per
-// site hold two directions each, so the gathered links fit the registers.
+// functions of 1-2 trials per subgroup add ~20 % arithmetic).  The heat bath
+// is the arithmetic of a whole site, so every lane that shares a site repeats
+// it: on FP64-12 links one lane holds all 8 links of its site (96 VGPRs of
+// rows 0 and 1; the kernel runs one wave per SIMD with part of its state in
+// the accumulation registers) and the heat bath is paid once per site, 1.4-1.5x
+// faster than two lanes per site; the 8 FP64-18 links do not fit one lane, so
+// that format keeps two lanes per site, each holding two directions.
 #include <type_traits>
 
 #include "lgf_device.hpp"
@@ -119,14 +124,16 @@ __device__ __forceinline__ uint32_t heatbath_step(mat3<double> &W, mat3<double> 
     return trials;
 }
 
-constexpr int kSaLanes = 2;    // lanes per site
+// lanes per site: 1 on FP64-12 links, 2 on FP64-18 links
+template <int F> constexpr int sa_lanes() { return F == kF64_12 ? 1 : 2; }
 constexpr int kSaBlock = 128;  // lanes per workgroup
 
-// One annealing half-sweep over the sites of one parity, two lanes per site
-// (lane l gathers and stores directions l and l + 2).  Both lanes of a site
-// run the same heat-bath steps on the same K and the same random words, so
-// they hold the same G.  trials (may be NULL) accumulates the accept-reject
-// trials of the launch: a wave sum, then one 64-bit atomic add per wave.
+// One annealing half-sweep over the sites of one parity, LANES lanes per site
+// (lane l gathers and stores directions l, l + LANES, ...).  With two lanes
+// both run the same heat-bath steps on the same K and the same random words,
+// so they hold the same G.  trials (may be NULL) accumulates the
+// accept-reject trials of the launch: a wave sum, then one 64-bit atomic add
+// per wave.
 template <int F>
 __global__ void __launch_bounds__(kSaBlock) anneal_kernel(void *__restrict__ field, Geom g, int parity, double temp,
                                                           uint32_t sweep, uint32_t instance, uint32_t k0, uint32_t k1,
@@ -134,11 +141,12 @@ __global__ void __launch_bounds__(kSaBlock) anneal_kernel(void *__restrict__ fie
 {
     static_assert(std::is_same<typename Fmt<F>::T, double>::value, "the heat bath runs on FP64 links");
     using S = Fmt<F>;
-    constexpr int NL = 4 / kSaLanes;
+    constexpr int LANES = sa_lanes<F>();
+    constexpr int NL = 4 / LANES;
     // Vh <= 2^30, so blockIdx * blockDim + lane < 2^32
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t grp = tid / kSaLanes;
-    const int lane = (int)(tid % kSaLanes);
+    const uint32_t grp = tid / LANES;
+    const int lane = (int)(tid % LANES);
     const bool active = grp < g.Vh;
     const uint32_t h = active ? grp : g.Vh - 1;
     const Site c = decode(g, parity, h);
@@ -147,7 +155,7 @@ __global__ void __launch_bounds__(kSaBlock) anneal_kernel(void *__restrict__ fie
     uint32_t hb[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        const int mu = lane + k * kSaLanes;
+        const int mu = lane + k * LANES;
         hb[k] = back_half(g, c, h, mu);
         load_link<F, true>(uf[k], block_ptr<F>(field, g.Vh, parity, mu), g.Vh, h);
         load_link<F, true>(ub[k], block_ptr<F>(field, g.Vh, parity ^ 1, mu), g.Vh, hb[k]);
@@ -156,13 +164,15 @@ __global__ void __launch_bounds__(kSaBlock) anneal_kernel(void *__restrict__ fie
     set_zero(K);
 #pragma unroll
     for (int k = 0; k < NL; ++k) add_fwd_bwd(K, uf[k], ub[k]);
+    if constexpr (LANES == 2) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            K.e[i][j].re += shfl_xor_t(K.e[i][j].re, 1);
-            K.e[i][j].im += shfl_xor_t(K.e[i][j].im, 1);
-        }
+            for (int j = 0; j < 3; ++j) {
+                K.e[i][j].re += shfl_xor_t(K.e[i][j].re, 1);
+                K.e[i][j].im += shfl_xor_t(K.e[i][j].im, 1);
+            }
+    }
 
     const SaKey key{lex_index(g, c), sweep, instance, k0, k1};
     mat3<double> G;
@@ -174,7 +184,7 @@ __global__ void __launch_bounds__(kSaBlock) anneal_kernel(void *__restrict__ fie
     if (active) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int mu = lane + k * kSaLanes;
+            const int mu = lane + k * LANES;
             mat3<double> r, rb;
             left_mul<S::R>(r, G, uf[k]);
             right_mul_dag<S::R>(rb, ub[k], G);
@@ -194,7 +204,7 @@ template <int F>
 hipError_t launch_anneal_f(void *field, const Geom &g, int parity, double temp, uint64_t seed, uint64_t sweep,
                            uint32_t instance, unsigned long long *trials, hipStream_t s)
 {
-    const uint64_t threads = (uint64_t)g.Vh * kSaLanes;
+    const uint64_t threads = (uint64_t)g.Vh * sa_lanes<F>();
     const uint32_t nb = (uint32_t)((threads + kSaBlock - 1) / kSaBlock);
     hipLaunchKernelGGL((anneal_kernel<F>), dim3(nb), dim3(kSaBlock), 0, s, field, g, parity, temp, (uint32_t)sweep,
                        instance, (uint32_t)seed, (uint32_t)(seed >> 32), trials);
