@@ -58,8 +58,18 @@ KERNEL_SOURCES = ["paper_1305_3440_amd/csrc/lgf_kernels.hip", "paper_1305_3440_a
 # sweep variants the counter passes cover: (lanes per site, block, xcd remap, non-temporal, schedule)
 TRAFFIC_VARIANTS = [(1, 128, 0, 1, 0), (2, 128, 0, 1, 0), (4, 128, 0, 1, 0), (1, 128, 0, 1, 2),
                     (2, 128, 0, 1, 2), (4, 128, 0, 1, 2), (1, 128, 0, 0, 0), (2, 128, 0, 0, 0)]
-# fixed-link sweep variants the counter passes cover: (lanes per site, block, tile order)
-TRAFFIC_FIXED_VARIANTS = [(lps, block, order) for lps in (2, 4) for block in (64, 128, 256) for order in (0, 1, 2)]
+# fixed-link sweep variants the counter passes cover, per sweep format:
+# (lanes per site, block, tile order, link layout)
+TRAFFIC_FIXED_VARIANTS = {
+    2: [(lps, block, order, layout) for lps in (1, 2) for block in (64, 128, 256) for order in (0, 3)
+        for layout in (0, 1)],
+    3: [(2, block, order, layout) for block in (64, 128, 256) for order in (0, 2, 3) for layout in (0, 1)] +
+       [(4, 256, order, layout) for order in (2, 3) for layout in (0, 1)],
+    4: [(2, block, order, 0) for block in (64, 128, 256) for order in (0, 2, 3)],
+}
+FIXED_TUNING_KEYS = ("lanes_per_site", "block", "order", "layout")
+TILE_ORDERS = ["lexicographic", "XCD ranges", "t-z blocks per XCD", "lockstep planes, an eighth per XCD"]
+LINK_LAYOUTS = ["link field", "per-site link records"]
 TRAFFIC_FIXED_SWEEPS = 4   # full sweeps per variant: 2 x 3 plain launches + the chunk's last sweep
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_64x4_hbm_traffic.json")
 
@@ -83,10 +93,10 @@ def traffic_key(fmt: int, lanes: int, nontemporal: int, schedule: int, dims) -> 
             f"{'x'.join(map(str, dims))}")
 
 
-def fixed_traffic_key(fmt: int, lanes: int, block: int, order: int, dims) -> str:
+def fixed_traffic_key(fmt: int, lanes: int, block: int, order: int, layout: int, dims) -> str:
     """Key of one fixed-link sweep variant on one lattice (the tile order and
     the workgroup size set which neighbouring g come from the caches)."""
-    return f"fixed:fmt{fmt}:lanes{lanes}:block{block}:order{order}:{'x'.join(map(str, dims))}"
+    return f"fixed:fmt{fmt}:lanes{lanes}:block{block}:order{order}:layout{layout}:{'x'.join(map(str, dims))}"
 
 
 def measured_traffic(key: str):
@@ -171,7 +181,7 @@ def traffic_run(lgf, torch, dims, seed, eps, omega):
     h = lgf.lgf_create(dims, lgf.LGF_FP64_18, stream)
     lgf.lgf_generate_links(h, seed, eps, True)
     for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_12S):
-        for v in TRAFFIC_FIXED_VARIANTS:
+        for v in TRAFFIC_FIXED_VARIANTS[fmt]:
             lgf.lgf_set_fixed_tuning(h, fmt, *v)
             p = lgf.fix_params(omega=omega, theta_target=1e-300, check_every=TRAFFIC_FIXED_SWEEPS,
                                max_sweeps=TRAFFIC_FIXED_SWEEPS, fixed_links=1, use_graph=0, bulk_format=fmt,
@@ -199,9 +209,9 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     hash so a stale figure is never reported."""
     import csv
     per = {}
-    fixed_seq = {}  # (counter, format, lanes) -> plain fixed-sweep readings in dispatch order
-    # fixed_sweep_kernel<format, lanes, SR, post, mu0>: the plain Landau instances
-    fixed_pat = re.compile(r"fixed_sweep_kernel<(\d+),\s*(\d+),\s*false,\s*0,\s*0>")
+    fixed_seq = {}  # (counter, format, lanes, layout) -> plain fixed-sweep readings in dispatch order
+    # fixed_sweep_kernel<format, lanes, SR, post, mu0, records>: the plain Landau instances
+    fixed_pat = re.compile(r"fixed_sweep_kernel<(\d+),\s*(\d+),\s*false,\s*0,\s*0,\s*(true|false)>")
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         with open(_find(d, "counter_collection.csv")) as f:
             rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
@@ -210,8 +220,8 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
             per.setdefault((counter, row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
             m = fixed_pat.search(row["Kernel_Name"])
             if m:
-                fixed_seq.setdefault((counter, int(m.group(1)), int(m.group(2))), []).append(
-                    float(row["Counter_Value"]))
+                fixed_seq.setdefault((counter, int(m.group(1)), int(m.group(2)), int(m.group(3) == "true")),
+                                     []).append(float(row["Counter_Value"]))
     copy_bytes = float(1 << 30)
     out = {"source_sha": kernel_source_sha(), "command": command, "kernels": {}, "calibration": {}}
     scale = {}
@@ -238,15 +248,17 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     # the fixed-link sweep: the plain (no reunitarization) launches of each
     # variant, 2 (TRAFFIC_FIXED_SWEEPS - 1) per variant, in the traffic run's order
     per_variant = 2 * (TRAFFIC_FIXED_SWEEPS - 1)
-    for (counter, fmt, lanes), vals in fixed_seq.items():
-        vs = [v for v in TRAFFIC_FIXED_VARIANTS if v[0] == lanes]
+    for (counter, fmt, lanes, layout), vals in fixed_seq.items():
+        vs = [v for v in TRAFFIC_FIXED_VARIANTS.get(fmt, []) if v[0] == lanes and v[3] == layout]
         for i, v in enumerate(vs):
             chunk = vals[i * per_variant:(i + 1) * per_variant]
             if len(chunk) != per_variant:
                 continue
-            key = fixed_traffic_key(fmt, v[0], v[1], v[2], dims)
-            e = out["kernels"].setdefault(key, {"kernel": f"fixed_sweep_kernel<{fmt}, {lanes}, false, 0, 0>",
-                                                "format": fmt, "fixed": True, "block": v[1], "order": v[2]})
+            key = fixed_traffic_key(fmt, v[0], v[1], v[2], v[3], dims)
+            e = out["kernels"].setdefault(key, {"kernel": f"fixed_sweep_kernel<{fmt}, {lanes}, false, 0, 0, "
+                                                          f"{'true' if layout else 'false'}>",
+                                                "format": fmt, "fixed": True, "block": v[1], "order": v[2],
+                                                "layout": v[3]})
             e[counter.lower() + "_bytes_per_launch"] = sum(chunk) / len(chunk) * scale[counter]
             e[counter.lower() + "_dispatches"] = len(chunk)
     for key, e in out["kernels"].items():
@@ -678,7 +690,7 @@ def main():
     lgf.lgf_autotune_fixed(hw, bulk, 4)
     torch.cuda.synchronize()
     fixed_tuning = {f: lgf.lgf_get_fixed_tuning(hw, f) for f in (bulk, finish)}
-    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning (lanes, block, order) "
+    log(f"[bench] {dims} V={V} generated; field {nbytes / 1e9:.2f} GB; fixed-link tuning {FIXED_TUNING_KEYS} "
         f"fp64-12 {fixed_tuning[finish]} fp32-12 {fixed_tuning[bulk]}; {elapsed():.1f} s")
 
     # ---- the timed steps: check intervals of the FP64 gauge fixing
@@ -705,14 +717,14 @@ def main():
 
     # roofline of the dominant kernel (the step's sweep), from the HIP events
     # the library records around each chunk's sweeps on the launch stream
-    lanes, block, order = fixed_tuning[finish]
+    lanes, block, order, layout = fixed_tuning[finish]
     by = Vh * fixed_site_bytes(finish)
     achieved = by / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(fixed_traffic_key(finish, lanes, block, order, dims))
+    traffic = measured_traffic(fixed_traffic_key(finish, lanes, block, order, layout, dims))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"fixed_sweep_kernel<fp64-12, lanes/site {lanes}> block {block}, tile order "
-                          f"{['lexicographic', 'XCD ranges', 't-z blocks per XCD'][order]}",
+                          f"{TILE_ORDERS[order]}, links from the {LINK_LAYOUTS[layout]}",
                 "avg_launch_ms": round(launch_ms, 4), "launches": 2 * chunk * args.steps,
                 "bytes_per_launch": by,
                 "basis": f"{Vh} site updates per launch x {fixed_site_bytes(finish)} B: the fixed-link form "
@@ -816,11 +828,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) Landau overrelaxation (omega {omega}): one step = "
                                f"{chunk} full sweeps of the fixed-link form (FP64 arithmetic, links and g in "
-                               f"FP64 12-real storage) from a hipGraph + FP64 reunitarization of g + FP64 "
-                               f"F/theta measurement",
+                               f"FP64 12-real storage, the links read from the {LINK_LAYOUTS[layout]}) from a "
+                               f"hipGraph + FP64 reunitarization of g + FP64 F/theta measurement",
                    "dims": list(dims), "seed": seed, "eps": eps, "haar": True, "omega": omega,
                    "sweeps_per_step": chunk, "theta_after_steps": steps[-1][1],
-                   "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(("lanes_per_site", "block", "order"), t))
+                   "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(FIXED_TUNING_KEYS, t))
                                           for f, t in fixed_tuning.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -351,26 +351,46 @@ lgf_status lgf_get_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tu
 lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
 
 /* Tuning of the fixed-link sweep (lgf_fix_params.fixed_links) per sweep
- * format (LGF_FP64_12S included, the default that of the FP64 formats):
- * lanes_per_site 2 or 4 (one lane per site does not fit the registers),
- * block 64, 128 or 256, xcd_remap 0 (lexicographic tiles), 1 (contiguous
- * ranges per XCD) or 2 (each XCD takes blocks of 8, 4 or 2 t-slices x z-planes,
- * walked z, t, then y, so that the neighbouring g a site update reads were
- * read by a nearby workgroup of the same XCD; lexicographic where the lattice
- * does not divide into a multiple of 8 such blocks); sites_per_thread must be 1,
- * nontemporal 1 (links and g(x) are streamed, the neighbouring g go through
- * the caches) and schedule 0.  Default: 2 lanes; FP64 formats 64-lane
- * workgroups, order 2; FP32 formats 256-lane workgroups, order 0.  LGF_EINVAL
- * on other values. */
+ * format (LGF_FP64_12S included):
+ *  lanes_per_site 2 or 4, or 1 in the FP32 formats (in FP64 one lane per site
+ *    takes all 512 registers and runs slower);
+ *  block 64, 128 or 256;
+ *  xcd_remap = tile order: 0 lexicographic tiles; 1 contiguous ranges per
+ *    XCD; 2 each XCD takes blocks of 8, 4 or 2 t-slices x z-planes, walked z,
+ *    t, then y, so that the neighbouring g a site update reads were read by a
+ *    nearby workgroup of the same XCD; 3 every XCD walks the (t, z) planes in
+ *    lexicographic order taking its own eighth of each plane, so that the
+ *    neighbouring g were read by the same XCD one plane or one t-slice
+ *    earlier while the 8 XCDs stream through the same region of memory
+ *    (orders 2 and 3 fall back to 0 where the lattice does not divide into
+ *    such blocks or planes of a multiple of 8 tiles);
+ *  schedule = layout of the read-only links: 0 the link field (the handle's
+ *    own, or its copy in the sweep format); 1 (FP32-12 and FP64-12 only)
+ *    per-site link records -- for each parity and tile of 32 consecutive
+ *    sites the 8 links of each site (U_mu(x), then U_mu(x-mu)), so that a
+ *    wavefront reads one contiguous block; a copy of twice the link field's
+ *    size, rebuilt from the field whenever a gauge fixing or session starts
+ *    (Landau gauge; the Coulomb sweeps read the link field whatever this
+ *    says).  The records hold the field's values, and neither layout nor tile
+ *    order changes a bit of the result; without device memory for the
+ *    records the format falls back to layout 0;
+ *  sites_per_thread must be 1 and nontemporal 1 (links and g(x) are streamed,
+ *  the neighbouring g go through the caches).
+ * Default: FP64-12 2 lanes, 128-lane workgroups, order 2, records; FP32-12 1
+ * lane, 128-lane workgroups, order 0, records; the other FP64 formats 2 lanes,
+ * 64-lane workgroups, order 2, layout 0; FP32-18 2 lanes, 256-lane
+ * workgroups, order 0, layout 0.  LGF_EINVAL on other values. */
 lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
 lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
 
 /* Pick the fastest fixed-link sweep variant for `format` on this lattice
- * (lanes 2/4 x block 64/128/256 x tile order 0/1/2; the FP64 formats keep
- * tile order 2 wherever the lattice admits it): each timed over `trials`
- * full sweeps, the fastest again over ten times as many in five interleaved
- * rounds; the default stays unless another is 1 % faster.  The sweeps read the
- * handle's links (or their copy in `format`) and write only the gauge
+ * (lanes 1 (FP32 formats)/2/4 x block 64/128/256 x tile order 0-3 x link
+ * layout 0/1 (FP32-12, FP64-12); the FP64 formats keep tile order 2
+ * wherever the lattice admits it; orders the lattice does not admit are
+ * left out): each timed over `trials` full sweeps, the fastest again over ten
+ * times as many in five interleaved rounds; the default stays unless another
+ * is 1 % faster.  The sweeps read the handle's links (or their copy in
+ * `format`, and its per-site records) and write only the gauge
  * transformation, which lgf_gauge_fix resets: the links are untouched.  Needs
  * an FP64 handle.  Synchronises. */
 lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials);

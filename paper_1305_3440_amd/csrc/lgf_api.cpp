@@ -152,6 +152,7 @@ struct lgf_lattice {
     void *gfix[4];
     lgf::SweepTuning tune_fixed[5];  // per sweep format, LGF_FP64_12S included
     void *split;       // the links in the split storage of LGF_FP64_12S (owned)
+    void *rec[5];      // per-site link records of the 12-real formats (owned)
     // stepwise fixed-link gauge fixing (lgf_fix_begin .. lgf_fix_end)
     bool fix_on;
     int fix_format;
@@ -599,10 +600,13 @@ bool pick_variant(const std::vector<lgf::SweepTuning> &variants, const lgf::Swee
 // transformation g, a site field in the sweep's format.
 // ----------------------------------------------------------------------------
 
-// Starting tuning of the fixed-link sweep: 2 lanes per site (one lane per site
-// does not fit the registers in FP64); FP64 formats in 64-lane workgroups over
-// the blocked tile order, FP32 ones in 256-lane workgroups in lexicographic
-// order (the fastest measured at 64^4).
+// Starting tuning of the fixed-link sweep (the fastest measured at 64^4):
+// FP64-12 with 2 lanes per site (one lane runs one wave per SIMD in FP64) in
+// 128-lane workgroups over the blocked tile order on per-site link records;
+// FP32-12 with one lane per site in 128-lane workgroups, lexicographic, on
+// records; the other FP64 formats with 2 lanes in 64-lane workgroups over the
+// blocked tile order, FP32-18 with 2 lanes in 256-lane workgroups,
+// lexicographic.
 lgf::SweepTuning default_fixed_tuning(int format)
 {
     lgf::SweepTuning t{};
@@ -610,6 +614,14 @@ lgf::SweepTuning default_fixed_tuning(int format)
     const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12 || format == LGF_FP64_12S);
     t.block = fp64 ? 64 : 256;
     t.xcd_remap = fp64 ? 2 : 0;
+    if (format == LGF_FP64_12) {
+        t.block = 128;
+        t.schedule = lgf::kLayoutRecords;
+    } else if (format == LGF_FP32_12) {
+        t.lanes_per_site = 1;
+        t.block = 128;
+        t.schedule = lgf::kLayoutRecords;
+    }
     return t;
 }
 
@@ -662,6 +674,52 @@ lgf_status links_in_format(lgf_lattice *h, int format, void **links)
     return LGF_OK;
 }
 
+// whether the Landau fixed-link sweeps in `format` read per-site link records
+bool fixed_records(const lgf_lattice *h, int format)
+{
+    return h->tune_fixed[format].schedule == lgf::kLayoutRecords;
+}
+
+// the per-site link records of format (a 12-real format) built from its link
+// field, in h->rec[format]; false (and nothing built) without memory for them
+lgf_status build_records(lgf_lattice *h, int format, bool *built)
+{
+    *built = false;
+    void *planes = nullptr;
+    LGF_TRY(links_in_format(h, format, &planes));
+    if (!h->rec[format]) {
+        const size_t bytes = lgf::record_links_bytes(format, h->geom);
+        if (bytes == 0) return fail(LGF_EINVAL, "format %d has no per-site link records", format);
+        if (hipMalloc(&h->rec[format], bytes) != hipSuccess) {
+            h->rec[format] = nullptr;
+            (void)hipGetLastError();
+            return LGF_OK;
+        }
+    }
+    LGF_HIP(lgf::launch_record_links(format, planes, h->rec[format], h->geom, h->stream));
+    *built = true;
+    return LGF_OK;
+}
+
+// the links of the Landau fixed-link sweeps in `format`, laid out as the
+// format's tuning reads them: the link field (links_in_format) or its
+// per-site records.  Without memory for the records the tuning falls back to
+// the link field.
+lgf_status fixed_links(lgf_lattice *h, int format, void **links)
+{
+    if (fixed_records(h, format)) {
+        bool built = false;
+        LGF_TRY(build_records(h, format, &built));
+        if (built) {
+            *links = h->rec[format];
+            return LGF_OK;
+        }
+        h->tune_fixed[format].schedule = lgf::kLayoutPlanes;
+        drop_graphs(h);
+    }
+    return links_in_format(h, format, links);
+}
+
 // n full sweeps in the fixed-link form.  The chunk's last sweep stores every g
 // reunitarized (both half-sweeps); with fused, its parity-1 half-sweep also
 // leaves the (F, theta) partial sums of its sites in h->d_fused.
@@ -710,14 +768,16 @@ lgf_status measure_fixed_field(lgf_lattice *h, int format, const void *links, co
     int n0 = 0, n1 = 0;
     if (fused) {
         const int ng = (int)lgf::fixed_sweep_groups(h->geom, h->tune_fixed[format]);
-        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused + 2 * (size_t)ng, &n0, h->stream));
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused + 2 * (size_t)ng, &n0, h->stream,
+                                          fixed_records(h, format)));
         LGF_HIP(lgf::launch_finish_measure(h->d_fused, ng + n0, (double)h->V, h->d_out, h->stream));
     } else {
         // the two passes' partial sums in the fused-measurement buffer
         LGF_TRY(ensure_fused_cap(h, 2 * (size_t)lgf::fixed_measure_blocks(h->geom)));
-        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused, &n0, h->stream));
+        LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 0, h->d_fused, &n0, h->stream,
+                                          fixed_records(h, format)));
         LGF_HIP(lgf::launch_measure_fixed(format, links, gf, h->geom, 1, h->d_fused + 2 * (size_t)n0, &n1,
-                                          h->stream));
+                                          h->stream, fixed_records(h, format)));
         LGF_HIP(lgf::launch_finish_measure(h->d_fused, n0 + n1, (double)h->V, h->d_out, h->stream));
     }
     LGF_HIP(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -785,7 +845,7 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
     if (status == LGF_ENOTCONV && p.max_sweeps > 0) {
         LGF_TRY(ensure_gfix(h, cur));
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-            LGF_TRY(links_in_format(h, cur, &links));
+            LGF_TRY(fixed_links(h, cur, &links));
             LGF_HIP(lgf::launch_site_field(gf_format(cur), gfix_of(h, cur), h->geom, 0, h->stream));
             return LGF_OK;
         }));
@@ -816,7 +876,7 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
                 // formats agree)
                 LGF_TRY(ensure_gfix(h, finish));
                 LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-                    LGF_TRY(links_in_format(h, finish, &links));
+                    LGF_TRY(fixed_links(h, finish, &links));
                     // FP64-12 and the split format share one g field (stored
                     // reunitarized by the chunk's last sweep): nothing to hand over
                     if (gf_format(bulk) != gf_format(finish))
@@ -861,7 +921,7 @@ lgf_status gauge_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, in
                     if (sweeps < p.max_sweeps) {
                         LGF_TRY(ensure_gfix(h, LGF_FP64_12));
                         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-                            LGF_TRY(links_in_format(h, LGF_FP64_12, &links));
+                            LGF_TRY(fixed_links(h, LGF_FP64_12, &links));
                             LGF_HIP(lgf::launch_site_field(LGF_FP64_12, gfix_of(h, LGF_FP64_12), h->geom, 0,
                                                            h->stream));
                             return LGF_OK;
@@ -1142,6 +1202,8 @@ lgf_status lgf_destroy(lgf_lattice *h)
         if (h->gfix[f]) (void)hipFree(h->gfix[f]);
     }
     if (h->split) (void)hipFree(h->split);
+    for (int f = 0; f < 5; ++f)
+        if (h->rec[f]) (void)hipFree(h->rec[f]);
     if (h->d_partials) (void)hipFree(h->d_partials);
     if (h->d_fused) (void)hipFree(h->d_fused);
     if (h->d_sweep_base) (void)hipFree(h->d_sweep_base);
@@ -1508,7 +1570,7 @@ lgf_status lgf_fix_begin(lgf_lattice *h, int format)
     LGF_TRY(use_device(h));
     void *links = nullptr;
     LGF_TRY(ensure_gfix(h, format));
-    LGF_TRY(links_in_format(h, format, &links));
+    LGF_TRY(fixed_links(h, format, &links));
     LGF_HIP(lgf::launch_site_field(gf_format(format), gfix_of(h, format), h->geom, 0, h->stream));
     LGF_HIP(hipStreamSynchronize(h->stream));
     h->fix_format = format;
@@ -1959,16 +2021,20 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
     if (!h || !t) return fail(LGF_EINVAL, "NULL handle or tuning");
     if (!valid_fixed_format(format)) return fail(LGF_EINVAL, "unknown format %d", format);
     const lgf_sweep_tuning u = *t;
-    if (u.lanes_per_site != 2 && u.lanes_per_site != 4)
-        return fail(LGF_EINVAL, "the fixed-link sweep takes lanes_per_site 2 or 4");
+    if (!(u.lanes_per_site == 2 || u.lanes_per_site == 4 ||
+          (u.lanes_per_site == 1 && lgf::fixed_one_lane_format(format))))
+        return fail(LGF_EINVAL, "the fixed-link sweep takes lanes_per_site 2 or 4 (or 1 in the FP32 formats)");
     if (u.block != 64 && u.block != 128 && u.block != 256) return fail(LGF_EINVAL, "block must be 64, 128 or 256");
-    if (u.xcd_remap < 0 || u.xcd_remap > 2) return fail(LGF_EINVAL, "xcd_remap must be 0, 1 or 2");
-    if (u.sites_per_thread != 1 || u.nontemporal != 1 || u.schedule != lgf::kScheduleInPlace)
-        return fail(LGF_EINVAL, "the fixed-link sweep takes sites_per_thread 1, nontemporal 1, schedule 0");
+    if (u.xcd_remap < 0 || u.xcd_remap > 3) return fail(LGF_EINVAL, "xcd_remap (tile order) must be 0, 1, 2 or 3");
+    if (u.sites_per_thread != 1 || u.nontemporal != 1)
+        return fail(LGF_EINVAL, "the fixed-link sweep takes sites_per_thread 1, nontemporal 1");
+    if (!(u.schedule == lgf::kLayoutPlanes || (u.schedule == lgf::kLayoutRecords && lgf::fixed_records_format(format))))
+        return fail(LGF_EINVAL, "schedule (link layout) must be 0, or 1 (per-site records) in FP32-12 and FP64-12");
     lgf::SweepTuning n{};
     n.lanes_per_site = u.lanes_per_site;
     n.block = u.block;
     n.xcd_remap = u.xcd_remap;
+    n.schedule = u.schedule;
     h->tune_fixed[format] = n;
     drop_graphs(h);
     return LGF_OK;
@@ -1998,19 +2064,26 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
         return fail(LGF_EINVAL, "the fixed-link form needs an FP64 handle");
     LGF_TRY(use_device(h));
     // The fixed-link sweeps only read the links (the handle's own, or their
-    // working copy in this format) and write the gauge transformation, which
-    // the gauge fixing resets before use: nothing needs saving.
-    void *links = nullptr;
+    // working copy in this format, and its per-site records) and write the
+    // gauge transformation, which the gauge fixing resets before use: nothing
+    // needs saving.
+    void *links = nullptr, *records = nullptr;
     LGF_TRY(ensure_gfix(h, format));
     LGF_TRY(links_in_format(h, format, &links));
+    if (lgf::fixed_records_format(format)) {
+        bool built = false;
+        LGF_TRY(build_records(h, format, &built));
+        if (built) records = h->rec[format];
+    }
     void *gf = gfix_of(h, format);
     LGF_HIP(lgf::launch_site_field(gf_format(format), gf, h->geom, 0, h->stream));
     hipError_t e = hipSuccess;
     auto sweep = [&](const lgf::SweepTuning &t) {
+        const void *l = (t.schedule == lgf::kLayoutRecords) ? records : links;
         lgf::SweepArgs a{0, 1.7, 0.0, 0, 0, 0u};
-        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, 0, h->stream);
+        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, l, gf, h->geom, a, t, 0, h->stream);
         a.parity = 1;
-        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, links, gf, h->geom, a, t, 0, h->stream);
+        if (e == hipSuccess) e = lgf::launch_fixed_sweep(format, l, gf, h->geom, a, t, 0, h->stream);
     };
     auto time_variant = [&](const lgf::SweepTuning &t, int n, double *ms) {
         sweep(t);
@@ -2022,7 +2095,8 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
         *ms = elapsed_ms(h->ev0, h->ev1) / n;
         return true;
     };
-    const lgf::SweepTuning dflt = default_fixed_tuning(format);
+    lgf::SweepTuning dflt = default_fixed_tuning(format);
+    if (!records) dflt.schedule = lgf::kLayoutPlanes;
     // warm-up under the same sustained load, as for the link sweeps
     const auto w0 = std::chrono::steady_clock::now();
     for (int k = 0; k < 2000 && e == hipSuccess; k += 20) {
@@ -2031,23 +2105,32 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
         if (std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count() > 3.0) break;
     }
     // FP64 sweep formats keep the blocked tile order wherever the lattice
-    // admits it: it reads each neighbouring g about once (counted HBM traffic
-    // 1.05-1.07x the algorithmic bytes at 64^4, against 1.2-1.4x for the
-    // other orders, which win only within the timing noise)
+    // admits it: it reads each neighbouring g about once (counted
+    // L2-to-memory traffic 1.06-1.07x the algorithmic bytes at 64^4, against
+    // 1.2x for the lockstep order and 1.2-1.4x for the lexicographic one, which
+    // are no faster); an order the lattice does not admit would run as order 0
+    // and is left out
     const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12 || format == LGF_FP64_12S);
     std::vector<lgf::SweepTuning> variants;
-    for (int lps : {2, 4})
+    for (int lps : {1, 2, 4}) {
+        if (lps == 1 && !lgf::fixed_one_lane_format(format)) continue;
         for (int block : {64, 128, 256}) {
             lgf::SweepTuning t{};
             t.lanes_per_site = lps;
             t.block = block;
-            const bool blocked = fp64 && lgf::fixed_blocked_order(h->geom, t);
-            for (int order = 0; order < 3; ++order) {
+            const bool blocked = fp64 && lgf::fixed_order_admitted(h->geom, t, 2);
+            for (int order = 0; order < 4; ++order) {
+                if (order >= 2 && !lgf::fixed_order_admitted(h->geom, t, order)) continue;
                 if (blocked && order != 2) continue;
                 t.xcd_remap = order;
-                variants.push_back(t);
+                for (int layout : {lgf::kLayoutPlanes, lgf::kLayoutRecords}) {
+                    if (layout == lgf::kLayoutRecords && !records) continue;
+                    t.schedule = layout;
+                    variants.push_back(t);
+                }
             }
         }
+    }
     lgf::SweepTuning best = h->tune_fixed[format];
     const bool ok = e == hipSuccess &&
                     pick_variant(variants, dflt, trials, "lgf_autotune_fixed", format, time_variant, &best);

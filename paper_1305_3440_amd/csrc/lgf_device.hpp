@@ -174,16 +174,11 @@ __device__ __forceinline__ typename Fmt<F>::V *block_ptr(void *field, uint32_t V
            (size_t)((parity * 4 + mu) * Fmt<F>::NV) * Vh;
 }
 
-// ROW2 = false leaves row 2 of a 12-real link unset (for callers that only
-// read rows 0 and 1)
-template <int F, bool NT = false, bool ROW2 = true>
-__device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *blk,
-                                          uint32_t Vh, uint32_t h)
+// the NV vectors of one link, row-major, into a matrix (rows 0..R-1)
+template <int F>
+__device__ __forceinline__ void unpack_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *v)
 {
     using S = Fmt<F>;
-    typename S::V v[S::NV];
-#pragma unroll
-    for (int k = 0; k < S::NV; ++k) v[k] = vload<NT>(blk + (size_t)k * Vh + h);
     if constexpr (S::CPV == 1) {
 #pragma unroll
         for (int k = 0; k < S::NV; ++k) u.e[k / 3][k % 3] = {v[k].x, v[k].y};
@@ -194,7 +189,54 @@ __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typ
             u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v[k].z, v[k].w};
         }
     }
+}
+
+// ROW2 = false leaves row 2 of a 12-real link unset (for callers that only
+// read rows 0 and 1)
+template <int F, bool NT = false, bool ROW2 = true>
+__device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typename Fmt<F>::V *blk,
+                                          uint32_t Vh, uint32_t h)
+{
+    using S = Fmt<F>;
+    typename S::V v[S::NV];
+#pragma unroll
+    for (int k = 0; k < S::NV; ++k) v[k] = vload<NT>(blk + (size_t)k * Vh + h);
+    unpack_link<F>(u, v);
     if constexpr (S::R == 2 && ROW2) rebuild_row2(u);
+}
+
+// Per-site link records: a read-only copy of a 12-real link field for the
+// sweeps that keep the links fixed.  For each parity, the sites are grouped
+// in tiles of kRecTile consecutive half indices; a tile holds, for each of
+// its sites, the 8 links one site update reads -- U_mu(x) in slot mu and
+// U_mu(x - mu) in slot 4 + mu -- vector by vector across the tile's sites:
+//     vector index = ((parity * rec_tiles(Vh) + h / T) * 8 + slot) * NV * T
+//                    + k * T + h % T,    T = kRecTile, k < NV
+// so the 8 links of a wavefront's 32 sites are one contiguous block (every
+// link is stored twice, once with each end; a last partial tile is padded).
+constexpr uint32_t kRecTile = 32;
+__host__ __device__ inline uint32_t rec_tiles(uint32_t Vh) { return (Vh + kRecTile - 1) / kRecTile; }
+
+template <int F>
+__device__ __forceinline__ const typename Fmt<F>::V *rec_ptr(const void *rec, uint32_t Vh, int parity, int slot,
+                                                             uint32_t h)
+{
+    return reinterpret_cast<const typename Fmt<F>::V *>(rec) +
+           (((size_t)parity * rec_tiles(Vh) + h / kRecTile) * 8 + (size_t)slot) * Fmt<F>::NV * kRecTile +
+           h % kRecTile;
+}
+
+// link `slot` of site h's record, rows 0 and 1 (streamed past the caches)
+template <int F>
+__device__ __forceinline__ void load_link_rec(mat3<typename Fmt<F>::T> &u, const void *rec, uint32_t Vh, int parity,
+                                              int slot, uint32_t h)
+{
+    static_assert(Fmt<F>::R == 2, "records hold 12-real links");
+    const typename Fmt<F>::V *b = rec_ptr<F>(rec, Vh, parity, slot, h);
+    typename Fmt<F>::V v[Fmt<F>::NV];
+#pragma unroll
+    for (int k = 0; k < Fmt<F>::NV; ++k) v[k] = vload<true>(b + (size_t)k * kRecTile);
+    unpack_link<F>(u, v);
 }
 
 template <int F, bool NT = false>

@@ -29,6 +29,12 @@ namespace lgf {
 //           the t-, z- and y-neighbours of a tile are 1, Bz and Bt Bz tiles
 //           earlier or later on the same XCD.  Block k goes to XCD k % 8 (the
 //           dispatch deals workgroup b to XCD b % 8).
+//   mode 3: the (t, z) planes in lexicographic order on all XCDs at once, each
+//           XCD taking its own eighth of every plane (P / 8 consecutive tiles,
+//           P tiles per plane): the y-neighbours of a tile are mostly on its
+//           XCD, its z- and t-neighbours were read by the same XCD one plane
+//           and one t-slice earlier, and the 8 XCDs stream through the same
+//           region of memory together.
 struct TileOrder {
     uint32_t mode;
     uint32_t tile;   // sites per tile
@@ -41,8 +47,8 @@ struct TileOrder {
 // One half-sweep over all Vh sites of a parity, LPS lanes per site; POST as
 // in update_site_fixed, with workgroup b's (F, theta) sums in partials[2b]
 // when POST == 2.  MU0 = 1: Coulomb gauge, with the timeslice flags
-// slice_active.
-template <int F, int LPS, bool SR, int POST, int MU0 = 0>
+// slice_active.  REC: the links are per-site link records.
+template <int F, int LPS, bool SR, int POST, int MU0 = 0, bool REC = false>
 __global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict__ links, void *__restrict__ gf,
                                                           Geom g, int parity, RelaxArgs<typename Fmt<F>::T> a,
                                                           TileOrder o, uint32_t n_groups,
@@ -51,12 +57,18 @@ __global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict
 {
     const uint32_t b = blockIdx.x;
     uint32_t h0;        // first site of the tile (Vh <= 2^30, LPS <= 4)
-    uint32_t slot = b;  // partial-sum slot of the tile, < n_groups
+    uint32_t slot = b;  // partial-sum slot: the tile's index, < n_groups, so
+                        // that the final sum does not depend on the order
     if (o.mode == 2) {
         const uint32_t s = b >> 3, blk = (s / o.tpb) * 8u + (b & 7u), i = s % o.tpb;
         const uint32_t r = i % (o.Bt * o.Bz);
         const uint32_t t = (blk / o.nzb) * o.Bt + r / o.Bz, z = (blk % o.nzb) * o.Bz + r % o.Bz;
         h0 = (t * g.L[1] + z) * o.plane + (i / (o.Bt * o.Bz)) * o.tile;
+        slot = h0 / o.tile;
+    } else if (o.mode == 3) {
+        const uint32_t s = b >> 3, G = o.P >> 3;
+        h0 = (s / G) * o.plane + ((b & 7u) * G + s % G) * o.tile;
+        slot = h0 / o.tile;
     } else if (o.mode == 1) {
         const uint32_t per = gridDim.x >> 3, w = (b & 7u) * per + (b >> 3);
         if (w >= n_groups) return;  // the whole workgroup: no tile
@@ -68,7 +80,7 @@ __global__ void __launch_bounds__(256) fixed_sweep_kernel(const void *__restrict
     const uint32_t grp = h0 + threadIdx.x / LPS;
     const bool active = grp < g.Vh;
     MeasAcc acc;
-    update_site_fixed<F, LPS, SR, POST, MU0>(links, gf, g, parity, active ? grp : g.Vh - 1,
+    update_site_fixed<F, LPS, SR, POST, MU0, REC>(links, gf, g, parity, active ? grp : g.Vh - 1,
                                              (int)(threadIdx.x % LPS), active, a, &acc, slice_active);
     if constexpr (POST == 2) block_sum2_any(acc.f, acc.th, partials + 2 * slot);
 }
@@ -81,13 +93,21 @@ uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t)
 
 // The tile order of a tuning on this lattice; mode 2 takes the largest
 // blocks of 8, 4 or 2 t-slices and z-planes that divide the lattice into a
-// multiple of 8 blocks of whole tiles, else it falls back to mode 0.
+// multiple of 8 blocks of whole tiles, mode 3 needs planes of a multiple of
+// 8 whole tiles; otherwise both fall back to mode 0.
 static TileOrder tile_order(const Geom &g, const SweepTuning &t)
 {
     TileOrder o{};
     o.mode = (uint32_t)t.xcd_remap;
     o.tile = (uint32_t)(t.block / t.lanes_per_site);
     o.plane = g.L[2] * g.hx;
+    if (o.mode == 3) {
+        o.mode = 0;
+        if (o.plane % o.tile != 0 || (o.plane / o.tile) % 8 != 0) return o;
+        o.P = o.plane / o.tile;
+        o.mode = 3;
+        return o;
+    }
     if (o.mode != 2) return o;
     o.mode = 0;
     if (o.plane % o.tile != 0) return o;
@@ -105,14 +125,14 @@ static TileOrder tile_order(const Geom &g, const SweepTuning &t)
     return o;
 }
 
-bool fixed_blocked_order(const Geom &g, const SweepTuning &t)
+bool fixed_order_admitted(const Geom &g, const SweepTuning &t, int order)
 {
     SweepTuning b = t;
-    b.xcd_remap = 2;
-    return tile_order(g, b).mode == 2;
+    b.xcd_remap = order;
+    return (int)tile_order(g, b).mode == order;
 }
 
-template <int F, int LPS>
+template <int F, int LPS, bool REC>
 static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
@@ -127,12 +147,13 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     double *m = a.meas;
     if (post == 2 && (!m || coulomb)) return hipErrorInvalidValue;
 #define LGF_FIX_LAUNCH(SRV, P) \
-    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, m, \
-                       nullptr)
+    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 0, REC>), grid, block, 0, s, links, gf, g, a.parity, ra, o, \
+                       ng, m, nullptr)
 #define LGF_FIX_LAUNCH_C(SRV, P) \
     hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 1>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, \
                        nullptr, slices)
     if (coulomb) {
+        if constexpr (REC) return hipErrorInvalidValue;  // Landau only
         if (sr) {
             if (post == 0) LGF_FIX_LAUNCH_C(true, 0);
             else LGF_FIX_LAUNCH_C(true, 1);
@@ -154,21 +175,48 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     return hipGetLastError();
 }
 
+// per-site link records: the 12-real formats, Landau gauge
+bool fixed_records_format(int format) { return format == kF32_12 || format == kF64_12; }
+// one lane per site: the FP32 formats (in FP64 the update takes all 512
+// registers and runs one wave per SIMD, slower than two lanes per site)
+bool fixed_one_lane_format(int format) { return format == kF32_12 || format == kF32_18; }
+
+template <int F, bool REC>
+static hipError_t launch_fixed_r(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
+                                 int post, const uint8_t *slices, bool coulomb, hipStream_t s)
+{
+    switch (t.lanes_per_site) {
+    case 1:
+        if constexpr (F == kF32_12 || F == kF32_18)
+            return launch_fixed_t<F, 1, REC>(links, gf, g, a, t, post, slices, coulomb, s);
+        else
+            return hipErrorInvalidValue;
+    case 2: return launch_fixed_t<F, 2, REC>(links, gf, g, a, t, post, slices, coulomb, s);
+    case 4: return launch_fixed_t<F, 4, REC>(links, gf, g, a, t, post, slices, coulomb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int F>
 static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
-    switch (t.lanes_per_site) {
-    case 2: return launch_fixed_t<F, 2>(links, gf, g, a, t, post, slices, coulomb, s);
-    case 4: return launch_fixed_t<F, 4>(links, gf, g, a, t, post, slices, coulomb, s);
-    default: return hipErrorInvalidValue;
+    // the Coulomb sweeps read the link field itself (their tuning's layout
+    // applies to the Landau sweeps only)
+    if (t.schedule == kLayoutRecords && !coulomb) {
+        if constexpr (F == kF32_12 || F == kF64_12)
+            return launch_fixed_r<F, true>(links, gf, g, a, t, post, slices, coulomb, s);
+        else
+            return hipErrorInvalidValue;
     }
+    return launch_fixed_r<F, false>(links, gf, g, a, t, post, slices, coulomb, s);
 }
 
 static hipError_t launch_fixed_any(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                                    const SweepTuning &t, int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
-    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0 || post < 0 || post > 2 || a.h_end != 0 || a.out)
+    if (t.block <= 0 || t.block > 256 || (t.block % 64) != 0 || post < 0 || post > 2 || a.h_end != 0 || a.out ||
+        (t.schedule != kLayoutPlanes && t.schedule != kLayoutRecords))
         return hipErrorInvalidValue;
     switch (format) {
     case kF64_18: return launch_fixed_f<kF64_18>(links, gf, g, a, t, post, slices, coulomb, s);
@@ -201,7 +249,7 @@ int fixed_measure_blocks(const Geom &g)
     return (int)(((uint64_t)g.Vh * kMeasureFixedLanes + kMeasureBlock - 1) / kMeasureBlock);
 }
 
-template <int F>
+template <int F, bool REC = false>
 __global__ void __launch_bounds__(kMeasureBlock) measure_fixed_kernel(const void *__restrict__ links,
                                                                       const void *__restrict__ gf, Geom g,
                                                                       int parity, double *partials)
@@ -210,17 +258,25 @@ __global__ void __launch_bounds__(kMeasureBlock) measure_fixed_kernel(const void
     const uint32_t h0 = tid / kMeasureFixedLanes;
     const bool active = h0 < g.Vh;
     double f, th;
-    measure_site_fixed<F, kMeasureFixedLanes>(links, gf, g, parity, active ? h0 : g.Vh - 1,
-                                              (int)(tid % kMeasureFixedLanes), active, f, th);
+    measure_site_fixed<F, kMeasureFixedLanes, 0, REC>(links, gf, g, parity, active ? h0 : g.Vh - 1,
+                                                      (int)(tid % kMeasureFixedLanes), active, f, th);
     block_sum2<kMeasureBlock>(f, th, partials + 2 * blockIdx.x);
 }
 
 hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
-                                double *partials, int *n_partials, hipStream_t s)
+                                double *partials, int *n_partials, hipStream_t s, bool records)
 {
     const int nb = fixed_measure_blocks(g);
     *n_partials = nb;
     const dim3 grid(nb), block(kMeasureBlock);
+    if (records) {
+        switch (format) {
+        case kF32_12: hipLaunchKernelGGL((measure_fixed_kernel<kF32_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        case kF64_12: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (format) {
     case kF64_18: hipLaunchKernelGGL((measure_fixed_kernel<kF64_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF32_18: hipLaunchKernelGGL((measure_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
@@ -314,6 +370,50 @@ hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const
     case kF64_12: return launch_site_convert_s<kF64_12>(src, fd, dst, g.Vh, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// A link field of the 12-real format F (planes) into per-site link records:
+// one lane per (site, parity); the stores of a wavefront are contiguous.
+template <int F>
+__global__ void __launch_bounds__(256) record_links_kernel(const void *__restrict__ src, void *__restrict__ rec,
+                                                           Geom g)
+{
+    using V = typename Fmt<F>::V;
+    constexpr int NV = Fmt<F>::NV;
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= g.Vh) return;
+    const int parity = blockIdx.y;
+    const Site c = decode(g, parity, h);
+    void *L = const_cast<void *>(src);
+    V *out = const_cast<V *>(rec_ptr<F>(rec, g.Vh, parity, 0, h));
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const V *f = block_ptr<F>(L, g.Vh, parity, mu) + h;
+        const V *b = block_ptr<F>(L, g.Vh, parity ^ 1, mu) + back_half(g, c, h, mu);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            out[((size_t)mu * NV + k) * kRecTile] = f[(size_t)k * g.Vh];
+            out[((size_t)(4 + mu) * NV + k) * kRecTile] = b[(size_t)k * g.Vh];
+        }
+    }
+}
+
+size_t record_links_bytes(int format, const Geom &g)
+{
+    if (!fixed_records_format(format)) return 0;
+    const size_t link = (format == kF64_12) ? 96 : 48;
+    return (size_t)2 * rec_tiles(g.Vh) * kRecTile * 8 * link;
+}
+
+hipError_t launch_record_links(int format, const void *src, void *rec, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((g.Vh + 255) / 256, 2), block(256);
+    switch (format) {
+    case kF32_12: hipLaunchKernelGGL((record_links_kernel<kF32_12>), grid, block, 0, s, src, rec, g); break;
+    case kF64_12: hipLaunchKernelGGL((record_links_kernel<kF64_12>), grid, block, 0, s, src, rec, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // FP64 links (format fs, a link field) into the split storage of kF64_12S:

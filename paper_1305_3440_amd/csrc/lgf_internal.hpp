@@ -25,6 +25,8 @@ struct SweepTuning {
 };
 
 constexpr int kScheduleInPlace = 0, kSchedulePipeline = 1, kScheduleOutOfPlace = 2;
+// the fixed-link sweep's `schedule`: layout of the links it reads
+constexpr int kLayoutPlanes = 0, kLayoutRecords = 1;
 
 inline bool operator==(const SweepTuning &a, const SweepTuning &b)
 {
@@ -117,13 +119,23 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 // FP64-12 and the links in the split storage of launch_split_links).  post: 0
 // plain, 1 the new g reunitarized in FP64 as it is stored, 2 as 1 plus the
 // per-workgroup (F, theta) partial sums of the updated sites in a.meas.
-// Tuning: lanes per site 2 or 4, block, xcd_remap.
+// Tuning: lanes per site (1 in the FP32 formats, 2, 4), block, xcd_remap =
+// tile order (0..3), schedule = link layout (kLayoutRecords: links holds the
+// per-site records of launch_record_links, 12-real formats, Landau only).
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
-// whether tile order 2 (blocks of t-slices x z-planes per XCD) applies to
-// this lattice with the tuning's tile size (else it falls back to order 0)
-bool fixed_blocked_order(const Geom &g, const SweepTuning &t);
+// whether tile order `order` (2: blocks of t-slices x z-planes per XCD; 3:
+// an eighth of every plane per XCD) applies to this lattice with the
+// tuning's tile size (else the launch falls back to order 0)
+bool fixed_order_admitted(const Geom &g, const SweepTuning &t, int order);
+// formats with per-site link records; formats that run one lane per site
+bool fixed_records_format(int format);
+bool fixed_one_lane_format(int format);
+// the per-site link records of a 12-real link field src (format, planes):
+// record_links_bytes(format, g) bytes at rec (0 for other formats)
+size_t record_links_bytes(int format, const Geom &g);
+hipError_t launch_record_links(int format, const void *src, void *rec, const Geom &g, hipStream_t s);
 // Coulomb gauge in the fixed-link form (post 0 or 1; slice_active: device
 // array of Lt flags)
 hipError_t launch_fixed_sweep_coulomb(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
@@ -134,10 +146,11 @@ int coulomb_fixed_blocks(const Geom &g);
 hipError_t launch_measure_coulomb_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
                                         double *partials, hipStream_t s);
 // per-block (F, theta) partial sums over one parity's sites, fixed-link form;
-// *n_partials = fixed_measure_blocks(g) pairs
+// *n_partials = fixed_measure_blocks(g) pairs; records: links holds per-site
+// link records
 int fixed_measure_blocks(const Geom &g);
 hipError_t launch_measure_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
-                                double *partials, int *n_partials, hipStream_t s);
+                                double *partials, int *n_partials, hipStream_t s, bool records);
 // site field dst (format fd) <- src (format fs), reunitarized in FP64
 hipError_t launch_site_convert(int fs, const void *src, int fd, void *dst, const Geom &g, hipStream_t s);
 // FP64 link field src (format fs, kF64_18 or kF64_12) into the split storage

@@ -421,7 +421,9 @@ __device__ __forceinline__ void load_fixed_link(mat3<typename Fmt<F>::T> &u, voi
 // temporal links are not read at all); slice_active (optional, one flag per
 // timeslice) leaves the sites of frozen timeslices alone -- the LPS lanes of
 // a site share its timeslice, so they leave together.
-template <int F, int LPS, bool SR, int POST, int MU0 = 0>
+// REC: links holds the per-site link records of the 12-real format F (the
+// same values, so the same arithmetic and bits as from the link field).
+template <int F, int LPS, bool SR, int POST, int MU0 = 0, bool REC = false>
 __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links, void *__restrict__ gf,
                                                   const Geom &g, int parity, uint32_t h, int lane, bool active,
                                                   const RelaxArgs<typename Fmt<F>::T> &a, MeasAcc *acc,
@@ -451,7 +453,8 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
         const int mu = lane + k * LPS;
         if (mu < MU0) continue;
         mat3<T> u, y, p;
-        load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
+        if constexpr (REC) load_link_rec<F>(u, U, g.Vh, parity, mu, h);
+        else load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
         if constexpr (R == 2) row2_fma(y);
         mul_dag_fma<R>(p, u, y);  // U_mu(x) g(x+mu)^dag
@@ -462,7 +465,8 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
             else meas_term_fwd<R>(Mf, u, y);
         }
         const uint32_t hb = back_half(g, c, h, mu);
-        load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
+        if constexpr (REC) load_link_rec<F>(u, U, g.Vh, parity, 4 + mu, h);
+        else load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
         load_link<F, false, false>(y, gn, g.Vh, hb);
         if constexpr (R == 2) row2_fma(u);
         mul_fma<R>(p, y, u);  // g(x-mu) U_mu(x-mu)
@@ -529,7 +533,8 @@ __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links
 // store-and-load rebuilds it, so that the fused measurement of a sweep gets
 // the same terms.  Only lane 0 of an active site returns non-zero sums.
 // MU0 = 1: the Coulomb-gauge F_C and theta_C contributions (spatial links).
-template <int F, int LPS, int MU0 = 0>
+// REC: links holds the per-site link records (as in update_site_fixed).
+template <int F, int LPS, int MU0 = 0, bool REC = false>
 __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ links, const void *__restrict__ gf,
                                                    const Geom &g, int parity, uint32_t h, int lane, bool active,
                                                    double &f, double &th)
@@ -549,12 +554,14 @@ __device__ __forceinline__ void measure_site_fixed(const void *__restrict__ link
         const int mu = lane + k * LPS;
         if (mu < MU0) continue;
         mat3<T> u, y;
-        load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
+        if constexpr (REC) load_link_rec<F>(u, U, g.Vh, parity, mu, h);
+        else load_fixed_link<F>(u, U, g.Vh, parity, mu, h);
         load_link<F, false, false>(y, gn, g.Vh, fwd_half(g, c, h, mu));
         if constexpr (R == 2) row2_fma(y);
         meas_term_fwd<R>(Mf, u, y);
         const uint32_t hb = back_half(g, c, h, mu);
-        load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
+        if constexpr (REC) load_link_rec<F>(u, U, g.Vh, parity, 4 + mu, h);
+        else load_fixed_link<F>(u, U, g.Vh, parity ^ 1, mu, hb);
         load_link<F, false, false>(y, gn, g.Vh, hb);
         if constexpr (R == 2) row2_fma(u);
         meas_term_bwd<R>(Mb, y, u);

@@ -274,17 +274,20 @@ def lgf_get_tuning(h, fmt: int):
     return tuple(getattr(t, k) for k in TUNING_FIELDS)
 
 
-def lgf_set_fixed_tuning(h, fmt: int, lanes_per_site: int = 2, block: int = 128, xcd_remap: int = 0) -> None:
+def lgf_set_fixed_tuning(h, fmt: int, lanes_per_site: int = 2, block: int = 128, xcd_remap: int = 0,
+                         layout: int = 0) -> None:
+    """xcd_remap is the tile order (0..3), layout the link layout (0 the
+    link field, 1 per-site link records) of the fixed-link sweep"""
     t = lgf_sweep_tuning(lanes_per_site=lanes_per_site, sites_per_thread=1, block=block, xcd_remap=xcd_remap,
-                         nontemporal=1, schedule=0)
+                         nontemporal=1, schedule=layout)
     _check(load_library().lgf_set_fixed_tuning(h, fmt, ctypes.byref(t)))
 
 
 def lgf_get_fixed_tuning(h, fmt: int):
-    """(lanes_per_site, block, xcd_remap) of the fixed-link sweep"""
+    """(lanes_per_site, block, tile order, link layout) of the fixed-link sweep"""
     t = lgf_sweep_tuning()
     _check(load_library().lgf_get_fixed_tuning(h, fmt, ctypes.byref(t)))
-    return (t.lanes_per_site, t.block, t.xcd_remap)
+    return (t.lanes_per_site, t.block, t.xcd_remap, t.schedule)
 
 
 def lgf_autotune_fixed(h, fmt: int, trials: int = 4) -> None:

@@ -279,7 +279,8 @@ def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
     sites), mixed FP32-12 / FP64-12, mixed FP32-12 / FP64-12S (the finish on
     the split links) and plain FP64-18: every configuration with the sweeps,
     the links and (split finish) the final F and theta, bit for bit, of the
-    single-lattice fixed-link driver, theta < 1e-12 on the links handed back
+    single-lattice fixed-link driver at 2 lanes per site (the FP32 bulk sums
+    M over the lanes as the ensemble does), theta < 1e-12 on the links handed back
     (the oracle measures them), and the input's Wilson loops kept to 1e-12."""
     announce("ensemble fixed fix", tile)
     dims = [(4, 4, 6, 10), (8, 8, 8, 8), (6, 4, 4, 8), (8, 6, 4, 12), (2, 2, 2, 2)]
@@ -303,6 +304,7 @@ def test_ensemble_fixed_gauge_fix_equals_single(lgf, orc, tile):
             for mu, nu in ((0, 1), (2, 3)):
                 assert abs(orc.wilson_loop(d, got[i], mu, nu, 1, 2) - orc.wilson_loop(d, Us[i], mu, nu, 1, 2)) < 1e-12
             with lgf.Lattice(d, lgf.LGF_FP64_18) as lat:
+                lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP32_12, 2, 256, 0, 1)
                 lat.load(Us[i])
                 st1, r1, _ = lat.gauge_fix(**kw)
                 ref = lat.store()

@@ -24,6 +24,26 @@ SMALL_DIMS = [(2, 2, 2, 2), (4, 4, 6, 10), (8, 6, 4, 12), (4, 8, 8, 8)]
 # lattice does not split into 8k blocks of t-slices x z-planes of whole tiles
 # ((4, 8, 8, 8) takes it, with 32-site tiles)
 FIXED_TUNINGS = [(2, 128, 0), (4, 64, 1), (2, 256, 1), (4, 128, 0), (2, 64, 2), (4, 128, 2)]
+# (lanes per site, block, tile order, link layout): per-site link records in
+# the 12-real formats, one lane per site in the FP32 formats
+RECORD_TUNINGS = [(2, 256, 3, 1), (4, 64, 0, 1), (2, 64, 2, 1)]
+ONE_LANE_TUNINGS = [(1, 128, 0, 0), (1, 64, 3, 0)]
+
+
+def tunings_for(fmt):
+    return (FIXED_TUNINGS + (RECORD_TUNINGS if fmt in (2, 3) else []) +
+            (ONE_LANE_TUNINGS + [(1, 256, 1, 1)] * (fmt == 2) if fmt in (1, 2) else []))
+
+
+def apply_tune(lgf, h, fmt, tune):
+    """set a tuning on one format, leaving out what the format does not take
+    (records outside the 12-real formats, one lane outside FP32)"""
+    lps, block, order, layout = (tuple(tune) + (0,))[:4]
+    if fmt not in (2, 3):
+        layout = 0
+    if lps == 1 and fmt not in (1, 2):
+        lps = 2
+    lgf.lgf_set_fixed_tuning(h, fmt, lps, block, order, layout)
 
 
 @pytest.fixture(scope="module")
@@ -92,7 +112,7 @@ def test_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fmt, omega
     env = None
     if sweep_fmt not in (0, 3):
         env = fm.fixed_sweep_envelope(orc, dims, U, sweep_fmt, ref, omega, p_sr, 9, 3)
-    for tune in FIXED_TUNINGS:
+    for tune in tunings_for(sweep_fmt):
         got, res, hist = one_fixed_sweep(lgf, dims, U, handle_fmt, sweep_fmt, tune, omega, p_sr, 9, 3)
         if sweep_fmt in (0, 3):
             assert maxabs(got, ref) <= 1e-12, (tune, maxabs(got, ref))
@@ -162,7 +182,7 @@ def test_fixed_mixed_keeps_the_orbit(lgf, orc, finish):
         assert unitarity_error(got) < 1e-12
 
 
-@pytest.mark.parametrize("tune", [(2, 128, 0), (4, 64, 1), (2, 128, 2)])
+@pytest.mark.parametrize("tune", [(2, 128, 0), (4, 64, 1), (2, 128, 2), (2, 64, 3, 1), (1, 256, 0, 1)])
 def test_fixed_fused_measure_equals_separate_passes(lgf, orc, tune):
     """F and theta inside the chunk's last half-sweep (plus one read-only pass
     over parity 0) against two read-only passes: the same g, hence the same
@@ -180,7 +200,7 @@ def test_fixed_fused_measure_equals_separate_passes(lgf, orc, tune):
         for sep in (1, 0):
             with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
                 for f in range(4):
-                    lgf.lgf_set_fixed_tuning(lat.h, f, *tune)
+                    apply_tune(lgf, lat.h, f, tune)
                 lat.load(U)
                 st, res, hist = lat.gauge_fix(separate_measure=sep, fixed_links=1, **kw)
                 out.append((st, res, hist, lat.store()))
@@ -233,6 +253,38 @@ def test_fixed_tunings_agree(lgf, orc):
     assert maxabs(outs[(2, 64, 0)][0], outs[(4, 128, 0)][0]) < 1e-14
 
 
+def test_fixed_records_and_lockstep_order_change_no_bit(lgf, orc):
+    """The per-site link records hold the link field's values and the lockstep
+    tile order only reorders the workgroups (each keeps its tile's partial-sum
+    slot): the links, F and theta of two chunks are bit for bit those of the
+    link field in lexicographic order, for FP64-12 and FP32-12,
+    overrelaxation and stochastic relaxation, 1, 2 and 4 lanes per site; the
+    lockstep order is taken on this lattice (planes of 8 tiles of 64 sites)."""
+    dims = (4, 4, 32, 32)
+    announce("fixed records", dims)
+    U = orc.generate_links(dims, 17, 0.3)
+    for fmt, lanes in [(3, (2, 4)), (2, (1, 2, 4))]:
+        for lps in lanes:
+            block = 64 * lps
+            outs = []
+            for order, layout in [(0, 0), (0, 1), (3, 0), (3, 1)]:
+                for omega, p_sr in [(1.8, 0.0), (1.0, 0.4)]:
+                    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+                        lgf.lgf_set_fixed_tuning(lat.h, fmt, lps, block, order, layout)
+                        assert lgf.lgf_get_fixed_tuning(lat.h, fmt) == (lps, block, order, layout)
+                        lat.load(U)
+                        kw = dict(omega=omega, p_sr=p_sr, seed=3, theta_target=1e-300, check_every=3,
+                                  max_sweeps=6, fixed_links=1, bulk_format=fmt, finish_format=fmt)
+                        st, res, hist = lat.gauge_fix(**kw)
+                        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 6, res
+                        outs.append(((order, layout, omega), lat.store(), hist))
+            base = {k[2]: (U1, h1) for k, U1, h1 in outs if k[:2] == (0, 0)}
+            for k, U1, h1 in outs:
+                U0, h0 = base[k[2]]
+                assert np.array_equal(U0, U1), (fmt, lps, k, maxabs(U0, U1))
+                assert np.array_equal(h0, h1), (fmt, lps, k)
+
+
 def test_fixed_autotune_leaves_links_untouched(lgf, orc):
     """The fixed-link autotuner reads the links and writes only the gauge
     transformation: the links come back bit for bit, the pick is a valid
@@ -261,13 +313,26 @@ def test_fixed_links_argument_checks(lgf, orc):
         with pytest.raises(lgf.LgfError):
             lat.gauge_fix(omega=1.7, fixed_links=1)   # needs an FP64 handle
     with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
-        for bad in [(1, 128, 0), (8, 128, 0), (2, 96, 0), (2, 128, 3)]:
+        # defaults: FP64-12 on per-site records in the blocked tile order,
+        # FP32-12 one lane per site on records
+        assert lgf.lgf_get_fixed_tuning(lat.h, 3) == (2, 128, 2, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 0) == (2, 64, 2, 0)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (1, 128, 0, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 1) == (2, 256, 0, 0)
+        for bad in [(1, 128, 0), (8, 128, 0), (2, 96, 0), (2, 128, 4), (2, 128, -1), (2, 128, 0, 1),
+                    (2, 128, 0, 2)]:
             with pytest.raises(lgf.LgfError):
                 lgf.lgf_set_fixed_tuning(lat.h, 0, *bad)
+        for fmt, bad in [(3, (1, 128, 0)), (3, (2, 128, 0, 2)), (1, (2, 128, 0, 1)), (4, (2, 64, 2, 1)),
+                         (4, (1, 64, 2))]:
+            with pytest.raises(lgf.LgfError):
+                lgf.lgf_set_fixed_tuning(lat.h, fmt, *bad)
         lgf.lgf_set_fixed_tuning(lat.h, 3, 4, 256, 1)
-        assert lgf.lgf_get_fixed_tuning(lat.h, 3) == (4, 256, 1)
-        assert lgf.lgf_get_fixed_tuning(lat.h, 0) == (2, 64, 2)
-        assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (2, 256, 0)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 3) == (4, 256, 1, 0)
+        lgf.lgf_set_fixed_tuning(lat.h, 2, 1, 64, 3, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (1, 64, 3, 1)
+        lgf.lgf_set_fixed_tuning(lat.h, 1, 1, 128, 0)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 1) == (1, 128, 0, 0)
 
 
 def fixed_links8_model(R, orc, dims, seed, eps, omega, ys, fmt):
@@ -397,6 +462,11 @@ def _random_cases():
         cases.append((dims, tune, fmt) + [(1.7, 0.0), (1.0, 0.5), (1.9, 0.2)][k % 3])
     cases += [((8, 8, 16, 8), (2, 64, 2), 3, 1.7, 0.0), ((16, 8, 4, 16), (4, 128, 2), 0, 1.0, 0.5),
               ((16, 16, 8, 16), (2, 128, 2), 2, 1.8, 0.0), ((8, 8, 8, 16), (4, 256, 2), 3, 1.9, 0.2)]
+    # per-site link records (a last partial tile of records on the 6^4 and
+    # 6 x 4 x 2 x 10 lattices), the lockstep tile order (taken on the last two)
+    # and one lane per site
+    cases += [((6, 6, 6, 6), (2, 128, 0, 1), 3, 1.9, 0.2), ((6, 4, 2, 10), (1, 64, 0, 1), 2, 1.0, 0.5),
+              ((4, 8, 16, 32), (2, 64, 3, 1), 3, 1.7, 0.0), ((4, 4, 32, 32), (1, 64, 3, 1), 2, 1.8, 0.0)]
     return cases
 
 

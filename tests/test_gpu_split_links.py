@@ -308,9 +308,9 @@ def test_split_argument_checks(lgf, orc):
             lat.coulomb_gauge_fix(omega=1.7, finish_format=lgf.LGF_FP64_12S)   # link-rewriting form
         with pytest.raises(lgf.LgfError):
             lgf.lgf_set_tuning(lat.h, lgf.LGF_FP64_12S, 1, 128)
-        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 64, 2)
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 64, 2, 0)
         lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 4, 128, 1)
-        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (4, 128, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (4, 128, 1, 0)
         lgf.lgf_autotune_fixed(lat.h, lgf.LGF_FP64_12S, 1)
         st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-13, fixed_links=1,
                                    bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
