@@ -379,7 +379,8 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
  * Default: FP64-12 2 lanes, 128-lane workgroups, order 2, records; FP32-12 1
  * lane, 128-lane workgroups, order 0, records; the other FP64 formats 2 lanes,
  * 64-lane workgroups, order 2, layout 0; FP32-18 2 lanes, 256-lane
- * workgroups, order 0, layout 0.  LGF_EINVAL on other values. */
+ * workgroups, order 0, layout 0.  LGF_EINVAL on other values.  Setting a
+ * tuning closes an open stepwise session (lgf_fix_begin) without applying g. */
 lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
 lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuning *tuning);
 

@@ -2035,6 +2035,9 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
     n.block = u.block;
     n.xcd_remap = u.xcd_remap;
     n.schedule = u.schedule;
+    // an open stepwise session holds its links in the layout of the old
+    // tuning: it is closed (without applying g)
+    h->fix_on = false;
     h->tune_fixed[format] = n;
     drop_graphs(h);
     return LGF_OK;
@@ -2138,6 +2141,11 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
     if (e != hipSuccess) return fail(LGF_EHIP, "autotune_fixed: %s", hipGetErrorString(e));
     if (ok) h->tune_fixed[format] = best;
     drop_graphs(h);
+    if (h->rec[format] && !fixed_records(h, format)) {
+        // the picked variant reads the link field: the records' memory goes back
+        (void)hipFree(h->rec[format]);
+        h->rec[format] = nullptr;
+    }
     return LGF_OK;
 }
 
