@@ -15,15 +15,15 @@ the gauge fixing repeats until theta < 1e-14.  value = site updates per
 second (V x 20 x steps / timed wall time).
 
 Reported beside it, each run once: time to theta < 1e-14 of the mixed form
-(FP32 12-real bulk, FP64 finish below theta = 1e-8) and of the plain FP64 form
-on the same input, the same with the finish reading the links from a split
+(FP32 12-real bulk, FP64 finish below theta = 1e-8, and again below 1e-11) and
+of the plain FP64 form on the same input, the same with the finish reading the links from a split
 copy (fl32 + 16-bit remainder), the paper's link-rewriting FP64 form, the
 roofline of the dominant kernel from HIP events, the FP64 CPU oracle timed
 on 10 sweeps of the same 64^4 field on all host cores and on one more sweep
 on one core, and the overrelaxation kernels at 32^4 per storage format.
 Optional items are skipped (and say so) past a wall-clock budget.  Other
 workloads run alone through --leg (link64, gauge32, ensemble, coulomb, anneal,
-or32).
+or32, switch).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--budget 420]
 """
@@ -68,6 +68,7 @@ TRAFFIC_FIXED_VARIANTS = {
     4: [(2, block, order, 0) for block in (64, 128, 256) for order in (0, 2, 3)],
 }
 FIXED_TUNING_KEYS = ("lanes_per_site", "block", "order", "layout")
+LOW_SWITCH = 1e-11   # a later precision switch of the mixed form, reported beside the 1e-8 one
 TILE_ORDERS = ["lexicographic", "XCD ranges", "t-z blocks per XCD", "lockstep planes, an eighth per XCD"]
 LINK_LAYOUTS = ["link field", "per-site link records"]
 TRAFFIC_FIXED_SWEEPS = 4   # full sweeps per variant: 2 x 3 plain launches + the chunk's last sweep
@@ -517,6 +518,47 @@ def link64_bench(lgf, torch, stream, dims, seed, eps, omega):
     return out
 
 
+def switch_bench(lgf, torch, stream, dims, seed, eps, omega, switches):
+    """Where the mixed gauge fixing of the 64^4 workload (fixed-link form,
+    FP32-12 bulk, FP64-12 finish, autotuned) leaves FP32: time to theta <
+    1e-14 for each switch precision (the first is the reference), each once
+    from the same input, with F against the first run.  A bulk that cannot
+    reach its switch stops at max_sweeps (status LGF_ENOTCONV)."""
+    dev = torch.device("cuda:0")
+    bulk, home, finish = lgf.LGF_FP32_12, lgf.LGF_FP64_18, lgf.LGF_FP64_12
+    nbytes = lgf.lgf_required_bytes(dims, home)
+    pristine = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    work = torch.empty_like(pristine)
+    hp = lgf.lgf_create(dims, home, stream, pristine)
+    lgf.lgf_generate_links(hp, seed, eps, True)
+    hw = lgf.lgf_create(dims, home, stream, work)
+    work.copy_(pristine)
+    lgf.lgf_autotune_fixed(hw, finish, 4)
+    lgf.lgf_autotune_fixed(hw, bulk, 4)
+    out = {"dims": list(dims), "fixed_sweep_tuning": {lgf.FORMAT_NAMES[f]: dict(zip(FIXED_TUNING_KEYS,
+                                                                                   lgf.lgf_get_fixed_tuning(hw, f)))
+                                                      for f in (bulk, finish)}}
+    F_ref = None
+    for sw in switches:
+        p = lgf.fix_params(omega=omega, theta_target=1e-14, theta_switch=sw, bulk_format=bulk,
+                           finish_format=finish, fixed_links=1, max_sweeps=30000)
+        work.copy_(pristine)
+        st, r, _ = lgf.lgf_gauge_fix(hw, p)
+        e = {"status": lgf.STATUS_NAMES.get(int(st), int(st)), "time_to_theta_s": r["t_total_ms"] / 1e3,
+             "sweeps": r["sweeps"], "sweeps_bulk": r["sweeps_bulk"], "theta": r["theta"], "F": r["F"],
+             "t_sweep_bulk_s": r["t_sweep_bulk_ms"] / 1e3, "t_sweep_finish_s": r["t_sweep_finish_ms"] / 1e3}
+        if F_ref is None:
+            F_ref = r["F"]
+        e["dF_vs_first"] = r["F"] - F_ref
+        out[f"switch_{sw:.0e}"] = e
+        log(f"[switch] {sw:.0e}: {json.dumps(e)}")
+    lgf.lgf_destroy(hw)
+    lgf.lgf_destroy(hp)
+    del work, pristine
+    torch.cuda.empty_cache()
+    return out
+
+
 def or_kernels_32x4(lgf, stream, omega):
     """The paper's single-GPU measurement (Sec. 4, Fig. 1: the overrelaxation
     kernel on a 32^4 lattice in single, mixed and double precision), per
@@ -615,8 +657,10 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders into profiles/sweep_64x4_hbm_traffic.json")
     ap.add_argument("--traffic-command", default="", help="command line recorded with the summary")
-    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64", "anneal", "or32"),
+    ap.add_argument("--leg", choices=("coulomb", "ensemble", "gauge32", "link64", "anneal", "or32", "switch"),
                     help="run only this extra workload and print its JSON")
+    ap.add_argument("--switches", default="1e-8,1e-9,1e-10,1e-11",
+                    help="switch precisions of --leg switch (comma separated)")
     args = ap.parse_args()
     if args.summarize_traffic:
         dims = tuple(int(x) for x in args.dims.split(","))
@@ -661,7 +705,9 @@ def main():
                 "gauge32": lambda: gauge_32x4_bench(lgf, torch, stream),
                 "link64": lambda: link64_bench(lgf, torch, stream, dims, seed, eps, omega),
                 "anneal": lambda: anneal_bench(lgf, torch, stream, dims, seed, eps, omega),
-                "or32": lambda: or_kernels_32x4(lgf, stream, 1.7)}
+                "or32": lambda: or_kernels_32x4(lgf, stream, 1.7),
+                "switch": lambda: switch_bench(lgf, torch, stream, dims, seed, eps, omega,
+                                               [float(x) for x in args.switches.split(",")])}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
 
@@ -772,6 +818,16 @@ def main():
             time_to_theta["fp64_s"] = plain["time_to_theta_s"]
             time_to_theta["mixed_speedup_vs_fp64"] = plain["time_to_theta_s"] / mixed["time_to_theta_s"]
             time_to_theta["dF_mixed_vs_fp64"] = mixed["F"] - plain["F"]
+        # the same mixed form leaving FP32 three decades later (its bulk reaches
+        # about 9e-13 on this field before rounding stops it)
+        if fits("mixed time-to-theta with the switch at 1e-11", 0.9 * mixed["time_to_theta_s"] + args.cpu_seconds + 40):
+            pl = lgf.fix_params(omega=omega, theta_target=theta_target, theta_switch=LOW_SWITCH, bulk_format=bulk,
+                                finish_format=finish, fixed_links=1)
+            low = fix_once("mixed_fp32-12_bulk_to_1e-11_fp64-12_finish", pl)
+            time_to_theta["mixed_switch_1e-11_s"] = low["time_to_theta_s"]
+            if "fp64_s" in time_to_theta:
+                time_to_theta["mixed_switch_1e-11_speedup_vs_fp64"] = time_to_theta["fp64_s"] / low["time_to_theta_s"]
+                time_to_theta["dF_mixed_switch_1e-11_vs_fp64"] = low["F"] - plain["F"]
     # the CPU baseline before the optional runs (the line needs it)
     if not args.no_cpu_baseline and fits("cpu_baseline", args.cpu_seconds + 40.0):
         log("[bench] timing the FP64 oracle on the host")

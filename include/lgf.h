@@ -370,8 +370,8 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
  *    sites the 8 links of each site (U_mu(x), then U_mu(x-mu)), so that a
  *    wavefront reads one contiguous block; a copy of twice the link field's
  *    size, rebuilt from the field whenever a gauge fixing or session starts
- *    (Landau gauge; the Coulomb sweeps read the link field whatever this
- *    says).  The records hold the field's values, and neither layout nor tile
+ *    (Landau and Coulomb gauge; a Coulomb update reads the 6 spatial slots of
+ *    its record).  The records hold the field's values, and neither layout nor tile
  *    order changes a bit of the result; without device memory for the
  *    records the format falls back to layout 0;
  *  sites_per_thread must be 1 and nontemporal 1 (links and g(x) are streamed,

@@ -792,8 +792,9 @@ lgf_status measure_coulomb_fixed_field(lgf_lattice *h, int format, const void *l
 {
     const int bps = lgf::coulomb_fixed_blocks(h->geom);
     const size_t half = (size_t)2 * h->dims[0] * bps;
-    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 0, h->d_cpart, h->stream));
-    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 1, h->d_cpart + half, h->stream));
+    const bool rec = fixed_records(h, format);
+    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 0, h->d_cpart, h->stream, rec));
+    LGF_HIP(lgf::launch_measure_coulomb_fixed(format, links, gf, h->geom, 1, h->d_cpart + half, h->stream, rec));
     LGF_HIP(lgf::launch_finish_coulomb(h->d_cpart, h->geom, bps, h->d_cout, h->stream));
     LGF_HIP(hipMemcpyAsync(h->h_cout, h->d_cout, 2 * h->dims[0] * sizeof(double), hipMemcpyDeviceToHost,
                            h->stream));
@@ -1005,7 +1006,7 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
     if (status != LGF_ENUMERIC && n_live() > 0 && p.max_sweeps > 0) {
         LGF_TRY(ensure_gfix(h, cur));
         LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-            LGF_TRY(links_in_format(h, cur, &links));
+            LGF_TRY(fixed_links(h, cur, &links));
             LGF_HIP(lgf::launch_site_field(gf_format(cur), gfix_of(h, cur), h->geom, 0, h->stream));
             return LGF_OK;
         }));
@@ -1036,7 +1037,7 @@ lgf_status coulomb_fix_fixed(lgf_lattice *h, const lgf_fix_params &p, int bulk, 
             if (worst() < p.theta_switch) {
                 LGF_TRY(ensure_gfix(h, finish));
                 LGF_TRY(timed(res->t_convert_ms, [&]() -> lgf_status {
-                    LGF_TRY(links_in_format(h, finish, &links));
+                    LGF_TRY(fixed_links(h, finish, &links));
                     LGF_HIP(lgf::launch_site_convert(gf_format(bulk), gfix_of(h, bulk), gf_format(finish),
                                                      gfix_of(h, finish), h->geom, h->stream));
                     return LGF_OK;

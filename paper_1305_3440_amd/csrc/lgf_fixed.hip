@@ -150,10 +150,9 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 0, REC>), grid, block, 0, s, links, gf, g, a.parity, ra, o, \
                        ng, m, nullptr)
 #define LGF_FIX_LAUNCH_C(SRV, P) \
-    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 1>), grid, block, 0, s, links, gf, g, a.parity, ra, o, ng, \
-                       nullptr, slices)
+    hipLaunchKernelGGL((fixed_sweep_kernel<F, LPS, SRV, P, 1, REC>), grid, block, 0, s, links, gf, g, a.parity, ra, o, \
+                       ng, nullptr, slices)
     if (coulomb) {
-        if constexpr (REC) return hipErrorInvalidValue;  // Landau only
         if (sr) {
             if (post == 0) LGF_FIX_LAUNCH_C(true, 0);
             else LGF_FIX_LAUNCH_C(true, 1);
@@ -175,7 +174,7 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     return hipGetLastError();
 }
 
-// per-site link records: the 12-real formats, Landau gauge
+// per-site link records: the 12-real formats
 bool fixed_records_format(int format) { return format == kF32_12 || format == kF64_12; }
 // one lane per site: the FP32 formats (in FP64 the update takes all 512
 // registers and runs one wave per SIMD, slower than two lanes per site)
@@ -201,9 +200,7 @@ template <int F>
 static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, const SweepArgs &a, const SweepTuning &t,
                                  int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
-    // the Coulomb sweeps read the link field itself (their tuning's layout
-    // applies to the Landau sweeps only)
-    if (t.schedule == kLayoutRecords && !coulomb) {
+    if (t.schedule == kLayoutRecords) {
         if constexpr (F == kF32_12 || F == kF64_12)
             return launch_fixed_r<F, true>(links, gf, g, a, t, post, slices, coulomb, s);
         else
@@ -296,7 +293,7 @@ int coulomb_fixed_blocks(const Geom &g)
     return (int)(((uint64_t)g.hs[0] * kMeasureFixedLanes + kMeasureBlock - 1) / kMeasureBlock);
 }
 
-template <int F>
+template <int F, bool REC = false>
 __global__ void __launch_bounds__(kMeasureBlock) measure_coulomb_fixed_kernel(const void *__restrict__ links,
                                                                               const void *__restrict__ gf, Geom g,
                                                                               int parity, double *partials)
@@ -307,15 +304,23 @@ __global__ void __launch_bounds__(kMeasureBlock) measure_coulomb_fixed_kernel(co
     const bool active = i < g.hs[0];
     const uint32_t h = t * g.hs[0] + (active ? i : g.hs[0] - 1);
     double f, th;
-    measure_site_fixed<F, kMeasureFixedLanes, 1>(links, gf, g, parity, h, (int)(tid % kMeasureFixedLanes), active,
-                                                 f, th);
+    measure_site_fixed<F, kMeasureFixedLanes, 1, REC>(links, gf, g, parity, h, (int)(tid % kMeasureFixedLanes),
+                                                      active, f, th);
     block_sum2<kMeasureBlock>(f, th, partials + 2 * ((size_t)t * gridDim.x + blockIdx.x));
 }
 
 hipError_t launch_measure_coulomb_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
-                                        double *partials, hipStream_t s)
+                                        double *partials, hipStream_t s, bool records)
 {
     const dim3 grid(coulomb_fixed_blocks(g), g.L[0]), block(kMeasureBlock);
+    if (records) {
+        switch (format) {
+        case kF32_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        case kF64_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (format) {
     case kF64_18: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_18>), grid, block, 0, s, links, gf, g, parity, partials); break;
     case kF32_18: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_18>), grid, block, 0, s, links, gf, g, parity, partials); break;

@@ -121,7 +121,7 @@ hipError_t launch_plaquette(int format, void *field, const Geom &g, double *part
 // per-workgroup (F, theta) partial sums of the updated sites in a.meas.
 // Tuning: lanes per site (1 in the FP32 formats, 2, 4), block, xcd_remap =
 // tile order (0..3), schedule = link layout (kLayoutRecords: links holds the
-// per-site records of launch_record_links, 12-real formats, Landau only).
+// per-site records of launch_record_links, 12-real formats).
 hipError_t launch_fixed_sweep(int format, const void *links, void *gf, const Geom &g, const SweepArgs &a,
                               const SweepTuning &t, int post, hipStream_t s);
 uint32_t fixed_sweep_groups(const Geom &g, const SweepTuning &t);
@@ -144,7 +144,7 @@ hipError_t launch_fixed_sweep_coulomb(int format, const void *links, void *gf, c
 // form: Lt x coulomb_fixed_blocks(g) pairs, summed by launch_finish_coulomb
 int coulomb_fixed_blocks(const Geom &g);
 hipError_t launch_measure_coulomb_fixed(int format, const void *links, const void *gf, const Geom &g, int parity,
-                                        double *partials, hipStream_t s);
+                                        double *partials, hipStream_t s, bool records);
 // per-block (F, theta) partial sums over one parity's sites, fixed-link form;
 // *n_partials = fixed_measure_blocks(g) pairs; records: links holds per-site
 // link records

@@ -203,8 +203,9 @@ def test_coulomb_48x3x96_sampled(lgf, orc, fmt):
 def test_coulomb_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fmt, omega, p_sr):
     """One Coulomb sweep of every timeslice with the links fixed (a gauge
     fixing stopped after one sweep hands back g U g^dag, g reunitarized): the
-    oracle's Coulomb sweep of the links, then reunitarized; the blocked tile
-    order is taken on (8, 8, 8, 16)."""
+    oracle's Coulomb sweep of the links, then reunitarized, for tunings on the
+    link field and on per-site link records (the 12-real formats; one lane per
+    site in FP32); the blocked tile order is taken on (8, 8, 8, 16)."""
     announce("coulomb fixed sweep", dims, handle_fmt, sweep_fmt, omega, p_sr)
     U = orc.generate_links(dims, 31, 0.35)
     ref = U.copy()
@@ -214,7 +215,10 @@ def test_coulomb_fixed_sweep_matches_oracle(lgf, orc, dims, handle_fmt, sweep_fm
     env = None
     if sweep_fmt == 2:
         env = fm.fixed_sweep_envelope(orc, dims, U, 2, ref, omega, p_sr, 4, 2, mu_first=1)
-    for tune in [(2, 128, 0), (4, 64, 2), (2, 64, 2)]:
+    tunes = [(2, 128, 0, 0), (4, 64, 2, 0), (2, 64, 2, 0)]
+    if sweep_fmt in (2, 3):
+        tunes += [(2, 128, 2, 1), (4, 256, 0, 1)] + ([(1, 64, 3, 1)] if sweep_fmt == 2 else [])
+    for tune in tunes:
         with lgf.Lattice(dims, handle_fmt) as lat:
             lgf.lgf_set_fixed_tuning(lat.h, sweep_fmt, *tune)
             lat.load(U)
