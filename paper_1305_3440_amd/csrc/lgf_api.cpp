@@ -2041,6 +2041,11 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
     h->fix_on = false;
     h->tune_fixed[format] = n;
     drop_graphs(h);
+    if (h->rec[format] && n.schedule != lgf::kLayoutRecords) {
+        // the link field from now on: the records' memory goes back
+        (void)hipFree(h->rec[format]);
+        h->rec[format] = nullptr;
+    }
     return LGF_OK;
 }
 
