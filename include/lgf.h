@@ -107,7 +107,10 @@ typedef struct {
                               transformed FP64 links (one more history entry); if that one is not
                               below theta_target, the sweeps go on in FP64-12 from the transformed
                               links (g restarting at 1) while max_sweeps allows.  FP64-12 and
-                              LGF_FP64_12S may be paired as bulk and finish in either order.
+                              LGF_FP64_12S may be paired as bulk and finish in either order.  In
+                              FP32-12 and FP64-12 the sweeps read the links from per-site records
+                              by default (an exact copy laid out for the access pattern; see
+                              lgf_set_fixed_tuning), built when the run starts and at the switch.
                               0 (default): the sweeps rewrite the links. */
     int64_t max_sweeps;    /* give up after this many full sweeps (default 100000) */
     uint64_t seed;         /* key of the stochastic-relaxation Philox stream */
@@ -254,9 +257,9 @@ lgf_status lgf_gauge_fix(lgf_lattice *h, const lgf_fix_params *params, lgf_fix_r
  * sweeps from HIP events on the handle's stream.  Synchronises.  LGF_ENUMERIC
  * when F or theta is not finite.  lgf_fix_end writes g U g^dag (from the
  * untouched input) into the handle's field and closes the session.  Any call
- * that loads, generates, converts, sweeps, tunes or gauge-fixes the handle
- * closes the session without applying g; lgf_fix_chunk and lgf_fix_end then
- * return LGF_ESTATE. */
+ * that loads, generates, converts, reunitarizes, sweeps, anneals, autotunes,
+ * sets the fixed-link tuning or gauge-fixes the handle closes the session
+ * without applying g; lgf_fix_chunk and lgf_fix_end then return LGF_ESTATE. */
 lgf_status lgf_fix_begin(lgf_lattice *h, int format);
 lgf_status lgf_fix_chunk(lgf_lattice *h, int n, double omega, double p_sr, uint64_t seed, uint64_t sweep0,
                          int use_graph, double *F, double *theta, double *sweep_ms);
