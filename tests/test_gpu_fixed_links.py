@@ -450,6 +450,39 @@ def test_fixed_large_lattice_beyond_32bit_vector_indices(lgf, orc):
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
 
 
+def test_fixed_records_beyond_32bit_vector_indices(lgf, orc):
+    """64 x 128^3 (134M sites) on an FP64-12 handle, the sweeps reading its
+    per-site link records (the format's default): 6.4e9 16-byte record
+    vectors, parity 1's from 3.2e9 on, so their addresses pass 2^32 vectors.
+    One fixed-link sweep checked on sampled parity-1 sites, the last tiles
+    among them, against the oracle's updates of the neighbourhood; the
+    records stay in use (no fall-back to the link field)."""
+    dims = (64, 128, 128, 128)
+    seed, eps, omega = 6, 0.3, 1.8
+    announce("fixed records 64x128^3")
+    from test_gpu_parity import gpu_links8, oracle_links8, sample_sites
+    rng = np.random.default_rng(7)
+
+    def upd(s):
+        out, _ = orc.local_update(oracle_links8(orc, dims, seed, eps, s), omega, [0, 0, 0])
+        return out
+
+    with lgf.Lattice(dims, lgf.LGF_FP64_12) as lat:
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12)[3] == 1
+        lat.generate(seed, eps, True)
+        st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1)
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12)[3] == 1
+        for y in sample_sites(orc, dims, 1, 6, rng):
+            links = np.zeros((8, 3, 3), dtype=np.complex128)
+            for mu in range(4):
+                links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]
+                links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]
+            ref, _ = orc.local_update(links, omega, [0, 0, 0])
+            assert maxabs(gpu_links8(lat, orc, dims, y), ref) < 1e-12, y
+        assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+
+
 def _random_cases():
     """Seeded lattice shapes (even extents 2..12), formats and tunings, plus
     shapes on which the blocked tile order is taken (with 2 and 4 t-z blocks)."""
