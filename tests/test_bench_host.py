@@ -50,11 +50,12 @@ def test_traffic_summary_groups_dispatches_by_variant(tmp_path, monkeypatch):
             alg = Vh * bench.fixed_site_bytes(fmt)
             fetch = 0.9 * alg * (1 + k / 100) / 2048.0
             write = 0.1 * alg * (1 + k / 100) / 1024.0
-            name = f"void lgf::fixed_sweep_kernel<{fmt}, {lanes}, false, 0, 0, {'true' if layout else 'false'}>(...)"
+            rec = "true" if layout else "false"
+            name = f"void lgf::fixed_sweep_kernel<{fmt}, {lanes}, false, 0, 0, {rec}>(...)"
             fetch_rows += [(name, fetch)] * per
             write_rows += [(name, write)] * per
             # the reunitarizing last sweep of the chunk is not a plain launch
-            post1 = f"void lgf::fixed_sweep_kernel<{fmt}, {lanes}, false, 1, 0, {'true' if layout else 'false'}>(...)"
+            post1 = f"void lgf::fixed_sweep_kernel<{fmt}, {lanes}, false, 1, 0, {rec}>(...)"
             fetch_rows.append((post1, 1e9))
             write_rows.append((post1, 1e9))
             expect[bench.fixed_traffic_key(fmt, lanes, block, order, layout, dims)] = 1 + k / 100
