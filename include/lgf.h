@@ -380,7 +380,8 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
  *  sites_per_thread must be 1 and nontemporal 1 (links and g(x) are streamed,
  *  the neighbouring g go through the caches).
  * Default: FP64-12 2 lanes, 128-lane workgroups, order 2, records; FP32-12 1
- * lane, 128-lane workgroups, order 0, records; the other FP64 formats 2 lanes,
+ * lane, 128-lane workgroups, order 0, records (both on the link field for
+ * lattices of fewer than 2^18 sites); the other FP64 formats 2 lanes,
  * 64-lane workgroups, order 2, layout 0; FP32-18 2 lanes, 256-lane
  * workgroups, order 0, layout 0.  LGF_EINVAL on other values.  Setting a
  * tuning closes an open stepwise session (lgf_fix_begin) without applying g. */

@@ -600,27 +600,34 @@ bool pick_variant(const std::vector<lgf::SweepTuning> &variants, const lgf::Swee
 // transformation g, a site field in the sweep's format.
 // ----------------------------------------------------------------------------
 
+// Lattices from this many sites on read per-site link records by default:
+// measured faster from 24^4 up (FP64-12 4-6 % at 24^4 and 32^4), slower at
+// 16^4, where a half-sweep takes about 10 us and the records' larger
+// footprint costs more than their layout returns.
+constexpr int64_t kRecordsMinSites = 1 << 18;
+
 // Starting tuning of the fixed-link sweep (the fastest measured at 64^4):
 // FP64-12 with 2 lanes per site (one lane runs one wave per SIMD in FP64) in
 // 128-lane workgroups over the blocked tile order on per-site link records;
 // FP32-12 with one lane per site in 128-lane workgroups, lexicographic, on
 // records; the other FP64 formats with 2 lanes in 64-lane workgroups over the
 // blocked tile order, FP32-18 with 2 lanes in 256-lane workgroups,
-// lexicographic.
-lgf::SweepTuning default_fixed_tuning(int format)
+// lexicographic.  Below kRecordsMinSites sites the link field.
+lgf::SweepTuning default_fixed_tuning(int format, int64_t V)
 {
     lgf::SweepTuning t{};
     t.lanes_per_site = 2;
     const bool fp64 = (format == LGF_FP64_18 || format == LGF_FP64_12 || format == LGF_FP64_12S);
     t.block = fp64 ? 64 : 256;
     t.xcd_remap = fp64 ? 2 : 0;
+    const int layout = (V >= kRecordsMinSites) ? lgf::kLayoutRecords : lgf::kLayoutPlanes;
     if (format == LGF_FP64_12) {
         t.block = 128;
-        t.schedule = lgf::kLayoutRecords;
+        t.schedule = layout;
     } else if (format == LGF_FP32_12) {
         t.lanes_per_site = 1;
         t.block = 128;
-        t.schedule = lgf::kLayoutRecords;
+        t.schedule = layout;
     }
     return t;
 }
@@ -1149,7 +1156,7 @@ lgf_status lgf_create(const int dims[4], int format, void *stream, void *device_
     // defaults: one lane per site, 128-thread workgroups, non-temporal
     // streaming (fastest measured at 64^4 for every format)
     for (int f = 0; f < 4; ++f) h->tune[f] = default_tuning(f);
-    for (int f = 0; f <= LGF_FP64_12S; ++f) h->tune_fixed[f] = default_fixed_tuning(f);
+    for (int f = 0; f <= LGF_FP64_12S; ++f) h->tune_fixed[f] = default_fixed_tuning(f, h->V);
 
     auto bail = [&](lgf_status st) {
         lgf_destroy(h);
@@ -2104,7 +2111,7 @@ lgf_status lgf_autotune_fixed(lgf_lattice *h, int format, int trials)
         *ms = elapsed_ms(h->ev0, h->ev1) / n;
         return true;
     };
-    lgf::SweepTuning dflt = default_fixed_tuning(format);
+    lgf::SweepTuning dflt = default_fixed_tuning(format, h->V);
     if (!records) dflt.schedule = lgf::kLayoutPlanes;
     // warm-up under the same sustained load, as for the link sweeps
     const auto w0 = std::chrono::steady_clock::now();

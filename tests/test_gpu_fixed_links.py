@@ -313,12 +313,18 @@ def test_fixed_links_argument_checks(lgf, orc):
         with pytest.raises(lgf.LgfError):
             lat.gauge_fix(omega=1.7, fixed_links=1)   # needs an FP64 handle
     with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
-        # defaults: FP64-12 on per-site records in the blocked tile order,
-        # FP32-12 one lane per site on records
-        assert lgf.lgf_get_fixed_tuning(lat.h, 3) == (2, 128, 2, 1)
+        # defaults: FP64-12 in the blocked tile order, FP32-12 one lane per
+        # site, both on the link field below 2^18 sites, on per-site records
+        # from there on
+        assert lgf.lgf_get_fixed_tuning(lat.h, 3) == (2, 128, 2, 0)
         assert lgf.lgf_get_fixed_tuning(lat.h, 0) == (2, 64, 2, 0)
-        assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (1, 128, 0, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, 2) == (1, 128, 0, 0)
         assert lgf.lgf_get_fixed_tuning(lat.h, 1) == (2, 256, 0, 0)
+        with lgf.Lattice((16, 16, 32, 32), lgf.LGF_FP64_18) as big:
+            assert lgf.lgf_get_fixed_tuning(big.h, 3) == (2, 128, 2, 1)
+            assert lgf.lgf_get_fixed_tuning(big.h, 2) == (1, 128, 0, 1)
+        with lgf.Lattice((16, 16, 32, 30), lgf.LGF_FP64_18) as small:
+            assert lgf.lgf_get_fixed_tuning(small.h, 3) == (2, 128, 2, 0)
         for bad in [(1, 128, 0), (8, 128, 0), (2, 96, 0), (2, 128, 4), (2, 128, -1), (2, 128, 0, 1),
                     (2, 128, 0, 2)]:
             with pytest.raises(lgf.LgfError):

@@ -89,7 +89,7 @@ def test_session_state_errors(lgf, orc):
         # are held in) closes the session too
         lat.fix_begin(lgf.LGF_FP64_12)
         lat.fix_chunk(2, 1.7)
-        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 0)
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 1)
         assert lib.lgf_fix_chunk(lat.h, 1, 1.7, 0.0, 0, 0, 1, None, None, None) == lgf.LGF_ESTATE
         assert lib.lgf_fix_end(lat.h) == lgf.LGF_ESTATE
         assert np.array_equal(lat.store(), U)
