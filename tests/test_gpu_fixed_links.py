@@ -489,6 +489,50 @@ def test_fixed_records_beyond_32bit_vector_indices(lgf, orc):
         assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
 
 
+def test_fixed_records_fall_back_without_memory(lgf, orc):
+    """With too little device memory left for the per-site records (twice
+    the FP64-12 field), a gauge fixing that asks for them runs on the link
+    field instead: the same links and history bit for bit as a run on the
+    link field, the tuning switched to the field layout.  The memory is taken
+    from the host side by a torch allocation sized to leave room for the
+    field, g and the sums but not for the records."""
+    import torch
+    dims = (48, 48, 48, 48)
+    announce("fixed records without memory", dims)
+    kw = dict(omega=1.8, theta_target=1e-300, check_every=5, max_sweeps=10, fixed_links=1)
+    with lgf.Lattice(dims, lgf.LGF_FP64_12) as lat:
+        lat.generate(8, 0.3, True)
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 0)
+        st, res, hist = lat.gauge_fix(**kw)
+        ref, ref_hist = lat.store(), hist
+    field = 48 ** 4 * 4 * 96
+    with lgf.Lattice(dims, lgf.LGF_FP64_12) as lat:
+        lat.generate(8, 0.3, True)
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 1)
+        # g and the partial sums of a first run on the field, then the block
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 0)
+        lat.gauge_fix(omega=1.8, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1)
+        lat.generate(8, 0.3, True)
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12, 2, 128, 2, 1)
+        # leave about one field's worth free (the records need two), taken in
+        # pieces of at most 8 GiB
+        block = []
+        free, _ = torch.cuda.mem_get_info()
+        while free > field + (64 << 20):
+            block.append(torch.empty(min(free - field, 8 << 30), dtype=torch.uint8, device="cuda"))
+            free, _ = torch.cuda.mem_get_info()
+        try:
+            st1, res1, hist1 = lat.gauge_fix(**kw)
+            got = lat.store()
+            assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12)[3] == 0
+        finally:
+            del block
+            torch.cuda.empty_cache()
+    assert st1 == st and res1["sweeps"] == res["sweeps"] == 10
+    assert np.array_equal(got, ref)
+    assert np.array_equal(hist1, ref_hist)
+
+
 def _random_cases():
     """Seeded lattice shapes (even extents 2..12), formats and tunings, plus
     shapes on which the blocked tile order is taken (with 2 and 4 t-z blocks)."""
