@@ -67,7 +67,7 @@ TRAFFIC_FIXED_VARIANTS = {
         for layout in (0, 1)],
     3: [(2, block, order, layout) for block in (64, 128, 256) for order in (0, 2, 3) for layout in (0, 1)] +
        [(4, 256, order, layout) for order in (2, 3) for layout in (0, 1)],
-    4: [(2, block, order, 0) for block in (64, 128, 256) for order in (0, 2, 3)],
+    4: [(2, block, order, layout) for block in (64, 128, 256) for order in (0, 2, 3) for layout in (0, 1)],
 }
 FIXED_TUNING_KEYS = ("lanes_per_site", "block", "order", "layout")
 LOW_SWITCH = 1e-11   # a later precision switch of the mixed form, reported beside the 1e-8 one

@@ -108,7 +108,7 @@ typedef struct {
                               below theta_target, the sweeps go on in FP64-12 from the transformed
                               links (g restarting at 1) while max_sweeps allows.  FP64-12 and
                               LGF_FP64_12S may be paired as bulk and finish in either order.  In
-                              FP32-12 and FP64-12 the sweeps read the links from per-site records
+                              FP32-12, FP64-12 and LGF_FP64_12S the sweeps read the links from per-site records
                               by default (an exact copy laid out for the access pattern; see
                               lgf_set_fixed_tuning), built when the run starts and at the switch.
                               0 (default): the sweeps rewrite the links. */
@@ -368,21 +368,23 @@ lgf_status lgf_autotune(lgf_lattice *h, int format, int trials);
  *    (orders 2 and 3 fall back to 0 where the lattice does not divide into
  *    such blocks or planes of a multiple of 8 tiles);
  *  schedule = layout of the read-only links: 0 the link field (the handle's
- *    own, or its copy in the sweep format); 1 (FP32-12 and FP64-12 only)
- *    per-site link records -- for each parity and tile of 32 consecutive
- *    sites the 8 links of each site (U_mu(x), then U_mu(x-mu)), so that a
- *    wavefront reads one contiguous block; a copy of twice the link field's
- *    size, rebuilt from the field whenever a gauge fixing or session starts
+ *    own, or its copy in the sweep format); 1 (FP32-12, FP64-12 and
+ *    LGF_FP64_12S only) per-site link records -- for each parity and tile of
+ *    32 consecutive sites the 8 links of each site (U_mu(x), then
+ *    U_mu(x-mu)), so that a wavefront reads one contiguous block (in
+ *    LGF_FP64_12S each link's FP32 part, then its remainders); a copy of
+ *    twice the link field's size (of the split storage's), rebuilt from the
+ *    field whenever a gauge fixing or session starts
  *    (Landau and Coulomb gauge; a Coulomb update reads the 6 spatial slots of
  *    its record).  The records hold the field's values, and neither layout nor tile
  *    order changes a bit of the result; without device memory for the
  *    records the format falls back to layout 0;
  *  sites_per_thread must be 1 and nontemporal 1 (links and g(x) are streamed,
  *  the neighbouring g go through the caches).
- * Default: FP64-12 2 lanes, 128-lane workgroups, order 2, records; FP32-12 1
- * lane, 128-lane workgroups, order 0, records (both on the link field for
- * lattices of fewer than 2^18 sites); the other FP64 formats 2 lanes,
- * 64-lane workgroups, order 2, layout 0; FP32-18 2 lanes, 256-lane
+ * Default: FP64-12 and LGF_FP64_12S 2 lanes, 128-lane workgroups, order 2,
+ * records; FP32-12 1 lane, 128-lane workgroups, order 0, records (all three
+ * on the link field for lattices of fewer than 2^18 sites); FP64-18 2
+ * lanes, 64-lane workgroups, order 2, layout 0; FP32-18 2 lanes, 256-lane
  * workgroups, order 0, layout 0.  LGF_EINVAL on other values.  Setting a
  * tuning closes an open stepwise session (lgf_fix_begin) without applying g. */
 lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuning *tuning);
@@ -390,7 +392,7 @@ lgf_status lgf_get_fixed_tuning(const lgf_lattice *h, int format, lgf_sweep_tuni
 
 /* Pick the fastest fixed-link sweep variant for `format` on this lattice
  * (lanes 1 (FP32 formats)/2/4 x block 64/128/256 x tile order 0-3 x link
- * layout 0/1 (FP32-12, FP64-12); the FP64 formats keep tile order 2
+ * layout 0/1 (FP32-12, FP64-12, LGF_FP64_12S); the FP64 formats keep tile order 2
  * wherever the lattice admits it; orders the lattice does not admit are
  * left out): each timed over `trials` full sweeps, the fastest again over ten
  * times as many in five interleaved rounds; the default stays unless another

@@ -607,12 +607,12 @@ bool pick_variant(const std::vector<lgf::SweepTuning> &variants, const lgf::Swee
 constexpr int64_t kRecordsMinSites = 1 << 18;
 
 // Starting tuning of the fixed-link sweep (the fastest measured at 64^4):
-// FP64-12 with 2 lanes per site (one lane runs one wave per SIMD in FP64) in
-// 128-lane workgroups over the blocked tile order on per-site link records;
-// FP32-12 with one lane per site in 128-lane workgroups, lexicographic, on
-// records; the other FP64 formats with 2 lanes in 64-lane workgroups over the
-// blocked tile order, FP32-18 with 2 lanes in 256-lane workgroups,
-// lexicographic.  Below kRecordsMinSites sites the link field.
+// FP64-12 and the split links with 2 lanes per site (one lane runs one wave
+// per SIMD in FP64) in 128-lane workgroups over the blocked tile order on
+// per-site link records; FP32-12 with one lane per site in 128-lane
+// workgroups, lexicographic, on records; FP64-18 with 2 lanes in 64-lane
+// workgroups over the blocked tile order, FP32-18 with 2 lanes in 256-lane
+// workgroups, lexicographic.  Below kRecordsMinSites sites the link field.
 lgf::SweepTuning default_fixed_tuning(int format, int64_t V)
 {
     lgf::SweepTuning t{};
@@ -621,7 +621,7 @@ lgf::SweepTuning default_fixed_tuning(int format, int64_t V)
     t.block = fp64 ? 64 : 256;
     t.xcd_remap = fp64 ? 2 : 0;
     const int layout = (V >= kRecordsMinSites) ? lgf::kLayoutRecords : lgf::kLayoutPlanes;
-    if (format == LGF_FP64_12) {
+    if (format == LGF_FP64_12 || format == LGF_FP64_12S) {
         t.block = 128;
         t.schedule = layout;
     } else if (format == LGF_FP32_12) {
@@ -2037,7 +2037,7 @@ lgf_status lgf_set_fixed_tuning(lgf_lattice *h, int format, const lgf_sweep_tuni
     if (u.sites_per_thread != 1 || u.nontemporal != 1)
         return fail(LGF_EINVAL, "the fixed-link sweep takes sites_per_thread 1, nontemporal 1");
     if (!(u.schedule == lgf::kLayoutPlanes || (u.schedule == lgf::kLayoutRecords && lgf::fixed_records_format(format))))
-        return fail(LGF_EINVAL, "schedule (link layout) must be 0, or 1 (per-site records) in FP32-12 and FP64-12");
+        return fail(LGF_EINVAL, "schedule (link layout) must be 0, or 1 (per-site records) in FP32-12, FP64-12 and FP64-12S");
     lgf::SweepTuning n{};
     n.lanes_per_site = u.lanes_per_site;
     n.block = u.block;

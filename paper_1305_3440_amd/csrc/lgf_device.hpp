@@ -205,61 +205,6 @@ __device__ __forceinline__ void load_link(mat3<typename Fmt<F>::T> &u, const typ
     if constexpr (S::R == 2 && ROW2) rebuild_row2(u);
 }
 
-// Per-site link records: a read-only copy of a 12-real link field for the
-// sweeps that keep the links fixed.  For each parity, the sites are grouped
-// in tiles of kRecTile consecutive half indices; a tile holds, for each of
-// its sites, the 8 links one site update reads -- U_mu(x) in slot mu and
-// U_mu(x - mu) in slot 4 + mu -- vector by vector across the tile's sites:
-//     vector index = ((parity * rec_tiles(Vh) + h / T) * 8 + slot) * NV * T
-//                    + k * T + h % T,    T = kRecTile, k < NV
-// so the 8 links of a wavefront's 32 sites are one contiguous block (every
-// link is stored twice, once with each end; a last partial tile is padded).
-constexpr uint32_t kRecTile = 32;
-__host__ __device__ inline uint32_t rec_tiles(uint32_t Vh) { return (Vh + kRecTile - 1) / kRecTile; }
-
-template <int F>
-__device__ __forceinline__ const typename Fmt<F>::V *rec_ptr(const void *rec, uint32_t Vh, int parity, int slot,
-                                                             uint32_t h)
-{
-    return reinterpret_cast<const typename Fmt<F>::V *>(rec) +
-           (((size_t)parity * rec_tiles(Vh) + h / kRecTile) * 8 + (size_t)slot) * Fmt<F>::NV * kRecTile +
-           h % kRecTile;
-}
-
-// link `slot` of site h's record, rows 0 and 1 (streamed past the caches)
-template <int F>
-__device__ __forceinline__ void load_link_rec(mat3<typename Fmt<F>::T> &u, const void *rec, uint32_t Vh, int parity,
-                                              int slot, uint32_t h)
-{
-    static_assert(Fmt<F>::R == 2, "records hold 12-real links");
-    const typename Fmt<F>::V *b = rec_ptr<F>(rec, Vh, parity, slot, h);
-    typename Fmt<F>::V v[Fmt<F>::NV];
-#pragma unroll
-    for (int k = 0; k < Fmt<F>::NV; ++k) v[k] = vload<true>(b + (size_t)k * kRecTile);
-    unpack_link<F>(u, v);
-}
-
-template <int F, bool NT = false>
-__device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh, uint32_t h,
-                                           const mat3<typename Fmt<F>::T> &u)
-{
-    using S = Fmt<F>;
-#pragma unroll
-    for (int k = 0; k < S::NV; ++k) {
-        typename S::V v;
-        if constexpr (S::CPV == 1) {
-            v.x = u.e[k / 3][k % 3].re;
-            v.y = u.e[k / 3][k % 3].im;
-        } else {
-            v.x = u.e[(2 * k) / 3][(2 * k) % 3].re;
-            v.y = u.e[(2 * k) / 3][(2 * k) % 3].im;
-            v.z = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].re;
-            v.w = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].im;
-        }
-        vstore<NT>(blk + (size_t)k * Vh + h, v);
-    }
-}
-
 // Split FP64 storage of read-only links: rows 0 and 1 of each link rounded
 // to FP32, laid out as the FP32-12 field, followed by a second field of the
 // same shape holding each element's remainder x - hi as a 16-bit integer q in
@@ -296,6 +241,99 @@ __device__ __forceinline__ void load_link_split(mat3<double> &u, void *field, ui
                                          (double)a.y + (double)q.y * kSplitUnit};
         u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(double)a.z + (double)q.z * kSplitUnit,
                                                  (double)a.w + (double)q.w * kSplitUnit};
+    }
+}
+
+// Per-site link records: a read-only copy of a 12-real link field for the
+// sweeps that keep the links fixed.  For each parity, the sites are grouped
+// in tiles of kRecTile consecutive half indices; a tile holds, for each of
+// its sites, the 8 links one site update reads -- U_mu(x) in slot mu and
+// U_mu(x - mu) in slot 4 + mu -- vector by vector across the tile's sites:
+//     vector index = ((parity * rec_tiles(Vh) + h / T) * 8 + slot) * NV * T
+//                    + k * T + h % T,    T = kRecTile, k < NV
+// so the 8 links of a wavefront's 32 sites are one contiguous block (every
+// link is stored twice, once with each end; a last partial tile is padded).
+// kF64_12S records hold the split storage: per (parity, tile, slot) the 3
+// FP32 vectors of the tile's links as above (NV = 3), then their 3 remainder
+// vectors (v4s) in the same order, 72 B per link.
+constexpr uint32_t kRecTile = 32;
+__host__ __device__ inline uint32_t rec_tiles(uint32_t Vh) { return (Vh + kRecTile - 1) / kRecTile; }
+
+// first FP32 vector and first remainder vector of link `slot` of site h in
+// kF64_12S records
+__device__ __forceinline__ const v4f *rec_split_hi(const void *rec, uint32_t Vh, int parity, int slot, uint32_t h)
+{
+    const size_t blk = ((size_t)parity * rec_tiles(Vh) + h / kRecTile) * 8 + (size_t)slot;
+    return reinterpret_cast<const v4f *>(reinterpret_cast<const char *>(rec) + blk * (kRecTile * 72)) +
+           h % kRecTile;
+}
+__device__ __forceinline__ const v4s *rec_split_lo(const void *rec, uint32_t Vh, int parity, int slot, uint32_t h)
+{
+    const size_t blk = ((size_t)parity * rec_tiles(Vh) + h / kRecTile) * 8 + (size_t)slot;
+    return reinterpret_cast<const v4s *>(reinterpret_cast<const char *>(rec) + blk * (kRecTile * 72) +
+                                         kRecTile * 48) +
+           h % kRecTile;
+}
+
+template <int F>
+__device__ __forceinline__ const typename Fmt<F>::V *rec_ptr(const void *rec, uint32_t Vh, int parity, int slot,
+                                                             uint32_t h)
+{
+    return reinterpret_cast<const typename Fmt<F>::V *>(rec) +
+           (((size_t)parity * rec_tiles(Vh) + h / kRecTile) * 8 + (size_t)slot) * Fmt<F>::NV * kRecTile +
+           h % kRecTile;
+}
+
+// link `slot` of site h's record, rows 0 and 1 (streamed past the caches)
+template <int F>
+__device__ __forceinline__ void load_link_rec(mat3<typename Fmt<F>::T> &u, const void *rec, uint32_t Vh, int parity,
+                                              int slot, uint32_t h)
+{
+    static_assert(Fmt<F>::R == 2, "records hold 12-real links");
+    if constexpr (F == kF64_12S) {
+        const v4f *hb = rec_split_hi(rec, Vh, parity, slot, h);
+        const v4s *qb = rec_split_lo(rec, Vh, parity, slot, h);
+        v4f a[3];
+        v4s q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            a[k] = vload<true>(hb + (size_t)k * kRecTile);
+            q[k] = vload<true>(qb + (size_t)k * kRecTile);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            u.e[(2 * k) / 3][(2 * k) % 3] = {(double)a[k].x + (double)q[k].x * kSplitUnit,
+                                             (double)a[k].y + (double)q[k].y * kSplitUnit};
+            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {(double)a[k].z + (double)q[k].z * kSplitUnit,
+                                                     (double)a[k].w + (double)q[k].w * kSplitUnit};
+        }
+    } else {
+        const typename Fmt<F>::V *b = rec_ptr<F>(rec, Vh, parity, slot, h);
+        typename Fmt<F>::V v[Fmt<F>::NV];
+#pragma unroll
+        for (int k = 0; k < Fmt<F>::NV; ++k) v[k] = vload<true>(b + (size_t)k * kRecTile);
+        unpack_link<F>(u, v);
+    }
+}
+
+template <int F, bool NT = false>
+__device__ __forceinline__ void store_link(typename Fmt<F>::V *blk, uint32_t Vh, uint32_t h,
+                                           const mat3<typename Fmt<F>::T> &u)
+{
+    using S = Fmt<F>;
+#pragma unroll
+    for (int k = 0; k < S::NV; ++k) {
+        typename S::V v;
+        if constexpr (S::CPV == 1) {
+            v.x = u.e[k / 3][k % 3].re;
+            v.y = u.e[k / 3][k % 3].im;
+        } else {
+            v.x = u.e[(2 * k) / 3][(2 * k) % 3].re;
+            v.y = u.e[(2 * k) / 3][(2 * k) % 3].im;
+            v.z = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].re;
+            v.w = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3].im;
+        }
+        vstore<NT>(blk + (size_t)k * Vh + h, v);
     }
 }
 

@@ -174,8 +174,8 @@ static hipError_t launch_fixed_t(const void *links, void *gf, const Geom &g, con
     return hipGetLastError();
 }
 
-// per-site link records: the 12-real formats
-bool fixed_records_format(int format) { return format == kF32_12 || format == kF64_12; }
+// per-site link records: the 12-real formats and the split storage
+bool fixed_records_format(int format) { return format == kF32_12 || format == kF64_12 || format == kF64_12S; }
 // one lane per site: the FP32 formats (in FP64 the update takes all 512
 // registers and runs one wave per SIMD, slower than two lanes per site)
 bool fixed_one_lane_format(int format) { return format == kF32_12 || format == kF32_18; }
@@ -201,7 +201,7 @@ static hipError_t launch_fixed_f(const void *links, void *gf, const Geom &g, con
                                  int post, const uint8_t *slices, bool coulomb, hipStream_t s)
 {
     if (t.schedule == kLayoutRecords) {
-        if constexpr (F == kF32_12 || F == kF64_12)
+        if constexpr (F == kF32_12 || F == kF64_12 || F == kF64_12S)
             return launch_fixed_r<F, true>(links, gf, g, a, t, post, slices, coulomb, s);
         else
             return hipErrorInvalidValue;
@@ -270,6 +270,7 @@ hipError_t launch_measure_fixed(int format, const void *links, const void *gf, c
         switch (format) {
         case kF32_12: hipLaunchKernelGGL((measure_fixed_kernel<kF32_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
         case kF64_12: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        case kF64_12S: hipLaunchKernelGGL((measure_fixed_kernel<kF64_12S, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -317,6 +318,7 @@ hipError_t launch_measure_coulomb_fixed(int format, const void *links, const voi
         switch (format) {
         case kF32_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF32_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
         case kF64_12: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
+        case kF64_12S: hipLaunchKernelGGL((measure_coulomb_fixed_kernel<kF64_12S, true>), grid, block, 0, s, links, gf, g, parity, partials); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -403,10 +405,41 @@ __global__ void __launch_bounds__(256) record_links_kernel(const void *__restric
     }
 }
 
+// the same for the split storage of kF64_12S (src as launch_split_links
+// writes it): both parts of every link copied as they are
+__global__ void __launch_bounds__(256) record_split_links_kernel(const void *__restrict__ src, void *__restrict__ rec,
+                                                                 Geom g)
+{
+    const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= g.Vh) return;
+    const int parity = blockIdx.y;
+    const Site c = decode(g, parity, h);
+    void *L = const_cast<void *>(src);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const uint32_t hb = back_half(g, c, h, mu);
+        const v4f *fh = block_ptr<kF32_12>(L, g.Vh, parity, mu) + h;
+        const v4s *fq = split_res_ptr(L, g.Vh, parity, mu) + h;
+        const v4f *bh = block_ptr<kF32_12>(L, g.Vh, parity ^ 1, mu) + hb;
+        const v4s *bq = split_res_ptr(L, g.Vh, parity ^ 1, mu) + hb;
+        v4f *ofh = const_cast<v4f *>(rec_split_hi(rec, g.Vh, parity, mu, h));
+        v4s *ofq = const_cast<v4s *>(rec_split_lo(rec, g.Vh, parity, mu, h));
+        v4f *obh = const_cast<v4f *>(rec_split_hi(rec, g.Vh, parity, 4 + mu, h));
+        v4s *obq = const_cast<v4s *>(rec_split_lo(rec, g.Vh, parity, 4 + mu, h));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ofh[(size_t)k * kRecTile] = fh[(size_t)k * g.Vh];
+            ofq[(size_t)k * kRecTile] = fq[(size_t)k * g.Vh];
+            obh[(size_t)k * kRecTile] = bh[(size_t)k * g.Vh];
+            obq[(size_t)k * kRecTile] = bq[(size_t)k * g.Vh];
+        }
+    }
+}
+
 size_t record_links_bytes(int format, const Geom &g)
 {
     if (!fixed_records_format(format)) return 0;
-    const size_t link = (format == kF64_12) ? 96 : 48;
+    const size_t link = (format == kF64_12) ? 96 : (format == kF64_12S) ? 72 : 48;
     return (size_t)2 * rec_tiles(g.Vh) * kRecTile * 8 * link;
 }
 
@@ -416,6 +449,7 @@ hipError_t launch_record_links(int format, const void *src, void *rec, const Geo
     switch (format) {
     case kF32_12: hipLaunchKernelGGL((record_links_kernel<kF32_12>), grid, block, 0, s, src, rec, g); break;
     case kF64_12: hipLaunchKernelGGL((record_links_kernel<kF64_12>), grid, block, 0, s, src, rec, g); break;
+    case kF64_12S: hipLaunchKernelGGL(record_split_links_kernel, grid, block, 0, s, src, rec, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -421,7 +421,7 @@ __device__ __forceinline__ void load_fixed_link(mat3<typename Fmt<F>::T> &u, voi
 // temporal links are not read at all); slice_active (optional, one flag per
 // timeslice) leaves the sites of frozen timeslices alone -- the LPS lanes of
 // a site share its timeslice, so they leave together.
-// REC: links holds the per-site link records of the 12-real format F (the
+// REC: links holds the per-site link records of format F (12-real or split; the
 // same values, so the same arithmetic and bits as from the link field).
 template <int F, int LPS, bool SR, int POST, int MU0 = 0, bool REC = false>
 __device__ __forceinline__ void update_site_fixed(const void *__restrict__ links, void *__restrict__ gf,

@@ -82,16 +82,17 @@ def test_traffic_summary_groups_dispatches_by_variant(tmp_path, monkeypatch):
 
 def test_committed_traffic_summary_covers_the_step_variants():
     """The committed counter summary was taken on the current kernel sources
-    and holds every FP64-12 variant the autotuner may pick for the step on
-    the 64^4 lattice (2 lanes, each workgroup size, the blocked order, both
-    link layouts)."""
+    and holds every FP64-12 and split-storage variant the autotuner may pick
+    on the 64^4 lattice (2 lanes, each workgroup size, the blocked order,
+    both link layouts)."""
     t = json.load(open(bench.TRAFFIC_FILE))
     assert t["source_sha"] == bench.kernel_source_sha()
-    for block in (64, 128, 256):
-        for layout in (0, 1):
-            key = bench.fixed_traffic_key(3, 2, block, 2, layout, (64, 64, 64, 64))
-            e = t["kernels"][key]
-            assert 1.0 <= e["hbm_over_algorithmic"] < 1.10, (key, e["hbm_over_algorithmic"])
+    for fmt in (3, 4):
+        for block in (64, 128, 256):
+            for layout in (0, 1):
+                key = bench.fixed_traffic_key(fmt, 2, block, 2, layout, (64, 64, 64, 64))
+                e = t["kernels"][key]
+                assert 1.0 <= e["hbm_over_algorithmic"] < 1.10, (key, e["hbm_over_algorithmic"])
 
 
 def test_more_than_one_gpu_is_refused():

@@ -37,9 +37,9 @@ def tunings_for(fmt):
 
 def apply_tune(lgf, h, fmt, tune):
     """set a tuning on one format, leaving out what the format does not take
-    (records outside the 12-real formats, one lane outside FP32)"""
+    (records outside the 12-real and split formats, one lane outside FP32)"""
     lps, block, order, layout = (tuple(tune) + (0,))[:4]
-    if fmt not in (2, 3):
+    if fmt not in (2, 3, 4):
         layout = 0
     if lps == 1 and fmt not in (1, 2):
         lps = 2
@@ -329,7 +329,7 @@ def test_fixed_links_argument_checks(lgf, orc):
                     (2, 128, 0, 2)]:
             with pytest.raises(lgf.LgfError):
                 lgf.lgf_set_fixed_tuning(lat.h, 0, *bad)
-        for fmt, bad in [(3, (1, 128, 0)), (3, (2, 128, 0, 2)), (1, (2, 128, 0, 1)), (4, (2, 64, 2, 1)),
+        for fmt, bad in [(3, (1, 128, 0)), (3, (2, 128, 0, 2)), (1, (2, 128, 0, 1)), (4, (2, 64, 2, 2)),
                          (4, (1, 64, 2))]:
             with pytest.raises(lgf.LgfError):
                 lgf.lgf_set_fixed_tuning(lat.h, fmt, *bad)

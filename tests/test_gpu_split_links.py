@@ -23,7 +23,9 @@ from lattice_np import SPLIT_UNIT, split_stored, unitarity_error
 pytestmark = pytest.mark.gpu
 
 DIMS = [(2, 2, 2, 2), (4, 4, 6, 10), (8, 6, 4, 12), (4, 8, 8, 8)]
-TUNINGS = [(2, 64, 2), (2, 128, 0), (4, 64, 1), (4, 128, 2)]
+# (lanes per site, block, tile order[, link layout]): the last three read
+# the links from per-site records ((2, 2, 2, 2) has a partial last tile)
+TUNINGS = [(2, 64, 2), (2, 128, 0), (4, 64, 1), (4, 128, 2), (2, 64, 2, 1), (2, 256, 3, 1), (4, 128, 0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -123,6 +125,9 @@ def test_split_sweep_on_ordinary_links(lgf, orc, dims, omega, p_sr):
     # the storage's definition: rows 0 and 1 within 2^-40 (row 2 is rebuilt)
     assert maxabs(Us[..., :2, :], U[..., :2, :]) <= SPLIT_UNIT
     assert err <= bar, (err, bar)
+    # the per-site records hold the same split values: the same bits
+    got_rec, _ = fixed_sweep(lgf, dims, U, 0, lgf.LGF_FP64_12S, (2, 64, 2, 1), omega, p_sr)
+    assert np.array_equal(got_rec, got)
 
 
 def test_split_history_matches_oracle(lgf, orc):
@@ -264,7 +269,8 @@ def test_split_large_lattice_beyond_32bit_vector_indices(lgf, orc):
     """64 x 128^3 (134M sites): the split copy's residual planes start 24 Vh
     16-byte vectors into it (3.2e9), so its addresses pass 2^32 vectors.  One
     split sweep checked on sampled parity-1 sites, the last planes among
-    them, with the bar of the 64^4 sampled test."""
+    them, with the bar of the 64^4 sampled test; the same sweep on the
+    per-site records (77 GB) and on the split field gives the same bits."""
     dims = (64, 128, 128, 128)
     seed, eps, omega = 4, 0.3, 1.8
     announce("split 64x128^3")
@@ -276,19 +282,30 @@ def test_split_large_lattice_beyond_32bit_vector_indices(lgf, orc):
         out, _ = orc.local_update(split_stored(oracle_links8(orc, dims, seed, eps, s)), omega, [0, 0, 0])
         return out
 
+    ys = sample_sites(orc, dims, 1, 6, rng)
     with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
-        lat.generate(seed, eps, True)
-        st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1,
-                                   bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
-        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
-        for y in sample_sites(orc, dims, 1, 6, rng):
+        # per-site records (the default at this size; their addresses pass
+        # 2^32 bytes many times over), then the split field itself
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S)[3] == 1
+        seen = []
+        for layout in (1, 0):
+            lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 2, 128, 2, layout)
+            lat.generate(seed, eps, True)
+            st, res, _ = lat.gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1,
+                                       fixed_links=1, bulk_format=lgf.LGF_FP64_12S,
+                                       finish_format=lgf.LGF_FP64_12S)
+            assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1
+            seen.append(([gpu_links8(lat, orc, dims, y) for y in ys], res["F"], res["theta"]))
+            assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+        for k, y in enumerate(ys):
             links = np.zeros((8, 3, 3), dtype=np.complex128)
             for mu in range(4):
                 links[mu] = upd(orc.neighbor(dims, y, mu, +1))[4 + mu]
                 links[4 + mu] = upd(orc.neighbor(dims, y, mu, -1))[mu]
             ref, _ = orc.local_update(split_stored(links), omega, [0, 0, 0])
-            assert maxabs(gpu_links8(lat, orc, dims, y), ref) < bar, y
-        assert 0 < res["F"] < 1 and np.isfinite(res["theta"])
+            assert maxabs(seen[0][0][k], ref) < bar, y
+            assert np.array_equal(seen[1][0][k], seen[0][0][k]), y
+        assert seen[0][1:] == seen[1][1:]
 
 
 def test_split_argument_checks(lgf, orc):
@@ -308,9 +325,17 @@ def test_split_argument_checks(lgf, orc):
             lat.coulomb_gauge_fix(omega=1.7, finish_format=lgf.LGF_FP64_12S)   # link-rewriting form
         with pytest.raises(lgf.LgfError):
             lgf.lgf_set_tuning(lat.h, lgf.LGF_FP64_12S, 1, 128)
-        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 64, 2, 0)
+        # default: as FP64-12, per-site records from 2^18 sites on
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 128, 2, 0)
+        with lgf.Lattice((16, 16, 32, 32), lgf.LGF_FP64_18) as big:
+            assert lgf.lgf_get_fixed_tuning(big.h, lgf.LGF_FP64_12S) == (2, 128, 2, 1)
         lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 4, 128, 1)
         assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (4, 128, 1, 0)
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 2, 64, 3, 1)
+        assert lgf.lgf_get_fixed_tuning(lat.h, lgf.LGF_FP64_12S) == (2, 64, 3, 1)
+        for bad in [(1, 128, 0), (2, 128, 0, 2)]:
+            with pytest.raises(lgf.LgfError):
+                lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, *bad)
         lgf.lgf_autotune_fixed(lat.h, lgf.LGF_FP64_12S, 1)
         st, res, _ = lat.gauge_fix(omega=1.7, theta_target=1e-13, fixed_links=1,
                                    bulk_format=lgf.LGF_FP64_12S, finish_format=lgf.LGF_FP64_12S)
@@ -337,7 +362,7 @@ def test_split_coulomb_sweep_matches_fp64_12_and_oracle(lgf, orc, dims, omega, p
     bar = 1e-12 + 2 * unitarity_error(U)
     ref = U.copy()
     orc.sweep_coulomb(dims, ref, omega, p_sr, seed=4, sweep_index=2)
-    for tune in [(2, 128, 0), (4, 64, 2), (2, 64, 2)]:
+    for tune in [(2, 128, 0), (4, 64, 2), (2, 64, 2), (2, 128, 3, 1)]:
         out = {}
         for fmt in (lgf.LGF_FP64_12S, lgf.LGF_FP64_12):
             with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
@@ -382,3 +407,31 @@ def test_split_coulomb_mixed_keeps_the_orbit(lgf, orc):
     assert st4 == lgf.LGF_OK and res4["sweeps_bulk"] == res["sweeps_bulk"]
     assert np.abs(sw4 - sw).max() <= 20
     assert np.abs(F4 - F).max() < 1e-12
+
+
+def test_split_session_on_records_equals_link_field(lgf, orc):
+    """A stepwise session on the split format's per-site records (two chunks
+    of 10 sweeps, a partial last tile on this lattice) against lgf_gauge_fix
+    reading the split field: the same links and the same F and theta at each
+    check, bit for bit."""
+    dims = (6, 6, 6, 6)
+    announce("split session on records", dims)
+    U = orc.generate_links(dims, 29, 0.3)
+    with lgf.Lattice(dims, 0) as lat:
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 2, 128, 0, 1)
+        lat.load(U)
+        lat.fix_begin(lgf.LGF_FP64_12S)
+        seen = [lat.fix_chunk(10, 1.8, 0.0, 5, 10 * k, 1) for k in range(2)]
+        lat.fix_end()
+        got = lat.store()
+    with lgf.Lattice(dims, 0) as lat:
+        lgf.lgf_set_fixed_tuning(lat.h, lgf.LGF_FP64_12S, 2, 128, 0, 0)
+        lat.load(U)
+        st, res, hist = lat.gauge_fix(omega=1.8, seed=5, theta_target=1e-300, max_sweeps=20, check_every=10,
+                                      fixed_links=1, bulk_format=lgf.LGF_FP64_12S,
+                                      finish_format=lgf.LGF_FP64_12S)
+        ref = lat.store()
+    assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 20
+    assert np.array_equal(got, ref)
+    for k in range(2):
+        assert seen[k][0] == hist[k + 1, 1] and seen[k][1] == hist[k + 1, 2], k
