@@ -497,8 +497,12 @@ lgf_status lgf_ensemble_measure(lgf_ensemble *e, double *F, double *theta);
  * `tile` lanes covers tile/2 sites; FP64 home format; bulk/finish FP32-12 /
  * FP64-12 or FP64-12S, or one of them, or FP64-18 alone: LGF_EINVAL
  * otherwise; a configuration whose last sweeps ran in FP64-12S gets its F,
- * theta and status from one more measurement of its FP64 home links);
- * accumulate_g is rejected. */
+ * theta and status from one more measurement of its FP64 home links; in
+ * FP32-12, FP64-12 and FP64-12S the launches read each configuration's links
+ * from its per-site records (see lgf_set_fixed_tuning), built when its links
+ * are prepared in that format and kept, twice the links' size, until
+ * lgf_ensemble_destroy; without device memory for them the link fields:
+ * the same bits either way); accumulate_g is rejected. */
 lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
                                   lgf_fix_result *results);
 

@@ -17,6 +17,7 @@ struct EnsCfg {         // one configuration as the kernels see it
     Geom g;
     void *field;        // links in the current storage format
     void *gf;           // fixed-link form: the gauge transformation (site field, same format), else NULL
+    const void *rec;    // fixed-link form: the links' per-site records (launch_record_links), else NULL
     int fmt;            // current storage format
     uint32_t instance;  // the configuration's index: third word of the SR counter
 };
@@ -69,13 +70,16 @@ int ensemble_persistent_grid(int fa, int fb, bool sr, bool nt, int tile, int gri
 // updated; post as launch_fixed_sweep: 0 plain, 1 g reunitarized as stored,
 // 2 also the per-tile (F, theta) sums in the second-pass slots of meas) and
 // its read-only measurement pass (one workgroup per listed tile).  Format
-// pairs: ensemble_fixed_pair.
+// pairs: ensemble_fixed_pair.  rec: every listed configuration reads its
+// links from cfgs[].rec (pairs of ensemble_fixed_records_pair only).
 bool ensemble_fixed_pair(int fa, int fb);
+bool ensemble_fixed_records_pair(int fa, int fb);
 hipError_t launch_ensemble_fixed_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
-                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s);
+                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s,
+                                       bool rec);
 hipError_t launch_ensemble_fixed_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
-                                         double *partials, hipStream_t s);
-int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult);
+                                         double *partials, hipStream_t s, bool rec);
+int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult, bool rec);
 // *p = v, as a one-lane kernel on the stream (safe inside a captured graph)
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 

@@ -32,6 +32,7 @@ struct EnsGraph {
     int tile, grid_mult;
     bool fused;
     bool fixed;  // fixed-link form
+    bool rec;    // fixed-link form on per-site link records
     hipGraphExec_t exec;
 };
 
@@ -57,6 +58,11 @@ struct lgf_ensemble {
     // fixed-link form: per-format gauge transformations (site fields) of every configuration
     void *gfix[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<size_t> gfix_off[4];
+    // fixed-link form: per-format per-site link records of every configuration
+    // (the 12-real formats and the split links), rebuilt whenever a gauge
+    // fixing prepares a configuration's links in that format
+    void *rec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::vector<size_t> rec_off[5];
     // work list (device) and its pinned host mirrors
     lgf::EnsCfg *d_cfgs = nullptr;
     lgf::EnsTile *d_tiles = nullptr;
@@ -130,6 +136,37 @@ lgf_status ensure_gfix(lgf_ensemble *e, int fmt)
     return LGF_OK;
 }
 
+void *rec_of(lgf_ensemble *e, int fmt, int i) { return (char *)e->rec[fmt] + e->rec_off[fmt][i]; }
+
+// per-site link records of format fmt for every configuration; false (and
+// nothing allocated) for a format without records or without device memory
+// for them: the sweeps then read the link fields
+bool ensure_rec(lgf_ensemble *e, int fmt)
+{
+    if (!lgf::fixed_records_format(fmt)) return false;
+    if (e->rec[fmt]) return true;
+    std::vector<size_t> off(e->n);
+    size_t total = 0;
+    for (int i = 0; i < e->n; ++i) {
+        off[i] = total;
+        total += align_up(lgf::record_links_bytes(fmt, e->geom[i]));
+    }
+    if (hipMalloc(&e->rec[fmt], total) != hipSuccess) {
+        e->rec[fmt] = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    e->rec_off[fmt] = off;
+    return true;
+}
+
+// whether the fixed-link sweeps of the format pair (fa, fb) read per-site
+// records: both formats have them, and both are allocated
+bool fixed_on_records(const lgf_ensemble *e, int fa, int fb)
+{
+    return lgf::ensemble_fixed_records_pair(fa, fb) && e->rec[fa] && e->rec[fb];
+}
+
 lgf_status ensure_work(lgf_ensemble *e, int fmt)
 {
     if (fmt == e->format || e->work[fmt]) return LGF_OK;
@@ -157,7 +194,8 @@ void drop_graphs(lgf_ensemble *e)
 
 // Work list of the configurations not done (all with include_done), each in
 // format fmt_of[i], in tiles of `sites` sites (0: e->tile, one lane per site);
-// fixed: the descriptors also carry the gauge transformation of that format.
+// fixed: the descriptors also carry the gauge transformation of that format
+// and the records of its links (where allocated).
 // Fills the host mirrors and returns the tiles (upload_work sends them).
 uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::vector<int> &fmt_of,
                     bool include_done, std::vector<int> &listed, int sites = 0, bool fixed = false)
@@ -169,6 +207,7 @@ uint32_t build_work(lgf_ensemble *e, const std::vector<int> &phase, const std::v
         e->h_cfgs[i].fmt = fmt_of[i];
         e->h_cfgs[i].field = field_of(e, fmt_of[i], i);
         e->h_cfgs[i].gf = (fixed && e->gfix[gf_format(fmt_of[i])]) ? gf_of(e, fmt_of[i], i) : nullptr;
+        e->h_cfgs[i].rec = (fixed && e->rec[fmt_of[i]]) ? rec_of(e, fmt_of[i], i) : nullptr;
         e->h_cfgs[i].instance = (uint32_t)i;
         if (!include_done && phase[i] == kDone) continue;
         const uint32_t w = (uint32_t)(sites > 0 ? sites : e->tile);
@@ -260,7 +299,7 @@ lgf_status run_chunk(lgf_ensemble *e, int fa, int fb, int n, double omega, doubl
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, false, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, false, false, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }
@@ -303,8 +342,9 @@ lgf_status run_chunk_fixed(lgf_ensemble *e, int fa, int fb, int n, double omega,
     LGF_HIP(lgf::launch_set_u64(e->d_sweep_base, sweep0, e->stream));
     const bool sr = p_sr > 0.0;
     const lgf::EnsRelax r = relax_args(omega, p_sr, seed);
+    const bool rec = fixed_on_records(e, fa, fb);
     lgf::EnsLaunch L = launch_desc(e, fa, fb, sr);
-    L.grid = (uint32_t)lgf::ensemble_fixed_grid(fa, fb, sr, e->tile, e->grid_mult);
+    L.grid = (uint32_t)lgf::ensemble_fixed_grid(fa, fb, sr, e->tile, e->grid_mult, rec);
     auto issue = [&]() -> hipError_t {
         hipError_t err = hipSuccess;
         for (int k = 0; k < n && err == hipSuccess; ++k)
@@ -312,7 +352,7 @@ lgf_status run_chunk_fixed(lgf_ensemble *e, int fa, int fb, int n, double omega,
                 const bool last = (k == n - 1);
                 const int post = last ? ((parity == 1 && fused) ? 2 : 1) : 0;
                 err = lgf::launch_ensemble_fixed_sweep(fa, fb, L, parity, r, (uint32_t)k, sr, post,
-                                                       post == 2 ? e->d_partials : nullptr, e->stream);
+                                                       post == 2 ? e->d_partials : nullptr, e->stream, rec);
             }
         return err;
     };
@@ -324,7 +364,7 @@ lgf_status run_chunk_fixed(lgf_ensemble *e, int fa, int fb, int n, double omega,
     for (auto &g : e->graphs)
         if (g.fa == fa && g.fb == fb && g.n_sweeps == n && g.omega == omega && g.p_sr == p_sr &&
             (!sr || g.seed == seed) && g.nt == nt && g.tile == e->tile && g.grid_mult == e->grid_mult &&
-            g.fused == fused && g.fixed) {
+            g.fused == fused && g.fixed && g.rec == rec) {
             LGF_HIP(hipGraphLaunch(g.exec, e->stream));
             return LGF_OK;
         }
@@ -344,7 +384,7 @@ lgf_status run_chunk_fixed(lgf_ensemble *e, int fa, int fb, int n, double omega,
         (void)hipGraphExecDestroy(e->graphs.front().exec);
         e->graphs.erase(e->graphs.begin());
     }
-    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, true, exec});
+    e->graphs.push_back(EnsGraph{fa, fb, n, omega, p_sr, seed, nt, e->tile, e->grid_mult, fused, true, rec, exec});
     LGF_HIP(hipGraphLaunch(exec, e->stream));
     return LGF_OK;
 }
@@ -357,8 +397,10 @@ lgf_status measure_listed_fixed(lgf_ensemble *e, int fa, int fb, uint32_t nt, co
 {
     if (nt == 0) return LGF_OK;
     const lgf::EnsLaunch L = launch_desc(e, fa, fb, false);
-    LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 0, e->d_partials, e->stream));
-    if (!fused) LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 1, e->d_partials + 2 * (size_t)nt, e->stream));
+    const bool rec = fixed_on_records(e, fa, fb);
+    LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 0, e->d_partials, e->stream, rec));
+    if (!fused)
+        LGF_HIP(lgf::launch_ensemble_fixed_measure(fa, fb, L, nt, 1, e->d_partials + 2 * (size_t)nt, e->stream, rec));
     LGF_HIP(lgf::launch_ensemble_finish(e->d_partials, nt, e->d_spans, (uint32_t)listed.size(), e->d_out, e->stream));
     LGF_HIP(hipMemcpyAsync(e->h_out, e->d_out, sizeof(double) * 2 * e->n, hipMemcpyDeviceToHost, e->stream));
     LGF_HIP(hipStreamSynchronize(e->stream));
@@ -438,16 +480,20 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
         acc_ms += lgf::elapsed_ms(e->ev0, e->ev1);
         return LGF_OK;
     };
-    // configuration i's links in format f: its home field, or a copy of it
+    // configuration i's links in format f: its home field, or a copy of it,
+    // and their per-site records where the format has them (and memory allows)
     auto links_to = [&](int i, int f) -> lgf_status {
-        if (f == e->format) return LGF_OK;
-        LGF_TRY(ensure_work(e, f));
-        if (f == LGF_FP64_12S)
-            LGF_HIP(lgf::launch_split_links(e->format, field_of(e, e->format, i), field_of(e, f, i), e->geom[i],
-                                            e->stream));
-        else
-            LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i],
-                                        false, e->stream));
+        if (f != e->format) {
+            LGF_TRY(ensure_work(e, f));
+            if (f == LGF_FP64_12S)
+                LGF_HIP(lgf::launch_split_links(e->format, field_of(e, e->format, i), field_of(e, f, i), e->geom[i],
+                                                e->stream));
+            else
+                LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i],
+                                            false, e->stream));
+        }
+        if (ensure_rec(e, f))
+            LGF_HIP(lgf::launch_record_links(f, field_of(e, f, i), rec_of(e, f, i), e->geom[i], e->stream));
         return LGF_OK;
     };
     std::vector<int> phase(e->n, mixed ? kBulk : kFinish), fmt(e->n, e->format), listed;
@@ -671,6 +717,8 @@ lgf_status lgf_ensemble_destroy(lgf_ensemble *e)
         if (e->work[f]) (void)hipFree(e->work[f]);
         if (e->gfix[f]) (void)hipFree(e->gfix[f]);
     }
+    for (int f = 0; f < 5; ++f)
+        if (e->rec[f]) (void)hipFree(e->rec[f]);
     if (e->scratch) (void)hipFree(e->scratch);
     void *dev[] = {e->d_cfgs, e->d_tiles, e->d_n_tiles, e->d_sweep_base, e->d_spans, e->d_partials, e->d_out};
     for (void *p : dev)

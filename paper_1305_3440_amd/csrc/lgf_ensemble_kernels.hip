@@ -102,16 +102,18 @@ __global__ void __launch_bounds__(256) ensemble_finish_kernel(const double *__re
 // transformation cfgs[].gf is updated (update_site_fixed, 2 lanes per site).
 // ----------------------------------------------------------------------------
 
-template <int F, bool SR, int POST>
+// REC: the links come from the configuration's per-site records
+template <int F, bool SR, int POST, bool REC>
 __device__ __forceinline__ void ensemble_site_fixed(const EnsCfg &c, int parity, uint32_t h, int lane, bool active,
                                                     const EnsRelax &r, uint32_t sweep, MeasAcc *acc)
 {
     using T = typename Fmt<F>::T;
     const RelaxArgs<T> a{(T)r.omega, r.overrelax, r.sr_threshold, r.key0, r.key1, sweep, c.instance};
-    update_site_fixed<F, kEnsFixedLanes, SR, POST>(c.field, c.gf, c.g, parity, h, lane, active, a, acc);
+    update_site_fixed<F, kEnsFixedLanes, SR, POST, 0, REC>(REC ? c.rec : c.field, c.gf, c.g, parity, h, lane, active,
+                                                          a, acc);
 }
 
-template <int FA, int FB, bool SR, int POST>
+template <int FA, int FB, bool SR, int POST, bool REC>
 __global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_kernel(const EnsCfg *__restrict__ cfgs,
                                                                    const EnsTile *__restrict__ tiles,
                                                                    const uint32_t *__restrict__ n_tiles,
@@ -129,8 +131,9 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_kernel(const EnsCf
         const bool active = h0 < c.g.Vh;
         const uint32_t h = active ? h0 : c.g.Vh - 1;
         MeasAcc acc;
-        if (c.fmt == FA) ensemble_site_fixed<FA, SR, POST>(c, parity, h, lane, active, r, sweep, &acc);
-        else if (FB != FA && c.fmt == FB) ensemble_site_fixed<FB, SR, POST>(c, parity, h, lane, active, r, sweep, &acc);
+        if (c.fmt == FA) ensemble_site_fixed<FA, SR, POST, REC>(c, parity, h, lane, active, r, sweep, &acc);
+        else if (FB != FA && c.fmt == FB)
+            ensemble_site_fixed<FB, SR, POST, REC>(c, parity, h, lane, active, r, sweep, &acc);
         if constexpr (POST == 2) {
             block_sum2_any(acc.f, acc.th, partials + 2 * ((size_t)n + t));
             __syncthreads();  // the block sum's shared slots are reused by the next tile
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_kernel(const EnsCf
     }
 }
 
-template <int FA, int FB>
+template <int FA, int FB, bool REC>
 __global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_measure_kernel(const EnsCfg *__restrict__ cfgs,
                                                                            const EnsTile *__restrict__ tiles,
                                                                            int parity, double *partials)
@@ -150,9 +153,10 @@ __global__ void __launch_bounds__(kEnsMaxTile) ensemble_fixed_measure_kernel(con
     const bool active = h0 < c.g.Vh;
     const uint32_t h = active ? h0 : c.g.Vh - 1;
     double f = 0.0, th = 0.0;
-    if (c.fmt == FA) measure_site_fixed<FA, kEnsFixedLanes>(c.field, c.gf, c.g, parity, h, lane, active, f, th);
+    const void *links = REC ? c.rec : c.field;
+    if (c.fmt == FA) measure_site_fixed<FA, kEnsFixedLanes, 0, REC>(links, c.gf, c.g, parity, h, lane, active, f, th);
     else if (FB != FA && c.fmt == FB)
-        measure_site_fixed<FB, kEnsFixedLanes>(c.field, c.gf, c.g, parity, h, lane, active, f, th);
+        measure_site_fixed<FB, kEnsFixedLanes, 0, REC>(links, c.gf, c.g, parity, h, lane, active, f, th);
     block_sum2_any(f, th, partials + 2 * blockIdx.x);
 }
 
@@ -247,14 +251,25 @@ bool ensemble_fixed_pair(int fa, int fb)
     return false;
 }
 
+// pairs whose formats both have per-site link records (the 12-real formats
+// and the split links)
+constexpr bool has_records(int f) { return f == kF32_12 || f == kF64_12 || f == kF64_12S; }
 template <int FA, int FB>
-static hipError_t launch_ens_fixed_t(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
+constexpr bool kRecPair = has_records(FA) && has_records(FB);
+
+bool ensemble_fixed_records_pair(int fa, int fb)
+{
+    return ensemble_fixed_pair(fa, fb) && has_records(fa) && has_records(fb);
+}
+
+template <int FA, int FB, bool REC>
+static hipError_t launch_ens_fixed_r(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
                                      bool sr, int post, double *meas, hipStream_t s)
 {
     const dim3 grid(L.grid), block(L.tile);
-#define LGF_EF(SRV, P)                                                                                      \
-    hipLaunchKernelGGL((ensemble_fixed_kernel<FA, FB, SRV, P>), grid, block, 0, s, L.cfgs, L.tiles, L.n_tiles, \
-                       L.sweep_base, parity, r, sweep_offset, meas)
+#define LGF_EF(SRV, P)                                                                                          \
+    hipLaunchKernelGGL((ensemble_fixed_kernel<FA, FB, SRV, P, REC>), grid, block, 0, s, L.cfgs, L.tiles,         \
+                       L.n_tiles, L.sweep_base, parity, r, sweep_offset, meas)
     if (post == 2 && !meas) return hipErrorInvalidValue;
     if (sr) {
         if (post == 0) LGF_EF(true, 0);
@@ -269,41 +284,78 @@ static hipError_t launch_ens_fixed_t(const EnsLaunch &L, int parity, const EnsRe
     return hipGetLastError();
 }
 
+template <int FA, int FB>
+static hipError_t launch_ens_fixed_t(const EnsLaunch &L, int parity, const EnsRelax &r, uint32_t sweep_offset,
+                                     bool sr, int post, double *meas, hipStream_t s, bool rec)
+{
+    if (rec) {
+        if constexpr (kRecPair<FA, FB>)
+            return launch_ens_fixed_r<FA, FB, true>(L, parity, r, sweep_offset, sr, post, meas, s);
+        else
+            return hipErrorInvalidValue;
+    }
+    return launch_ens_fixed_r<FA, FB, false>(L, parity, r, sweep_offset, sr, post, meas, s);
+}
+
 hipError_t launch_ensemble_fixed_sweep(int fa, int fb, const EnsLaunch &L, int parity, const EnsRelax &r,
-                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s)
+                                       uint32_t sweep_offset, bool sr, int post, double *meas, hipStream_t s,
+                                       bool rec)
 {
     if (post < 0 || post > 2 || L.tile % 64 != 0) return hipErrorInvalidValue;
     if (fa > fb) { const int t = fa; fa = fb; fb = t; }
-#define LGF_CASE(A, B) if (fa == A && fb == B) return launch_ens_fixed_t<A, B>(L, parity, r, sweep_offset, sr, post, meas, s);
+#define LGF_CASE(A, B)                                                                                       \
+    if (fa == A && fb == B) return launch_ens_fixed_t<A, B>(L, parity, r, sweep_offset, sr, post, meas, s, rec);
     LGF_ENS_FIXED_PAIRS(LGF_CASE)
 #undef LGF_CASE
     return hipErrorInvalidValue;
+}
+
+template <int FA, int FB>
+static hipError_t launch_ens_fixed_measure_t(const EnsLaunch &L, uint32_t n_tiles, int parity, double *partials,
+                                             hipStream_t s, bool rec)
+{
+    if (rec) {
+        if constexpr (kRecPair<FA, FB>)
+            hipLaunchKernelGGL((ensemble_fixed_measure_kernel<FA, FB, true>), dim3(n_tiles), dim3(L.tile), 0, s,
+                               L.cfgs, L.tiles, parity, partials);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((ensemble_fixed_measure_kernel<FA, FB, false>), dim3(n_tiles), dim3(L.tile), 0, s,
+                           L.cfgs, L.tiles, parity, partials);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_ensemble_fixed_measure(int fa, int fb, const EnsLaunch &L, uint32_t n_tiles, int parity,
-                                         double *partials, hipStream_t s)
+                                         double *partials, hipStream_t s, bool rec)
 {
     if (n_tiles == 0) return hipSuccess;
     if (fa > fb) { const int t = fa; fa = fb; fb = t; }
-#define LGF_CASE(A, B)                                                                                        \
-    if (fa == A && fb == B) {                                                                                 \
-        hipLaunchKernelGGL((ensemble_fixed_measure_kernel<A, B>), dim3(n_tiles), dim3(L.tile), 0, s, L.cfgs,   \
-                           L.tiles, parity, partials);                                                       \
-        return hipGetLastError();                                                                             \
-    }
+#define LGF_CASE(A, B) \
+    if (fa == A && fb == B) return launch_ens_fixed_measure_t<A, B>(L, n_tiles, parity, partials, s, rec);
     LGF_ENS_FIXED_PAIRS(LGF_CASE)
 #undef LGF_CASE
     return hipErrorInvalidValue;
 }
 
-int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult)
+template <int FA, int FB>
+static const void *fixed_symbol(bool sr, bool rec)
+{
+    if constexpr (kRecPair<FA, FB>)
+        if (rec)
+            return sr ? reinterpret_cast<const void *>(&ensemble_fixed_kernel<FA, FB, true, 0, true>)
+                      : reinterpret_cast<const void *>(&ensemble_fixed_kernel<FA, FB, false, 0, true>);
+    return sr ? reinterpret_cast<const void *>(&ensemble_fixed_kernel<FA, FB, true, 0, false>)
+              : reinterpret_cast<const void *>(&ensemble_fixed_kernel<FA, FB, false, 0, false>);
+}
+
+int ensemble_fixed_grid(int fa, int fb, bool sr, int tile, int grid_mult, bool rec)
 {
     if (fa > fb) { const int t = fa; fa = fb; fb = t; }
     const void *fn = nullptr;
-#define LGF_CASE(A, B)                                                                                      \
-    if (fa == A && fb == B)                                                                                 \
-        fn = sr ? reinterpret_cast<const void *>(&ensemble_fixed_kernel<A, B, true, 0>)                      \
-                : reinterpret_cast<const void *>(&ensemble_fixed_kernel<A, B, false, 0>);
+#define LGF_CASE(A, B) \
+    if (fa == A && fb == B) fn = fixed_symbol<A, B>(sr, rec);
     LGF_ENS_FIXED_PAIRS(LGF_CASE)
 #undef LGF_CASE
     int dev = 0, cus = 256, per_cu = 1;
