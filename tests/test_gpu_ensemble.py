@@ -370,3 +370,42 @@ def test_ensemble_fixed_args(lgf, orc):
                           finish_format=lgf.LGF_FP64_18)
         st, res = ens.gauge_fix(omega=1.7, theta_target=1e-30, max_sweeps=20, fixed_links=1)
         assert st == lgf.LGF_ENOTCONV and all(r["sweeps"] == 20 for r in res)
+
+
+def test_ensemble_fixed_without_records_memory(lgf, orc):
+    """With too little device memory left for a configuration's per-site
+    records (twice its FP64-12 links), the fixed-link ensemble sweeps read the
+    link fields instead: the same links, F and theta bit for bit as the run on
+    records.  The memory is taken by a torch allocation sized to leave room
+    for the FP64-12 copy of the links and g but not for the records."""
+    import torch
+    dims = [(48, 48, 48, 48)]
+    V = 48 ** 4
+    announce("ensemble fixed without records memory", dims)
+    kw = dict(omega=1.8, theta_target=1e-300, check_every=5, max_sweeps=10, fixed_links=1,
+              bulk_format=lgf.LGF_FP64_12, finish_format=lgf.LGF_FP64_12)
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        ens.generate(0, 8, 0.3)
+        st, res = ens.gauge_fix(**kw)
+        ref = ens.store(0)
+    work, gf, rec = V * 4 * 96, V * 96, V * 8 * 96
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        ens.generate(0, 8, 0.3)
+        # leave the copy of the links, g and 1 GiB free (the records need 4 GB),
+        # taken in pieces of at most 8 GiB
+        keep = work + gf + (1 << 30)
+        assert keep < work + rec
+        block = []
+        free, _ = torch.cuda.mem_get_info()
+        while free > keep + (64 << 20):
+            block.append(torch.empty(min(free - keep, 8 << 30), dtype=torch.uint8, device="cuda"))
+            free, _ = torch.cuda.mem_get_info()
+        try:
+            st1, res1 = ens.gauge_fix(**kw)
+            got = ens.store(0)
+        finally:
+            del block
+            torch.cuda.empty_cache()
+    assert st1 == st == lgf.LGF_ENOTCONV and res1[0]["sweeps"] == res[0]["sweeps"] == 10
+    assert res1[0]["F"] == res[0]["F"] and res1[0]["theta"] == res[0]["theta"]
+    assert np.array_equal(got, ref)
