@@ -298,6 +298,15 @@ def ensemble_bench(lgf, stream):
         out[f"batched_{lgf.FORMAT_NAMES[fmt]}"] = {"ms_per_launch": ms,
                                                    "site_updates_per_s": Vtot / 2 / (ms * 1e-3),
                                                    "GBs": by / (ms * 1e-3) / 1e9}
+    # the fixed-link form of the same launches (the mixed fixing below runs
+    # it): the links read from their per-site records, g(x) read and written
+    for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12):
+        lgf.lgf_ensemble_time_fixed_sweeps(e, fmt, 20, 1.7)
+        ms = lgf.lgf_ensemble_time_fixed_sweeps(e, fmt, 40, 1.7)
+        by = Vtot // 2 * fixed_site_bytes(fmt)
+        out[f"batched_fixed_{lgf.FORMAT_NAMES[fmt]}"] = {"ms_per_launch": ms,
+                                                         "site_updates_per_s": Vtot / 2 / (ms * 1e-3),
+                                                         "GBs": by / (ms * 1e-3) / 1e9}
     # the same sweeps as one launch per lattice (each lattice its own handle)
     singles = []
     for c in man:
@@ -842,6 +851,7 @@ def main():
         ens = ensemble_bench(lgf, stream)
         extras["ensemble48"] = ens
         b32, b64 = ens["batched_fp32-12"], ens["batched_fp64-12"]
+        f32, f64 = ens["batched_fixed_fp32-12"], ens["batched_fixed_fp64-12"]
         mixed_e, plain_e = ens["gauge_fix_mixed_fixed_links"]["wall_s"], ens["gauge_fix_fp64"]["wall_s"]
         batched = {"workload": f"{ens['configs']} lattices of {min(ens['sizes'])}^4..{max(ens['sizes'])}^4 "
                                f"({ens['sites']} sites, seeds 100..147), one persistent launch per parity",
@@ -849,6 +859,10 @@ def main():
                    "fp32-12_frac_of_8TBs": b32["GBs"] / HBM_PEAK_GBS,
                    "fp64-12_site_updates_per_s": b64["site_updates_per_s"], "fp64-12_GBs": b64["GBs"],
                    "fp64-12_frac_of_8TBs": b64["GBs"] / HBM_PEAK_GBS,
+                   "fixed_fp32-12_site_updates_per_s": f32["site_updates_per_s"], "fixed_fp32-12_GBs": f32["GBs"],
+                   "fixed_fp32-12_frac_of_8TBs": f32["GBs"] / HBM_PEAK_GBS,
+                   "fixed_fp64-12_site_updates_per_s": f64["site_updates_per_s"], "fixed_fp64-12_GBs": f64["GBs"],
+                   "fixed_fp64-12_frac_of_8TBs": f64["GBs"] / HBM_PEAK_GBS,
                    "speedup_vs_one_launch_per_lattice": ens["batched_speedup_fp32-12"],
                    "time_to_theta_mixed_s": mixed_e, "time_to_theta_fp64_s": plain_e,
                    "mixed_speedup_vs_fp64": plain_e / mixed_e}

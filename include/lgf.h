@@ -512,6 +512,17 @@ lgf_status lgf_ensemble_gauge_fix(lgf_ensemble *e, const lgf_fix_params *params,
 lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
                                     double *ms_per_launch);
 
+/* The same for the fixed-link form (lgf_fix_params.fixed_links): average ms
+ * per persistent launch of n full fixed-link sweeps of every configuration in
+ * `format` (FP32-12, FP64-12, LGF_FP64_12S or FP64-18; an FP64 ensemble), the
+ * links read as lgf_ensemble_gauge_fix reads them (copies in `format` and
+ * per-site records where the format has them; the home links are only read),
+ * each configuration's gauge transformation starting at 1 and left as the
+ * sweeps leave it (the next gauge fixing resets it).  LGF_EINVAL for other
+ * formats or an FP32 ensemble. */
+lgf_status lgf_ensemble_time_fixed_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
+                                          double *ms_per_launch);
+
 /* Tuning of the persistent ensemble launches: tile = sites per work-list tile
  * and lanes per workgroup (64, 128 or 256), grid_mult = persistent workgroups
  * as a multiple (1, 2 or 4) of what fits on the GPU at once, nontemporal

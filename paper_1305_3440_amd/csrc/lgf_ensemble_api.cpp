@@ -458,6 +458,25 @@ void drop_scratch(lgf_ensemble *e)
     e->scratch_off.clear();
 }
 
+// configuration i's links for the fixed-link sweeps in format f: its home
+// field, or a copy of it, and their per-site records where the format has
+// them (and memory allows)
+lgf_status fixed_links_to(lgf_ensemble *e, int i, int f)
+{
+    if (f != e->format) {
+        LGF_TRY(ensure_work(e, f));
+        if (f == LGF_FP64_12S)
+            LGF_HIP(lgf::launch_split_links(e->format, field_of(e, e->format, i), field_of(e, f, i), e->geom[i],
+                                            e->stream));
+        else
+            LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i],
+                                        false, e->stream));
+    }
+    if (ensure_rec(e, f))
+        LGF_HIP(lgf::launch_record_links(f, field_of(e, f, i), rec_of(e, f, i), e->geom[i], e->stream));
+    return LGF_OK;
+}
+
 // lgf_ensemble_gauge_fix with fixed_links set (parameters checked by the
 // caller): per-configuration phases and stopping as in the link form, on
 // (U, g); at the end every configuration that was swept gets
@@ -480,22 +499,7 @@ lgf_status ensemble_fix_fixed(lgf_ensemble *e, const lgf_fix_params &p, int bulk
         acc_ms += lgf::elapsed_ms(e->ev0, e->ev1);
         return LGF_OK;
     };
-    // configuration i's links in format f: its home field, or a copy of it,
-    // and their per-site records where the format has them (and memory allows)
-    auto links_to = [&](int i, int f) -> lgf_status {
-        if (f != e->format) {
-            LGF_TRY(ensure_work(e, f));
-            if (f == LGF_FP64_12S)
-                LGF_HIP(lgf::launch_split_links(e->format, field_of(e, e->format, i), field_of(e, f, i), e->geom[i],
-                                                e->stream));
-            else
-                LGF_HIP(lgf::launch_convert(e->format, field_of(e, e->format, i), f, field_of(e, f, i), e->geom[i],
-                                            false, e->stream));
-        }
-        if (ensure_rec(e, f))
-            LGF_HIP(lgf::launch_record_links(f, field_of(e, f, i), rec_of(e, f, i), e->geom[i], e->stream));
-        return LGF_OK;
-    };
+    auto links_to = [&](int i, int f) { return fixed_links_to(e, i, f); };
     std::vector<int> phase(e->n, mixed ? kBulk : kFinish), fmt(e->n, e->format), listed;
     std::vector<char> started(e->n, 0);
     // measurement 0 on the home links (g = 1)
@@ -1004,6 +1008,36 @@ lgf_status lgf_ensemble_time_sweeps(lgf_ensemble *e, int format, int n, double o
     const lgf_status st = timed();
     drop_scratch(e);
     return st;
+}
+
+lgf_status lgf_ensemble_time_fixed_sweeps(lgf_ensemble *e, int format, int n, double omega, double p_sr,
+                                          double *ms_per_launch)
+{
+    if (!e || !ms_per_launch) return fail(LGF_EINVAL, "NULL ensemble or output");
+    if (!is_fp64(e->format)) return fail(LGF_EINVAL, "the fixed-link form needs an FP64 ensemble");
+    if (!lgf::ensemble_fixed_pair(format, format))
+        return fail(LGF_EINVAL, "format %d has no fixed-link ensemble sweep of its own", format);
+    if (n < 1) return fail(LGF_EINVAL, "n must be >= 1");
+    if (!(omega >= 1.0 && omega <= 2.0)) return fail(LGF_EINVAL, "omega %g outside [1, 2]", omega);
+    if (!(p_sr >= 0.0 && p_sr <= 1.0)) return fail(LGF_EINVAL, "p_sr %g outside [0, 1]", p_sr);
+    LGF_TRY(ens_use_device(e));
+    // the links as a fixed-link gauge fixing reads them (copies and records;
+    // the home fields are only read), every g from 1
+    LGF_TRY(ensure_gfix(e, format));
+    for (int i = 0; i < e->n; ++i) {
+        LGF_TRY(fixed_links_to(e, i, format));
+        LGF_HIP(lgf::launch_site_field(gf_format(format), gf_of(e, format, i), e->geom[i], 0, e->stream));
+    }
+    std::vector<int> phase(e->n, kFinish), fmt(e->n, format), listed;
+    const uint32_t nt = build_work(e, phase, fmt, true, listed, e->tile / lgf::kEnsFixedLanes, true);
+    LGF_TRY(upload_work(e, nt, listed.size()));
+    LGF_TRY(run_chunk_fixed(e, format, format, 1, omega, p_sr, 0, 0, false, false));  // warm-up
+    LGF_HIP(hipEventRecord(e->ev0, e->stream));
+    LGF_TRY(run_chunk_fixed(e, format, format, n, omega, p_sr, 0, 1, false, false));
+    LGF_HIP(hipEventRecord(e->ev1, e->stream));
+    LGF_HIP(hipEventSynchronize(e->ev1));
+    *ms_per_launch = lgf::elapsed_ms(e->ev0, e->ev1) / (2.0 * n);
+    return LGF_OK;
 }
 
 lgf_status lgf_ensemble_set_tuning(lgf_ensemble *e, int tile, int grid_mult, int nontemporal)

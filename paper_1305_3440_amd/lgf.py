@@ -451,7 +451,8 @@ ENSEMBLE_EXPORTS = [
     "lgf_ensemble_create", "lgf_ensemble_destroy", "lgf_ensemble_generate",
     "lgf_ensemble_load_links", "lgf_ensemble_store_links", "lgf_ensemble_sweep",
     "lgf_ensemble_measure", "lgf_ensemble_gauge_fix", "lgf_ensemble_time_sweeps",
-    "lgf_ensemble_set_tuning", "lgf_ensemble_get_tuning", "lgf_ensemble_autotune",
+    "lgf_ensemble_time_fixed_sweeps", "lgf_ensemble_set_tuning", "lgf_ensemble_get_tuning",
+    "lgf_ensemble_autotune",
 ]
 EXPORTS = EXPORTS + ENSEMBLE_EXPORTS + ["lgf_sweep_coulomb", "lgf_measure_coulomb",
                                         "lgf_coulomb_gauge_fix", "lgf_plaquette"]
@@ -471,6 +472,7 @@ def _ens_lib():
             "lgf_ensemble_measure": (I, [P, P, P]),
             "lgf_ensemble_gauge_fix": (I, [P, P, P]),
             "lgf_ensemble_time_sweeps": (I, [P, I, I, D, D, P]),
+            "lgf_ensemble_time_fixed_sweeps": (I, [P, I, I, D, D, P]),
             "lgf_ensemble_set_tuning": (I, [P, I, I, I]),
             "lgf_ensemble_get_tuning": (I, [P, P, P, P]),
             "lgf_ensemble_autotune": (I, [P, I, I]),
@@ -554,6 +556,12 @@ def lgf_ensemble_time_sweeps(e, fmt: int, n: int, omega: float, p_sr: float = 0.
     return ms.value
 
 
+def lgf_ensemble_time_fixed_sweeps(e, fmt: int, n: int, omega: float, p_sr: float = 0.0) -> float:
+    ms = ctypes.c_double()
+    _check(_ens_lib().lgf_ensemble_time_fixed_sweeps(e, fmt, n, omega, p_sr, ctypes.byref(ms)))
+    return ms.value
+
+
 def lgf_sweep_coulomb(h, parity: int, omega: float, p_sr: float = 0.0, seed: int = 0,
                       sweep_index: int = 0, slice_active=None) -> None:
     act = None if slice_active is None else np.ascontiguousarray(np.asarray(slice_active, dtype=np.uint8))
@@ -630,3 +638,6 @@ class Ensemble:
 
     def time_sweeps(self, fmt, n, omega, p_sr=0.0):
         return lgf_ensemble_time_sweeps(self.e, fmt, n, omega, p_sr)
+
+    def time_fixed_sweeps(self, fmt, n, omega, p_sr=0.0):
+        return lgf_ensemble_time_fixed_sweeps(self.e, fmt, n, omega, p_sr)

@@ -409,3 +409,43 @@ def test_ensemble_fixed_without_records_memory(lgf, orc):
     assert st1 == st == lgf.LGF_ENOTCONV and res1[0]["sweeps"] == res[0]["sweeps"] == 10
     assert res1[0]["F"] == res[0]["F"] and res1[0]["theta"] == res[0]["theta"]
     assert np.array_equal(got, ref)
+
+
+def test_ensemble_time_fixed_sweeps(lgf, orc):
+    """lgf_ensemble_time_fixed_sweeps times the fixed-link launches in each
+    format that has its own (OR and SR) without touching the links; a gauge
+    fixing after it (which resets g) equals one on a fresh ensemble bit for
+    bit; other formats, an FP32 ensemble and out-of-range arguments are
+    rejected."""
+    announce("ensemble time fixed sweeps")
+    dims = [(4, 4, 6, 10), (8, 8, 8, 8), (2, 2, 2, 2)]
+    Us = [orc.generate_links(d, 140 + i, 0.3) for i, d in enumerate(dims)]
+    kw = dict(omega=1.7, theta_target=1e-12, theta_switch=1e-8, bulk_format=lgf.LGF_FP32_12,
+              finish_format=lgf.LGF_FP64_12, fixed_links=1)
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        before = [ens.store(i) for i in range(len(dims))]
+        for fmt in (lgf.LGF_FP32_12, lgf.LGF_FP64_12, lgf.LGF_FP64_12S, lgf.LGF_FP64_18):
+            assert ens.time_fixed_sweeps(fmt, 3, 1.7) > 0.0, fmt
+        assert ens.time_fixed_sweeps(lgf.LGF_FP32_12, 2, 1.0, 0.5) > 0.0
+        for fmt, n, omega, p in [(lgf.LGF_FP32_18, 3, 1.7, 0.0), (9, 3, 1.7, 0.0), (lgf.LGF_FP64_12, 0, 1.7, 0.0),
+                                 (lgf.LGF_FP64_12, 3, 2.5, 0.0), (lgf.LGF_FP64_12, 3, 1.7, 1.5)]:
+            with pytest.raises(lgf.LgfError):
+                ens.time_fixed_sweeps(fmt, n, omega, p)
+        for i in range(len(dims)):
+            assert np.array_equal(ens.store(i), before[i]), i
+        st, res = ens.gauge_fix(**kw)
+        got = [ens.store(i) for i in range(len(dims))]
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        for i, U in enumerate(Us):
+            ens.load(i, U)
+        st2, res2 = ens.gauge_fix(**kw)
+        ref = [ens.store(i) for i in range(len(dims))]
+    assert st == st2 == lgf.LGF_OK
+    assert [r["sweeps"] for r in res] == [r["sweeps"] for r in res2]
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    with lgf.Ensemble(dims, lgf.LGF_FP32_12) as ens:
+        with pytest.raises(lgf.LgfError):
+            ens.time_fixed_sweeps(lgf.LGF_FP32_12, 3, 1.7)
