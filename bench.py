@@ -772,6 +772,22 @@ def main():
     log(f"[bench] {args.steps} steps in {step_s * 1e3:.1f} ms ({step_s / args.steps * 1e3:.2f} ms per step); "
         f"sweep kernels {launch_ms:.4f} ms per launch; theta {steps[-1][1]:.3e}")
 
+    # the mixed form's bulk sweep (FP32-12 links and g, its autotuned variant)
+    # in a session of its own, against the step's FP64 sweep
+    lgf.lgf_fix_begin(hw, bulk)
+    lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, 0)
+    bulk_ms = sum(lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, chunk * (k + 1))[2] for k in range(5)) / (10 * chunk)
+    lgf.lgf_fix_end(hw)
+    b_lanes, b_block, b_order, b_layout = fixed_tuning[bulk]
+    b_gbs = Vh * fixed_site_bytes(bulk) / (bulk_ms * 1e-3) / 1e9
+    mixed_bulk = {"kernel": f"fixed_sweep_kernel<fp32-12, lanes/site {b_lanes}> block {b_block}, tile order "
+                            f"{TILE_ORDERS[b_order]}, links from the {LINK_LAYOUTS[b_layout]}",
+                  "ms_per_launch": round(bulk_ms, 4), "site_updates_per_s": Vh / (bulk_ms * 1e-3),
+                  "GBs": round(b_gbs, 1), "frac_of_8TBs": round(b_gbs / HBM_PEAK_GBS, 4),
+                  "bytes_per_site_update": fixed_site_bytes(bulk),
+                  "site_updates_vs_fp64_sweep": round(launch_ms / bulk_ms, 3)}
+    log(f"[bench] mixed bulk sweep: {json.dumps(mixed_bulk)}")
+
     # roofline of the dominant kernel (the step's sweep), from the HIP events
     # the library records around each chunk's sweeps on the launch stream
     lanes, block, order, layout = fixed_tuning[finish]
@@ -927,6 +943,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_theta": time_to_theta,
+        "mixed_bulk": mixed_bulk,
         "batched": batched,
         "extras": extras,
         "skipped": skipped,
