@@ -449,3 +449,46 @@ def test_ensemble_time_fixed_sweeps(lgf, orc):
     with lgf.Ensemble(dims, lgf.LGF_FP32_12) as ens:
         with pytest.raises(lgf.LgfError):
             ens.time_fixed_sweeps(lgf.LGF_FP32_12, 3, 1.7)
+
+
+@pytest.mark.parametrize("tile", [256, 64])
+def test_manifest_ensemble_fixed_sweep(lgf, orc, tile):
+    """The 48-configuration workload of the benchmark in the launch its mixed
+    fixing uses: one FP64-12 fixed-link sweep of every configuration through
+    the persistent launch, links on per-site records, in the tile widths the
+    autotuner picks.  Every configuration of 8^4 or 12^4 matches the oracle's
+    sweep (then reunitarization) of the same input links to 1e-12; two of the
+    16^4 and 24^4 ones equal the single-lattice fixed-link driver bit for bit."""
+    man = json.load(open(os.path.join(HERE, "golden", "ensemble48_manifest.json")))["configs"]
+    dims = [tuple(c["dims"]) for c in man]
+    announce("manifest ensemble fixed sweep", len(dims), tile)
+    kw = dict(omega=1.7, theta_target=1e-300, check_every=1, max_sweeps=1, fixed_links=1,
+              bulk_format=lgf.LGF_FP64_12, finish_format=lgf.LGF_FP64_12)
+    small = [c for c in man if c["dims"][0] <= 12]
+    large = [c for c in man if c["dims"][0] >= 16][:2]
+    with lgf.Ensemble(dims, lgf.LGF_FP64_18) as ens:
+        lgf.lgf_ensemble_set_tuning(ens.e, tile, 2, 1)
+        for c in man:
+            ens.generate(c["index"], c["seed"], c["eps"], True)
+        inputs = {c["index"]: ens.store(c["index"]) for c in small + large}
+        st, res = ens.gauge_fix(**kw)
+        assert st == lgf.LGF_ENOTCONV and all(r["sweeps"] == 1 for r in res)
+        got = {c["index"]: ens.store(c["index"]) for c in small + large}
+    assert len(small) > 0 and len(large) == 2
+    worst = 0.0
+    for c in small:
+        i, d = c["index"], tuple(c["dims"])
+        ref = inputs[i].copy()
+        orc.sweep(d, ref, 1.7, 0.0, seed=0, sweep_index=0, instance=i)
+        orc.reunitarize(ref)
+        e = maxabs(got[i], ref)
+        worst = max(worst, e)
+        assert e <= 1e-12, (i, d, e)
+    announce(f"manifest fixed sweep: {len(small)} configurations against the oracle, worst {worst:.2e}")
+    for c in large:
+        i, d = c["index"], tuple(c["dims"])
+        with lgf.Lattice(d, lgf.LGF_FP64_18) as lat:
+            lat.load(inputs[i])
+            st1, r1, _ = lat.gauge_fix(**kw)
+            assert r1["sweeps"] == 1
+            assert np.array_equal(lat.store(), got[i]), (i, d)
