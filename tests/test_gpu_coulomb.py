@@ -308,3 +308,47 @@ def test_coulomb_fixed_graph_equals_direct(lgf, orc):
                 out.append((st, sw, F, th, lat.store()))
         for a, b in zip(out[0], out[1]):
             assert np.array_equal(np.asarray(a), np.asarray(b)), kw
+
+
+@pytest.mark.parametrize("fmt", [3, 4])
+def test_coulomb_fixed_48x3x96_sampled(lgf, orc, fmt):
+    """The Coulomb workload at its full size (48^3 x 96, seed 5, eps 0.3, Haar
+    gauge) in the form its benchmark leg runs: one full fixed-link Coulomb
+    sweep, the links read from their per-site records (the default at this
+    size), FP64-12 or the split links (format 4).  Checked on sampled parity-1
+    sites (edges and wrap-arounds included): the oracle redoes the parity-0
+    Coulomb updates at the other ends of the site's links, then the site's own
+    update; all 8 links move, the temporal ones too.  Bar 1e-12 in FP64-12; on
+    the split links the oracle's updates take the split-stored links, whose
+    entries differ from the input by at most 2^-40 (rows 0, 1) and 4 x 2^-40
+    (row 2), so 9 x 4 x 2^-40 more per entry of g (U - U') g^dag."""
+    from lattice_np import SPLIT_UNIT, split_stored
+    from test_gpu_parity import gpu_links8, sample_sites
+    dims = (96, 48, 48, 48)
+    seed, eps, omega = 5, 0.3, 1.7
+    announce("coulomb fixed 48^3x96 sampled", fmt)
+    rng = np.random.default_rng(4)
+    split = fmt == lgf.LGF_FP64_12S
+    bar = 1e-12 + (36 * SPLIT_UNIT if split else 0.0)
+
+    def upd(links):
+        out, _ = orc.local_update_coulomb(split_stored(links) if split else links, omega, [0, 0, 0])
+        return out
+
+    with lgf.Lattice(dims, lgf.LGF_FP64_18) as lat:
+        assert lgf.lgf_get_fixed_tuning(lat.h, fmt)[3] == 1
+        lat.generate(seed, eps, True)
+        st, res, sw, F, th = lat.coulomb_gauge_fix(omega=omega, theta_target=1e-300, check_every=1, max_sweeps=1,
+                                                   fixed_links=1, bulk_format=fmt, finish_format=fmt)
+        assert st == lgf.LGF_ENOTCONV and res["sweeps"] == 1 and np.all(sw == 1)
+        ys = sample_sites(orc, dims, 1, 8, rng)
+        for y in ys:
+            links = np.zeros((8, 3, 3), dtype=np.complex128)
+            for mu in range(4):
+                links[mu] = upd(_links8(orc, dims, seed, eps, orc.neighbor(dims, y, mu, +1)))[4 + mu]
+                links[4 + mu] = upd(_links8(orc, dims, seed, eps, orc.neighbor(dims, y, mu, -1)))[mu]
+            ref = upd(links)
+            e = maxabs(gpu_links8(lat, orc, dims, y), ref)
+            assert e < bar, (y, e, bar)
+        assert np.all(np.isfinite(F)) and np.all(np.isfinite(th)) and np.all(th > 0)
+    assert len(ys) == 8
