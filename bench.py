@@ -277,6 +277,40 @@ def summarize_traffic(fetch_dir, write_dir, dims, command):
     print(json.dumps(out, indent=1))
 
 
+def mixed_bulk_summary(fmt, tuning, Vh, bulk_ms, fp64_launch_ms):
+    """The mixed form's bulk sweep (format fmt, its fixed-link tuning (lanes
+    per site, block, tile order, link layout)) at ms per launch over Vh site
+    updates, against the FP64 sweep of the step at fp64_launch_ms."""
+    lanes, block, order, layout = tuning
+    gbs = Vh * fixed_site_bytes(fmt) / (bulk_ms * 1e-3) / 1e9
+    return {"kernel": f"fixed_sweep_kernel<fp32-12, lanes/site {lanes}> block {block}, tile order "
+                      f"{TILE_ORDERS[order]}, links from the {LINK_LAYOUTS[layout]}",
+            "ms_per_launch": round(bulk_ms, 4), "site_updates_per_s": Vh / (bulk_ms * 1e-3),
+            "GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_site_update": fixed_site_bytes(fmt),
+            "site_updates_vs_fp64_sweep": round(fp64_launch_ms / bulk_ms, 3)}
+
+
+def batched_summary(ens):
+    """The line's `batched` object from the ensemble workload's output
+    (ensemble_bench): the persistent launches' rates in both sweep forms with
+    their fraction of 8 TB/s, the speed-up over one launch per lattice, and
+    the ensemble's time to theta mixed (fixed-link form) against plain FP64."""
+    out = {"workload": f"{ens['configs']} lattices of {min(ens['sizes'])}^4..{max(ens['sizes'])}^4 "
+                       f"({ens['sites']} sites, seeds 100..147), one persistent launch per parity"}
+    for prefix, key in (("", "batched_"), ("fixed_", "batched_fixed_")):
+        for name in ("fp32-12", "fp64-12"):
+            r = ens[key + name]
+            out[f"{prefix}{name}_site_updates_per_s"] = r["site_updates_per_s"]
+            out[f"{prefix}{name}_GBs"] = r["GBs"]
+            out[f"{prefix}{name}_frac_of_8TBs"] = r["GBs"] / HBM_PEAK_GBS
+    mixed_e, plain_e = ens["gauge_fix_mixed_fixed_links"]["wall_s"], ens["gauge_fix_fp64"]["wall_s"]
+    out.update({"speedup_vs_one_launch_per_lattice": ens["batched_speedup_fp32-12"],
+                "time_to_theta_mixed_s": mixed_e, "time_to_theta_fp64_s": plain_e,
+                "mixed_speedup_vs_fp64": plain_e / mixed_e})
+    return out
+
+
 def ensemble_bench(lgf, stream):
     """The 48-configuration batched workload (manifest under tests/golden):
     one persistent launch per parity over all lattices vs one launch per
@@ -778,14 +812,7 @@ def main():
     lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, 0)
     bulk_ms = sum(lgf.lgf_fix_chunk(hw, chunk, omega, 0.0, 0, chunk * (k + 1))[2] for k in range(5)) / (10 * chunk)
     lgf.lgf_fix_end(hw)
-    b_lanes, b_block, b_order, b_layout = fixed_tuning[bulk]
-    b_gbs = Vh * fixed_site_bytes(bulk) / (bulk_ms * 1e-3) / 1e9
-    mixed_bulk = {"kernel": f"fixed_sweep_kernel<fp32-12, lanes/site {b_lanes}> block {b_block}, tile order "
-                            f"{TILE_ORDERS[b_order]}, links from the {LINK_LAYOUTS[b_layout]}",
-                  "ms_per_launch": round(bulk_ms, 4), "site_updates_per_s": Vh / (bulk_ms * 1e-3),
-                  "GBs": round(b_gbs, 1), "frac_of_8TBs": round(b_gbs / HBM_PEAK_GBS, 4),
-                  "bytes_per_site_update": fixed_site_bytes(bulk),
-                  "site_updates_vs_fp64_sweep": round(launch_ms / bulk_ms, 3)}
+    mixed_bulk = mixed_bulk_summary(bulk, fixed_tuning[bulk], Vh, bulk_ms, launch_ms)
     log(f"[bench] mixed bulk sweep: {json.dumps(mixed_bulk)}")
 
     # roofline of the dominant kernel (the step's sweep), from the HIP events
@@ -866,22 +893,7 @@ def main():
     if not args.no_extras and fits("the 48-configuration ensemble", 45.0):
         ens = ensemble_bench(lgf, stream)
         extras["ensemble48"] = ens
-        b32, b64 = ens["batched_fp32-12"], ens["batched_fp64-12"]
-        f32, f64 = ens["batched_fixed_fp32-12"], ens["batched_fixed_fp64-12"]
-        mixed_e, plain_e = ens["gauge_fix_mixed_fixed_links"]["wall_s"], ens["gauge_fix_fp64"]["wall_s"]
-        batched = {"workload": f"{ens['configs']} lattices of {min(ens['sizes'])}^4..{max(ens['sizes'])}^4 "
-                               f"({ens['sites']} sites, seeds 100..147), one persistent launch per parity",
-                   "fp32-12_site_updates_per_s": b32["site_updates_per_s"], "fp32-12_GBs": b32["GBs"],
-                   "fp32-12_frac_of_8TBs": b32["GBs"] / HBM_PEAK_GBS,
-                   "fp64-12_site_updates_per_s": b64["site_updates_per_s"], "fp64-12_GBs": b64["GBs"],
-                   "fp64-12_frac_of_8TBs": b64["GBs"] / HBM_PEAK_GBS,
-                   "fixed_fp32-12_site_updates_per_s": f32["site_updates_per_s"], "fixed_fp32-12_GBs": f32["GBs"],
-                   "fixed_fp32-12_frac_of_8TBs": f32["GBs"] / HBM_PEAK_GBS,
-                   "fixed_fp64-12_site_updates_per_s": f64["site_updates_per_s"], "fixed_fp64-12_GBs": f64["GBs"],
-                   "fixed_fp64-12_frac_of_8TBs": f64["GBs"] / HBM_PEAK_GBS,
-                   "speedup_vs_one_launch_per_lattice": ens["batched_speedup_fp32-12"],
-                   "time_to_theta_mixed_s": mixed_e, "time_to_theta_fp64_s": plain_e,
-                   "mixed_speedup_vs_fp64": plain_e / mixed_e}
+        batched = batched_summary(ens)
         log(f"[bench] ensemble: {json.dumps(batched)}; {elapsed():.1f} s")
     if not args.no_extras and "mixed_s" in time_to_theta:
         # the finish on the split copy of the links (FP64 arithmetic; links

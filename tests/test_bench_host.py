@@ -100,3 +100,38 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_mixed_bulk_summary():
+    """The mixed form's bulk sweep: 528 B per FP32-12 update over the launch
+    time, its fraction of 8 TB/s and the site updates against the FP64 sweep."""
+    Vh = 64 ** 4 // 2
+    m = bench.mixed_bulk_summary(2, (1, 128, 0, 1), Vh, 0.8, 1.6)
+    assert m["bytes_per_site_update"] == 528
+    assert m["site_updates_per_s"] == pytest.approx(Vh / 0.8e-3)
+    assert m["GBs"] == pytest.approx(Vh * 528 / 0.8e-3 / 1e9, abs=0.05)
+    assert m["frac_of_8TBs"] == pytest.approx(m["GBs"] / 8000.0, abs=1e-4)
+    assert m["site_updates_vs_fp64_sweep"] == 2.0
+    assert "lanes/site 1" in m["kernel"] and "per-site link records" in m["kernel"]
+
+
+def test_batched_summary():
+    """The line's batched object from an ensemble workload's output: the rates
+    of both sweep forms with their fractions of 8 TB/s, the speed-up over one
+    launch per lattice and the mixed-vs-FP64 time to theta."""
+    rate = lambda su, gbs: {"ms_per_launch": 1.0, "site_updates_per_s": su, "GBs": gbs}
+    ens = {"configs": 48, "sites": 4860928, "sizes": [8, 12, 16, 24],
+           "batched_fp32-12": rate(6.6e9, 5040.0), "batched_fp64-12": rate(3.3e9, 5080.0),
+           "batched_fixed_fp32-12": rate(9.6e9, 5070.0), "batched_fixed_fp64-12": rate(4.8e9, 5010.0),
+           "batched_speedup_fp32-12": 1.5,
+           "gauge_fix_mixed_fixed_links": {"wall_s": 1.5}, "gauge_fix_fp64": {"wall_s": 4.05}}
+    b = bench.batched_summary(ens)
+    assert b["workload"].startswith("48 lattices of 8^4..24^4 (4860928 sites")
+    for prefix, key in (("", "batched_"), ("fixed_", "batched_fixed_")):
+        for name in ("fp32-12", "fp64-12"):
+            assert b[f"{prefix}{name}_site_updates_per_s"] == ens[key + name]["site_updates_per_s"]
+            assert b[f"{prefix}{name}_GBs"] == ens[key + name]["GBs"]
+            assert b[f"{prefix}{name}_frac_of_8TBs"] == pytest.approx(ens[key + name]["GBs"] / 8000.0)
+    assert b["speedup_vs_one_launch_per_lattice"] == 1.5
+    assert b["time_to_theta_mixed_s"] == 1.5 and b["time_to_theta_fp64_s"] == 4.05
+    assert b["mixed_speedup_vs_fp64"] == pytest.approx(2.7)
